@@ -1,0 +1,206 @@
+/*
+ * kfx -- Kalman-filter track building and fitting on AMD Instinct MI355X
+ * (gfx950).  C ABI of libkfx.so.
+ *
+ * What it computes (arXiv 2002.06295, "Reconstruction of Charged Particle
+ * Tracks in Realistic Detector Geometry Using a Vectorized and Parallelized
+ * Kalman Filter Algorithm"):
+ *   Sec. 1   the Kalman filter propagates the track state (parameters and
+ *            their uncertainties) from one layer to the next, material
+ *            effects included, then updates it with the hit's position;
+ *            track building is a combinatorial search for the hits of a
+ *            track that starts from a seed in the innermost layers and
+ *            proceeds outward; fitting applies the filter to the hits that
+ *            building found.
+ *   Sec. 2   lightweight geometry: barrel layers at their radius, forward
+ *            layers at their z, hits known by their 3D position; only the
+ *            best ranking candidates are cloned at each layer, with a
+ *            per-seed cap.
+ *   Sec. 3   missing hits are counted consistently and enter the score.
+ *
+ * Conventions.  Units cm, GeV, T, rad.  Field along +z.  Track state
+ * p = (x, y, z, k = q/pT, phi, theta) with (x, y, z) on the current surface
+ * and (phi, theta) the momentum direction there.  Covariances are the 21
+ * floats of the lower triangle of the 6x6 matrix, row-major: element (i, j),
+ * i >= j, at index i(i+1)/2 + j.
+ *
+ * Memory.  Every pointer marked "device" is HIP device memory owned by the
+ * caller (the library never frees it); host pointers are read during the
+ * call only.  The context owns its geometry and its workspaces (a pool that
+ * grows on demand and is reused; growing synchronizes the given stream).
+ * Calls are ordered on the given HIP stream (NULL = default stream) and do
+ * not synchronize otherwise; results are valid once the stream has reached
+ * them.
+ *
+ * Errors.  Every int-returning call returns KFX_OK (0) or a negative code;
+ * kfx_last_error() gives a message.  Invalid arguments are rejected before
+ * any work is queued.  A context is not thread-safe: one host thread at a
+ * time.
+ */
+#ifndef KFX_H
+#define KFX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define KFX_OK 0
+#define KFX_EINVAL (-1)     /* bad argument (sizes, NULL, non-finite, order) */
+#define KFX_EOVERFLOW (-2)  /* output capacity too small; see kfx_tracks.needed */
+#define KFX_EHIP (-3)       /* HIP runtime error */
+#define KFX_ESTATE (-4)     /* call out of order (no geometry, no hit index) */
+#define KFX_ENOMEM (-5)     /* workspace allocation failed */
+
+#define KFX_MODE_PLAIN 0    /* one kernel per piece of each step */
+#define KFX_MODE_FUSED 1    /* one persistent kernel for all steps */
+
+#define KFX_MAX_LAYERS 64
+#define KFX_MAX_CANDS 16
+#define KFX_MAX_STEPS 40
+
+typedef struct kfx_ctx kfx_ctx;
+
+/* Track states, structure of arrays over `stride` entries (device). */
+typedef struct {
+  double* pos;     /* [4][stride] x, y, z, phi (float64)                  */
+  float* kt;       /* [2][stride] k = q/pT, theta (float32)               */
+  float* cov;      /* [21][stride] packed covariance (float32)            */
+  int64_t stride;  /* entries per row; >= number of states written        */
+} kfx_states;
+
+/* Hits of one or more events, structure of arrays (device).  Hits of
+ * event e are [event_offsets[e], event_offsets[e+1]); hit indices are
+ * global.  layer[i] outside [0, n_layers) marks a hit to ignore. */
+typedef struct {
+  const float* x;
+  const float* y;
+  const float* z;
+  const int32_t* layer;
+  const int32_t* event_offsets; /* [n_events + 1], device */
+  int32_t n_hits;
+  int32_t n_events;
+} kfx_hits;
+
+/* Prior covariance of the three-hit start estimate: diagonal with
+ * sigma_pos^2 on x, y, z, (sk_rel |k|)^2, sigma_phi^2, sigma_theta^2. */
+typedef struct {
+  float spos, sk_rel, sphi, stheta;
+} kfx_prior;
+
+typedef struct {
+  float chi2_cut;        /* keep candidate-hit pairs with 3x3 chi2 < cut      */
+  int32_t max_cands;     /* K: candidates kept per seed, 1..KFX_MAX_CANDS     */
+  int32_t max_holes;     /* a hole child is offered while consecutive holes
+                            are below this                                    */
+  int32_t max_steps;     /* surfaces searched after the seed, 1..KFX_MAX_STEPS */
+  kfx_prior prior;
+  int32_t mode;          /* KFX_MODE_PLAIN or KFX_MODE_FUSED                  */
+  int32_t block_threads; /* fused: threads per block, 64..256, multiple of 64;
+                            0 = library choice                                */
+  int32_t blocks;        /* fused: persistent blocks; 0 = library choice      */
+} kfx_build_params;
+
+/* Output of building, per seed s and slot j < K, best first (device). */
+typedef struct {
+  int32_t* n_cands;  /* [S] candidates kept                                   */
+  int32_t* hits;     /* [S][K][max_hits]: the 3 seed hits, then one entry per
+                        surface reached (hit index, or -1 for a hole);
+                        unused entries -3                                     */
+  int32_t* n_hits;   /* [S][K]                                               */
+  int32_t* n_holes;  /* [S][K]                                               */
+  float* chi2;       /* [S][K] total chi2 (seed hits included)               */
+  kfx_states state;  /* S*K entries: state on the last surface reached       */
+  uint64_t* stats;   /* [3] device, added to: steps (candidate-surface pairs
+                        propagated), compatible pairs, Kalman updates        */
+  int32_t max_hits;  /* capacity of each hit list (>= 3)                     */
+  int64_t capacity;  /* candidate entries allocated in the arrays (>= S*K)   */
+  int64_t needed;    /* written on KFX_EOVERFLOW: entries required           */
+} kfx_tracks;
+
+/* Create a context on HIP device `device`.  *out receives the handle. */
+int kfx_create(int device, kfx_ctx** out);
+
+/* Release the context and its workspaces.  NULL is ignored.  The caller
+ * must make sure no queued work still uses the context. */
+void kfx_destroy(kfx_ctx* ctx);
+
+/* Last error message of this context ("" if none; never NULL). */
+const char* kfx_last_error(const kfx_ctx* ctx);
+
+/* Load the geometry (Sec. 2: barrel cylinders at a radius, disks at a z).
+ * table: host float64 [n_layers][8] rows (kind 0 barrel / 1 disk, pos = R
+ * or Z, lo, hi = z bounds (barrel) or r bounds (disk), x/X0, sigma_u,
+ * sigma_v, sigma_n), with u = r*phi direction, v = z (barrel) or r (disk),
+ * n = surface normal.  bz: field [T].  n_eta x n_phi: hit bins per layer.
+ * Copied; the caller may free the table.  KFX_EINVAL on more than
+ * KFX_MAX_LAYERS layers, non-finite values, lo >= hi, a barrel radius or
+ * disk bound <= 0, duplicate barrel radii or duplicate disk positions. */
+int kfx_load_layers(kfx_ctx* ctx, const double* table, int n_layers, double bz, int n_eta,
+                    int n_phi);
+
+/* Hit index (Sec. 2 works with 3D hit positions; the (eta, phi) binning is
+ * this library's index): bin of each hit, eta_bin * n_phi + phi_bin, in
+ * FP64 from the FP32 coordinates, and a stable counting sort by
+ * (event, layer, bin).  The index stays in the context for
+ * kfx_step_compat on the same hits.  Optional device outputs (NULL to
+ * skip): bin_out [n_hits] (-1 for ignored hits), offsets_out
+ * [n_events * n_layers * n_eta * n_phi + 1], perm_out [n_hits] (hit
+ * indices in index order; entries past offsets_out[last] unused). */
+int kfx_bin_hits(kfx_ctx* ctx, const kfx_hits* hits, int32_t* bin_out, int32_t* offsets_out,
+                 int32_t* perm_out, void* stream);
+
+/* Start states of seeds (Sec. 1: seeds from the innermost layers): a
+ * three-hit helix estimate at hit 1 with the prior covariance, then the
+ * Kalman filter over the three hits.  seeds: device int32 [n][3] hit
+ * indices.  out: state at hit 3; chi2 [n]; status [n] 1 = ok, 0 = failed
+ * (a seed hit off the geometry or a surface not reached). */
+int kfx_seed_states(kfx_ctx* ctx, const kfx_hits* hits, const int32_t* seeds, int32_t n,
+                    const kfx_prior* prior, kfx_states* out, float* chi2, int32_t* status,
+                    void* stream);
+
+/* One building step on given states (device inputs): navigate from
+ * cand_layer to the next surface, propagate with material noise, and list
+ * every hit of that surface in event cand_event with chi2 < chi2_cut,
+ * ascending hit index.  Needs kfx_bin_hits on the same hits first
+ * (KFX_ESTATE otherwise).  Outputs (device): next_layer [n] (-1: none),
+ * pred (predicted states), pair_count [n] (all compatible hits, may exceed
+ * max_pairs), pair_hit / pair_chi2 [n][max_pairs]. */
+int kfx_step_compat(kfx_ctx* ctx, const kfx_hits* hits, const int32_t* cand_event,
+                    const int32_t* cand_layer, const kfx_states* in, int32_t n, float chi2_cut,
+                    int32_t* next_layer, kfx_states* pred, int32_t* pair_count, int32_t* pair_hit,
+                    float* pair_chi2, int32_t max_pairs, void* stream);
+
+/* Track building (Sec. 1-3).  seeds: device int32 [n_seeds][3];
+ * seed_event: device int32 [n_seeds].  Bins the hits, starts every seed,
+ * then per step keeps the best K children of each seed.  KFX_EOVERFLOW
+ * (with out->needed) when out->capacity < n_seeds * K. */
+int kfx_build_tracks(kfx_ctx* ctx, const kfx_hits* hits, const int32_t* seeds,
+                     const int32_t* seed_event, int32_t n_seeds, const kfx_build_params* params,
+                     kfx_tracks* out, void* stream);
+
+/* Track fit (Sec. 1): the Kalman filter over fixed hit lists.  trk_off:
+ * device int32 [n_tracks+1] into trk_hits (device int32 hit indices in
+ * crossing order).  Starts at hit 1 from the three-hit estimate with the
+ * prior, updates at hit 1, then propagates and updates through hit N.
+ * align: device float32 [3 n_layers] (dr, drphi, dz) per layer or NULL;
+ * for a barrel layer the hit moves to ((R+dr) cos(phi+drphi/R),
+ * (R+dr) sin(phi+drphi/R), z+dz) and the track is propagated to radius
+ * R+dr (disks are not aligned).  The field is bz * field_scale.
+ * Outputs (device): state at hit N, chi2 [n] (float32, accumulated in
+ * float64), ndof [n] = 2N - 5, status [n]: 1 ok, 0 failed (fewer than 3
+ * hits, a hit off the geometry, a surface not reached), -1 checkpoint
+ * capacity too small for this track.  ckpt: NULL, or states with stride
+ * >= trk_off[n_tracks] receiving the filtered state after every hit
+ * (entry trk_off[t] + i). */
+int kfx_fit_tracks(kfx_ctx* ctx, const kfx_hits* hits, const int32_t* trk_off,
+                   const int32_t* trk_hits, int32_t n_tracks, const kfx_prior* prior,
+                   const float* align, float field_scale, kfx_states* out, float* chi2,
+                   int32_t* ndof, int32_t* status, kfx_states* ckpt, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KFX_H */

@@ -504,7 +504,7 @@ static int phi_bin_of(const Geom& g, double phi) {
 
 static double hit_eta(const Layer& Lr, double x, double y, double z) {
   if (Lr.kind == BARREL) return std::asinh(z / Lr.pos);
-  return std::asinh(Lr.pos / std::hypot(x, y));
+  return std::asinh(Lr.pos / std::sqrt(x * x + y * y));  // r of a float32 hit
 }
 
 static int hit_bin(const Geom& g, int layer, double x, double y, double z) {

@@ -1,0 +1,471 @@
+// C ABI of libkfx.so (declared in include/kfx.h): argument checks, the
+// context (geometry + workspace pool) and the calls into the kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/kfx.h"
+#include "kfx_internal.h"
+
+using namespace kfx;
+
+struct kfx_ctx {
+  int device = 0;
+  std::string err;
+  Geometry host_geo{};
+  Geometry* dev_geo = nullptr;
+  bool have_geo = false;
+  // workspace pool: named device buffers, grown on demand
+  std::map<std::string, std::pair<void*, size_t>> pool;
+  // hit index of the last kfx_bin_hits / kfx_build_tracks call
+  bool have_index = false;
+  const void* index_hits_key[3] = {nullptr, nullptr, nullptr};
+  int index_n_hits = -1, index_n_events = -1;
+  BinWork bw{};
+};
+
+namespace {
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    (void)hipGetDevice(&prev);
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    (void)hipGetDevice(&cur);
+    if (prev >= 0 && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+int fail(kfx_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+int hip_check(kfx_ctx* c, hipError_t e, const char* what) {
+  if (e == hipSuccess) return KFX_OK;
+  return fail(c, KFX_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Named workspace of at least `bytes`, 256-byte aligned.  Growing waits for
+// the stream so that queued work never sees a freed buffer.
+void* ws(kfx_ctx* c, const char* name, size_t bytes, hipStream_t st, int& rc) {
+  rc = KFX_OK;
+  bytes = std::max<size_t>(bytes, 256);
+  auto it = c->pool.find(name);
+  if (it != c->pool.end() && it->second.second >= bytes) return it->second.first;
+  if (it != c->pool.end()) {
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(it->second.first);
+    c->pool.erase(it);
+  }
+  void* p = nullptr;
+  const size_t grown = bytes + bytes / 4;
+  if (hipMalloc(&p, grown) != hipSuccess) {
+    rc = fail(c, KFX_ENOMEM, std::string("workspace allocation failed: ") + name);
+    return nullptr;
+  }
+  c->pool[name] = {p, grown};
+  return p;
+}
+
+bool is_finite(double v) { return std::isfinite(v); }
+
+int check_hits(kfx_ctx* c, const kfx_hits* h) {
+  if (!h) return fail(c, KFX_EINVAL, "hits is NULL");
+  if (h->n_hits < 0 || h->n_events < 1) return fail(c, KFX_EINVAL, "n_hits < 0 or n_events < 1");
+  if (h->n_hits > 0 && (!h->x || !h->y || !h->z || !h->layer))
+    return fail(c, KFX_EINVAL, "hit arrays must not be NULL");
+  if (!h->event_offsets) return fail(c, KFX_EINVAL, "event_offsets is NULL");
+  return KFX_OK;
+}
+
+HitsView view(const kfx_hits* h) {
+  HitsView v;
+  v.x = h->x;
+  v.y = h->y;
+  v.z = h->z;
+  v.layer = h->layer;
+  v.ev_off = h->event_offsets;
+  v.n_hits = h->n_hits;
+  v.n_events = h->n_events;
+  return v;
+}
+
+StateSoA soa(const kfx_states* s) {
+  StateSoA a;
+  a.pos = s->pos;
+  a.kt = s->kt;
+  a.cov = s->cov;
+  a.stride = (long)s->stride;
+  return a;
+}
+
+int check_states(kfx_ctx* c, const kfx_states* s, long n, const char* what) {
+  if (!s || !s->pos || !s->kt || !s->cov) return fail(c, KFX_EINVAL, std::string(what) + ": NULL state arrays");
+  if (s->stride < n) return fail(c, KFX_EINVAL, std::string(what) + ": stride smaller than the entry count");
+  return KFX_OK;
+}
+
+Prior prior_of(const kfx_prior* p) {
+  Prior r;
+  r.spos = p->spos;
+  r.sk_rel = p->sk_rel;
+  r.sphi = p->sphi;
+  r.stheta = p->stheta;
+  return r;
+}
+
+int check_prior(kfx_ctx* c, const kfx_prior* p) {
+  if (!p) return fail(c, KFX_EINVAL, "prior is NULL");
+  const float v[4] = {p->spos, p->sk_rel, p->sphi, p->stheta};
+  for (float x : v)
+    if (!std::isfinite(x) || x < 0.0f) return fail(c, KFX_EINVAL, "prior must be finite and >= 0");
+  return KFX_OK;
+}
+
+// Build the hit index into the context workspace.
+int build_index(kfx_ctx* c, const kfx_hits* h, int32_t* bin_out, hipStream_t st) {
+  const Geometry& G = c->host_geo;
+  const long nb = (long)G.n_eta * G.n_phi;
+  const long n_keys = (long)h->n_events * G.n_layers * nb;
+  if (n_keys >= (1L << 31) - 2) return fail(c, KFX_EINVAL, "events x layers x bins exceeds 2^31");
+  int rc;
+  BinWork& w = c->bw;
+  const long nh = std::max<long>(h->n_hits, 1);
+  w.key = (int*)ws(c, "bin.key", nh * 4, st, rc); if (rc) return rc;
+  w.counts = (int*)ws(c, "bin.counts", (n_keys + 1) * 4, st, rc); if (rc) return rc;
+  w.fill = (int*)ws(c, "bin.fill", (n_keys + 1) * 4, st, rc); if (rc) return rc;
+  w.off = (int*)ws(c, "bin.off", (n_keys + 2) * 4, st, rc); if (rc) return rc;
+  w.perm = (int*)ws(c, "bin.perm", nh * 4, st, rc); if (rc) return rc;
+  w.sorted = (float4*)ws(c, "bin.sorted", nh * 16, st, rc); if (rc) return rc;
+  w.scan_scratch = (int*)ws(c, "bin.scan", ((n_keys + 1) / 4096 + 4) * 4, st, rc); if (rc) return rc;
+  launch_bin(c->dev_geo, view(h), G.n_layers, (int)nb, w, bin_out, st);
+  if ((rc = hip_check(c, hipGetLastError(), "binning kernels"))) return rc;
+  c->have_index = true;
+  c->index_hits_key[0] = h->x;
+  c->index_hits_key[1] = h->layer;
+  c->index_hits_key[2] = h->event_offsets;
+  c->index_n_hits = h->n_hits;
+  c->index_n_events = h->n_events;
+  return KFX_OK;
+}
+
+BinIndex index_view(const kfx_ctx* c) {
+  BinIndex B;
+  B.off = c->bw.off;
+  B.sorted = c->bw.sorted;
+  B.n_layers = c->host_geo.n_layers;
+  B.n_bins = c->host_geo.n_eta * c->host_geo.n_phi;
+  return B;
+}
+
+}  // namespace
+
+extern "C" {
+
+int kfx_create(int device, kfx_ctx** out) {
+  if (!out) return KFX_EINVAL;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) return KFX_EHIP;
+  if (device < 0 || device >= n) return KFX_EINVAL;
+  kfx_ctx* c = new kfx_ctx();
+  c->device = device;
+  *out = c;
+  return KFX_OK;
+}
+
+void kfx_destroy(kfx_ctx* c) {
+  if (!c) return;
+  {
+    DeviceGuard g(c->device);
+    for (auto& kv : c->pool) (void)hipFree(kv.second.first);
+    if (c->dev_geo) (void)hipFree(c->dev_geo);
+  }
+  delete c;
+}
+
+const char* kfx_last_error(const kfx_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int kfx_load_layers(kfx_ctx* c, const double* table, int n_layers, double bz, int n_eta, int n_phi) {
+  if (!c) return KFX_EINVAL;
+  c->err.clear();
+  if (!table) return fail(c, KFX_EINVAL, "layer table is NULL");
+  if (n_layers < 1 || n_layers > KFX_MAX_LAYERS) return fail(c, KFX_EINVAL, "n_layers out of range");
+  if (n_eta < 1 || n_phi < 1 || n_eta > 4096 || n_phi > 4096) return fail(c, KFX_EINVAL, "bad bin counts");
+  if (!is_finite(bz)) return fail(c, KFX_EINVAL, "non-finite field");
+  Geometry G{};
+  G.n_layers = n_layers;
+  G.bz = bz;
+  G.n_eta = n_eta;
+  G.n_phi = n_phi;
+  std::vector<int> bar, dp, dn;
+  for (int i = 0; i < n_layers; ++i) {
+    const double* r = table + 8 * i;
+    for (int j = 0; j < 8; ++j)
+      if (!is_finite(r[j])) return fail(c, KFX_EINVAL, "non-finite layer table entry");
+    Layer& L = G.L[i];
+    const int kind = (int)r[0];
+    if ((kind != kBarrel && kind != kDisk) || (double)kind != r[0]) return fail(c, KFX_EINVAL, "layer kind must be 0 or 1");
+    L.kind = kind;
+    L.pos = r[1];
+    L.lo = r[2];
+    L.hi = r[3];
+    if (!(L.lo < L.hi)) return fail(c, KFX_EINVAL, "layer lo >= hi");
+    if (r[4] < 0 || r[5] <= 0 || r[6] <= 0 || r[7] <= 0) return fail(c, KFX_EINVAL, "x/X0 < 0 or sigma <= 0");
+    L.x0 = (float)r[4];
+    L.v_u = (float)(r[5] * r[5]);
+    L.v_v = (float)(r[6] * r[6]);
+    L.v_n = (float)(r[7] * r[7]);
+    if (kind == kBarrel) {
+      if (!(L.pos > 0)) return fail(c, KFX_EINVAL, "barrel radius <= 0");
+      L.side = 0;
+      L.eta_lo = std::asinh(L.lo / L.pos);
+      L.eta_hi = std::asinh(L.hi / L.pos);
+      bar.push_back(i);
+    } else {
+      if (L.pos == 0 || !(L.lo > 0)) return fail(c, KFX_EINVAL, "disk at z = 0 or r bound <= 0");
+      L.side = L.pos > 0 ? 1 : -1;
+      const double a = std::asinh(L.pos / L.hi), b = std::asinh(L.pos / L.lo);
+      L.eta_lo = std::min(a, b);
+      L.eta_hi = std::max(a, b);
+      (L.pos > 0 ? dp : dn).push_back(i);
+    }
+  }
+  std::sort(bar.begin(), bar.end(), [&](int a, int b) { return G.L[a].pos < G.L[b].pos; });
+  std::sort(dp.begin(), dp.end(), [&](int a, int b) { return G.L[a].pos < G.L[b].pos; });
+  std::sort(dn.begin(), dn.end(), [&](int a, int b) { return G.L[a].pos > G.L[b].pos; });
+  for (size_t i = 1; i < bar.size(); ++i)
+    if (G.L[bar[i]].pos == G.L[bar[i - 1]].pos) return fail(c, KFX_EINVAL, "duplicate barrel radius");
+  for (size_t i = 1; i < dp.size(); ++i)
+    if (G.L[dp[i]].pos == G.L[dp[i - 1]].pos) return fail(c, KFX_EINVAL, "duplicate disk position");
+  for (size_t i = 1; i < dn.size(); ++i)
+    if (G.L[dn[i]].pos == G.L[dn[i - 1]].pos) return fail(c, KFX_EINVAL, "duplicate disk position");
+  G.n_barrel = (int)bar.size();
+  G.n_dpos = (int)dp.size();
+  G.n_dneg = (int)dn.size();
+  for (int i = 0; i < kMaxLayers; ++i) G.next_barrel[i] = -1;
+  for (size_t i = 0; i < bar.size(); ++i) {
+    G.barrel[i] = bar[i];
+    G.next_barrel[bar[i]] = (i + 1 < bar.size()) ? bar[i + 1] : -1;
+  }
+  for (size_t i = 0; i < dp.size(); ++i) G.dpos[i] = dp[i];
+  for (size_t i = 0; i < dn.size(); ++i) G.dneg[i] = dn[i];
+  DeviceGuard dg(c->device);
+  if (!c->dev_geo) {
+    if (hipMalloc(&c->dev_geo, sizeof(Geometry)) != hipSuccess) return fail(c, KFX_ENOMEM, "geometry allocation");
+  }
+  int rc = hip_check(c, hipMemcpy(c->dev_geo, &G, sizeof(Geometry), hipMemcpyHostToDevice), "geometry upload");
+  if (rc) return rc;
+  c->host_geo = G;
+  c->have_geo = true;
+  c->have_index = false;
+  return KFX_OK;
+}
+
+int kfx_bin_hits(kfx_ctx* c, const kfx_hits* hits, int32_t* bin_out, int32_t* offsets_out, int32_t* perm_out,
+                 void* stream) {
+  if (!c) return KFX_EINVAL;
+  c->err.clear();
+  if (!c->have_geo) return fail(c, KFX_ESTATE, "kfx_load_layers first");
+  int rc = check_hits(c, hits);
+  if (rc) return rc;
+  DeviceGuard dg(c->device);
+  hipStream_t st = (hipStream_t)stream;
+  if ((rc = build_index(c, hits, bin_out, st))) return rc;
+  const long n_keys = (long)hits->n_events * c->host_geo.n_layers * c->host_geo.n_eta * c->host_geo.n_phi;
+  if (offsets_out &&
+      (rc = hip_check(c, hipMemcpyAsync(offsets_out, c->bw.off, (n_keys + 1) * 4, hipMemcpyDeviceToDevice, st),
+                      "offsets copy")))
+    return rc;
+  if (perm_out && hits->n_hits > 0 &&
+      (rc = hip_check(c, hipMemcpyAsync(perm_out, c->bw.perm, (size_t)hits->n_hits * 4, hipMemcpyDeviceToDevice, st),
+                      "perm copy")))
+    return rc;
+  return KFX_OK;
+}
+
+int kfx_seed_states(kfx_ctx* c, const kfx_hits* hits, const int32_t* seeds, int32_t n, const kfx_prior* prior,
+                    kfx_states* out, float* chi2, int32_t* status, void* stream) {
+  if (!c) return KFX_EINVAL;
+  c->err.clear();
+  if (!c->have_geo) return fail(c, KFX_ESTATE, "kfx_load_layers first");
+  int rc = check_hits(c, hits);
+  if (rc || (rc = check_prior(c, prior))) return rc;
+  if (n < 0) return fail(c, KFX_EINVAL, "n < 0");
+  if (n > 0 && (!seeds || !chi2 || !status)) return fail(c, KFX_EINVAL, "NULL seed arrays");
+  if ((rc = check_states(c, out, n, "out"))) return rc;
+  DeviceGuard dg(c->device);
+  hipStream_t st = (hipStream_t)stream;
+  launch_seed_states(c->dev_geo, view(hits), seeds, n, prior_of(prior), soa(out), chi2, status, st);
+  return hip_check(c, hipGetLastError(), "seed kernel");
+}
+
+int kfx_step_compat(kfx_ctx* c, const kfx_hits* hits, const int32_t* cand_event, const int32_t* cand_layer,
+                    const kfx_states* in, int32_t n, float chi2_cut, int32_t* next_layer, kfx_states* pred,
+                    int32_t* pair_count, int32_t* pair_hit, float* pair_chi2, int32_t max_pairs, void* stream) {
+  if (!c) return KFX_EINVAL;
+  c->err.clear();
+  if (!c->have_geo) return fail(c, KFX_ESTATE, "kfx_load_layers first");
+  int rc = check_hits(c, hits);
+  if (rc) return rc;
+  if (!c->have_index || c->index_hits_key[0] != hits->x || c->index_hits_key[1] != hits->layer ||
+      c->index_hits_key[2] != hits->event_offsets || c->index_n_hits != hits->n_hits ||
+      c->index_n_events != hits->n_events)
+    return fail(c, KFX_ESTATE, "kfx_bin_hits on these hits first");
+  if (n < 0 || max_pairs < 0) return fail(c, KFX_EINVAL, "n or max_pairs < 0");
+  if (!(chi2_cut > 0.0f) || !std::isfinite(chi2_cut)) return fail(c, KFX_EINVAL, "chi2_cut must be finite and > 0");
+  if (n > 0 && (!cand_event || !cand_layer || !next_layer || !pair_count || (max_pairs > 0 && (!pair_hit || !pair_chi2))))
+    return fail(c, KFX_EINVAL, "NULL arrays");
+  if ((rc = check_states(c, in, n, "in")) || (rc = check_states(c, pred, n, "pred"))) return rc;
+  DeviceGuard dg(c->device);
+  hipStream_t st = (hipStream_t)stream;
+  launch_step_compat(c->dev_geo, view(hits), index_view(c), cand_event, cand_layer, soa(in), n, chi2_cut, next_layer,
+                     soa(pred), pair_count, pair_hit, pair_chi2, max_pairs, st);
+  return hip_check(c, hipGetLastError(), "step kernel");
+}
+
+int kfx_build_tracks(kfx_ctx* c, const kfx_hits* hits, const int32_t* seeds, const int32_t* seed_event,
+                     int32_t n_seeds, const kfx_build_params* p, kfx_tracks* out, void* stream) {
+  if (!c) return KFX_EINVAL;
+  c->err.clear();
+  if (!c->have_geo) return fail(c, KFX_ESTATE, "kfx_load_layers first");
+  int rc = check_hits(c, hits);
+  if (rc) return rc;
+  if (!p || !out) return fail(c, KFX_EINVAL, "params or out is NULL");
+  if ((rc = check_prior(c, &p->prior))) return rc;
+  if (n_seeds < 0) return fail(c, KFX_EINVAL, "n_seeds < 0");
+  if (p->max_cands < 1 || p->max_cands > KFX_MAX_CANDS) return fail(c, KFX_EINVAL, "max_cands out of [1, 16]");
+  if (p->max_steps < 1 || p->max_steps > KFX_MAX_STEPS) return fail(c, KFX_EINVAL, "max_steps out of [1, 40]");
+  if (p->max_holes < 0 || p->max_holes > 200) return fail(c, KFX_EINVAL, "max_holes out of range");
+  if (!(p->chi2_cut > 0.0f) || !std::isfinite(p->chi2_cut)) return fail(c, KFX_EINVAL, "chi2_cut must be finite and > 0");
+  if (p->mode != KFX_MODE_PLAIN && p->mode != KFX_MODE_FUSED) return fail(c, KFX_EINVAL, "unknown mode");
+  if (p->block_threads != 0 && (p->block_threads < 64 || p->block_threads > 256 || p->block_threads % 64))
+    return fail(c, KFX_EINVAL, "block_threads must be 0 or a multiple of 64 in [64, 256]");
+  if (p->blocks < 0) return fail(c, KFX_EINVAL, "blocks < 0");
+  const int K = p->max_cands;
+  const long SK = (long)n_seeds * K;
+  if (out->capacity < SK) {
+    out->needed = SK;
+    return fail(c, KFX_EOVERFLOW, "output capacity below n_seeds * max_cands");
+  }
+  if (out->max_hits < kSeedHits) return fail(c, KFX_EINVAL, "max_hits < 3");
+  if (n_seeds > 0 && (!seeds || !seed_event || !out->n_cands || !out->hits || !out->n_hits || !out->n_holes ||
+                      !out->chi2 || !out->stats))
+    return fail(c, KFX_EINVAL, "NULL seed or output arrays");
+  if ((rc = check_states(c, &out->state, SK, "out.state"))) return rc;
+  DeviceGuard dg(c->device);
+  hipStream_t st = (hipStream_t)stream;
+  if ((rc = build_index(c, hits, nullptr, st))) return rc;
+  if (n_seeds == 0) return KFX_OK;
+
+  BuildArgs a{};
+  a.G = c->dev_geo;
+  a.H = view(hits);
+  a.B = index_view(c);
+  a.seeds = seeds;
+  a.seed_event = seed_event;
+  a.n_seeds = n_seeds;
+  a.prior = prior_of(&p->prior);
+  a.cut = p->chi2_cut;
+  a.K = K;
+  a.max_holes = p->max_holes;
+  a.max_steps = p->max_steps;
+  const long N = std::max<long>(SK, 1);
+  auto alloc_states = [&](const char* name, StateSoA& s) -> int {
+    char* base = (char*)ws(c, name, (size_t)N * (4 * 8 + 2 * 4 + 21 * 4), st, rc);
+    if (rc) return rc;
+    s.pos = (double*)base;
+    s.kt = (float*)(base + (size_t)N * 32);
+    s.cov = (float*)(base + (size_t)N * 40);
+    s.stride = N;
+    return KFX_OK;
+  };
+  if ((rc = alloc_states("b.cand0", a.cand[0])) || (rc = alloc_states("b.cand1", a.cand[1])) ||
+      (rc = alloc_states("b.pred", a.pred)))
+    return rc;
+  a.layer[0] = (int*)ws(c, "b.layer0", N * 4, st, rc); if (rc) return rc;
+  a.layer[1] = (int*)ws(c, "b.layer1", N * 4, st, rc); if (rc) return rc;
+  a.chi2[0] = (float*)ws(c, "b.chi20", N * 4, st, rc); if (rc) return rc;
+  a.chi2[1] = (float*)ws(c, "b.chi21", N * 4, st, rc); if (rc) return rc;
+  a.meta[0] = (int*)ws(c, "b.meta0", N * 4, st, rc); if (rc) return rc;
+  a.meta[1] = (int*)ws(c, "b.meta1", N * 4, st, rc); if (rc) return rc;
+  a.next_layer = (int*)ws(c, "b.next", N * 4, st, rc); if (rc) return rc;
+  a.kid_c = (float*)ws(c, "b.kidc", N * K * 4, st, rc); if (rc) return rc;
+  a.kid_h = (int*)ws(c, "b.kidh", N * K * 4, st, rc); if (rc) return rc;
+  a.kid_n = (int*)ws(c, "b.kidn", N * 4, st, rc); if (rc) return rc;
+  a.sel_parent = (int*)ws(c, "b.selp", N * 4, st, rc); if (rc) return rc;
+  a.sel_code = (int*)ws(c, "b.selc", N * 4, st, rc); if (rc) return rc;
+  a.sel_chi2 = (float*)ws(c, "b.selx", N * 4, st, rc); if (rc) return rc;
+  a.hist_parent = (signed char*)ws(c, "b.histp", (size_t)N * p->max_steps, st, rc); if (rc) return rc;
+  a.hist_code = (int*)ws(c, "b.histc", (size_t)N * p->max_steps * 4, st, rc); if (rc) return rc;
+  a.n_steps = (int*)ws(c, "b.nsteps", (size_t)std::max(n_seeds, 1) * 4, st, rc); if (rc) return rc;
+  a.stats = (unsigned long long*)out->stats;
+
+  TracksOut o;
+  o.n_cands = out->n_cands;
+  o.hits = out->hits;
+  o.n_hits = out->n_hits;
+  o.n_holes = out->n_holes;
+  o.chi2 = out->chi2;
+  o.state = soa(&out->state);
+  o.max_hits = out->max_hits;
+
+  if (p->mode == KFX_MODE_PLAIN) {
+    launch_build_plain(a, o, st);
+  } else {
+    int* counter = (int*)ws(c, "b.counter", 256, st, rc);
+    if (rc) return rc;
+    const int threads = p->block_threads ? p->block_threads : 256;
+    int blocks = p->blocks;
+    if (blocks == 0) {
+      hipDeviceProp_t prop;
+      if (hipGetDeviceProperties(&prop, c->device) != hipSuccess) prop.multiProcessorCount = 256;
+      blocks = prop.multiProcessorCount * 4;
+    }
+    // no more groups than seeds need
+    const int groups_per_block = threads / fused_lanes_for(K) ;
+    const long max_blocks = (n_seeds + groups_per_block - 1) / groups_per_block;
+    blocks = (int)std::max<long>(1, std::min<long>(blocks, max_blocks));
+    launch_build_fused(a, o, counter, blocks, threads, st);
+  }
+  return hip_check(c, hipGetLastError(), "build kernels");
+}
+
+int kfx_fit_tracks(kfx_ctx* c, const kfx_hits* hits, const int32_t* trk_off, const int32_t* trk_hits,
+                   int32_t n_tracks, const kfx_prior* prior, const float* align, float field_scale,
+                   kfx_states* out, float* chi2, int32_t* ndof, int32_t* status, kfx_states* ckpt, void* stream) {
+  if (!c) return KFX_EINVAL;
+  c->err.clear();
+  if (!c->have_geo) return fail(c, KFX_ESTATE, "kfx_load_layers first");
+  int rc = check_hits(c, hits);
+  if (rc || (rc = check_prior(c, prior))) return rc;
+  if (n_tracks < 0) return fail(c, KFX_EINVAL, "n_tracks < 0");
+  if (!std::isfinite(field_scale)) return fail(c, KFX_EINVAL, "non-finite field scale");
+  if (n_tracks > 0 && (!trk_off || !trk_hits || !chi2 || !ndof || !status))
+    return fail(c, KFX_EINVAL, "NULL track arrays");
+  if ((rc = check_states(c, out, n_tracks, "out"))) return rc;
+  if (ckpt && (!ckpt->pos || !ckpt->kt || !ckpt->cov)) return fail(c, KFX_EINVAL, "ckpt: NULL state arrays");
+  DeviceGuard dg(c->device);
+  hipStream_t st = (hipStream_t)stream;
+  FitOut o;
+  o.state = soa(out);
+  o.chi2 = chi2;
+  o.ndof = ndof;
+  o.status = status;
+  if (ckpt) o.ckpt = soa(ckpt);
+  else o.ckpt.pos = nullptr, o.ckpt.kt = nullptr, o.ckpt.cov = nullptr, o.ckpt.stride = 0;
+  launch_fit(c->dev_geo, view(hits), trk_off, trk_hits, n_tracks, prior_of(prior), align, field_scale, o, st);
+  return hip_check(c, hipGetLastError(), "fit kernel");
+}
+
+}  // extern "C"

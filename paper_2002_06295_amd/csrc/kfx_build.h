@@ -1,0 +1,330 @@
+// Track building work items: the beam search of Sec. 1-3 of the paper
+// (arXiv 2002.06295) as four per-step pieces shared by the plain per-step
+// kernels and the fused persistent kernel.
+//
+// Per step every live candidate of a seed is moved to its next surface,
+// offers children (one per compatible hit, a hole child while its
+// consecutive holes stay below the limit, or a stop child when it cannot
+// continue), and the seed keeps the best K children by the ranking key of
+// child_key().  Kept hit children get the Kalman update.
+#pragma once
+
+#include "kfx_work.h"
+
+namespace kfx {
+
+struct BuildArgs {
+  const Geometry* G;
+  HitsView H;
+  BinIndex B;
+  const int* seeds;       // [S][3]
+  const int* seed_event;  // [S]
+  int n_seeds;
+  Prior prior;
+  float cut;
+  int K;
+  int max_holes;
+  int max_steps;
+  // candidate slots (S K), two buffers used in turn
+  StateSoA cand[2];
+  int* layer[2];
+  float* chi2[2];
+  int* meta[2];
+  // predicted state of each slot and its surface (-1 none, -2 empty slot)
+  StateSoA pred;
+  int* next_layer;
+  // best K children (chi2, hit) of each slot and their count
+  float* kid_c;
+  int* kid_h;
+  int* kid_n;
+  // selection for each new slot: parent slot (-1 empty), child code, chi2
+  int* sel_parent;
+  int* sel_code;
+  float* sel_chi2;
+  // history, per seed: [S][max_steps][K] parent slot and child code
+  signed char* hist_parent;
+  int* hist_code;
+  int* n_steps;           // [S] steps recorded
+  unsigned long long* stats;  // steps, pairs, updates
+};
+
+KFX_HD long hist_index(const BuildArgs& a, int seed, int t, int slot) {
+  return ((long)seed * a.max_steps + t) * a.K + slot;
+}
+
+// Step 0: the seed state in slot 0 of each seed, other slots empty.
+KFX_HD void init_seed_slots(const BuildArgs& a, int s) {
+  const int* sh = a.seeds + 3 * s;
+  State st;
+  float c2 = 0.0f;
+  const int ev = a.seed_event[s];
+  const bool ok = ev >= 0 && ev < a.H.n_events && seed_state(*a.G, a.H, sh, a.prior, st, c2);
+  for (int j = 0; j < a.K; ++j) {
+    const long slot = (long)s * a.K + j;
+    if (j == 0 && ok) {
+      store_state(a.cand[0], slot, st);
+      a.layer[0][slot] = a.H.layer[sh[2]];
+      a.chi2[0][slot] = c2;
+      a.meta[0][slot] = meta_pack(kSeedHits, 0, 0, kFlagLive);
+    } else {
+      a.meta[0][slot] = 0;
+      a.layer[0][slot] = -1;
+      a.chi2[0][slot] = 0.0f;
+    }
+  }
+  a.n_steps[s] = 0;
+}
+
+// (a) navigate + transport (+ material) of one slot.  Returns 1 when a
+// step was taken (a candidate moved to a surface).
+KFX_HD int predict_slot(const BuildArgs& a, int cur, long slot) {
+  const int m = a.meta[cur][slot];
+  if (!(meta_flags(m) & kFlagLive)) {
+    a.next_layer[slot] = -2;
+    return 0;
+  }
+  if (meta_flags(m) & kFlagDone) {
+    a.next_layer[slot] = -1;
+    return 0;
+  }
+  const Geometry& G = *a.G;
+  State st, pr;
+  load_state(a.cand[cur], slot, st);
+  const double cphi = cos(st.phi), sphi = sin(st.phi);
+  const float kappa = -kHc * (float)G.bz;
+  float s = 0.0f;
+  const int nl = navigate(G, a.layer[cur][slot], st, cphi, sphi, kappa * st.k, s);
+  if (nl < 0) {
+    a.next_layer[slot] = -1;
+    return 0;
+  }
+  transport(st, G.L[nl], cphi, sphi, s, kappa, pr);
+  store_state(a.pred, slot, pr);
+  a.next_layer[slot] = nl;
+  return 1;
+}
+
+// (b) compatible hits of one predicted slot; keeps the best K.  Returns the
+// number of compatible pairs.
+KFX_HD int pairs_slot(const BuildArgs& a, long slot, int ev) {
+  const int nl = a.next_layer[slot];
+  if (nl < 0) {
+    a.kid_n[slot] = 0;
+    return 0;
+  }
+  State pr;
+  load_state(a.pred, slot, pr);
+  Frame F;
+  make_frame(pr, a.G->L[nl], F);
+  BestK b;
+  const int found = scan_window(*a.G, a.B, ev, nl, pr, F, a.cut, a.K, b);
+  for (int r = 0; r < b.n; ++r) {
+    a.kid_c[slot * a.K + r] = b.c[r];
+    a.kid_h[slot * a.K + r] = b.h[r];
+  }
+  a.kid_n[slot] = b.n;
+  return found;
+}
+
+// Children of one parent slot, in rank order, as (key, code, chi2).
+// Shared by the per-seed selection and the fused kernel's lane streams.
+struct KidStream {
+  int nh, nho, consec, parent;
+  float chi2;
+  int nkids;      // hit children available
+  bool hole;      // hole child allowed
+  bool stop;      // the single child is a stop child
+  bool live;
+};
+
+KFX_HD KidStream kid_stream(const BuildArgs& a, int meta, float chi2, int next_layer, int nkids,
+                            int parent) {
+  KidStream k;
+  k.live = (meta_flags(meta) & kFlagLive) != 0;
+  k.nh = meta_nhits(meta);
+  k.nho = meta_nholes(meta);
+  k.consec = meta_consec(meta);
+  k.parent = parent;
+  k.chi2 = chi2;
+  k.nkids = 0;
+  k.hole = false;
+  k.stop = false;
+  if (!k.live) return k;
+  if (next_layer < 0) {
+    k.stop = true;
+    return k;
+  }
+  k.nkids = nkids;
+  k.hole = k.consec < a.max_holes;
+  if (k.nkids == 0 && !k.hole) k.stop = true;
+  return k;
+}
+
+// key of child number r of a stream (r < nkids: hit child r; r == nkids:
+// hole; stop: r == 0); ~0 when exhausted.
+KFX_HD uint64_t kid_key(const KidStream& k, int K, int r, const float* kc, float& chi2_out) {
+  if (!k.live) return ~0ull;
+  if (k.stop) {
+    if (r > 0) return ~0ull;
+    chi2_out = k.chi2;
+    return child_key(k.nh, k.nho, k.chi2, k.parent, 0);
+  }
+  if (r < k.nkids) {
+    chi2_out = k.chi2 + kc[r];
+    return child_key(k.nh + 1, k.nho, chi2_out, k.parent, r);
+  }
+  if (r == k.nkids && k.hole) {
+    chi2_out = k.chi2;
+    return child_key(k.nh, k.nho + 1, k.chi2, k.parent, K);
+  }
+  return ~0ull;
+}
+
+// (c) per seed: keep the best K children over all its parents.
+KFX_HD void select_seed(const BuildArgs& a, int cur, int s) {
+  const int K = a.K;
+  KidStream ks[kMaxK];
+  int pos[kMaxK];
+  uint64_t head[kMaxK];
+  float hc[kMaxK];
+  for (int j = 0; j < K; ++j) {
+    const long slot = (long)s * K + j;
+    ks[j] = kid_stream(a, a.meta[cur][slot], a.chi2[cur][slot], a.next_layer[slot],
+                       a.next_layer[slot] >= 0 ? a.kid_n[slot] : 0, j);
+    pos[j] = 0;
+    head[j] = kid_key(ks[j], K, 0, a.kid_c + slot * K, hc[j]);
+  }
+  for (int i = 0; i < K; ++i) {
+    int w = -1;
+    uint64_t best = ~0ull;
+    for (int j = 0; j < K; ++j)
+      if (head[j] < best) {
+        best = head[j];
+        w = j;
+      }
+    const long out = (long)s * K + i;
+    if (w < 0) {
+      a.sel_parent[out] = -1;
+      a.sel_code[out] = kStop;
+      a.sel_chi2[out] = 0.0f;
+      continue;
+    }
+    const long ps = (long)s * K + w;
+    int code;
+    if (ks[w].stop) code = kStop;
+    else if (pos[w] < ks[w].nkids) code = a.kid_h[ps * K + pos[w]];
+    else code = kHole;
+    a.sel_parent[out] = w;
+    a.sel_code[out] = code;
+    a.sel_chi2[out] = hc[w];
+    pos[w]++;
+    head[w] = kid_key(ks[w], K, pos[w], a.kid_c + ps * K, hc[w]);
+  }
+}
+
+// (d) one new slot: copy its parent (predicted state for hit and hole
+// children, current state for a stop child) and apply the update.
+// Returns 1 when a Kalman update was applied.
+KFX_HD int update_slot(const BuildArgs& a, int cur, int s, int j, int t) {
+  const int nxt = 1 - cur;
+  const long slot = (long)s * a.K + j;
+  const int par = a.sel_parent[slot];
+  const long hidx = hist_index(a, s, t, j);
+  if (par < 0) {
+    a.meta[nxt][slot] = 0;
+    a.layer[nxt][slot] = -1;
+    a.chi2[nxt][slot] = 0.0f;
+    a.hist_parent[hidx] = -1;
+    a.hist_code[hidx] = kStop;
+    return 0;
+  }
+  const long ps = (long)s * a.K + par;
+  const int code = a.sel_code[slot];
+  const int pm = a.meta[cur][ps];
+  State st;
+  int upd = 0;
+  if (code == kStop) {
+    load_state(a.cand[cur], ps, st);
+    a.layer[nxt][slot] = a.layer[cur][ps];
+    a.meta[nxt][slot] = meta_pack(meta_nhits(pm), meta_nholes(pm), meta_consec(pm), kFlagLive | kFlagDone);
+  } else {
+    load_state(a.pred, ps, st);
+    const int nl = a.next_layer[ps];
+    a.layer[nxt][slot] = nl;
+    if (code >= 0) {
+      Frame F;
+      make_frame(st, a.G->L[nl], F);
+      kf_update(st, F, (double)a.H.x[code], (double)a.H.y[code], (double)a.H.z[code]);
+      a.meta[nxt][slot] = meta_pack(meta_nhits(pm) + 1, meta_nholes(pm), 0, kFlagLive);
+      upd = 1;
+    } else {
+      a.meta[nxt][slot] = meta_pack(meta_nhits(pm), meta_nholes(pm) + 1, meta_consec(pm) + 1, kFlagLive);
+    }
+  }
+  store_state(a.cand[nxt], slot, st);
+  a.chi2[nxt][slot] = a.sel_chi2[slot];
+  a.hist_parent[hidx] = (signed char)par;
+  a.hist_code[hidx] = code;
+  if (j == 0) a.n_steps[s] = t + 1;
+  return upd;
+}
+
+// Output of building, per seed and slot (best first).
+struct TracksOut {
+  int* n_cands;     // [S]
+  int* hits;        // [S][K][max_hits]: seed hits then one entry per step
+                    // with a hit or a hole (-1); unused entries -3
+  int* n_hits;      // [S][K]
+  int* n_holes;     // [S][K]
+  float* chi2;      // [S][K]
+  StateSoA state;   // S K entries
+  int max_hits;
+};
+
+// Rebuild the hit list of one final slot from the per-step history.
+KFX_HD void finalize_slot(const BuildArgs& a, int fin, const TracksOut& o, int s, int j) {
+  const long slot = (long)s * a.K + j;
+  const int m = a.meta[fin][slot];
+  int* out = o.hits + slot * o.max_hits;
+  for (int q = 0; q < o.max_hits; ++q) out[q] = -3;
+  if (!(meta_flags(m) & kFlagLive)) {
+    o.n_hits[slot] = 0;
+    o.n_holes[slot] = 0;
+    o.chi2[slot] = 0.0f;
+    State z;
+    z.x = z.y = z.z = z.phi = 0.0;
+    z.k = z.th = 0.0f;
+    for (int q = 0; q < 21; ++q) z.C[q] = 0.0f;
+    store_state(o.state, slot, z);
+    return;
+  }
+  // count the entries first (stop entries add nothing)
+  const int T = a.n_steps[s];
+  int n = 0, cj = j;
+  for (int t = T - 1; t >= 0; --t) {
+    const long h = hist_index(a, s, t, cj);
+    if (a.hist_code[h] != kStop) ++n;
+    cj = a.hist_parent[h];
+  }
+  const int total = kSeedHits + n;
+  for (int q = 0; q < kSeedHits && q < o.max_hits; ++q) out[q] = a.seeds[3 * s + q];
+  int w = total - 1;
+  cj = j;
+  for (int t = T - 1; t >= 0; --t) {
+    const long h = hist_index(a, s, t, cj);
+    const int code = a.hist_code[h];
+    if (code != kStop) {
+      if (w < o.max_hits) out[w] = code >= 0 ? code : -1;
+      --w;
+    }
+    cj = a.hist_parent[h];
+  }
+  o.n_hits[slot] = meta_nhits(m);
+  o.n_holes[slot] = meta_nholes(m);
+  o.chi2[slot] = a.chi2[fin][slot];
+  State st;
+  load_state(a.cand[fin], slot, st);
+  store_state(o.state, slot, st);
+}
+
+}  // namespace kfx

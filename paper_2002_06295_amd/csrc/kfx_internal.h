@@ -1,0 +1,40 @@
+// Internal interface between the C ABI (kfx_api.cpp) and the kernels
+// (kfx_kernels.hip): workspace layouts and launch wrappers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "kfx_build.h"
+
+namespace kfx {
+
+// Workspace of the hit binning (a counting sort keyed by event, layer and
+// (eta, phi) bin).  counts must hold n_keys + 1 entries.
+struct BinWork {
+  int* key;       // [n_hits]
+  int* counts;    // [n_keys + 1]
+  int* fill;      // [n_keys]
+  int* off;       // [n_keys + 1]
+  int* perm;      // [n_hits]
+  float4* sorted; // [n_hits]
+  int* scan_scratch;  // [n_keys / tile + 2]
+};
+
+void launch_fill(int* p, long n, int v, hipStream_t st);
+void exclusive_scan(const int* in, long n, int* out, int* scratch, hipStream_t st);
+void launch_bin(const Geometry* G, const HitsView& H, int n_layers, int n_bins, BinWork& w, int* bin_out,
+                hipStream_t st);
+void launch_fit(const Geometry* G, const HitsView& H, const int* trk_off, const int* trk_hits, int n,
+                const Prior& pr, const float* align, float fscale, const FitOut& o, hipStream_t st);
+void launch_seed_states(const Geometry* G, const HitsView& H, const int* seeds, int n, const Prior& pr,
+                        const StateSoA& out, float* chi2, int* status, hipStream_t st);
+void launch_step_compat(const Geometry* G, const HitsView& H, const BinIndex& B, const int* cand_event,
+                        const int* cand_layer, const StateSoA& in, int n, float cut, int* next_layer,
+                        const StateSoA& pred, int* pair_count, int* pair_hit, float* pair_chi2, int max_pairs,
+                        hipStream_t st);
+void launch_build_plain(const BuildArgs& a, const TracksOut& o, hipStream_t st);
+void launch_build_fused(const BuildArgs& a, const TracksOut& o, int* seed_counter, int blocks, int threads,
+                        hipStream_t st);
+int fused_lanes_for(int K);
+
+}  // namespace kfx

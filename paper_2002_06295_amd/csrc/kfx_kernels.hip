@@ -1,0 +1,612 @@
+// HIP kernels for gfx950 (MI355X): hit binning, seed states, the plain
+// per-step building path, the fused persistent building kernel and the
+// Kalman fit.  Launch wrappers at the bottom are called by the C ABI
+// (kfx_api.cpp).
+//
+// Paper: arXiv 2002.06295, Sec. 1-3 (Kalman-filter track building and
+// fitting over a lightweight barrel/disk geometry, best-ranking candidates
+// cloned with a per-seed cap).
+#include <hip/hip_runtime.h>
+
+#include "kfx_build.h"
+#include "kfx_internal.h"
+
+namespace kfx {
+
+// ---------------------------------------------------------------- utility
+__global__ void k_fill_i32(int* p, long n, int v) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) p[i] = v;
+}
+
+// Exclusive scan of int32 in three passes: block sums, scan of the sums,
+// block-local scan plus offset.  Each block covers kScanTile elements.
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+__device__ inline int block_exclusive_scan(int v, int* lds, int& total) {
+  // wave-level inclusive scan (64 lanes), then across the 4 waves
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  int x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) lds[wid] = x;
+  __syncthreads();
+  int base = 0, tot = 0;
+  for (int w = 0; w < kScanThreads / 64; ++w) {
+    if (w < wid) base += lds[w];
+    tot += lds[w];
+  }
+  __syncthreads();
+  total = tot;
+  return base + x - v;
+}
+
+__global__ void k_scan_reduce(const int* in, long n, int* block_sums) {
+  __shared__ int lds[kScanThreads / 64];
+  const long base = (long)blockIdx.x * kScanTile;
+  int s = 0;
+  for (int i = 0; i < kScanItems; ++i) {
+    const long idx = base + (long)i * kScanThreads + threadIdx.x;
+    if (idx < n) s += in[idx];
+  }
+  int tot;
+  block_exclusive_scan(s, lds, tot);
+  if (threadIdx.x == 0) block_sums[blockIdx.x] = tot;
+}
+
+__global__ void k_scan_sums(int* sums, int nb) {
+  // single block: sequential over chunks of kScanThreads
+  __shared__ int lds[kScanThreads / 64];
+  int carry = 0;
+  for (int b0 = 0; b0 < nb; b0 += kScanThreads) {
+    const int i = b0 + threadIdx.x;
+    const int v = i < nb ? sums[i] : 0;
+    int tot;
+    const int ex = block_exclusive_scan(v, lds, tot);
+    if (i < nb) sums[i] = carry + ex;
+    carry += tot;
+    __syncthreads();
+  }
+}
+
+__global__ void k_scan_apply(const int* in, long n, const int* block_offsets, int* out) {
+  __shared__ int lds[kScanThreads / 64];
+  // thread t owns the contiguous run [t*items, (t+1)*items) of the tile
+  const long base = (long)blockIdx.x * kScanTile + (long)threadIdx.x * kScanItems;
+  int v[kScanItems];
+  int s = 0;
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    v[i] = (base + i < n) ? in[base + i] : 0;
+    s += v[i];
+  }
+  int tot;
+  int ex = block_exclusive_scan(s, lds, tot) + block_offsets[blockIdx.x];
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    if (base + i < n) out[base + i] = ex;
+    ex += v[i];
+  }
+}
+
+// exclusive scan of n values; out has n + 1 entries (out[n] = total)
+void exclusive_scan(const int* in, long n, int* out, int* scratch, hipStream_t st) {
+  const long nb = (n + 1 + kScanTile - 1) / kScanTile;
+  // treat in[n] as 0 by scanning n + 1 values where the last is read as 0:
+  // simplest is to scan n values and compute the total from the sums.
+  hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kScanThreads), 0, st, in, n, scratch);
+  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanThreads), 0, st, scratch, (int)nb);
+  hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(kScanThreads), 0, st, in, n + 1, scratch, out);
+}
+
+// ------------------------------------------------------------- binning (a1)
+__device__ inline int event_of(const int* ev_off, int n_events, int hit) {
+  int lo = 0, hi = n_events;  // ev_off[lo] <= hit < ev_off[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (ev_off[mid] <= hit) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+__global__ void k_bin_keys(const Geometry* __restrict__ G, HitsView H, int* key_out, int* bin_out,
+                           int* counts) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= H.n_hits) return;
+  const int l = H.layer[i];
+  const int nb = G->n_eta * G->n_phi;
+  int bin = -1;
+  long key = -1;
+  if (l >= 0 && l < G->n_layers) {
+    bin = hit_bin(*G, l, H.x[i], H.y[i], H.z[i]);
+    const int e = event_of(H.ev_off, H.n_events, i);
+    key = ((long)e * G->n_layers + l) * nb + bin;
+    atomicAdd(counts + key, 1);
+  }
+  key_out[i] = (int)key;
+  if (bin_out) bin_out[i] = bin;
+}
+
+__global__ void k_bin_scatter(HitsView H, const int* key, const int* off, int* fill, int* perm) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= H.n_hits) return;
+  const int k = key[i];
+  if (k < 0) return;
+  const int p = off[k] + atomicAdd(fill + k, 1);
+  perm[p] = i;
+}
+
+// bins hold a handful of hits: insertion sort by hit index gives the same
+// order as a stable sort, whatever order the atomics produced
+__global__ void k_bin_sort(const int* off, long n_keys, int* perm) {
+  const long k = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (k >= n_keys) return;
+  const int a = off[k], b = off[k + 1];
+  for (int i = a + 1; i < b; ++i) {
+    const int v = perm[i];
+    int j = i - 1;
+    while (j >= a && perm[j] > v) {
+      perm[j + 1] = perm[j];
+      --j;
+    }
+    perm[j + 1] = v;
+  }
+}
+
+// only the first off[n_keys] entries of perm are filled (hits with a layer
+// id outside the geometry are not indexed)
+__global__ void k_bin_gather(HitsView H, const int* perm, const int* n_valid, float4* sorted) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= *n_valid) return;
+  const int h = perm[p];
+  float w;
+  __builtin_memcpy(&w, &h, 4);
+  sorted[p] = make_float4(H.x[h], H.y[h], H.z[h], w);
+}
+
+// ---------------------------------------------------------------- fit (a10)
+__global__ void __launch_bounds__(128) k_fit(const Geometry* __restrict__ G, HitsView H, const int* trk_off,
+                                             const int* trk_hits, int n_tracks, Prior pr,
+                                             const float* align, float fscale, FitOut o) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_tracks) return;
+  fit_track(*G, H, trk_off, trk_hits, t, pr, align, fscale, o);
+}
+
+// ------------------------------------------------------ seeds and step (a2-a6)
+__global__ void k_seed_states(const Geometry* __restrict__ G, HitsView H, const int* seeds, int n, Prior pr,
+                              StateSoA out, float* chi2, int* status) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  State st;
+  float c2 = 0.0f;
+  const bool ok = seed_state(*G, H, seeds + 3 * s, pr, st, c2);
+  if (!ok) {
+    st.x = st.y = st.z = st.phi = 0.0;
+    st.k = st.th = 0.0f;
+    for (int j = 0; j < 21; ++j) st.C[j] = 0.0f;
+    c2 = 0.0f;
+  }
+  store_state(out, s, st);
+  chi2[s] = c2;
+  status[s] = ok ? 1 : 0;
+}
+
+// One building step on given states: navigate, transport, then list every
+// compatible hit through the binned index (ascending hit index).
+__global__ void k_step_compat(const Geometry* __restrict__ G, HitsView H, BinIndex B, const int* cand_event,
+                              const int* cand_layer, StateSoA in, int n, float cut, int* next_layer,
+                              StateSoA pred, int* pair_count, int* pair_hit, float* pair_chi2,
+                              int max_pairs) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  State st, pr;
+  load_state(in, i, st);
+  const double cphi = cos(st.phi), sphi = sin(st.phi);
+  const float kappa = -kHc * (float)G->bz;
+  float s = 0.0f;
+  const int cl = cand_layer[i], ce = cand_event[i];
+  const int nl = (cl >= 0 && cl < G->n_layers && ce >= 0 && ce < H.n_events)
+                     ? navigate(*G, cl, st, cphi, sphi, kappa * st.k, s) : -1;
+  next_layer[i] = nl;
+  if (nl < 0) {
+    pair_count[i] = 0;
+    return;
+  }
+  transport(st, G->L[nl], cphi, sphi, s, kappa, pr);
+  store_state(pred, i, pr);
+  Frame F;
+  make_frame(pr, G->L[nl], F);
+  const Window w = window_bins(*G, G->L[nl], pr, F, cut);
+  int cnt = 0;
+  int* oh = pair_hit + (long)i * max_pairs;
+  float* oc = pair_chi2 + (long)i * max_pairs;
+  for (int eb = w.eb0; eb <= w.eb1; ++eb)
+    for (int j = 0; j < w.npb; ++j) {
+      int pb = w.pb0 + j;
+      if (pb >= G->n_phi) pb -= G->n_phi;
+      const long key = bin_key(B, ce, nl, eb * G->n_phi + pb);
+      for (int q = B.off[key]; q < B.off[key + 1]; ++q) {
+        const float4 hv = B.sorted[q];
+        float r[3];
+        residual(pr, F, (double)hv.x, (double)hv.y, (double)hv.z, r);
+        const float c2 = chi2_of(F, r);
+        if (c2 < cut) {
+          int hid;
+          __builtin_memcpy(&hid, &hv.w, 4);
+          if (cnt < max_pairs) {
+            // insertion by hit index
+            int k = cnt;
+            while (k > 0 && oh[k - 1] > hid) {
+              oh[k] = oh[k - 1];
+              oc[k] = oc[k - 1];
+              --k;
+            }
+            oh[k] = hid;
+            oc[k] = c2;
+          }
+          ++cnt;
+        }
+      }
+    }
+  pair_count[i] = cnt;
+}
+
+// -------------------------------------------------- plain building path (a3-a9)
+__device__ inline void add_stat(unsigned long long* p, unsigned long long v) {
+  // one atomic per wave
+  const unsigned long long lo = v;
+  unsigned long long s = lo;
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);
+  if ((threadIdx.x & 63) == 0 && s) atomicAdd(p, s);
+}
+
+__global__ void k_build_init(BuildArgs a) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= a.n_seeds) return;
+  init_seed_slots(a, s);
+}
+
+__global__ void k_build_predict(BuildArgs a, int cur) {
+  const long slot = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  int took = 0;
+  if (slot < (long)a.n_seeds * a.K) took = predict_slot(a, cur, slot);
+  add_stat(a.stats + 0, (unsigned long long)took);
+}
+
+__global__ void k_build_pairs(BuildArgs a) {
+  const long slot = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  int found = 0;
+  if (slot < (long)a.n_seeds * a.K) found = pairs_slot(a, slot, a.seed_event[slot / a.K]);
+  add_stat(a.stats + 1, (unsigned long long)found);
+}
+
+__global__ void k_build_select(BuildArgs a, int cur) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= a.n_seeds) return;
+  select_seed(a, cur, s);
+}
+
+__global__ void k_build_update(BuildArgs a, int cur, int t) {
+  const long slot = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  int upd = 0;
+  if (slot < (long)a.n_seeds * a.K) upd = update_slot(a, cur, (int)(slot / a.K), (int)(slot % a.K), t);
+  add_stat(a.stats + 2, (unsigned long long)upd);
+}
+
+__global__ void k_build_finalize(BuildArgs a, int fin, TracksOut o) {
+  const long slot = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (slot >= (long)a.n_seeds * a.K) return;
+  const int s = (int)(slot / a.K), j = (int)(slot % a.K);
+  finalize_slot(a, fin, o, s, j);
+  if (j == 0) {
+    int n = 0;
+    for (int q = 0; q < a.K; ++q) n += (meta_flags(a.meta[fin][(long)s * a.K + q]) & kFlagLive) ? 1 : 0;
+    o.n_cands[s] = n;
+  }
+}
+
+// ---------------------------------------------- fused persistent kernel (a12)
+// One wavefront runs 64 / G seed groups of G lanes (G = lanes per seed,
+// a power of two >= K); each lane holds one candidate slot in registers
+// for the whole search.  A group takes a new seed from a device counter as
+// soon as its seed finishes, so uneven events and candidates of uneven
+// length share the machine.  The per-step pieces are those of the plain
+// path: navigate + transport, window scan, selection (here K rounds of a
+// segmented wavefront minimum over the lanes' child streams) and update;
+// states move between lanes through LDS.
+struct FusedShared {
+  // per lane: state to hand to the children (predicted, or current for a
+  // stop child), its layer, meta and chi2
+  double pos[4];
+  float kt[2];
+  float cov[21];
+  int layer;
+  int meta;
+  float chi2;
+};
+
+template <int G_LANES>
+__global__ void __launch_bounds__(256) k_build_fused(BuildArgs a, int cur_unused, TracksOut o, int* seed_counter) {
+  (void)cur_unused;
+  extern __shared__ unsigned char smem_raw[];
+  FusedShared* sh = reinterpret_cast<FusedShared*>(smem_raw);
+  const Geometry& G = *a.G;
+  const int lane = threadIdx.x & 63;
+  const int gl = lane & (G_LANES - 1);          // slot within the seed
+  const int gbase = threadIdx.x & ~(G_LANES - 1);
+  const int K = a.K;
+  const float kappa = -kHc * (float)G.bz;
+  const unsigned long long gmask = ((G_LANES == 64) ? ~0ull : ((1ull << G_LANES) - 1ull)) << (lane & ~(G_LANES - 1));
+
+  unsigned long long n_steps = 0, n_pairs = 0, n_upd = 0;
+  int seed = -1;
+  int t = 0;
+  // register state of this lane's slot
+  State st;
+  int layer = -1, meta = 0;
+  float chi2 = 0.0f;
+
+  while (true) {
+    // a group without a seed takes the next one (all lanes take part in
+    // the broadcast; only groups that need a seed use it)
+    const bool need = seed == -1;
+    int ns = -1;
+    if (need && gl == 0) ns = atomicAdd(seed_counter, 1);
+    ns = __shfl(ns, gbase & 63, 64);
+    if (need) {
+      if (ns < a.n_seeds) {
+        seed = ns;
+        t = 0;
+        meta = 0;
+        layer = -1;
+        chi2 = 0.0f;
+        if (gl == 0) {
+          float c2 = 0.0f;
+          const int* sh3 = a.seeds + 3 * seed;
+          const int ev = a.seed_event[seed];
+          if (ev >= 0 && ev < a.H.n_events && seed_state(G, a.H, sh3, a.prior, st, c2)) {
+            layer = a.H.layer[sh3[2]];
+            chi2 = c2;
+            meta = meta_pack(kSeedHits, 0, 0, kFlagLive);
+          }
+        }
+      } else {
+        seed = -2;  // nothing left for this group
+      }
+    }
+    const bool active = seed >= 0;
+    if (__ballot(active) == 0) break;
+
+    // ---- (a) navigate + transport
+    int nl = -2;
+    State pr;
+    const bool live = active && (meta_flags(meta) & kFlagLive) && gl < K;
+    if (live) {
+      if (meta_flags(meta) & kFlagDone) {
+        nl = -1;
+      } else {
+        const double cphi = cos(st.phi), sphi = sin(st.phi);
+        float s = 0.0f;
+        nl = navigate(G, layer, st, cphi, sphi, kappa * st.k, s);
+        if (nl >= 0) {
+          transport(st, G.L[nl], cphi, sphi, s, kappa, pr);
+          ++n_steps;
+        }
+      }
+    }
+    // ---- (b) window scan, best K hit children
+    BestK best;
+    best.n = 0;
+    if (nl >= 0) {
+      Frame F;
+      make_frame(pr, G.L[nl], F);
+      n_pairs += (unsigned long long)scan_window(G, a.B, a.seed_event[seed], nl, pr, F, a.cut, K, best);
+    }
+    // ---- (c) selection: K rounds of a segmented minimum over child streams
+    const KidStream ks = kid_stream(a, live ? meta : 0, chi2, nl, best.n, gl);
+    int p = 0;
+    float hc = 0.0f;
+    uint64_t head = kid_key(ks, K, 0, best.c, hc);
+    int my_parent = -1, my_code = kStop;
+    float my_chi2 = 0.0f;
+    for (int i = 0; i < K; ++i) {
+      uint64_t m = head;
+#pragma unroll
+      for (int off = G_LANES / 2; off >= 1; off >>= 1) {
+        const uint64_t o2 = __shfl_xor(m, off, 64);
+        m = o2 < m ? o2 : m;
+      }
+      const unsigned long long win = __ballot(head == m && m != ~0ull) & gmask;
+      // winner lane in the wave (unique: keys differ by parent slot); a
+      // group with no child left reads its own first lane and ignores it
+      const int wl = win ? __ffsll((long long)win) - 1 : (lane & ~(G_LANES - 1));
+      int code = kStop;
+      if (ks.stop) code = kStop;
+      else if (p < ks.nkids) code = best.h[p];
+      else code = kHole;
+      const int wcode = __shfl(code, wl, 64);
+      const float wchi2 = __shfl(hc, wl, 64);
+      if (win && gl == i) {
+        my_parent = wl & (G_LANES - 1);
+        my_code = wcode;
+        my_chi2 = wchi2;
+      }
+      if (win && lane == wl) {
+        ++p;
+        head = kid_key(ks, K, p, best.c, hc);
+      }
+    }
+    // ---- hand states to the children through LDS
+    FusedShared& me = sh[threadIdx.x];
+    {
+      const State& src = (nl >= 0) ? pr : st;
+      me.pos[0] = src.x; me.pos[1] = src.y; me.pos[2] = src.z; me.pos[3] = src.phi;
+      me.kt[0] = src.k; me.kt[1] = src.th;
+#pragma unroll
+      for (int q = 0; q < 21; ++q) me.cov[q] = src.C[q];
+      me.layer = (nl >= 0) ? nl : layer;
+      me.meta = meta;
+      me.chi2 = chi2;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    int new_meta = 0, new_layer = -1;
+    if (active && gl < K) {
+      if (my_parent >= 0) {
+        const FusedShared& par = sh[gbase + my_parent];
+        State ns;
+        ns.x = par.pos[0]; ns.y = par.pos[1]; ns.z = par.pos[2]; ns.phi = par.pos[3];
+        ns.k = par.kt[0]; ns.th = par.kt[1];
+#pragma unroll
+        for (int q = 0; q < 21; ++q) ns.C[q] = par.cov[q];
+        const int pm = par.meta;
+        new_layer = par.layer;
+        if (my_code == kStop) {
+          new_meta = meta_pack(meta_nhits(pm), meta_nholes(pm), meta_consec(pm), kFlagLive | kFlagDone);
+        } else if (my_code >= 0) {
+          Frame F;
+          make_frame(ns, G.L[new_layer], F);
+          kf_update(ns, F, (double)a.H.x[my_code], (double)a.H.y[my_code], (double)a.H.z[my_code]);
+          new_meta = meta_pack(meta_nhits(pm) + 1, meta_nholes(pm), 0, kFlagLive);
+          ++n_upd;
+        } else {
+          new_meta = meta_pack(meta_nhits(pm), meta_nholes(pm) + 1, meta_consec(pm) + 1, kFlagLive);
+        }
+        st = ns;
+      }
+      const long hidx = hist_index(a, seed, t, gl);
+      a.hist_parent[hidx] = (signed char)my_parent;
+      a.hist_code[hidx] = my_parent >= 0 ? my_code : kStop;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (active) {
+      meta = (gl < K) ? new_meta : 0;
+      layer = new_layer;
+      chi2 = my_chi2;
+      ++t;
+    }
+    // ---- a group whose candidates are all done (or a full history) ends
+    const bool running = active && (meta_flags(meta) & kFlagLive) && !(meta_flags(meta) & kFlagDone);
+    const unsigned long long run_mask = __ballot(running) & gmask;
+    if (active && (run_mask == 0 || t >= a.max_steps)) {
+      if (gl == 0) a.n_steps[seed] = t;
+      // final state of this slot into the candidate buffer, then the output
+      const long slot = (long)seed * K + gl;
+      if (gl < K) {
+        store_state(a.cand[0], slot, st);
+        a.meta[0][slot] = meta;
+        a.layer[0][slot] = layer;
+        a.chi2[0][slot] = chi2;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
+      __builtin_amdgcn_wave_barrier();
+      if (gl < K) finalize_slot(a, 0, o, seed, gl);
+      if (gl == 0) {
+        int n = 0;
+        for (int q = 0; q < K; ++q) n += (meta_flags(a.meta[0][(long)seed * K + q]) & kFlagLive) ? 1 : 0;
+        o.n_cands[seed] = n;
+      }
+      seed = -1;
+    }
+  }
+  add_stat(a.stats + 0, n_steps);
+  add_stat(a.stats + 1, n_pairs);
+  add_stat(a.stats + 2, n_upd);
+}
+
+// ---------------------------------------------------------------- launchers
+static inline unsigned nblk(long n, int b) { return (unsigned)((n + b - 1) / b); }
+
+void launch_fill(int* p, long n, int v, hipStream_t st) {
+  if (n <= 0) return;
+  const long blocks = std::min<long>(nblk(n, 256), 65536);
+  hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)blocks), dim3(256), 0, st, p, n, v);
+}
+
+void launch_bin(const Geometry* G, const HitsView& H, int n_layers, int n_bins, BinWork& w,
+                int* bin_out, hipStream_t st) {
+  const long n_keys = (long)H.n_events * n_layers * n_bins;
+  launch_fill(w.counts, n_keys + 1, 0, st);
+  launch_fill(w.fill, n_keys, 0, st);
+  if (H.n_hits > 0)
+    hipLaunchKernelGGL(k_bin_keys, dim3(nblk(H.n_hits, 256)), dim3(256), 0, st, G, H, w.key, bin_out, w.counts);
+  exclusive_scan(w.counts, n_keys, w.off, w.scan_scratch, st);
+  if (H.n_hits > 0)
+    hipLaunchKernelGGL(k_bin_scatter, dim3(nblk(H.n_hits, 256)), dim3(256), 0, st, H, w.key, w.off, w.fill, w.perm);
+  hipLaunchKernelGGL(k_bin_sort, dim3(nblk(n_keys, 256)), dim3(256), 0, st, w.off, n_keys, w.perm);
+  if (H.n_hits > 0)
+    hipLaunchKernelGGL(k_bin_gather, dim3(nblk(H.n_hits, 256)), dim3(256), 0, st, H, w.perm, w.off + n_keys,
+                       w.sorted);
+}
+
+void launch_fit(const Geometry* G, const HitsView& H, const int* trk_off, const int* trk_hits, int n,
+                const Prior& pr, const float* align, float fscale, const FitOut& o, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fit, dim3(nblk(n, 128)), dim3(128), 0, st, G, H, trk_off, trk_hits, n, pr, align, fscale, o);
+}
+
+void launch_seed_states(const Geometry* G, const HitsView& H, const int* seeds, int n, const Prior& pr,
+                        const StateSoA& out, float* chi2, int* status, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_seed_states, dim3(nblk(n, 128)), dim3(128), 0, st, G, H, seeds, n, pr, out, chi2, status);
+}
+
+void launch_step_compat(const Geometry* G, const HitsView& H, const BinIndex& B, const int* cand_event,
+                        const int* cand_layer, const StateSoA& in, int n, float cut, int* next_layer,
+                        const StateSoA& pred, int* pair_count, int* pair_hit, float* pair_chi2,
+                        int max_pairs, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_step_compat, dim3(nblk(n, 128)), dim3(128), 0, st, G, H, B, cand_event, cand_layer, in, n,
+                     cut, next_layer, pred, pair_count, pair_hit, pair_chi2, max_pairs);
+}
+
+void launch_build_plain(const BuildArgs& a, const TracksOut& o, hipStream_t st) {
+  const long nslots = (long)a.n_seeds * a.K;
+  if (a.n_seeds <= 0) return;
+  hipLaunchKernelGGL(k_build_init, dim3(nblk(a.n_seeds, 128)), dim3(128), 0, st, a);
+  int cur = 0;
+  for (int t = 0; t < a.max_steps; ++t) {
+    hipLaunchKernelGGL(k_build_predict, dim3(nblk(nslots, 128)), dim3(128), 0, st, a, cur);
+    hipLaunchKernelGGL(k_build_pairs, dim3(nblk(nslots, 128)), dim3(128), 0, st, a);
+    hipLaunchKernelGGL(k_build_select, dim3(nblk(a.n_seeds, 128)), dim3(128), 0, st, a, cur);
+    hipLaunchKernelGGL(k_build_update, dim3(nblk(nslots, 128)), dim3(128), 0, st, a, cur, t);
+    cur = 1 - cur;
+  }
+  hipLaunchKernelGGL(k_build_finalize, dim3(nblk(nslots, 128)), dim3(128), 0, st, a, cur, o);
+}
+
+int fused_lanes_for(int K) {
+  int g = 1;
+  while (g < K) g <<= 1;
+  return g;
+}
+
+void launch_build_fused(const BuildArgs& a, const TracksOut& o, int* seed_counter, int blocks, int threads,
+                        hipStream_t st) {
+  if (a.n_seeds <= 0) return;
+  launch_fill(seed_counter, 1, 0, st);
+  const size_t shmem = sizeof(FusedShared) * threads;
+  const int g = fused_lanes_for(a.K);
+  switch (g) {
+    case 1: case 2: case 4:
+      hipLaunchKernelGGL(k_build_fused<4>, dim3(blocks), dim3(threads), shmem, st, a, 0, o, seed_counter);
+      break;
+    case 8:
+      hipLaunchKernelGGL(k_build_fused<8>, dim3(blocks), dim3(threads), shmem, st, a, 0, o, seed_counter);
+      break;
+    default:
+      hipLaunchKernelGGL(k_build_fused<16>, dim3(blocks), dim3(threads), shmem, st, a, 0, o, seed_counter);
+      break;
+  }
+}
+
+}  // namespace kfx

@@ -1,0 +1,398 @@
+// Per-thread work items of the track-building and fitting kernels.
+//
+// Each kernel of the plain path is a thin launcher around one of these
+// functions (one call per thread); the fused persistent kernel reuses the
+// same pieces per lane.  They are __host__ __device__ so that a test-only
+// host build can check the kernel logic on the CPU; the library itself only
+// runs them on the GPU.
+//
+// Paper: arXiv 2002.06295.  Sec. 1: building is a combinatorial search that
+// starts from a seed in the innermost layers and proceeds outward with the
+// propagate/update Kalman step; fitting applies the Kalman filter to the
+// hits that building found.  Sec. 2: only the best ranking candidates are
+// cloned at each layer, with a per-seed cap, and explored candidates are
+// kept with compact bookkeeping.  Sec. 3: missing hits are counted
+// consistently and enter the ranking score.
+#pragma once
+
+#include "kfx_math.h"
+
+namespace kfx {
+
+constexpr int kMaxK = 16;        // candidates per seed (compile-time cap)
+constexpr int kMaxSteps = 40;    // surfaces crossed after the seed
+constexpr int kSeedHits = 3;
+
+// ---- hit binning ---------------------------------------------------------
+// Per layer: n_eta equal bins of pseudorapidity over the layer's own range
+// (barrel: asinh(z/R) over +-zmax; disk: asinh(Z/r) over [rmin, rmax]) and
+// n_phi equal bins of phi over [-pi, pi).  Computed in FP64 from the FP32
+// hit coordinates; an edge belongs to the upper bin, phi = pi wraps to 0,
+// eta outside the range is clamped.
+KFX_HD int eta_bin(const Geometry& G, const Layer& Lr, double eta) {
+  double f = floor((eta - Lr.eta_lo) / (Lr.eta_hi - Lr.eta_lo) * (double)G.n_eta);
+  if (f < 0.0) f = 0.0;
+  if (f > (double)(G.n_eta - 1)) f = (double)(G.n_eta - 1);
+  return (int)f;
+}
+
+KFX_HD int phi_bin(const Geometry& G, double phi) {
+  int b = (int)floor((phi + kPi) / (2.0 * kPi) * (double)G.n_phi);
+  if (b >= G.n_phi) b -= G.n_phi;
+  if (b < 0) b += G.n_phi;
+  return b;
+}
+
+KFX_HD int hit_bin(const Geometry& G, int layer, float x, float y, float z) {
+  const Layer& Lr = G.L[layer];
+  const double xd = x, yd = y, zd = z;
+  const double eta = Lr.kind == kBarrel ? asinh(zd / Lr.pos) : asinh(Lr.pos / sqrt(xd * xd + yd * yd));
+  return eta_bin(G, Lr, eta) * G.n_phi + phi_bin(G, atan2(yd, xd));
+}
+
+// ---- window: bins that can hold a hit with chi2 < cut ------------------
+// The chi2 ellipsoid's bounding box |r_u| <= sqrt(cut S_uu) etc. mapped to
+// phi and eta ranges, widened to cover FP32 rounding, so the window is a
+// superset of the compatible hits.
+struct Window {
+  int eb0, eb1;  // eta bins, inclusive
+  int pb0, npb;  // phi bins pb0 .. pb0 + npb - 1 (mod n_phi)
+};
+
+KFX_HD int eta_bin_f(const Geometry& G, const Layer& Lr, float eta) {
+  float f = floorf((eta - (float)Lr.eta_lo) / (float)(Lr.eta_hi - Lr.eta_lo) * (float)G.n_eta);
+  f = fminf(fmaxf(f, 0.0f), (float)(G.n_eta - 1));
+  return (int)f;
+}
+
+KFX_HD Window window_bins(const Geometry& G, const Layer& Lr, const State& pr, const Frame& F,
+                          float cut) {
+  const float infl = 1.0f + 1e-4f;
+  const float wu = sqrtf(cut * F.S[0]) * infl + 1e-5f;
+  const float wv = sqrtf(cut * F.S[2]) * infl + 1e-5f;
+  const float wn = sqrtf(cut * F.S[5]) * infl + 1e-5f;
+  const float rp = (float)sqrt(pr.x * pr.x + pr.y * pr.y);
+  const float php = (float)atan2(pr.y, pr.x);
+  Window w;
+  if (!isfinite(wu) || !isfinite(wv) || !isfinite(wn) || !isfinite(rp) || !isfinite(php) ||
+      !isfinite((float)pr.z)) {
+    w.eb0 = 1;  // empty window
+    w.eb1 = 0;
+    w.pb0 = 0;
+    w.npb = 0;
+    return w;
+  }
+  float dphi, elo, ehi;
+  if (Lr.kind == kBarrel) {
+    const float rmin = rp - wn;
+    dphi = (rmin <= 0.0f || wu >= rmin) ? 4.0f : asinf(wu / rmin) + 1e-5f;
+    const float R = (float)Lr.pos;
+    elo = asinhf(((float)pr.z - wv) / R) - 1e-5f;
+    ehi = asinhf(((float)pr.z + wv) / R) + 1e-5f;
+  } else {
+    const float rmin = rp - wv;
+    const float rmax = sqrtf(wu * wu + (rp + wv) * (rp + wv));
+    dphi = (rmin <= 0.0f || wu >= rmin) ? 4.0f : asinf(wu / rmin) + 1e-5f;
+    const float Z = (float)Lr.pos;
+    const float a = asinhf(Z / rmax);
+    const float b = rmin > 0.0f ? asinhf(Z / rmin) : (Z > 0.0f ? 1e30f : -1e30f);
+    elo = fminf(a, b) - 1e-5f;
+    ehi = fmaxf(a, b) + 1e-5f;
+  }
+  w.eb0 = eta_bin_f(G, Lr, elo);
+  w.eb1 = eta_bin_f(G, Lr, ehi);
+  if (dphi >= 1.5f) {
+    w.pb0 = 0;
+    w.npb = G.n_phi;
+  } else {
+    const float bw = (float)(2.0 * kPi) / (float)G.n_phi;
+    const float pi = (float)kPi;
+    int b0 = (int)floorf((php - dphi + pi) / bw);
+    int b1 = (int)floorf((php + dphi + pi) / bw);
+    int n = b1 - b0 + 1;
+    if (n > G.n_phi) n = G.n_phi;
+    b0 %= G.n_phi;
+    if (b0 < 0) b0 += G.n_phi;
+    w.pb0 = b0;
+    w.npb = n;
+  }
+  return w;
+}
+
+// ---- candidate bookkeeping ---------------------------------------------
+// meta word: bits 0-7 n_hits, 8-15 n_holes, 16-23 consecutive holes,
+// 24-31 flags.
+constexpr int kFlagLive = 1;   // slot holds a candidate
+constexpr int kFlagDone = 2;   // candidate finished (no further surface)
+
+KFX_HD int meta_pack(int nh, int nho, int consec, int flags) {
+  return nh | (nho << 8) | (consec << 16) | (flags << 24);
+}
+KFX_HD int meta_nhits(int m) { return m & 0xff; }
+KFX_HD int meta_nholes(int m) { return (m >> 8) & 0xff; }
+KFX_HD int meta_consec(int m) { return (m >> 16) & 0xff; }
+KFX_HD int meta_flags(int m) { return (m >> 24) & 0xff; }
+
+// Ranking key of a child, smaller is better: more hits, then fewer holes,
+// then smaller total chi2, then parent slot, then the child's rank among
+// its parent's children (hits by (chi2, hit index), the hole after them).
+KFX_HD uint64_t child_key(int nhits, int nholes, float chi2, int parent, int rank) {
+  uint32_t cb;
+  __builtin_memcpy(&cb, &chi2, 4);
+  return ((uint64_t)(63 - nhits) << 58) | ((uint64_t)nholes << 52) | ((uint64_t)cb << 20) |
+         ((uint64_t)parent << 10) | ((uint64_t)rank << 5);
+}
+
+// Child codes: hit index >= 0, kHole, kStop.
+constexpr int kHole = -1;
+constexpr int kStop = -2;
+
+// Sorted best-K list of (chi2, hit) of one candidate's compatible hits.
+struct BestK {
+  float c[kMaxK];
+  int h[kMaxK];
+  int n;
+};
+
+KFX_HD void bestk_init(BestK& b) { b.n = 0; }
+
+// insert keeping ascending (chi2, hit); K is the runtime cap (<= kMaxK)
+KFX_HD void bestk_insert(BestK& b, int K, float c, int h) {
+  int n = b.n;
+  if (n == K) {
+    if (c > b.c[K - 1] || (c == b.c[K - 1] && h > b.h[K - 1])) return;
+    n = K - 1;
+  }
+  int i = n;
+  while (i > 0 && (b.c[i - 1] > c || (b.c[i - 1] == c && b.h[i - 1] > h))) {
+    b.c[i] = b.c[i - 1];
+    b.h[i] = b.h[i - 1];
+    --i;
+  }
+  b.c[i] = c;
+  b.h[i] = h;
+  b.n = n + 1;
+}
+
+// ---- SoA state access ---------------------------------------------------
+// pos: [4][stride] float64 (x, y, z, phi); kt: [2][stride] float32 (k,
+// theta); cov: [21][stride] float32 (packed lower triangle).
+struct StateSoA {
+  double* pos;
+  float* kt;
+  float* cov;
+  long stride;
+};
+
+KFX_HD void load_state(const StateSoA& a, long i, State& s) {
+  s.x = a.pos[i];
+  s.y = a.pos[a.stride + i];
+  s.z = a.pos[2 * a.stride + i];
+  s.phi = a.pos[3 * a.stride + i];
+  s.k = a.kt[i];
+  s.th = a.kt[a.stride + i];
+#pragma unroll
+  for (int j = 0; j < 21; ++j) s.C[j] = a.cov[j * a.stride + i];
+}
+
+KFX_HD void store_state(const StateSoA& a, long i, const State& s) {
+  a.pos[i] = s.x;
+  a.pos[a.stride + i] = s.y;
+  a.pos[2 * a.stride + i] = s.z;
+  a.pos[3 * a.stride + i] = s.phi;
+  a.kt[i] = s.k;
+  a.kt[a.stride + i] = s.th;
+#pragma unroll
+  for (int j = 0; j < 21; ++j) a.cov[j * a.stride + i] = s.C[j];
+}
+
+// ---- hits ----------------------------------------------------------------
+struct HitsView {
+  const float *x, *y, *z;
+  const int* layer;
+  const int* ev_off;   // [n_events + 1]
+  int n_hits, n_events;
+};
+
+// Binned index: for event e, layer l, bin b the sorted hits (x, y, z, index
+// as bits) occupy [off[key], off[key+1]), key = (e L + l) nb + b.
+struct BinIndex {
+  const int* off;
+  const float4* sorted;
+  int n_layers, n_bins;
+};
+
+KFX_HD long bin_key(const BinIndex& B, int ev, int layer, int bin) {
+  return ((long)ev * B.n_layers + layer) * B.n_bins + bin;
+}
+
+// Scan the window's bins and keep the best K compatible hits (chi2 < cut).
+// Returns the number of compatible hits found (all of them, not only K).
+KFX_HD int scan_window(const Geometry& G, const BinIndex& B, int ev, int layer, const State& pr,
+                       const Frame& F, float cut, int K, BestK& best) {
+  const Layer& Lr = G.L[layer];
+  const Window w = window_bins(G, Lr, pr, F, cut);
+  bestk_init(best);
+  int found = 0;
+  for (int eb = w.eb0; eb <= w.eb1; ++eb) {
+    for (int j = 0; j < w.npb; ++j) {
+      int pb = w.pb0 + j;
+      if (pb >= G.n_phi) pb -= G.n_phi;
+      const long key = bin_key(B, ev, layer, eb * G.n_phi + pb);
+      const int a = B.off[key], e = B.off[key + 1];
+      for (int q = a; q < e; ++q) {
+        const float4 hv = B.sorted[q];
+        float r[3];
+        residual(pr, F, (double)hv.x, (double)hv.y, (double)hv.z, r);
+        const float c2 = chi2_of(F, r);
+        if (c2 < cut) {
+          int hid;
+          __builtin_memcpy(&hid, &hv.w, 4);
+          ++found;
+          bestk_insert(best, K, c2, hid);
+        }
+      }
+    }
+  }
+  return found;
+}
+
+// ---- seed state: start estimate, then KF over the three seed hits ------
+KFX_HD bool seed_state(const Geometry& G, const HitsView& H, const int sh[3], const Prior& pr,
+                       State& st, float& chi2) {
+  double m[3][3];
+  for (int i = 0; i < 3; ++i)
+    if (sh[i] < 0 || sh[i] >= H.n_hits) return false;
+  for (int i = 0; i < 3; ++i) {
+    m[i][0] = H.x[sh[i]];
+    m[i][1] = H.y[sh[i]];
+    m[i][2] = H.z[sh[i]];
+  }
+  seed_estimate(G.bz, m[0], m[1], m[2], st);
+  prior_cov(pr, st);
+  const float kappa = -kHc * (float)G.bz;
+  chi2 = 0.0f;
+  for (int i = 0; i < 3; ++i) {
+    const int l = H.layer[sh[i]];
+    if (l < 0 || l >= G.n_layers) return false;
+    const Layer& Ld = G.L[l];
+    if (i == 0) {
+      add_material(st, Ld);
+    } else {
+      const double cphi = cos(st.phi), sphi = sin(st.phi);
+      const float s = Ld.kind == kBarrel ? path_to_cylinder(st, cphi, sphi, kappa * st.k, Ld.pos)
+                                         : path_to_disk(st, Ld.pos);
+      if (!(s > 0.0f)) return false;
+      State nx;
+      transport(st, Ld, cphi, sphi, s, kappa, nx);
+      st = nx;
+    }
+    Frame F;
+    make_frame(st, Ld, F);
+    chi2 += kf_update(st, F, m[i][0], m[i][1], m[i][2]);
+  }
+  return true;
+}
+
+// ---- fit of one track over a fixed hit list ------------------------------
+// Alignment of barrel layer l, a = (dr, drphi, dz): the hit recorded in the
+// nominal frame moves to ((R+dr) (cos, sin)(phi_h + drphi/R), z + dz) and
+// the track is propagated to the cylinder R + dr.  The field is B * fscale.
+KFX_HD void aligned_hit(const Layer& Ld, float hx, float hy, float hz, const float* a, double m[3]) {
+  if (Ld.kind == kBarrel) {
+    const double dr = a ? (double)a[0] : 0.0, drphi = a ? (double)a[1] : 0.0, dz = a ? (double)a[2] : 0.0;
+    const double x = hx, y = hy;
+    const double r = sqrt(x * x + y * y);
+    const double c = x / r, s = y / r;
+    const double d = drphi / Ld.pos;
+    const double cd = cos(d), sd = sin(d);
+    const double R = Ld.pos + dr;
+    m[0] = R * (c * cd - s * sd);
+    m[1] = R * (s * cd + c * sd);
+    m[2] = (double)hz + dz;
+  } else {
+    m[0] = hx;
+    m[1] = hy;
+    m[2] = hz;
+  }
+}
+
+struct FitOut {
+  StateSoA state;     // per track
+  float* chi2;
+  int* ndof;
+  int* status;        // 1 ok, 0 failed
+  StateSoA ckpt;      // per hit slot (pos == nullptr: none)
+};
+
+KFX_HD void fit_track(const Geometry& G, const HitsView& H, const int* trk_off, const int* trk_hits,
+                      int t, const Prior& pr, const float* align, float fscale, const FitOut& o) {
+  const int b = trk_off[t], n = trk_off[t + 1] - trk_off[t];
+  State st;
+  double chi2 = 0.0;
+  bool ok = n >= 3;
+  // checkpoints beyond the caller's capacity: the track is not fitted
+  const bool ckpt_fits = !o.ckpt.pos || (long)b + n <= o.ckpt.stride;
+  ok = ok && ckpt_fits;
+  for (int i = 0; ok && i < n; ++i) {
+    const int h = trk_hits[b + i];
+    if (h < 0 || h >= H.n_hits) ok = false;
+  }
+  if (ok) {
+    double m0[3][3];
+    for (int i = 0; i < 3; ++i) {
+      const int h = trk_hits[b + i];
+      m0[i][0] = H.x[h];
+      m0[i][1] = H.y[h];
+      m0[i][2] = H.z[h];
+    }
+    seed_estimate(G.bz, m0[0], m0[1], m0[2], st);
+    prior_cov(pr, st);
+    const float kappa = -kHc * (float)G.bz * fscale;
+    for (int i = 0; i < n && ok; ++i) {
+      const int h = trk_hits[b + i];
+      const int l = H.layer[h];
+      if (l < 0 || l >= G.n_layers) {
+        ok = false;
+        break;
+      }
+      const Layer& Ld = G.L[l];
+      const float* a = align ? align + 3 * l : nullptr;
+      double m[3];
+      aligned_hit(Ld, H.x[h], H.y[h], H.z[h], a, m);
+      if (i == 0) {
+        add_material(st, Ld);
+      } else {
+        const double cphi = cos(st.phi), sphi = sin(st.phi);
+        float s;
+        if (Ld.kind == kBarrel)
+          s = path_to_cylinder(st, cphi, sphi, kappa * st.k, Ld.pos + (a ? (double)a[0] : 0.0));
+        else
+          s = path_to_disk(st, Ld.pos);
+        if (!(s > 0.0f)) {
+          ok = false;
+          break;
+        }
+        State nx;
+        transport(st, Ld, cphi, sphi, s, kappa, nx);
+        st = nx;
+      }
+      Frame F;
+      make_frame(st, Ld, F);
+      chi2 += (double)kf_update(st, F, m[0], m[1], m[2]);
+      if (o.ckpt.pos) store_state(o.ckpt, b + i, st);
+    }
+  }
+  if (!ok) {
+    st.x = st.y = st.z = st.phi = 0.0;
+    st.k = st.th = 0.0f;
+    for (int j = 0; j < 21; ++j) st.C[j] = 0.0f;
+    chi2 = 0.0;
+  }
+  store_state(o.state, t, st);
+  o.chi2[t] = (float)chi2;
+  o.ndof[t] = 2 * n - 5;
+  o.status[t] = ok ? 1 : (ckpt_fits ? 0 : -1);
+}
+
+}  // namespace kfx

@@ -1,0 +1,357 @@
+"""Python binding of libkfx.so (C ABI in include/kfx.h).
+
+Argument marshalling only: torch supplies device memory and the current
+HIP stream; every step of the computation runs in the library's HIP
+kernels.  Importing this module does not touch the GPU; creating a Context
+loads the library and fails loudly if it is missing or no GPU is present.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libkfx.so")
+
+KFX_OK = 0
+KFX_EINVAL = -1
+KFX_EOVERFLOW = -2
+KFX_EHIP = -3
+KFX_ESTATE = -4
+KFX_ENOMEM = -5
+MODE_PLAIN = 0
+MODE_FUSED = 1
+MAX_CANDS = 16
+MAX_STEPS = 40
+
+EXPORTED = ["kfx_create", "kfx_destroy", "kfx_last_error", "kfx_load_layers", "kfx_bin_hits",
+            "kfx_seed_states", "kfx_step_compat", "kfx_build_tracks", "kfx_fit_tracks"]
+
+
+class c_states(ctypes.Structure):
+    _fields_ = [("pos", ctypes.c_void_p), ("kt", ctypes.c_void_p), ("cov", ctypes.c_void_p),
+                ("stride", ctypes.c_int64)]
+
+
+class c_hits(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("z", ctypes.c_void_p),
+                ("layer", ctypes.c_void_p), ("event_offsets", ctypes.c_void_p),
+                ("n_hits", ctypes.c_int32), ("n_events", ctypes.c_int32)]
+
+
+class c_prior(ctypes.Structure):
+    _fields_ = [("spos", ctypes.c_float), ("sk_rel", ctypes.c_float), ("sphi", ctypes.c_float),
+                ("stheta", ctypes.c_float)]
+
+
+class c_build_params(ctypes.Structure):
+    _fields_ = [("chi2_cut", ctypes.c_float), ("max_cands", ctypes.c_int32),
+                ("max_holes", ctypes.c_int32), ("max_steps", ctypes.c_int32),
+                ("prior", c_prior), ("mode", ctypes.c_int32), ("block_threads", ctypes.c_int32),
+                ("blocks", ctypes.c_int32)]
+
+
+class c_tracks(ctypes.Structure):
+    _fields_ = [("n_cands", ctypes.c_void_p), ("hits", ctypes.c_void_p), ("n_hits", ctypes.c_void_p),
+                ("n_holes", ctypes.c_void_p), ("chi2", ctypes.c_void_p), ("state", c_states),
+                ("stats", ctypes.c_void_p), ("max_hits", ctypes.c_int32), ("capacity", ctypes.c_int64),
+                ("needed", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def load_library():
+    """Load libkfx.so (built by __graft_entry__.build()); raises if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build the HIP library first "
+                           "(python -c 'import __graft_entry__ as g; g.build()')")
+    lib = ctypes.CDLL(LIB_PATH)
+    lib.kfx_create.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_void_p)]
+    lib.kfx_destroy.argtypes = [ctypes.c_void_p]
+    lib.kfx_destroy.restype = None
+    lib.kfx_last_error.argtypes = [ctypes.c_void_p]
+    lib.kfx_last_error.restype = ctypes.c_char_p
+    lib.kfx_load_layers.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_double,
+                                    ctypes.c_int, ctypes.c_int]
+    lib.kfx_bin_hits.argtypes = [ctypes.c_void_p, ctypes.POINTER(c_hits), ctypes.c_void_p,
+                                 ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    lib.kfx_seed_states.argtypes = [ctypes.c_void_p, ctypes.POINTER(c_hits), ctypes.c_void_p,
+                                    ctypes.c_int32, ctypes.POINTER(c_prior), ctypes.POINTER(c_states),
+                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    lib.kfx_step_compat.argtypes = [ctypes.c_void_p, ctypes.POINTER(c_hits), ctypes.c_void_p,
+                                    ctypes.c_void_p, ctypes.POINTER(c_states), ctypes.c_int32,
+                                    ctypes.c_float, ctypes.c_void_p, ctypes.POINTER(c_states),
+                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                    ctypes.c_void_p]
+    lib.kfx_build_tracks.argtypes = [ctypes.c_void_p, ctypes.POINTER(c_hits), ctypes.c_void_p,
+                                     ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(c_build_params),
+                                     ctypes.POINTER(c_tracks), ctypes.c_void_p]
+    lib.kfx_fit_tracks.argtypes = [ctypes.c_void_p, ctypes.POINTER(c_hits), ctypes.c_void_p,
+                                   ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(c_prior),
+                                   ctypes.c_void_p, ctypes.c_float, ctypes.POINTER(c_states),
+                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                   ctypes.POINTER(c_states), ctypes.c_void_p]
+    for name in EXPORTED:
+        if name not in ("kfx_destroy", "kfx_last_error"):
+            getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+class KfxError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"kfx error {code}: {msg}")
+        self.code = code
+
+
+@dataclass
+class States:
+    """Device SoA states: pos float64 [4, n] (x, y, z, phi), kt float32
+    [2, n] (k, theta), cov float32 [21, n] (packed lower triangle)."""
+
+    pos: object
+    kt: object
+    cov: object
+
+    @staticmethod
+    def empty(n, device):
+        import torch
+        n = max(int(n), 1)
+        return States(torch.zeros((4, n), dtype=torch.float64, device=device),
+                      torch.zeros((2, n), dtype=torch.float32, device=device),
+                      torch.zeros((21, n), dtype=torch.float32, device=device))
+
+    @staticmethod
+    def from_numpy(p, C, device):
+        """p: [n, 6] (x, y, z, k, phi, theta); C: [n, 6, 6] or [n, 21]."""
+        import torch
+        p = np.asarray(p, dtype=np.float64)
+        n = p.shape[0]
+        C = np.asarray(C)
+        if C.ndim == 3:
+            C = pack_cov(C)
+        pos = np.stack([p[:, 0], p[:, 1], p[:, 2], p[:, 4]])
+        kt = np.stack([p[:, 3], p[:, 5]]).astype(np.float32)
+        return States(torch.as_tensor(np.ascontiguousarray(pos), device=device),
+                      torch.as_tensor(np.ascontiguousarray(kt), device=device),
+                      torch.as_tensor(np.ascontiguousarray(C.T.astype(np.float32)), device=device))
+
+    @property
+    def n(self):
+        return int(self.pos.shape[1])
+
+    def c(self):
+        return c_states(self.pos.data_ptr(), self.kt.data_ptr(), self.cov.data_ptr(), self.n)
+
+    def to_numpy(self, n=None):
+        """Returns p [n, 6] (float64) and C [n, 6, 6] (float64)."""
+        pos = self.pos.cpu().numpy()
+        kt = self.kt.cpu().numpy().astype(np.float64)
+        cov = self.cov.cpu().numpy().astype(np.float64)
+        n = pos.shape[1] if n is None else n
+        p = np.stack([pos[0], pos[1], pos[2], kt[0], pos[3], kt[1]], axis=1)[:n]
+        return p, unpack_cov(cov.T[:n])
+
+
+def pack_cov(C):
+    idx = [(i, j) for i in range(6) for j in range(i + 1)]
+    return np.stack([C[:, i, j] for i, j in idx], axis=1)
+
+
+def unpack_cov(P):
+    n = P.shape[0]
+    C = np.zeros((n, 6, 6))
+    q = 0
+    for i in range(6):
+        for j in range(i + 1):
+            C[:, i, j] = P[:, q]
+            C[:, j, i] = P[:, q]
+            q += 1
+    return C
+
+
+class DeviceHits:
+    """Hits resident in device memory (kept alive with the struct)."""
+
+    def __init__(self, x, y, z, layer, event_offsets):
+        self.x, self.y, self.z, self.layer, self.event_offsets = x, y, z, layer, event_offsets
+        self.struct = c_hits(x.data_ptr(), y.data_ptr(), z.data_ptr(), layer.data_ptr(),
+                             event_offsets.data_ptr(), int(x.shape[0]), int(event_offsets.shape[0] - 1))
+
+    @staticmethod
+    def from_events(ev, device):
+        import torch
+        t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a, dtype=dt), device=device)
+        return DeviceHits(t(ev.x, np.float32), t(ev.y, np.float32), t(ev.z, np.float32),
+                          t(ev.layer, np.int32), t(ev.event_offsets, np.int32))
+
+    @property
+    def n_hits(self):
+        return int(self.struct.n_hits)
+
+    @property
+    def n_events(self):
+        return int(self.struct.n_events)
+
+
+def prior_struct(prior):
+    return c_prior(*[float(v) for v in prior])
+
+
+class Context:
+    """A kfx context on one HIP device."""
+
+    def __init__(self, device=0):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("kfx needs a HIP GPU (torch.cuda.is_available() is False)")
+        self.lib = load_library()
+        self.device = torch.device("cuda", device)
+        h = ctypes.c_void_p()
+        rc = self.lib.kfx_create(int(device), ctypes.byref(h))
+        if rc != KFX_OK:
+            raise KfxError(rc, "kfx_create failed")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.kfx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc != KFX_OK:
+            raise KfxError(rc, self.lib.kfx_last_error(self.h).decode())
+
+    def _stream(self):
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+
+    # ------------------------------------------------------------------
+    def load_layers(self, table, bz, n_eta, n_phi):
+        t = np.ascontiguousarray(table, dtype=np.float64)
+        self._check(self.lib.kfx_load_layers(self.h, t.ctypes.data_as(ctypes.c_void_p), int(t.shape[0]),
+                                             float(bz), int(n_eta), int(n_phi)))
+        self.n_layers = int(t.shape[0])
+        self.n_eta, self.n_phi = int(n_eta), int(n_phi)
+
+    def bin_hits(self, hits: DeviceHits, want=True):
+        import torch
+        n_keys = hits.n_events * self.n_layers * self.n_eta * self.n_phi
+        d = self.device
+        bins = torch.empty(max(hits.n_hits, 1), dtype=torch.int32, device=d) if want else None
+        off = torch.empty(n_keys + 1, dtype=torch.int32, device=d) if want else None
+        perm = torch.empty(max(hits.n_hits, 1), dtype=torch.int32, device=d) if want else None
+        self._check(self.lib.kfx_bin_hits(self.h, ctypes.byref(hits.struct), _ptr(bins), _ptr(off), _ptr(perm),
+                                          self._stream()))
+        return bins, off, perm
+
+    def seed_states(self, hits: DeviceHits, seeds, prior):
+        import torch
+        seeds = torch.as_tensor(np.ascontiguousarray(seeds, dtype=np.int32), device=self.device)
+        n = int(seeds.shape[0])
+        out = States.empty(n, self.device)
+        chi2 = torch.zeros(max(n, 1), dtype=torch.float32, device=self.device)
+        status = torch.zeros(max(n, 1), dtype=torch.int32, device=self.device)
+        pr = prior_struct(prior)
+        st = out.c()
+        self._check(self.lib.kfx_seed_states(self.h, ctypes.byref(hits.struct), _ptr(seeds), n, ctypes.byref(pr),
+                                             ctypes.byref(st), _ptr(chi2), _ptr(status), self._stream()))
+        return out, chi2[:n], status[:n]
+
+    def step_compat(self, hits: DeviceHits, cand_event, cand_layer, states: States, chi2_cut, max_pairs=64):
+        import torch
+        d = self.device
+        ce = torch.as_tensor(np.ascontiguousarray(cand_event, dtype=np.int32), device=d)
+        cl = torch.as_tensor(np.ascontiguousarray(cand_layer, dtype=np.int32), device=d)
+        n = int(ce.shape[0])
+        nxt = torch.zeros(max(n, 1), dtype=torch.int32, device=d)
+        pred = States.empty(n, d)
+        cnt = torch.zeros(max(n, 1), dtype=torch.int32, device=d)
+        ph = torch.full((max(n, 1), max_pairs), -1, dtype=torch.int32, device=d)
+        pc = torch.zeros((max(n, 1), max_pairs), dtype=torch.float32, device=d)
+        si, sp = states.c(), pred.c()
+        self._check(self.lib.kfx_step_compat(self.h, ctypes.byref(hits.struct), _ptr(ce), _ptr(cl), ctypes.byref(si),
+                                             n, float(chi2_cut), _ptr(nxt), ctypes.byref(sp), _ptr(cnt), _ptr(ph),
+                                             _ptr(pc), int(max_pairs), self._stream()))
+        return nxt[:n], pred, cnt[:n], ph[:n], pc[:n]
+
+    def build_tracks(self, hits: DeviceHits, seeds, seed_event, chi2_cut=30.0, max_cands=6, max_holes=3,
+                     max_steps=32, prior=(0.1, 0.5, 0.05, 0.05), mode=MODE_FUSED, block_threads=0,
+                     blocks=0, max_hits=48, out=None):
+        """Returns a dict of device tensors (see kfx_tracks in kfx.h)."""
+        import torch
+        d = self.device
+        if not isinstance(seeds, torch.Tensor):
+            seeds = torch.as_tensor(np.ascontiguousarray(seeds, dtype=np.int32), device=d)
+        if not isinstance(seed_event, torch.Tensor):
+            seed_event = torch.as_tensor(np.ascontiguousarray(seed_event, dtype=np.int32), device=d)
+        S = int(seeds.shape[0])
+        K = int(max_cands)
+        if out is None:
+            out = self.alloc_tracks(S, K, max_hits)
+        p = c_build_params(float(chi2_cut), K, int(max_holes), int(max_steps), prior_struct(prior), int(mode),
+                           int(block_threads), int(blocks))
+        t = out["_struct"]
+        self._check(self.lib.kfx_build_tracks(self.h, ctypes.byref(hits.struct), _ptr(seeds), _ptr(seed_event), S,
+                                              ctypes.byref(p), ctypes.byref(t), self._stream()))
+        return out
+
+    def alloc_tracks(self, S, K, max_hits=48):
+        import torch
+        d = self.device
+        n = max(S * K, 1)
+        out = dict(n_cands=torch.zeros(max(S, 1), dtype=torch.int32, device=d),
+                   hits=torch.zeros((n, max_hits), dtype=torch.int32, device=d),
+                   n_hits=torch.zeros(n, dtype=torch.int32, device=d),
+                   n_holes=torch.zeros(n, dtype=torch.int32, device=d),
+                   chi2=torch.zeros(n, dtype=torch.float32, device=d),
+                   state=States.empty(n, d),
+                   stats=torch.zeros(4, dtype=torch.int64, device=d))
+        out["_struct"] = c_tracks(out["n_cands"].data_ptr(), out["hits"].data_ptr(), out["n_hits"].data_ptr(),
+                                  out["n_holes"].data_ptr(), out["chi2"].data_ptr(), out["state"].c(),
+                                  out["stats"].data_ptr(), int(max_hits), n, 0)
+        out["S"], out["K"] = S, K
+        return out
+
+    def fit_tracks(self, hits: DeviceHits, trk_off, trk_hits, prior=(0.1, 0.5, 0.05, 0.05), align=None,
+                   field_scale=1.0, ckpt=False, out=None):
+        import torch
+        d = self.device
+        if not isinstance(trk_off, torch.Tensor):
+            trk_off = torch.as_tensor(np.ascontiguousarray(trk_off, dtype=np.int32), device=d)
+        if not isinstance(trk_hits, torch.Tensor):
+            trk_hits = torch.as_tensor(np.ascontiguousarray(trk_hits, dtype=np.int32), device=d)
+        if align is not None and not isinstance(align, torch.Tensor):
+            align = torch.as_tensor(np.ascontiguousarray(align, dtype=np.float32).reshape(-1), device=d)
+        T = int(trk_off.shape[0] - 1)
+        if out is None:
+            out = dict(state=States.empty(T, d), chi2=torch.zeros(max(T, 1), dtype=torch.float32, device=d),
+                       ndof=torch.zeros(max(T, 1), dtype=torch.int32, device=d),
+                       status=torch.zeros(max(T, 1), dtype=torch.int32, device=d))
+            if ckpt:
+                out["ckpt"] = States.empty(int(trk_hits.shape[0]), d)
+        pr = prior_struct(prior)
+        so = out["state"].c()
+        ck = out["ckpt"].c() if "ckpt" in out else None
+        self._check(self.lib.kfx_fit_tracks(self.h, ctypes.byref(hits.struct), _ptr(trk_off), _ptr(trk_hits), T,
+                                            ctypes.byref(pr), _ptr(align), float(field_scale), ctypes.byref(so),
+                                            _ptr(out["chi2"]), _ptr(out["ndof"]), _ptr(out["status"]),
+                                            ctypes.byref(ck) if ck is not None else None, self._stream()))
+        return out
