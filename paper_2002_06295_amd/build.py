@@ -16,6 +16,9 @@ FLAGS = [
     # packed FP32 (v_pk_*_f32) stays off: hipcc -O3 would form it from
     # plain float code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # contract a*b+c into FMA only within one expression, so that a device
+    # function inlined into different kernels rounds identically everywhere
+    "-ffp-contract=on",
     "-Wall", "-Wno-unused-function", "-Wno-unused-result",
 ]
 

@@ -91,9 +91,9 @@ KFX_HD int predict_slot(const BuildArgs& a, int cur, long slot) {
   State st, pr;
   load_state(a.cand[cur], slot, st);
   const double cphi = cos(st.phi), sphi = sin(st.phi);
-  const float kappa = -kHc * (float)G.bz;
-  float s = 0.0f;
-  const int nl = navigate(G, a.layer[cur][slot], st, cphi, sphi, kappa * st.k, s);
+  const double kappa = -kHcD * G.bz;
+  double s = 0.0;
+  const int nl = navigate(G, a.layer[cur][slot], st, cphi, sphi, kappa * (double)st.k, s);
   if (nl < 0) {
     a.next_layer[slot] = -1;
     return 0;
@@ -252,9 +252,7 @@ KFX_HD int update_slot(const BuildArgs& a, int cur, int s, int j, int t) {
     const int nl = a.next_layer[ps];
     a.layer[nxt][slot] = nl;
     if (code >= 0) {
-      Frame F;
-      make_frame(st, a.G->L[nl], F);
-      kf_update(st, F, (double)a.H.x[code], (double)a.H.y[code], (double)a.H.z[code]);
+      kf_update_fp64(st, a.G->L[nl], (double)a.H.x[code], (double)a.H.y[code], (double)a.H.z[code]);
       a.meta[nxt][slot] = meta_pack(meta_nhits(pm) + 1, meta_nholes(pm), 0, kFlagLive);
       upd = 1;
     } else {
@@ -292,8 +290,8 @@ KFX_HD void finalize_slot(const BuildArgs& a, int fin, const TracksOut& o, int s
     o.n_holes[slot] = 0;
     o.chi2[slot] = 0.0f;
     State z;
-    z.x = z.y = z.z = z.phi = 0.0;
-    z.k = z.th = 0.0f;
+    z.x = z.y = z.z = z.phi = z.th = 0.0;
+    z.k = 0.0f;
     for (int q = 0; q < 21; ++q) z.C[q] = 0.0f;
     store_state(o.state, slot, z);
     return;

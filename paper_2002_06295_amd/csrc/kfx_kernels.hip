@@ -186,8 +186,8 @@ __global__ void k_seed_states(const Geometry* __restrict__ G, HitsView H, const 
   float c2 = 0.0f;
   const bool ok = seed_state(*G, H, seeds + 3 * s, pr, st, c2);
   if (!ok) {
-    st.x = st.y = st.z = st.phi = 0.0;
-    st.k = st.th = 0.0f;
+    st.x = st.y = st.z = st.phi = st.th = 0.0;
+    st.k = 0.0f;
     for (int j = 0; j < 21; ++j) st.C[j] = 0.0f;
     c2 = 0.0f;
   }
@@ -207,11 +207,11 @@ __global__ void k_step_compat(const Geometry* __restrict__ G, HitsView H, BinInd
   State st, pr;
   load_state(in, i, st);
   const double cphi = cos(st.phi), sphi = sin(st.phi);
-  const float kappa = -kHc * (float)G->bz;
-  float s = 0.0f;
+  const double kappa = -kHcD * G->bz;
+  double s = 0.0;
   const int cl = cand_layer[i], ce = cand_event[i];
   const int nl = (cl >= 0 && cl < G->n_layers && ce >= 0 && ce < H.n_events)
-                     ? navigate(*G, cl, st, cphi, sphi, kappa * st.k, s) : -1;
+                     ? navigate(*G, cl, st, cphi, sphi, kappa * (double)st.k, s) : -1;
   next_layer[i] = nl;
   if (nl < 0) {
     pair_count[i] = 0;
@@ -323,8 +323,8 @@ __global__ void k_build_finalize(BuildArgs a, int fin, TracksOut o) {
 struct FusedShared {
   // per lane: state to hand to the children (predicted, or current for a
   // stop child), its layer, meta and chi2
-  double pos[4];
-  float kt[2];
+  double pos[5];
+  float k;
   float cov[21];
   int layer;
   int meta;
@@ -341,7 +341,7 @@ __global__ void __launch_bounds__(256) k_build_fused(BuildArgs a, int cur_unused
   const int gl = lane & (G_LANES - 1);          // slot within the seed
   const int gbase = threadIdx.x & ~(G_LANES - 1);
   const int K = a.K;
-  const float kappa = -kHc * (float)G.bz;
+  const double kappa = -kHcD * G.bz;
   const unsigned long long gmask = ((G_LANES == 64) ? ~0ull : ((1ull << G_LANES) - 1ull)) << (lane & ~(G_LANES - 1));
 
   unsigned long long n_steps = 0, n_pairs = 0, n_upd = 0;
@@ -392,8 +392,8 @@ __global__ void __launch_bounds__(256) k_build_fused(BuildArgs a, int cur_unused
         nl = -1;
       } else {
         const double cphi = cos(st.phi), sphi = sin(st.phi);
-        float s = 0.0f;
-        nl = navigate(G, layer, st, cphi, sphi, kappa * st.k, s);
+        double s = 0.0;
+        nl = navigate(G, layer, st, cphi, sphi, kappa * (double)st.k, s);
         if (nl >= 0) {
           transport(st, G.L[nl], cphi, sphi, s, kappa, pr);
           ++n_steps;
@@ -446,8 +446,8 @@ __global__ void __launch_bounds__(256) k_build_fused(BuildArgs a, int cur_unused
     FusedShared& me = sh[threadIdx.x];
     {
       const State& src = (nl >= 0) ? pr : st;
-      me.pos[0] = src.x; me.pos[1] = src.y; me.pos[2] = src.z; me.pos[3] = src.phi;
-      me.kt[0] = src.k; me.kt[1] = src.th;
+      me.pos[0] = src.x; me.pos[1] = src.y; me.pos[2] = src.z; me.pos[3] = src.phi; me.pos[4] = src.th;
+      me.k = src.k;
 #pragma unroll
       for (int q = 0; q < 21; ++q) me.cov[q] = src.C[q];
       me.layer = (nl >= 0) ? nl : layer;
@@ -462,8 +462,8 @@ __global__ void __launch_bounds__(256) k_build_fused(BuildArgs a, int cur_unused
       if (my_parent >= 0) {
         const FusedShared& par = sh[gbase + my_parent];
         State ns;
-        ns.x = par.pos[0]; ns.y = par.pos[1]; ns.z = par.pos[2]; ns.phi = par.pos[3];
-        ns.k = par.kt[0]; ns.th = par.kt[1];
+        ns.x = par.pos[0]; ns.y = par.pos[1]; ns.z = par.pos[2]; ns.phi = par.pos[3]; ns.th = par.pos[4];
+        ns.k = par.k;
 #pragma unroll
         for (int q = 0; q < 21; ++q) ns.C[q] = par.cov[q];
         const int pm = par.meta;
@@ -471,9 +471,8 @@ __global__ void __launch_bounds__(256) k_build_fused(BuildArgs a, int cur_unused
         if (my_code == kStop) {
           new_meta = meta_pack(meta_nhits(pm), meta_nholes(pm), meta_consec(pm), kFlagLive | kFlagDone);
         } else if (my_code >= 0) {
-          Frame F;
-          make_frame(ns, G.L[new_layer], F);
-          kf_update(ns, F, (double)a.H.x[my_code], (double)a.H.y[my_code], (double)a.H.z[my_code]);
+          kf_update_fp64(ns, G.L[new_layer], (double)a.H.x[my_code], (double)a.H.y[my_code],
+                         (double)a.H.z[my_code]);
           new_meta = meta_pack(meta_nhits(pm) + 1, meta_nholes(pm), 0, kFlagLive);
           ++n_upd;
         } else {

@@ -31,7 +31,8 @@
 namespace kfx {
 
 constexpr double kPi = 3.14159265358979323846;
-constexpr float kHc = 0.299792458e-2f;  // pT [GeV] = kHc * B [T] * rho [cm]
+constexpr double kHcD = 0.299792458e-2;  // pT [GeV] = kHc * B [T] * rho [cm]
+constexpr float kHc = (float)kHcD;
 constexpr int kBarrel = 0;
 constexpr int kDisk = 1;
 constexpr int kMaxLayers = 64;
@@ -62,11 +63,36 @@ struct Geometry {
   int n_eta, n_phi;
 };
 
-struct State {
-  double x, y, z, phi;
-  float k, th;
-  float C[21];
+template <class R>
+struct StateT {
+  double x, y, z, phi, th;  // position and direction (FP64)
+  R k;                      // q/pT
+  R C[21];                  // covariance of (x, y, z, k, phi, theta), packed
 };
+using State = StateT<float>;
+
+template <class A, class B>
+KFX_HD void convert_state(const StateT<A>& a, StateT<B>& b) {
+  b.x = a.x; b.y = a.y; b.z = a.z; b.phi = a.phi; b.th = a.th;
+  b.k = (B)a.k;
+#pragma unroll
+  for (int i = 0; i < 21; ++i) b.C[i] = (B)a.C[i];
+}
+
+// scalar math for float and double
+KFX_HD float msin(float x) { return sinf(x); }
+KFX_HD double msin(double x) { return sin(x); }
+KFX_HD float mcos(float x) { return cosf(x); }
+KFX_HD double mcos(double x) { return cos(x); }
+KFX_HD float msqrt(float x) { return sqrtf(x); }
+KFX_HD double msqrt(double x) { return sqrt(x); }
+KFX_HD float mabs(float x) { return fabsf(x); }
+KFX_HD double mabs(double x) { return fabs(x); }
+KFX_HD float mlog(float x) { return logf(x); }
+KFX_HD double mlog(double x) { return log(x); }
+KFX_HD float mmax(float a, float b) { return fmaxf(a, b); }
+KFX_HD double mmax(double a, double b) { return fmax(a, b); }
+template <class R> KFX_HD constexpr R newton_tol() { return sizeof(R) == 4 ? (R)2e-7 : (R)1e-13; }
 
 KFX_HD double wrap_pi(double a) {  // to (-pi, pi]
   if (a > kPi) a -= 2.0 * kPi;
@@ -75,13 +101,14 @@ KFX_HD double wrap_pi(double a) {  // to (-pi, pi]
 }
 
 // sin(a)/a and its derivative (cos a - sin(a)/a)/a, with series near 0.
-KFX_HD void sinc_d(float a, float sa, float ca, float& sinc, float& dsinc) {
-  if (fabsf(a) < 1e-3f) {
-    float a2 = a * a;
-    sinc = 1.0f - a2 * (1.0f / 6.0f) + a2 * a2 * (1.0f / 120.0f);
-    dsinc = a * (-1.0f / 3.0f + a2 * (1.0f / 30.0f));
+template <class R>
+KFX_HD void sinc_d(R a, R sa, R ca, R& sinc, R& dsinc) {
+  if (mabs(a) < (R)1e-3) {
+    const R a2 = a * a;
+    sinc = (R)1 - a2 * (R)(1.0 / 6.0) + a2 * a2 * (R)(1.0 / 120.0);
+    dsinc = a * ((R)(-1.0 / 3.0) + a2 * (R)(1.0 / 30.0));
   } else {
-    float ia = 1.0f / a;
+    const R ia = (R)1 / a;
     sinc = sa * ia;
     dsinc = (ca - sinc) * ia;
   }
@@ -90,65 +117,118 @@ KFX_HD void sinc_d(float a, float sa, float ca, float& sinc, float& dsinc) {
 // Displacement after a transverse path s on a helix that starts with
 // direction (cphi, sphi) and turns at omega = d(phi)/ds: a chord of length
 // s sinc(a) at angle phi0 + a, a = omega s / 2.  Stable at omega -> 0.
-struct Chord {
-  float a, sa, ca, sinc, dsinc;
+template <class R>
+struct ChordT {
+  R a, sa, ca, sinc, dsinc;
   double dx, dy;
 };
 
-KFX_HD Chord chord(float s, float omega, double cphi, double sphi) {
-  Chord c;
-  c.a = 0.5f * omega * s;
-  c.sa = sinf(c.a);
-  c.ca = cosf(c.a);
+template <class R>
+KFX_HD ChordT<R> chord(R s, R omega, double cphi, double sphi) {
+  ChordT<R> c;
+  c.a = (R)0.5 * omega * s;
+  c.sa = msin(c.a);
+  c.ca = mcos(c.a);
   sinc_d(c.a, c.sa, c.ca, c.sinc, c.dsinc);
-  float L = s * c.sinc;
-  double dpar = (double)(L * c.ca), dperp = (double)(L * c.sa);
+  const R L = s * c.sinc;
+  const double dpar = (double)(L * c.ca), dperp = (double)(L * c.sa);
   c.dx = cphi * dpar - sphi * dperp;
   c.dy = sphi * dpar + cphi * dperp;
   return c;
 }
 
-// Outgoing crossing of the cylinder of radius R.  The start must lie inside
-// it and move outward.  Newton on g(s) = |P(s)|^2 - R^2, with g evaluated
-// relative to the start in FP64, from the straight-line root.  Returns the
-// transverse path, or a negative value when there is no outgoing crossing.
-KFX_HD float path_to_cylinder(const State& st, double cphi, double sphi, float omega, double R) {
-  double c0 = st.x * st.x + st.y * st.y - R * R;
-  double Dd = st.x * cphi + st.y * sphi;
-  if (!(c0 < 0.0) || Dd < 0.0) return -1.0f;
-  float D = (float)Dd;
-  float s = (float)(-c0) / (D + sqrtf(D * D - (float)c0));
+// direction (cos, sin) at the end of a chord: phi0 + 2a
+template <class R>
+KFX_HD void chord_end_dir(const ChordT<R>& c, double cphi, double sphi, double& c1, double& s1) {
+  const R c2a = c.ca * c.ca - c.sa * c.sa, s2a = (R)2 * c.sa * c.ca;
+  c1 = cphi * (double)c2a - sphi * (double)s2a;
+  s1 = sphi * (double)c2a + cphi * (double)s2a;
+}
+
+// The same chord in FP64 (positions and the direction at the end): the
+// crossing point and the residuals are computed from it.
+struct ChordD {
+  double a, sa, ca;   // half turning angle and its sine/cosine
+  double dx, dy;      // displacement
+  double c1, s1;      // direction (cos, sin) at the end
+};
+
+KFX_HD ChordD chord_d(double s, double omega, double cphi, double sphi) {
+  ChordD c;
+  c.a = 0.5 * omega * s;
+  c.sa = sin(c.a);
+  c.ca = cos(c.a);
+  double sinc;
+  if (fabs(c.a) < 1e-4) {
+    const double a2 = c.a * c.a;
+    sinc = 1.0 - a2 * (1.0 / 6.0) + a2 * a2 * (1.0 / 120.0);
+  } else {
+    sinc = c.sa / c.a;
+  }
+  const double L = s * sinc;
+  const double dpar = L * c.ca, dperp = L * c.sa;
+  c.dx = cphi * dpar - sphi * dperp;
+  c.dy = sphi * dpar + cphi * dperp;
+  const double c2a = 1.0 - 2.0 * c.sa * c.sa, s2a = 2.0 * c.sa * c.ca;
+  c.c1 = cphi * c2a - sphi * s2a;
+  c.s1 = sphi * c2a + cphi * s2a;
+  return c;
+}
+
+// Outgoing crossing of the cylinder of radius Rc.  The start must lie
+// inside it and move outward.  Newton on g(s) = |P(s)|^2 - Rc^2 (g taken
+// relative to the start) from the straight-line root, first in R, then two
+// FP64 steps on the FP64 chord.  Returns the transverse path, or a negative
+// value when there is no outgoing crossing.
+template <class R>
+KFX_HD double path_to_cylinder(const StateT<R>& st, double cphi, double sphi, double omega_d, double Rc) {
+  const double c0 = st.x * st.x + st.y * st.y - Rc * Rc;
+  const double Dd = st.x * cphi + st.y * sphi;
+  if (!(c0 < 0.0) || Dd < 0.0) return -1.0;
+  const R D = (R)Dd;
+  const R omega = (R)omega_d;
+  R s = (R)(-c0) / (D + msqrt(D * D - (R)c0));
   bool conv = false;
   for (int it = 0; it < 12; ++it) {
-    Chord c = chord(s, omega, cphi, sphi);
-    double g = c0 + 2.0 * (st.x * c.dx + st.y * c.dy) + (c.dx * c.dx + c.dy * c.dy);
-    // direction at s: phi0 + 2a
-    float c2a = c.ca * c.ca - c.sa * c.sa, s2a = 2.0f * c.sa * c.ca;
-    double c1 = cphi * c2a - sphi * s2a, s1 = sphi * c2a + cphi * s2a;
-    float gp = 2.0f * (float)((st.x + c.dx) * c1 + (st.y + c.dy) * s1);
-    if (!(gp > 0.0f)) return -1.0f;
-    float ds = (float)g / gp;
+    const ChordT<R> c = chord(s, omega, cphi, sphi);
+    const double g = c0 + 2.0 * (st.x * c.dx + st.y * c.dy) + (c.dx * c.dx + c.dy * c.dy);
+    double c1, s1;
+    chord_end_dir(c, cphi, sphi, c1, s1);
+    const R gp = (R)2 * (R)((st.x + c.dx) * c1 + (st.y + c.dy) * s1);
+    if (!(gp > (R)0)) return -1.0;
+    const R ds = (R)g / gp;
     s -= ds;
-    if (fabsf(ds) <= 2e-7f * fabsf(s) + 1e-9f) {
+    if (mabs(ds) <= newton_tol<R>() * mabs(s) + (R)1e-9) {
       conv = true;
       break;
     }
   }
-  if (!conv || !(s > 0.0f)) return -1.0f;
-  // moving outward at the crossing
-  Chord c = chord(s, omega, cphi, sphi);
-  float c2a = c.ca * c.ca - c.sa * c.sa, s2a = 2.0f * c.sa * c.ca;
-  double c1 = cphi * c2a - sphi * s2a, s1 = sphi * c2a + cphi * s2a;
-  if ((st.x + c.dx) * c1 + (st.y + c.dy) * s1 < 0.0) return -1.0f;
-  return s;
+  if (!conv || !(s > (R)0)) return -1.0;
+  double sd = (double)s;
+  for (int it = 0; it < 2; ++it) {
+    const ChordD c = chord_d(sd, omega_d, cphi, sphi);
+    const double g = c0 + 2.0 * (st.x * c.dx + st.y * c.dy) + (c.dx * c.dx + c.dy * c.dy);
+    const double gp = 2.0 * ((st.x + c.dx) * c.c1 + (st.y + c.dy) * c.s1);
+    if (!(gp > 0.0)) return -1.0;  // moving inward: past the turning point
+    sd -= g / gp;
+  }
+  return sd > 0.0 ? sd : -1.0;
 }
 
-// Plane z = Z: s = (Z - z0) tan(theta), ahead of the track.
-KFX_HD float path_to_disk(const State& st, double Z) {
-  float sth = sinf(st.th), cth = cosf(st.th);
-  if (fabsf(cth) < 1e-12f) return -1.0f;
-  float s = (float)(Z - st.z) * (sth / cth);
-  return s > 1e-12f ? s : -1.0f;
+// Plane z = Z: s = (Z - z0) tan(theta), ahead of the track (FP64).
+template <class R>
+KFX_HD double path_to_disk(const StateT<R>& st, double Z) {
+  const double sth = sin(st.th), cth = cos(st.th);
+  if (fabs(cth) < 1e-12) return -1.0;
+  const double s = (Z - st.z) * (sth / cth);
+  return s > 1e-12 ? s : -1.0;
+}
+
+// Path to the surface of a layer (barrel radius r_surf, possibly aligned).
+template <class R>
+KFX_HD double path_to_layer(const StateT<R>& st, const Layer& Ld, double r_surf, double cphi, double sphi,
+                            double omega_d) {
+  return Ld.kind == kBarrel ? path_to_cylinder(st, cphi, sphi, omega_d, r_surf) : path_to_disk(st, Ld.pos);
 }
 
 // Navigation: the next surface is the nearer of the next barrel layer
@@ -156,15 +236,15 @@ KFX_HD float path_to_disk(const State& st, double Z) {
 // first disk ahead in z whose crossing lies within [rmin, rmax] while the
 // track still moves outward.  Returns the layer id (or -1) and its path.
 KFX_HD int navigate(const Geometry& G, int cur, const State& st, double cphi, double sphi,
-                    float omega, float& s_out) {
-  float best = 3.0e38f;
+                    double omega_d, double& s_out) {
+  double best = 3.0e38;
   int bl = -1;
   int nb = -1;
   const Layer& Lc = G.L[cur];
   if (Lc.kind == kBarrel) {
     nb = G.next_barrel[cur];
   } else {
-    double r = sqrt(st.x * st.x + st.y * st.y);
+    const double r = sqrt(st.x * st.x + st.y * st.y);
     for (int i = 0; i < G.n_barrel; ++i)
       if (G.L[G.barrel[i]].pos > r) {
         nb = G.barrel[i];
@@ -172,33 +252,31 @@ KFX_HD int navigate(const Geometry& G, int cur, const State& st, double cphi, do
       }
   }
   if (nb >= 0) {
-    float s = path_to_cylinder(st, cphi, sphi, omega, G.L[nb].pos);
-    if (s > 0.0f) {
-      double z = st.z + (double)(s * (cosf(st.th) / sinf(st.th)));
+    const double s = path_to_cylinder(st, cphi, sphi, omega_d, G.L[nb].pos);
+    if (s > 0.0) {
+      const double z = st.z + s * (cos(st.th) / sin(st.th));
       if (fabs(z) <= G.L[nb].hi) {
         best = s;
         bl = nb;
       }
     }
   }
-  float cth = cosf(st.th);
-  if (fabsf(cth) > 1e-12f) {
-    bool fwd = cth > 0.0f;
-    int n = fwd ? G.n_dpos : G.n_dneg;
+  const double cth = cos(st.th);
+  if (fabs(cth) > 1e-12) {
+    const bool fwd = cth > 0.0;
+    const int n = fwd ? G.n_dpos : G.n_dneg;
     const int* dl = fwd ? G.dpos : G.dneg;
     for (int i = 0; i < n; ++i) {
-      int id = dl[i];
+      const int id = dl[i];
       if (id == cur) continue;
-      double Z = G.L[id].pos;
+      const double Z = G.L[id].pos;
       if (fwd ? (Z <= st.z) : (Z >= st.z)) continue;
-      float s = path_to_disk(st, Z);
-      if (!(s > 0.0f)) continue;
-      Chord c = chord(s, omega, cphi, sphi);
-      double x = st.x + c.dx, y = st.y + c.dy;
-      float c2a = c.ca * c.ca - c.sa * c.sa, s2a = 2.0f * c.sa * c.ca;
-      double c1 = cphi * c2a - sphi * s2a, s1 = sphi * c2a + cphi * s2a;
-      if (x * c1 + y * s1 < 0.0) break;  // turned before reaching it
-      double r = sqrt(x * x + y * y);
+      const double s = path_to_disk(st, Z);
+      if (!(s > 0.0)) continue;
+      const ChordD c = chord_d(s, omega_d, cphi, sphi);
+      const double x = st.x + c.dx, y = st.y + c.dy;
+      if (x * c.c1 + y * c.s1 < 0.0) break;  // turned before reaching it
+      const double r = sqrt(x * x + y * y);
       if (r > G.L[id].hi) break;          // left radially
       if (r < G.L[id].lo) continue;       // passes inside the disk
       if (s < best) {
@@ -212,83 +290,107 @@ KFX_HD int navigate(const Geometry& G, int cur, const State& st, double cphi, do
   return bl;
 }
 
+// Multiple scattering at a layer for a state on it (Highland, beta = 1,
+// no energy loss): var(theta) = th0^2, var(phi) = th0^2 / sin^2(theta),
+// and k = q/(|p| sin theta) follows theta at fixed |p|.
+template <class R>
+KFX_HD void add_noise(StateT<R>& st, const Layer& Ld, R sth, R cth, R cinc) {
+  if (!(Ld.x0 > 0.0f)) return;
+  cinc = mmax(cinc, (R)1e-3);
+  const R t = (R)Ld.x0 / cinc;
+  const R th0 = (R)0.0136 * mabs(st.k) * sth * msqrt(t) * ((R)1 + (R)0.038 * mlog(t));
+  const R var = th0 * th0;
+  const R cot = cth / sth;
+  st.C[sidx(4, 4)] += var / (sth * sth);
+  st.C[sidx(5, 5)] += var;
+  st.C[sidx(3, 3)] += st.k * st.k * cot * cot * var;
+  st.C[sidx(5, 3)] += -st.k * cot * var;
+}
+
 // Transport (p, C) over transverse path s to the surface of layer Ld
-// (barrel radius Rsurf, possibly aligned): new parameters, C- = J C J^T + Q
-// with the surface-constrained Jacobian J = A + b c^T, where A = dF/dp at
-// fixed s, b = dF/ds and c = ds/dp from the surface equation.  Written as
+// (barrel radius possibly aligned): new parameters, C- = J C J^T + Q with
+// the surface-constrained Jacobian J = A + b c^T, where A = dF/dp at fixed
+// s, b = dF/ds and c = ds/dp from the surface equation.  Written as
 // C- = A C A^T + b u^T + u b^T + sigma b b^T, u = A C c, sigma = c^T C c,
 // which exploits the unit rows of A (k and theta) and needs no branch
 // between barrel and disk except in c.
-KFX_HD void transport(const State& in, const Layer& Ld, double cphi, double sphi, float s,
-                      float kappa, State& out) {
-  const float k = in.k, th = in.th;
-  const float omega = kappa * k;
-  Chord c = chord(s, omega, cphi, sphi);
-  const float sth = sinf(th), cth = cosf(th);
-  const float cot = cth / sth;
+template <class R>
+KFX_HD void transport(const StateT<R>& in, const Layer& Ld, double cphi, double sphi, double s_d,
+                      double kappa_d, StateT<R>& out) {
+  const R k = in.k;
+  const double omega_d = kappa_d * (double)k;
+  const ChordD cd = chord_d(s_d, omega_d, cphi, sphi);
+  const double sth_d = sin(in.th), cth_d = cos(in.th);
   const bool disk = Ld.kind == kDisk;
-  out.x = in.x + c.dx;
-  out.y = in.y + c.dy;
-  out.z = disk ? Ld.pos : in.z + (double)(s * cot);
-  out.phi = wrap_pi(in.phi + (double)(2.0f * c.a));
+  out.x = in.x + cd.dx;
+  out.y = in.y + cd.dy;
+  out.z = disk ? Ld.pos : in.z + s_d * (cth_d / sth_d);
+  out.phi = wrap_pi(in.phi + 2.0 * cd.a);
   out.k = k;
-  out.th = th;
+  out.th = in.th;
+  // Jacobian and noise in R from the rounded geometry
+  const R s = (R)s_d, kappa = (R)kappa_d, omega = (R)omega_d;
+  const R sth = (R)sth_d, cth = (R)cth_d;
+  const R cot = cth / sth;
+  ChordT<R> c;
+  c.a = (R)cd.a;
+  c.sa = (R)cd.sa;
+  c.ca = (R)cd.ca;
+  sinc_d(c.a, c.sa, c.ca, c.sinc, c.dsinc);
   // direction at the middle of the chord (psi) and at the end (phi1)
-  const float cpsi = (float)(cphi * c.ca - sphi * c.sa), spsi = (float)(sphi * c.ca + cphi * c.sa);
-  const float c2a = c.ca * c.ca - c.sa * c.sa, s2a = 2.0f * c.sa * c.ca;
-  const float c1 = (float)(cphi * c2a - sphi * s2a), s1 = (float)(sphi * c2a + cphi * s2a);
-  const float dxf = (float)c.dx, dyf = (float)c.dy;
+  const R cpsi = (R)(cphi * cd.ca - sphi * cd.sa);
+  const R spsi = (R)(sphi * cd.ca + cphi * cd.sa);
+  const R c1 = (R)cd.c1, s1 = (R)cd.s1;
+  const R dxf = (R)cd.dx, dyf = (R)cd.dy;
   // A: free-helix partials at fixed s
-  const float hs2 = 0.5f * kappa * s * s;
-  const float Axk = hs2 * (c.dsinc * cpsi - c.sinc * spsi);
-  const float Ayk = hs2 * (c.dsinc * spsi + c.sinc * cpsi);
-  const float Axp = -dyf, Ayp = dxf;
-  const float Azt = -s / (sth * sth);
-  const float Apk = kappa * s;
-  // b = dF/ds
-  const float b0 = c1, b1 = s1, b2 = cot, b4 = omega;
+  const R hs2 = (R)0.5 * kappa * s * s;
+  const R Axk = hs2 * (c.dsinc * cpsi - c.sinc * spsi);
+  const R Ayk = hs2 * (c.dsinc * spsi + c.sinc * cpsi);
+  const R Axp = -dyf, Ayp = dxf;
+  const R Azt = -s / (sth * sth);
+  const R Apk = kappa * s;
   // c = ds/dp from the surface equation
-  float cv[6];
+  R cv[6];
   if (disk) {
-    cv[0] = 0.0f; cv[1] = 0.0f; cv[3] = 0.0f; cv[4] = 0.0f;
+    cv[0] = (R)0; cv[1] = (R)0; cv[3] = (R)0; cv[4] = (R)0;
     cv[2] = -sth / cth;
     cv[5] = s / (sth * cth);
   } else {
-    const float x1 = (float)out.x, y1 = (float)out.y;
-    const float iDn = -1.0f / (x1 * c1 + y1 * s1);
+    const R x1 = (R)out.x, y1 = (R)out.y;
+    const R iDn = (R)-1 / (x1 * c1 + y1 * s1);
     cv[0] = x1 * iDn;
     cv[1] = y1 * iDn;
-    cv[2] = 0.0f;
+    cv[2] = (R)0;
     cv[3] = (x1 * Axk + y1 * Ayk) * iDn;
     cv[4] = (x1 * Axp + y1 * Ayp) * iDn;
-    cv[5] = 0.0f;
+    cv[5] = (R)0;
   }
-  const float* C = in.C;
+  const R* C = in.C;
   // v = C c
-  float v[6];
+  R v[6];
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
-    float acc = 0.0f;
+    R acc = (R)0;
 #pragma unroll
     for (int j = 0; j < 6; ++j) acc += C[sidx(i, j)] * cv[j];
     v[i] = acc;
   }
-  float sig = 0.0f;
+  R sig = (R)0;
 #pragma unroll
   for (int i = 0; i < 6; ++i) sig += cv[i] * v[i];
   // u = A v
-  float u[6];
+  R u[6];
   u[0] = v[0] + Axk * v[3] + Axp * v[4];
   u[1] = v[1] + Ayk * v[3] + Ayp * v[4];
   u[2] = v[2] + Azt * v[5];
   u[3] = v[3];
   u[4] = v[4] + Apk * v[3];
   u[5] = v[5];
-  // M = C A^T (column j = C a_j), full 6x6
-  float M[6][6];
+  // M = C A^T (column j = C a_j)
+  R M[6][6];
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
-    const float ck = C[sidx(i, 3)], cp = C[sidx(i, 4)], ct = C[sidx(i, 5)];
+    const R ck = C[sidx(i, 3)], cp = C[sidx(i, 4)], ct = C[sidx(i, 5)];
     M[i][0] = C[sidx(i, 0)] + Axk * ck + Axp * cp;
     M[i][1] = C[sidx(i, 1)] + Ayk * ck + Ayp * cp;
     M[i][2] = C[sidx(i, 2)] + Azt * ct;
@@ -296,8 +398,8 @@ KFX_HD void transport(const State& in, const Layer& Ld, double cphi, double sphi
     M[i][4] = cp + Apk * ck;
     M[i][5] = ct;
   }
-  // N = A M (lower triangle), then the rank terms and Q
-  float N[6][6];
+  // N = A M, then the rank terms
+  R N[6][6];
 #pragma unroll
   for (int j = 0; j < 6; ++j) {
     N[0][j] = M[0][j] + Axk * M[3][j] + Axp * M[4][j];
@@ -307,7 +409,7 @@ KFX_HD void transport(const State& in, const Layer& Ld, double cphi, double sphi
     N[4][j] = M[4][j] + Apk * M[3][j];
     N[5][j] = M[5][j];
   }
-  const float bv[6] = {b0, b1, b2, 0.0f, b4, 0.0f};
+  const R bv[6] = {c1, s1, cot, (R)0, omega, (R)0};
 #pragma unroll
   for (int i = 0; i < 6; ++i)
 #pragma unroll
@@ -316,65 +418,60 @@ KFX_HD void transport(const State& in, const Layer& Ld, double cphi, double sphi
   if (disk) {
     // the z row of J is identically zero on a plane
 #pragma unroll
-    for (int j = 0; j < 6; ++j) out.C[sidx(2, j)] = 0.0f;
+    for (int j = 0; j < 6; ++j) out.C[sidx(2, j)] = (R)0;
   }
-  // multiple scattering at the destination (Highland, beta = 1)
-  if (Ld.x0 > 0.0f) {
-    float cinc;
-    if (disk) {
-      cinc = fabsf(cth);
-    } else {
-      const float x1 = (float)out.x, y1 = (float)out.y;
-      cinc = fabsf(sth * (x1 * c1 + y1 * s1) * rsqrtf(x1 * x1 + y1 * y1));
-    }
-    cinc = fmaxf(cinc, 1e-3f);
-    const float t = Ld.x0 / cinc;
-    const float th0 = 0.0136f * fabsf(k) * sth * sqrtf(t) * (1.0f + 0.038f * logf(t));
-    const float var = th0 * th0;
-    out.C[sidx(4, 4)] += var / (sth * sth);
-    out.C[sidx(5, 5)] += var;
-    out.C[sidx(3, 3)] += k * k * cot * cot * var;
-    out.C[sidx(5, 3)] += -k * cot * var;
+  // multiple scattering at the destination
+  R cinc;
+  if (disk) {
+    cinc = mabs(cth);
+  } else {
+    const R x1 = (R)out.x, y1 = (R)out.y;
+    cinc = mabs(sth * (x1 * c1 + y1 * s1) / msqrt(x1 * x1 + y1 * y1));
   }
+  add_noise(out, Ld, sth, cth, cinc);
 }
 
 // Measurement frame at a predicted state: rows u, v, n of H (acting on the
-// position), and S^-1 for S = H C H^T + V (packed 3x3).
-struct Frame {
-  float h[3][3];
-  float Si[6];   // (0,0) (1,0) (1,1) (2,0) (2,1) (2,2)
-  float S[6];
-  float HC[3][6];
+// position), H C and S^-1 for S = H C H^T + V (packed 3x3).
+template <class R>
+struct FrameT {
+  R h[3][3];
+  R Si[6];   // (0,0) (1,0) (1,1) (2,0) (2,1) (2,2)
+  R S[6];
+  R HC[3][6];
 };
+using Frame = FrameT<float>;
 
-KFX_HD void make_frame(const State& st, const Layer& Ld, Frame& F) {
+template <class R>
+KFX_HD void make_frame(const StateT<R>& st, const Layer& Ld, FrameT<R>& F) {
   const double r = sqrt(st.x * st.x + st.y * st.y);
-  const float c = (float)(st.x / r), s = (float)(st.y / r);
+  const R c = (R)(st.x / r), s = (R)(st.y / r);
   const bool disk = Ld.kind == kDisk;
-  F.h[0][0] = -s; F.h[0][1] = c; F.h[0][2] = 0.0f;
-  F.h[1][0] = disk ? c : 0.0f; F.h[1][1] = disk ? s : 0.0f; F.h[1][2] = disk ? 0.0f : 1.0f;
-  F.h[2][0] = disk ? 0.0f : c; F.h[2][1] = disk ? 0.0f : s; F.h[2][2] = disk ? 1.0f : 0.0f;
+  const R z0 = (R)0, o1 = (R)1;
+  F.h[0][0] = -s; F.h[0][1] = c; F.h[0][2] = z0;
+  F.h[1][0] = disk ? c : z0; F.h[1][1] = disk ? s : z0; F.h[1][2] = disk ? z0 : o1;
+  F.h[2][0] = disk ? z0 : c; F.h[2][1] = disk ? z0 : s; F.h[2][2] = disk ? o1 : z0;
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
     for (int j = 0; j < 6; ++j)
       F.HC[a][j] = F.h[a][0] * st.C[sidx(0, j)] + F.h[a][1] * st.C[sidx(1, j)] + F.h[a][2] * st.C[sidx(2, j)];
-  const float V[3] = {Ld.v_u, Ld.v_v, Ld.v_n};
-  float S[3][3];
+  const R V[3] = {(R)Ld.v_u, (R)Ld.v_v, (R)Ld.v_n};
+  R S[3][3];
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
     for (int b = 0; b <= a; ++b) {
-      float acc = F.HC[a][0] * F.h[b][0] + F.HC[a][1] * F.h[b][1] + F.HC[a][2] * F.h[b][2];
-      S[a][b] = acc + (a == b ? V[a] : 0.0f);
+      const R acc = F.HC[a][0] * F.h[b][0] + F.HC[a][1] * F.h[b][1] + F.HC[a][2] * F.h[b][2];
+      S[a][b] = acc + (a == b ? V[a] : z0);
       S[b][a] = S[a][b];
     }
   F.S[0] = S[0][0]; F.S[1] = S[1][0]; F.S[2] = S[1][1];
   F.S[3] = S[2][0]; F.S[4] = S[2][1]; F.S[5] = S[2][2];
-  const float c00 = S[1][1] * S[2][2] - S[1][2] * S[2][1];
-  const float c01 = S[1][2] * S[2][0] - S[1][0] * S[2][2];
-  const float c02 = S[1][0] * S[2][1] - S[1][1] * S[2][0];
-  const float id = 1.0f / (S[0][0] * c00 + S[0][1] * c01 + S[0][2] * c02);
+  const R c00 = S[1][1] * S[2][2] - S[1][2] * S[2][1];
+  const R c01 = S[1][2] * S[2][0] - S[1][0] * S[2][2];
+  const R c02 = S[1][0] * S[2][1] - S[1][1] * S[2][0];
+  const R id = o1 / (S[0][0] * c00 + S[0][1] * c01 + S[0][2] * c02);
   F.Si[0] = c00 * id;
   F.Si[1] = c01 * id;
   F.Si[2] = (S[0][0] * S[2][2] - S[0][2] * S[2][0]) * id;
@@ -384,29 +481,32 @@ KFX_HD void make_frame(const State& st, const Layer& Ld, Frame& F) {
 }
 
 // Residual r = H (m - x) with the difference taken in FP64.
-KFX_HD void residual(const State& st, const Frame& F, double mx, double my, double mz, float r[3]) {
-  const float dx = (float)(mx - st.x), dy = (float)(my - st.y), dz = (float)(mz - st.z);
+template <class R>
+KFX_HD void residual(const StateT<R>& st, const FrameT<R>& F, double mx, double my, double mz, R r[3]) {
+  const R dx = (R)(mx - st.x), dy = (R)(my - st.y), dz = (R)(mz - st.z);
 #pragma unroll
   for (int a = 0; a < 3; ++a) r[a] = F.h[a][0] * dx + F.h[a][1] * dy + F.h[a][2] * dz;
 }
 
-KFX_HD float chi2_of(const Frame& F, const float r[3]) {
+template <class R>
+KFX_HD R chi2_of(const FrameT<R>& F, const R r[3]) {
   return r[0] * r[0] * F.Si[0] + r[1] * r[1] * F.Si[2] + r[2] * r[2] * F.Si[5] +
-         2.0f * (r[0] * r[1] * F.Si[1] + r[0] * r[2] * F.Si[3] + r[1] * r[2] * F.Si[4]);
+         (R)2 * (r[0] * r[1] * F.Si[1] + r[0] * r[2] * F.Si[3] + r[1] * r[2] * F.Si[4]);
 }
 
 // Kalman update (gain form): K = C H^T S^-1, p += K r, C -= K H C.
-KFX_HD float kf_update(State& st, const Frame& F, double mx, double my, double mz) {
-  float r[3];
+template <class R>
+KFX_HD R kf_update(StateT<R>& st, const FrameT<R>& F, double mx, double my, double mz) {
+  R r[3];
   residual(st, F, mx, my, mz, r);
-  const float chi2 = chi2_of(F, r);
-  const float Si[3][3] = {{F.Si[0], F.Si[1], F.Si[3]}, {F.Si[1], F.Si[2], F.Si[4]}, {F.Si[3], F.Si[4], F.Si[5]}};
-  float K[6][3];
+  const R chi2 = chi2_of(F, r);
+  const R Si[3][3] = {{F.Si[0], F.Si[1], F.Si[3]}, {F.Si[1], F.Si[2], F.Si[4]}, {F.Si[3], F.Si[4], F.Si[5]}};
+  R K[6][3];
 #pragma unroll
   for (int i = 0; i < 6; ++i)
 #pragma unroll
     for (int b = 0; b < 3; ++b) K[i][b] = F.HC[0][i] * Si[0][b] + F.HC[1][i] * Si[1][b] + F.HC[2][i] * Si[2][b];
-  float dp[6];
+  R dp[6];
 #pragma unroll
   for (int i = 0; i < 6; ++i) dp[i] = K[i][0] * r[0] + K[i][1] * r[1] + K[i][2] * r[2];
   st.x += (double)dp[0];
@@ -414,7 +514,7 @@ KFX_HD float kf_update(State& st, const Frame& F, double mx, double my, double m
   st.z += (double)dp[2];
   st.k += dp[3];
   st.phi = wrap_pi(st.phi + (double)dp[4]);
-  st.th += dp[5];
+  st.th += (double)dp[5];
 #pragma unroll
   for (int i = 0; i < 6; ++i)
 #pragma unroll
@@ -423,50 +523,60 @@ KFX_HD float kf_update(State& st, const Frame& F, double mx, double my, double m
   return chi2;
 }
 
+// The update of an FP32 state carried out in FP64.  C+ = C - K H C keeps
+// the fraction V/(H C H^T + V) of the predicted variance along the measured
+// directions; at a steep crossing that ratio reaches 1e-4 or less, and the
+// FP32 subtraction would keep only a few correct digits.  K, C+ and chi2 are
+// formed in FP64 from the FP32 covariance and rounded once.
+KFX_HD float kf_update_fp64(State& st, const Layer& Ld, double mx, double my, double mz) {
+  StateT<double> sd;
+  convert_state(st, sd);
+  FrameT<double> F;
+  make_frame(sd, Ld, F);
+  const double c2 = kf_update(sd, F, mx, my, mz);
+  convert_state(sd, st);
+  return (float)c2;
+}
+
 // Prior covariance of the start estimate: diagonal (sigma_pos^2 x3,
 // (sk_rel |k|)^2, sigma_phi^2, sigma_theta^2).
 struct Prior {
   float spos, sk_rel, sphi, stheta;
 };
 
-KFX_HD void prior_cov(const Prior& pr, State& st) {
+template <class R>
+KFX_HD void prior_cov(const Prior& pr, StateT<R>& st) {
 #pragma unroll
-  for (int i = 0; i < 21; ++i) st.C[i] = 0.0f;
-  st.C[sidx(0, 0)] = st.C[sidx(1, 1)] = st.C[sidx(2, 2)] = pr.spos * pr.spos;
-  const float sk = pr.sk_rel * fabsf(st.k);
+  for (int i = 0; i < 21; ++i) st.C[i] = (R)0;
+  st.C[sidx(0, 0)] = st.C[sidx(1, 1)] = st.C[sidx(2, 2)] = (R)pr.spos * (R)pr.spos;
+  const R sk = (R)pr.sk_rel * mabs(st.k);
   st.C[sidx(3, 3)] = sk * sk;
-  st.C[sidx(4, 4)] = pr.sphi * pr.sphi;
-  st.C[sidx(5, 5)] = pr.stheta * pr.stheta;
+  st.C[sidx(4, 4)] = (R)pr.sphi * (R)pr.sphi;
+  st.C[sidx(5, 5)] = (R)pr.stheta * (R)pr.stheta;
 }
 
-// Add the material noise of a layer to a state sitting on it (used at the
-// first hit, where there is no transport).
-KFX_HD void add_material(State& st, const Layer& Ld) {
-  if (!(Ld.x0 > 0.0f)) return;
-  const float sth = sinf(st.th), cth = cosf(st.th), cot = cth / sth;
-  float cinc;
+// Material noise of a layer added to a state sitting on it (the first hit,
+// where there is no transport).
+template <class R>
+KFX_HD void add_material(StateT<R>& st, const Layer& Ld) {
+  const R sth = (R)sin(st.th), cth = (R)cos(st.th);
+  R cinc;
   if (Ld.kind == kDisk) {
-    cinc = fabsf(cth);
+    cinc = mabs(cth);
   } else {
     const double r = sqrt(st.x * st.x + st.y * st.y);
-    cinc = fabsf(sth * (float)((st.x * cos(st.phi) + st.y * sin(st.phi)) / r));
+    cinc = mabs(sth * (R)((st.x * cos(st.phi) + st.y * sin(st.phi)) / r));
   }
-  cinc = fmaxf(cinc, 1e-3f);
-  const float t = Ld.x0 / cinc;
-  const float th0 = 0.0136f * fabsf(st.k) * sth * sqrtf(t) * (1.0f + 0.038f * logf(t));
-  const float var = th0 * th0;
-  st.C[sidx(4, 4)] += var / (sth * sth);
-  st.C[sidx(5, 5)] += var;
-  st.C[sidx(3, 3)] += st.k * st.k * cot * cot * var;
-  st.C[sidx(5, 3)] += -st.k * cot * var;
+  add_noise(st, Ld, sth, cth, cinc);
 }
 
 // Start estimate from three hits (FP64): signed curvature of the circle
 // through the transverse points (omega = 2 cross / product of the sides),
 // phi = tangent at hit 1 = chord direction minus half the turning angle,
 // cot(theta) = dz / arc(1 -> 3).  Position = hit 1.
+template <class R>
 KFX_HD void seed_estimate(double bz, const double m1[3], const double m2[3], const double m3[3],
-                          State& st) {
+                          StateT<R>& st) {
   const double ax = m2[0] - m1[0], ay = m2[1] - m1[1];
   const double bx = m3[0] - m1[0], by = m3[1] - m1[1];
   const double cx = m3[0] - m2[0], cy = m3[1] - m2[1];
@@ -477,13 +587,13 @@ KFX_HD void seed_estimate(double bz, const double m1[3], const double m2[3], con
   st.x = m1[0];
   st.y = m1[1];
   st.z = m1[2];
-  st.k = bz == 0.0 ? 0.0f : (float)(-omega / ((double)kHc * bz));
+  st.k = bz == 0.0 ? (R)0 : (R)(-omega / (kHcD * bz));
   // turning angle over the chord 1->2 is 2 asin(omega |P2-P1| / 2)
   const double half12 = asin(fmin(1.0, fmax(-1.0, 0.5 * omega * la)));
   st.phi = wrap_pi(atan2(ay, ax) - half12);
   const double half13 = asin(fmin(1.0, fmax(-1.0, 0.5 * omega * lb)));
   const double s13 = fabs(omega) > 0.0 ? 2.0 * half13 / omega : lb;
-  st.th = (float)atan2(s13, m3[2] - m1[2]);
+  st.th = atan2(s13, m3[2] - m1[2]);
 }
 
 }  // namespace kfx

@@ -175,11 +175,11 @@ KFX_HD void bestk_insert(BestK& b, int K, float c, int h) {
 }
 
 // ---- SoA state access ---------------------------------------------------
-// pos: [4][stride] float64 (x, y, z, phi); kt: [2][stride] float32 (k,
-// theta); cov: [21][stride] float32 (packed lower triangle).
+// pos: [5][stride] float64 (x, y, z, phi, theta); k: [stride] float32;
+// cov: [21][stride] float32 (packed lower triangle).
 struct StateSoA {
   double* pos;
-  float* kt;
+  float* k;
   float* cov;
   long stride;
 };
@@ -189,8 +189,8 @@ KFX_HD void load_state(const StateSoA& a, long i, State& s) {
   s.y = a.pos[a.stride + i];
   s.z = a.pos[2 * a.stride + i];
   s.phi = a.pos[3 * a.stride + i];
-  s.k = a.kt[i];
-  s.th = a.kt[a.stride + i];
+  s.th = a.pos[4 * a.stride + i];
+  s.k = a.k[i];
 #pragma unroll
   for (int j = 0; j < 21; ++j) s.C[j] = a.cov[j * a.stride + i];
 }
@@ -200,8 +200,8 @@ KFX_HD void store_state(const StateSoA& a, long i, const State& s) {
   a.pos[a.stride + i] = s.y;
   a.pos[2 * a.stride + i] = s.z;
   a.pos[3 * a.stride + i] = s.phi;
-  a.kt[i] = s.k;
-  a.kt[a.stride + i] = s.th;
+  a.pos[4 * a.stride + i] = s.th;
+  a.k[i] = s.k;
 #pragma unroll
   for (int j = 0; j < 21; ++j) a.cov[j * a.stride + i] = s.C[j];
 }
@@ -257,9 +257,43 @@ KFX_HD int scan_window(const Geometry& G, const BinIndex& B, int ev, int layer, 
   return found;
 }
 
+// Kalman update in FP64 for either state type.
+KFX_HD double update_at(StateT<double>& st, const Layer& Ld, const double m[3]) {
+  FrameT<double> F;
+  make_frame(st, Ld, F);
+  return kf_update(st, F, m[0], m[1], m[2]);
+}
+KFX_HD float update_at(State& st, const Layer& Ld, const double m[3]) {
+  return kf_update_fp64(st, Ld, m[0], m[1], m[2]);
+}
+
+// ---- one filter step: transport onto the hit's layer (not at the first
+// hit, where the state starts on the hit), material noise, update.
+template <class R>
+KFX_HD bool filter_step(StateT<R>& st, const Layer& Ld, double r_surf, double kappa, bool first,
+                        const double m[3], R& chi2) {
+  if (first) {
+    add_material(st, Ld);
+  } else {
+    const double cphi = cos(st.phi), sphi = sin(st.phi);
+    const double s = path_to_layer(st, Ld, r_surf, cphi, sphi, kappa * (double)st.k);
+    if (!(s > 0.0)) return false;
+    StateT<R> nx;
+    transport(st, Ld, cphi, sphi, s, kappa, nx);
+    st = nx;
+  }
+  chi2 = update_at(st, Ld, m);
+  return true;
+}
+
 // ---- seed state: start estimate, then KF over the three seed hits ------
+// The prior is ~1e4 times wider (in variance) than the hits, so the first
+// updates cancel most of it: C+ = C - K H C keeps only ~1e-4 of C, which
+// FP32 would resolve to ~1e-3.  These three updates run in FP64 (a handful
+// per seed, at the unpacked FP32 rate on CDNA); the search then continues in
+// FP32 from the rounded result.
 KFX_HD bool seed_state(const Geometry& G, const HitsView& H, const int sh[3], const Prior& pr,
-                       State& st, float& chi2) {
+                       State& out, float& chi2) {
   double m[3][3];
   for (int i = 0; i < 3; ++i)
     if (sh[i] < 0 || sh[i] >= H.n_hits) return false;
@@ -268,29 +302,21 @@ KFX_HD bool seed_state(const Geometry& G, const HitsView& H, const int sh[3], co
     m[i][1] = H.y[sh[i]];
     m[i][2] = H.z[sh[i]];
   }
+  StateT<double> st;
   seed_estimate(G.bz, m[0], m[1], m[2], st);
   prior_cov(pr, st);
-  const float kappa = -kHc * (float)G.bz;
-  chi2 = 0.0f;
+  const double kappa = -kHcD * G.bz;
+  double c2sum = 0.0;
   for (int i = 0; i < 3; ++i) {
     const int l = H.layer[sh[i]];
     if (l < 0 || l >= G.n_layers) return false;
     const Layer& Ld = G.L[l];
-    if (i == 0) {
-      add_material(st, Ld);
-    } else {
-      const double cphi = cos(st.phi), sphi = sin(st.phi);
-      const float s = Ld.kind == kBarrel ? path_to_cylinder(st, cphi, sphi, kappa * st.k, Ld.pos)
-                                         : path_to_disk(st, Ld.pos);
-      if (!(s > 0.0f)) return false;
-      State nx;
-      transport(st, Ld, cphi, sphi, s, kappa, nx);
-      st = nx;
-    }
-    Frame F;
-    make_frame(st, Ld, F);
-    chi2 += kf_update(st, F, m[i][0], m[i][1], m[i][2]);
+    double c2 = 0.0;
+    if (!filter_step(st, Ld, Ld.pos, kappa, i == 0, m[i], c2)) return false;
+    c2sum += c2;
   }
+  convert_state(st, out);
+  chi2 = (float)c2sum;
   return true;
 }
 
@@ -336,7 +362,7 @@ KFX_HD void fit_track(const Geometry& G, const HitsView& H, const int* trk_off, 
   ok = ok && ckpt_fits;
   for (int i = 0; ok && i < n; ++i) {
     const int h = trk_hits[b + i];
-    if (h < 0 || h >= H.n_hits) ok = false;
+    if (h < 0 || h >= H.n_hits || H.layer[h] < 0 || H.layer[h] >= G.n_layers) ok = false;
   }
   if (ok) {
     double m0[3][3];
@@ -346,46 +372,35 @@ KFX_HD void fit_track(const Geometry& G, const HitsView& H, const int* trk_off, 
       m0[i][1] = H.y[h];
       m0[i][2] = H.z[h];
     }
-    seed_estimate(G.bz, m0[0], m0[1], m0[2], st);
-    prior_cov(pr, st);
-    const float kappa = -kHc * (float)G.bz * fscale;
+    // the first three hits in FP64 (see seed_state), the rest in FP32
+    StateT<double> sd;
+    seed_estimate(G.bz, m0[0], m0[1], m0[2], sd);
+    prior_cov(pr, sd);
+    const double kappa_d = -kHcD * G.bz * (double)fscale;
     for (int i = 0; i < n && ok; ++i) {
       const int h = trk_hits[b + i];
       const int l = H.layer[h];
-      if (l < 0 || l >= G.n_layers) {
-        ok = false;
-        break;
-      }
       const Layer& Ld = G.L[l];
       const float* a = align ? align + 3 * l : nullptr;
       double m[3];
       aligned_hit(Ld, H.x[h], H.y[h], H.z[h], a, m);
-      if (i == 0) {
-        add_material(st, Ld);
+      const double r_surf = Ld.pos + ((a && Ld.kind == kBarrel) ? (double)a[0] : 0.0);
+      if (i < 3) {
+        double c2 = 0.0;
+        ok = filter_step(sd, Ld, r_surf, kappa_d, i == 0, m, c2);
+        chi2 += c2;
+        convert_state(sd, st);
       } else {
-        const double cphi = cos(st.phi), sphi = sin(st.phi);
-        float s;
-        if (Ld.kind == kBarrel)
-          s = path_to_cylinder(st, cphi, sphi, kappa * st.k, Ld.pos + (a ? (double)a[0] : 0.0));
-        else
-          s = path_to_disk(st, Ld.pos);
-        if (!(s > 0.0f)) {
-          ok = false;
-          break;
-        }
-        State nx;
-        transport(st, Ld, cphi, sphi, s, kappa, nx);
-        st = nx;
+        float c2 = 0.0f;
+        ok = filter_step(st, Ld, r_surf, kappa_d, false, m, c2);
+        chi2 += (double)c2;
       }
-      Frame F;
-      make_frame(st, Ld, F);
-      chi2 += (double)kf_update(st, F, m[0], m[1], m[2]);
-      if (o.ckpt.pos) store_state(o.ckpt, b + i, st);
+      if (ok && o.ckpt.pos) store_state(o.ckpt, b + i, st);
     }
   }
   if (!ok) {
-    st.x = st.y = st.z = st.phi = 0.0;
-    st.k = st.th = 0.0f;
+    st.x = st.y = st.z = st.phi = st.th = 0.0;
+    st.k = 0.0f;
     for (int j = 0; j < 21; ++j) st.C[j] = 0.0f;
     chi2 = 0.0;
   }

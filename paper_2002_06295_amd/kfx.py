@@ -32,7 +32,7 @@ EXPORTED = ["kfx_create", "kfx_destroy", "kfx_last_error", "kfx_load_layers", "k
 
 
 class c_states(ctypes.Structure):
-    _fields_ = [("pos", ctypes.c_void_p), ("kt", ctypes.c_void_p), ("cov", ctypes.c_void_p),
+    _fields_ = [("pos", ctypes.c_void_p), ("k", ctypes.c_void_p), ("cov", ctypes.c_void_p),
                 ("stride", ctypes.c_int64)]
 
 
@@ -117,19 +117,19 @@ class KfxError(RuntimeError):
 
 @dataclass
 class States:
-    """Device SoA states: pos float64 [4, n] (x, y, z, phi), kt float32
-    [2, n] (k, theta), cov float32 [21, n] (packed lower triangle)."""
+    """Device SoA states: pos float64 [5, n] (x, y, z, phi, theta), k
+    float32 [n], cov float32 [21, n] (packed lower triangle)."""
 
     pos: object
-    kt: object
+    k: object
     cov: object
 
     @staticmethod
     def empty(n, device):
         import torch
         n = max(int(n), 1)
-        return States(torch.zeros((4, n), dtype=torch.float64, device=device),
-                      torch.zeros((2, n), dtype=torch.float32, device=device),
+        return States(torch.zeros((5, n), dtype=torch.float64, device=device),
+                      torch.zeros(n, dtype=torch.float32, device=device),
                       torch.zeros((21, n), dtype=torch.float32, device=device))
 
     @staticmethod
@@ -141,10 +141,10 @@ class States:
         C = np.asarray(C)
         if C.ndim == 3:
             C = pack_cov(C)
-        pos = np.stack([p[:, 0], p[:, 1], p[:, 2], p[:, 4]])
-        kt = np.stack([p[:, 3], p[:, 5]]).astype(np.float32)
+        pos = np.stack([p[:, 0], p[:, 1], p[:, 2], p[:, 4], p[:, 5]])
+        k = p[:, 3].astype(np.float32)
         return States(torch.as_tensor(np.ascontiguousarray(pos), device=device),
-                      torch.as_tensor(np.ascontiguousarray(kt), device=device),
+                      torch.as_tensor(np.ascontiguousarray(k), device=device),
                       torch.as_tensor(np.ascontiguousarray(C.T.astype(np.float32)), device=device))
 
     @property
@@ -152,15 +152,15 @@ class States:
         return int(self.pos.shape[1])
 
     def c(self):
-        return c_states(self.pos.data_ptr(), self.kt.data_ptr(), self.cov.data_ptr(), self.n)
+        return c_states(self.pos.data_ptr(), self.k.data_ptr(), self.cov.data_ptr(), self.n)
 
     def to_numpy(self, n=None):
         """Returns p [n, 6] (float64) and C [n, 6, 6] (float64)."""
         pos = self.pos.cpu().numpy()
-        kt = self.kt.cpu().numpy().astype(np.float64)
+        k = self.k.cpu().numpy().astype(np.float64)
         cov = self.cov.cpu().numpy().astype(np.float64)
         n = pos.shape[1] if n is None else n
-        p = np.stack([pos[0], pos[1], pos[2], kt[0], pos[3], kt[1]], axis=1)[:n]
+        p = np.stack([pos[0], pos[1], pos[2], k, pos[3], pos[4]], axis=1)[:n]
         return p, unpack_cov(cov.T[:n])
 
 
@@ -253,7 +253,7 @@ class Context:
 
     def bin_hits(self, hits: DeviceHits, want=True):
         import torch
-        n_keys = hits.n_events * self.n_layers * self.n_eta * self.n_phi
+        n_keys = hits.n_events * getattr(self, "n_layers", 0) * getattr(self, "n_eta", 0) * getattr(self, "n_phi", 0)
         d = self.device
         bins = torch.empty(max(hits.n_hits, 1), dtype=torch.int32, device=d) if want else None
         off = torch.empty(n_keys + 1, dtype=torch.int32, device=d) if want else None

@@ -1,0 +1,119 @@
+// Test-only host build of the GPU library's device math (kfx_math.h,
+// kfx_work.h): the same __host__ __device__ functions, called on the CPU so
+// that their logic can be checked against the oracle without a GPU.  The
+// library never loads this; only tests/ do.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <vector>
+
+#include "../../paper_2002_06295_amd/csrc/kfx_work.h"
+
+using namespace kfx;
+
+namespace {
+Geometry make_geo(const double* table, int nl, double bz) {
+  Geometry G{};
+  G.n_layers = nl;
+  G.bz = bz;
+  G.n_eta = 20;
+  G.n_phi = 128;
+  for (int i = 0; i < nl; ++i) {
+    const double* r = table + 8 * i;
+    Layer& L = G.L[i];
+    L.kind = (int)r[0];
+    L.pos = r[1];
+    L.lo = r[2];
+    L.hi = r[3];
+    L.x0 = (float)r[4];
+    L.v_u = (float)(r[5] * r[5]);
+    L.v_v = (float)(r[6] * r[6]);
+    L.v_n = (float)(r[7] * r[7]);
+  }
+  return G;
+}
+
+void to_state(const double* p, const float* cov21, State& s) {
+  s.x = p[0]; s.y = p[1]; s.z = p[2]; s.k = (float)p[3]; s.phi = p[4]; s.th = p[5];
+  for (int i = 0; i < 21; ++i) s.C[i] = cov21[i];
+}
+
+void from_state(const State& s, double* p, float* cov21) {
+  p[0] = s.x; p[1] = s.y; p[2] = s.z; p[3] = s.k; p[4] = s.phi; p[5] = s.th;
+  for (int i = 0; i < 21; ++i) cov21[i] = s.C[i];
+}
+}  // namespace
+
+extern "C" {
+
+// transport to a layer along path s found by the device navigation rules
+// of that surface kind; returns s (< 0 if not reached)
+float hs_predict(const double* table, int nl, double bz, int layer, const double* p, const float* cov,
+                 double* p_out, float* cov_out) {
+  Geometry G = make_geo(table, nl, bz);
+  State st, out;
+  to_state(p, cov, st);
+  const double cphi = cos(st.phi), sphi = sin(st.phi);
+  const double kappa = -kHcD * bz;
+  const Layer& L = G.L[layer];
+  const double s = path_to_layer(st, L, L.pos, cphi, sphi, kappa * (double)st.k);
+  if (!(s > 0.0)) return -1.0f;
+  transport(st, L, cphi, sphi, s, kappa, out);
+  from_state(out, p_out, cov_out);
+  return (float)s;
+}
+
+float hs_update(const double* table, int nl, int layer, const double* p, const float* cov, const double* m,
+                double* p_out, float* cov_out) {
+  Geometry G = make_geo(table, nl, 0.0);
+  State st;
+  to_state(p, cov, st);
+  const float c2 = kf_update_fp64(st, G.L[layer], m[0], m[1], m[2]);
+  from_state(st, p_out, cov_out);
+  return c2;
+}
+
+}  // extern "C"
+
+extern "C" {
+
+// seed state (start estimate + KF over the three seed hits)
+int hs_seed_state(const double* table, int nl, double bz, const float* x, const float* y, const float* z,
+                  const int* layer, int nhits, const int* sh, const float* prior, double* p_out, float* cov_out,
+                  float* chi2) {
+  Geometry G = make_geo(table, nl, bz);
+  G.n_layers = nl;
+  HitsView H{x, y, z, layer, nullptr, nhits, 1};
+  Prior pr{prior[0], prior[1], prior[2], prior[3]};
+  State st;
+  float c2 = 0.0f;
+  const bool ok = seed_state(G, H, sh, pr, st, c2);
+  from_state(st, p_out, cov_out);
+  *chi2 = c2;
+  return ok ? 1 : 0;
+}
+
+// fit of tracks (CSR hit lists), results per track
+void hs_fit(const double* table, int nl, double bz, const float* x, const float* y, const float* z,
+            const int* layer, int nhits, const int* trk_off, const int* trk_hits, int nt, const float* prior,
+            const float* align, float fscale, double* p_out, float* cov_out, float* chi2, int* ndof, int* status) {
+  Geometry G = make_geo(table, nl, bz);
+  HitsView H{x, y, z, layer, nullptr, nhits, 1};
+  Prior pr{prior[0], prior[1], prior[2], prior[3]};
+  std::vector<double> pos(5 * (size_t)nt);
+  std::vector<float> kk((size_t)nt), cov(21 * (size_t)nt);
+  FitOut o;
+  o.state = StateSoA{pos.data(), kk.data(), cov.data(), nt};
+  o.chi2 = chi2;
+  o.ndof = ndof;
+  o.status = status;
+  o.ckpt = StateSoA{nullptr, nullptr, nullptr, 0};
+  for (int t = 0; t < nt; ++t) {
+    fit_track(G, H, trk_off, trk_hits, t, pr, align, fscale, o);
+    State s;
+    load_state(o.state, t, s);
+    from_state(s, p_out + 6 * t, cov_out + 21 * t);
+  }
+}
+
+}  // extern "C"

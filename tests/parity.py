@@ -1,0 +1,56 @@
+"""Comparison helpers for GPU-vs-oracle parity tests.
+
+States live on a surface, so their 6x6 covariance has rank 5: the position
+variance along the surface normal is zero up to rounding.  Covariances are
+therefore compared on the five free parameters (u, v, k, phi, theta), u and v
+the local surface coordinates (barrel: r*phi direction and z; disk: r*phi
+direction and r), element-wise to a fraction of sqrt(C_ii C_jj); the normal
+variance is checked separately against the position variances.
+"""
+import numpy as np
+
+BARREL = 0
+PARAM_FLOORS = np.array([1.0, 1.0, 1.0, 0.0, 1.0, 1.0])  # cm, cm, cm, -, rad, rad
+
+
+def wrap(a):
+    return (a + np.pi) % (2 * np.pi) - np.pi
+
+
+def param_rel(pg, po):
+    """|delta p_i| / max(|p_i|, floor_i) (phi difference wrapped)."""
+    d = pg - po
+    d[:, 4] = wrap(d[:, 4])
+    return np.abs(d) / np.maximum(np.abs(po), PARAM_FLOORS)
+
+
+def local_frame_T(p, kinds):
+    """5x6 maps from (x, y, z, k, phi, theta) to (u, v, k, phi, theta)."""
+    n = p.shape[0]
+    r = np.hypot(p[:, 0], p[:, 1])
+    c, s = p[:, 0] / r, p[:, 1] / r
+    T = np.zeros((n, 5, 6))
+    T[:, 0, 0], T[:, 0, 1] = -s, c
+    bar = kinds == BARREL
+    T[bar, 1, 2] = 1.0
+    T[~bar, 1, 0], T[~bar, 1, 1] = c[~bar], s[~bar]
+    T[:, 2, 3] = T[:, 3, 4] = T[:, 4, 5] = 1.0
+    nrm = np.zeros((n, 3))
+    nrm[bar, 0], nrm[bar, 1] = c[bar], s[bar]
+    nrm[~bar, 2] = 1.0
+    return T, nrm
+
+
+def cov_rel(Cg, Co, p, kinds):
+    """Per state: max |dC5_ij| / sqrt(C5_ii C5_jj) on the surface parameters,
+    and the normal variances (GPU, oracle) relative to the largest position
+    variance."""
+    T, nrm = local_frame_T(p, kinds)
+    Cg5 = T @ Cg @ T.transpose(0, 2, 1)
+    Co5 = T @ Co @ T.transpose(0, 2, 1)
+    d = np.sqrt(np.abs(np.einsum("nii->ni", Co5)))
+    rel = np.abs(Cg5 - Co5) / (d[:, :, None] * d[:, None, :] + 1e-300)
+    scale = np.max(np.einsum("nii->ni", Co[:, :3, :3]), axis=1)
+    ng = np.abs(np.einsum("ni,nij,nj->n", nrm, Cg[:, :3, :3], nrm)) / scale
+    no = np.abs(np.einsum("ni,nij,nj->n", nrm, Co[:, :3, :3], nrm)) / scale
+    return rel.max(axis=(1, 2)), ng, no
