@@ -445,12 +445,15 @@ __global__ void __launch_bounds__(256) k_build_fused(BuildArgs a, int cur_unused
     // ---- hand states to the children through LDS
     FusedShared& me = sh[threadIdx.x];
     {
-      const State& src = (nl >= 0) ? pr : st;
+      // a stop child keeps its parent's current state; hit and hole
+      // children start from the prediction (a lane with a stop child has
+      // no other child)
+      const State& src = (nl >= 0 && !ks.stop) ? pr : st;
       me.pos[0] = src.x; me.pos[1] = src.y; me.pos[2] = src.z; me.pos[3] = src.phi; me.pos[4] = src.th;
       me.k = src.k;
 #pragma unroll
       for (int q = 0; q < 21; ++q) me.cov[q] = src.C[q];
-      me.layer = (nl >= 0) ? nl : layer;
+      me.layer = (nl >= 0 && !ks.stop) ? nl : layer;
       me.meta = meta;
       me.chi2 = chi2;
     }

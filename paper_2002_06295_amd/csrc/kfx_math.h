@@ -92,7 +92,9 @@ KFX_HD float mlog(float x) { return logf(x); }
 KFX_HD double mlog(double x) { return log(x); }
 KFX_HD float mmax(float a, float b) { return fmaxf(a, b); }
 KFX_HD double mmax(double a, double b) { return fmax(a, b); }
-template <class R> KFX_HD constexpr R newton_tol() { return sizeof(R) == 4 ? (R)2e-7 : (R)1e-13; }
+// stopping test of the Newton phase in R (FP32 iterates can cycle a few ulps
+// apart; the FP64 steps that follow finish the convergence)
+template <class R> KFX_HD constexpr R newton_tol() { return sizeof(R) == 4 ? (R)2e-6 : (R)1e-13; }
 
 KFX_HD double wrap_pi(double a) {  // to (-pi, pi]
   if (a > kPi) a -= 2.0 * kPi;
@@ -176,28 +178,55 @@ KFX_HD ChordD chord_d(double s, double omega, double cphi, double sphi) {
 }
 
 // Outgoing crossing of the cylinder of radius Rc.  The start must lie
-// inside it and move outward.  Newton on g(s) = |P(s)|^2 - Rc^2 (g taken
-// relative to the start) from the straight-line root, first in R, then two
-// FP64 steps on the FP64 chord.  Returns the transverse path, or a negative
-// value when there is no outgoing crossing.
+// inside it and move outward; the crossing must come before the turning
+// point (the maximum radius of the transverse circle).  Newton on
+// g(s) = |P(s)|^2 - Rc^2 (g taken relative to the start) from the
+// straight-line root, first in R, then two FP64 steps on the FP64 chord.
+// When the cylinder lies near the maximum radius the iteration keeps a
+// bracket [0, s_turn] and falls back to bisection whenever a Newton step
+// leaves it.  Returns the transverse path, or a negative value when there
+// is no outgoing crossing.
 template <class R>
 KFX_HD double path_to_cylinder(const StateT<R>& st, double cphi, double sphi, double omega_d, double Rc) {
   const double c0 = st.x * st.x + st.y * st.y - Rc * Rc;
   const double Dd = st.x * cphi + st.y * sphi;
   if (!(c0 < 0.0) || Dd < 0.0) return -1.0;
+  double lo = 0.0, hi = 1e30;
+  bool guarded = false;
+  if (fabs(omega_d) > 1e-12) {
+    const double ir = 1.0 / omega_d;
+    const double cx = st.x - sphi * ir, cy = st.y + cphi * ir;
+    const double d = sqrt(cx * cx + cy * cy), rho = fabs(ir);
+    if (d + rho < Rc) return -1.0;  // the circle never reaches the cylinder
+    if (d + rho < 1.5 * Rc) {
+      guarded = true;
+      const double b0 = atan2(st.y - cy, st.x - cx), gam = atan2(cy, cx);
+      double db = fmod((gam - b0) * (omega_d > 0.0 ? 1.0 : -1.0), 2.0 * kPi);
+      if (db < 0.0) db += 2.0 * kPi;
+      hi = db * rho;  // path to the turning point
+    }
+  }
   const R D = (R)Dd;
   const R omega = (R)omega_d;
   R s = (R)(-c0) / (D + msqrt(D * D - (R)c0));
+  if (guarded && !((double)s < hi)) s = (R)(0.5 * (lo + hi));
   bool conv = false;
-  for (int it = 0; it < 12; ++it) {
+  for (int it = 0; it < 48; ++it) {
     const ChordT<R> c = chord(s, omega, cphi, sphi);
     const double g = c0 + 2.0 * (st.x * c.dx + st.y * c.dy) + (c.dx * c.dx + c.dy * c.dy);
     double c1, s1;
     chord_end_dir(c, cphi, sphi, c1, s1);
     const R gp = (R)2 * (R)((st.x + c.dx) * c1 + (st.y + c.dy) * s1);
-    if (!(gp > (R)0)) return -1.0;
-    const R ds = (R)g / gp;
-    s -= ds;
+    if (guarded) {
+      if (g < 0.0) lo = (double)s; else hi = (double)s;
+    }
+    R sn = s - (R)g / gp;
+    if (!(gp > (R)0) || (guarded && !((double)sn > lo && (double)sn < hi))) {
+      if (!guarded) return -1.0;
+      sn = (R)(0.5 * (lo + hi));
+    }
+    const R ds = sn - s;
+    s = sn;
     if (mabs(ds) <= newton_tol<R>() * mabs(s) + (R)1e-9) {
       conv = true;
       break;
@@ -209,7 +238,7 @@ KFX_HD double path_to_cylinder(const StateT<R>& st, double cphi, double sphi, do
     const ChordD c = chord_d(sd, omega_d, cphi, sphi);
     const double g = c0 + 2.0 * (st.x * c.dx + st.y * c.dy) + (c.dx * c.dx + c.dy * c.dy);
     const double gp = 2.0 * ((st.x + c.dx) * c.c1 + (st.y + c.dy) * c.s1);
-    if (!(gp > 0.0)) return -1.0;  // moving inward: past the turning point
+    if (!(gp > 0.0)) return -1.0;  // at the turning point: tangent, no crossing
     sd -= g / gp;
   }
   return sd > 0.0 ? sd : -1.0;
@@ -240,6 +269,11 @@ KFX_HD int navigate(const Geometry& G, int cur, const State& st, double cphi, do
   double best = 3.0e38;
   int bl = -1;
   int nb = -1;
+  s_out = best;
+  // a state that is not finite goes nowhere (comparisons with NaN are false)
+  if (!isfinite(st.x) || !isfinite(st.y) || !isfinite(st.z) || !isfinite(st.phi) || !isfinite(st.th) ||
+      !isfinite(st.k) || !isfinite(omega_d))
+    return -1;
   const Layer& Lc = G.L[cur];
   if (Lc.kind == kBarrel) {
     nb = G.next_barrel[cur];

@@ -117,3 +117,11 @@ void hs_fit(const double* table, int nl, double bz, const float* x, const float*
 }
 
 }  // extern "C"
+
+extern "C" double hs_path_cylinder(const double* p, double bz, double Rc) {
+  State st;
+  float c[21] = {0};
+  to_state(p, c, st);
+  const double cphi = cos(st.phi), sphi = sin(st.phi);
+  return path_to_cylinder(st, cphi, sphi, -kHcD * bz * (double)st.k, Rc);
+}

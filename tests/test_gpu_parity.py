@@ -216,7 +216,7 @@ def test_fit_barrel10(dev, kfx):
 
 
 def test_fit_full_geometry_with_disks(dev, kfx):
-    ev = kfsynth.generate("build5k", tracks_per_event=800, noise_per_event=0)
+    ev = kfsynth.generate(kfsynth.workload("build5k", noise_per_event=0), tracks_per_event=800)
     good, ok = fit_compare(kfx, dev, ev)
     assert good.sum() >= 0.97 * ok.sum()
 
