@@ -63,11 +63,11 @@ extern "C" {
 typedef struct kfx_ctx kfx_ctx;
 
 /* Track states, structure of arrays over `stride` entries (device).  The
- * position and direction are float64: a float32 coordinate at 100 cm has a
- * rounding error of ~2e-3 of the 20 um hit resolution. */
+ * six parameters are float64 (a float32 coordinate at 100 cm already has a
+ * rounding error of ~2e-3 of the 20 um hit resolution); the covariance is
+ * float32. */
 typedef struct {
-  double* pos;     /* [5][stride] x, y, z, phi, theta (float64)           */
-  float* k;        /* [stride] k = q/pT (float32)                         */
+  double* par;     /* [6][stride] x, y, z, k, phi, theta (float64)        */
   float* cov;      /* [21][stride] packed covariance (float32)            */
   int64_t stride;  /* entries per row; >= number of states written        */
 } kfx_states;

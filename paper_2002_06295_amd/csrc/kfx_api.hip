@@ -102,15 +102,14 @@ HitsView view(const kfx_hits* h) {
 
 StateSoA soa(const kfx_states* s) {
   StateSoA a;
-  a.pos = s->pos;
-  a.k = s->k;
+  a.par = s->par;
   a.cov = s->cov;
   a.stride = (long)s->stride;
   return a;
 }
 
 int check_states(kfx_ctx* c, const kfx_states* s, long n, const char* what) {
-  if (!s || !s->pos || !s->k || !s->cov) return fail(c, KFX_EINVAL, std::string(what) + ": NULL state arrays");
+  if (!s || !s->par || !s->cov) return fail(c, KFX_EINVAL, std::string(what) + ": NULL state arrays");
   if (s->stride < n) return fail(c, KFX_EINVAL, std::string(what) + ": stride smaller than the entry count");
   return KFX_OK;
 }
@@ -382,11 +381,10 @@ int kfx_build_tracks(kfx_ctx* c, const kfx_hits* hits, const int32_t* seeds, con
   a.max_steps = p->max_steps;
   const long N = std::max<long>(SK, 1);
   auto alloc_states = [&](const char* name, StateSoA& s) -> int {
-    char* base = (char*)ws(c, name, (size_t)N * (5 * 8 + 4 + 21 * 4), st, rc);
+    char* base = (char*)ws(c, name, (size_t)N * (6 * 8 + 21 * 4), st, rc);
     if (rc) return rc;
-    s.pos = (double*)base;
-    s.k = (float*)(base + (size_t)N * 40);
-    s.cov = (float*)(base + (size_t)N * 44);
+    s.par = (double*)base;
+    s.cov = (float*)(base + (size_t)N * 48);
     s.stride = N;
     return KFX_OK;
   };
@@ -454,7 +452,7 @@ int kfx_fit_tracks(kfx_ctx* c, const kfx_hits* hits, const int32_t* trk_off, con
   if (n_tracks > 0 && (!trk_off || !trk_hits || !chi2 || !ndof || !status))
     return fail(c, KFX_EINVAL, "NULL track arrays");
   if ((rc = check_states(c, out, n_tracks, "out"))) return rc;
-  if (ckpt && (!ckpt->pos || !ckpt->k || !ckpt->cov)) return fail(c, KFX_EINVAL, "ckpt: NULL state arrays");
+  if (ckpt && (!ckpt->par || !ckpt->cov)) return fail(c, KFX_EINVAL, "ckpt: NULL state arrays");
   DeviceGuard dg(c->device);
   hipStream_t st = (hipStream_t)stream;
   FitOut o;
@@ -463,7 +461,7 @@ int kfx_fit_tracks(kfx_ctx* c, const kfx_hits* hits, const int32_t* trk_off, con
   o.ndof = ndof;
   o.status = status;
   if (ckpt) o.ckpt = soa(ckpt);
-  else o.ckpt.pos = nullptr, o.ckpt.k = nullptr, o.ckpt.cov = nullptr, o.ckpt.stride = 0;
+  else o.ckpt.par = nullptr, o.ckpt.cov = nullptr, o.ckpt.stride = 0;
   launch_fit(c->dev_geo, view(hits), trk_off, trk_hits, n_tracks, prior_of(prior), align, field_scale, o, st);
   return hip_check(c, hipGetLastError(), "fit kernel");
 }

@@ -93,7 +93,7 @@ KFX_HD int predict_slot(const BuildArgs& a, int cur, long slot) {
   const double cphi = cos(st.phi), sphi = sin(st.phi);
   const double kappa = -kHcD * G.bz;
   double s = 0.0;
-  const int nl = navigate(G, a.layer[cur][slot], st, cphi, sphi, kappa * (double)st.k, s);
+  const int nl = navigate(G, a.layer[cur][slot], st, cphi, sphi, kappa * st.k, s);
   if (nl < 0) {
     a.next_layer[slot] = -1;
     return 0;
@@ -290,8 +290,7 @@ KFX_HD void finalize_slot(const BuildArgs& a, int fin, const TracksOut& o, int s
     o.n_holes[slot] = 0;
     o.chi2[slot] = 0.0f;
     State z;
-    z.x = z.y = z.z = z.phi = z.th = 0.0;
-    z.k = 0.0f;
+    z.x = z.y = z.z = z.k = z.phi = z.th = 0.0;
     for (int q = 0; q < 21; ++q) z.C[q] = 0.0f;
     store_state(o.state, slot, z);
     return;

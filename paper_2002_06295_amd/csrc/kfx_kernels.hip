@@ -186,8 +186,7 @@ __global__ void k_seed_states(const Geometry* __restrict__ G, HitsView H, const 
   float c2 = 0.0f;
   const bool ok = seed_state(*G, H, seeds + 3 * s, pr, st, c2);
   if (!ok) {
-    st.x = st.y = st.z = st.phi = st.th = 0.0;
-    st.k = 0.0f;
+    st.x = st.y = st.z = st.k = st.phi = st.th = 0.0;
     for (int j = 0; j < 21; ++j) st.C[j] = 0.0f;
     c2 = 0.0f;
   }
@@ -211,7 +210,7 @@ __global__ void k_step_compat(const Geometry* __restrict__ G, HitsView H, BinInd
   double s = 0.0;
   const int cl = cand_layer[i], ce = cand_event[i];
   const int nl = (cl >= 0 && cl < G->n_layers && ce >= 0 && ce < H.n_events)
-                     ? navigate(*G, cl, st, cphi, sphi, kappa * (double)st.k, s) : -1;
+                     ? navigate(*G, cl, st, cphi, sphi, kappa * st.k, s) : -1;
   next_layer[i] = nl;
   if (nl < 0) {
     pair_count[i] = 0;
@@ -323,8 +322,7 @@ __global__ void k_build_finalize(BuildArgs a, int fin, TracksOut o) {
 struct FusedShared {
   // per lane: state to hand to the children (predicted, or current for a
   // stop child), its layer, meta and chi2
-  double pos[5];
-  float k;
+  double par[6];
   float cov[21];
   int layer;
   int meta;
@@ -393,7 +391,7 @@ __global__ void __launch_bounds__(256) k_build_fused(BuildArgs a, int cur_unused
       } else {
         const double cphi = cos(st.phi), sphi = sin(st.phi);
         double s = 0.0;
-        nl = navigate(G, layer, st, cphi, sphi, kappa * (double)st.k, s);
+        nl = navigate(G, layer, st, cphi, sphi, kappa * st.k, s);
         if (nl >= 0) {
           transport(st, G.L[nl], cphi, sphi, s, kappa, pr);
           ++n_steps;
@@ -449,8 +447,8 @@ __global__ void __launch_bounds__(256) k_build_fused(BuildArgs a, int cur_unused
       // children start from the prediction (a lane with a stop child has
       // no other child)
       const State& src = (nl >= 0 && !ks.stop) ? pr : st;
-      me.pos[0] = src.x; me.pos[1] = src.y; me.pos[2] = src.z; me.pos[3] = src.phi; me.pos[4] = src.th;
-      me.k = src.k;
+      me.par[0] = src.x; me.par[1] = src.y; me.par[2] = src.z; me.par[3] = src.k; me.par[4] = src.phi;
+      me.par[5] = src.th;
 #pragma unroll
       for (int q = 0; q < 21; ++q) me.cov[q] = src.C[q];
       me.layer = (nl >= 0 && !ks.stop) ? nl : layer;
@@ -465,8 +463,8 @@ __global__ void __launch_bounds__(256) k_build_fused(BuildArgs a, int cur_unused
       if (my_parent >= 0) {
         const FusedShared& par = sh[gbase + my_parent];
         State ns;
-        ns.x = par.pos[0]; ns.y = par.pos[1]; ns.z = par.pos[2]; ns.phi = par.pos[3]; ns.th = par.pos[4];
-        ns.k = par.k;
+        ns.x = par.par[0]; ns.y = par.par[1]; ns.z = par.par[2]; ns.k = par.par[3]; ns.phi = par.par[4];
+        ns.th = par.par[5];
 #pragma unroll
         for (int q = 0; q < 21; ++q) ns.C[q] = par.cov[q];
         const int pm = par.meta;

@@ -63,18 +63,17 @@ struct Geometry {
   int n_eta, n_phi;
 };
 
+// Track parameters in FP64, covariance in R (FP32 on the hot path).
 template <class R>
 struct StateT {
-  double x, y, z, phi, th;  // position and direction (FP64)
-  R k;                      // q/pT
-  R C[21];                  // covariance of (x, y, z, k, phi, theta), packed
+  double x, y, z, k, phi, th;
+  R C[21];  // covariance of (x, y, z, k, phi, theta), packed
 };
 using State = StateT<float>;
 
 template <class A, class B>
 KFX_HD void convert_state(const StateT<A>& a, StateT<B>& b) {
-  b.x = a.x; b.y = a.y; b.z = a.z; b.phi = a.phi; b.th = a.th;
-  b.k = (B)a.k;
+  b.x = a.x; b.y = a.y; b.z = a.z; b.k = a.k; b.phi = a.phi; b.th = a.th;
 #pragma unroll
   for (int i = 0; i < 21; ++i) b.C[i] = (B)a.C[i];
 }
@@ -332,13 +331,14 @@ KFX_HD void add_noise(StateT<R>& st, const Layer& Ld, R sth, R cth, R cinc) {
   if (!(Ld.x0 > 0.0f)) return;
   cinc = mmax(cinc, (R)1e-3);
   const R t = (R)Ld.x0 / cinc;
-  const R th0 = (R)0.0136 * mabs(st.k) * sth * msqrt(t) * ((R)1 + (R)0.038 * mlog(t));
+  const R k = (R)st.k;
+  const R th0 = (R)0.0136 * mabs(k) * sth * msqrt(t) * ((R)1 + (R)0.038 * mlog(t));
   const R var = th0 * th0;
   const R cot = cth / sth;
   st.C[sidx(4, 4)] += var / (sth * sth);
   st.C[sidx(5, 5)] += var;
-  st.C[sidx(3, 3)] += st.k * st.k * cot * cot * var;
-  st.C[sidx(5, 3)] += -st.k * cot * var;
+  st.C[sidx(3, 3)] += k * k * cot * cot * var;
+  st.C[sidx(5, 3)] += -k * cot * var;
 }
 
 // Transport (p, C) over transverse path s to the surface of layer Ld
@@ -351,8 +351,7 @@ KFX_HD void add_noise(StateT<R>& st, const Layer& Ld, R sth, R cth, R cinc) {
 template <class R>
 KFX_HD void transport(const StateT<R>& in, const Layer& Ld, double cphi, double sphi, double s_d,
                       double kappa_d, StateT<R>& out) {
-  const R k = in.k;
-  const double omega_d = kappa_d * (double)k;
+  const double omega_d = kappa_d * in.k;
   const ChordD cd = chord_d(s_d, omega_d, cphi, sphi);
   const double sth_d = sin(in.th), cth_d = cos(in.th);
   const bool disk = Ld.kind == kDisk;
@@ -360,7 +359,7 @@ KFX_HD void transport(const StateT<R>& in, const Layer& Ld, double cphi, double 
   out.y = in.y + cd.dy;
   out.z = disk ? Ld.pos : in.z + s_d * (cth_d / sth_d);
   out.phi = wrap_pi(in.phi + 2.0 * cd.a);
-  out.k = k;
+  out.k = in.k;
   out.th = in.th;
   // Jacobian and noise in R from the rounded geometry
   const R s = (R)s_d, kappa = (R)kappa_d, omega = (R)omega_d;
@@ -453,6 +452,23 @@ KFX_HD void transport(const StateT<R>& in, const Layer& Ld, double cphi, double 
     // the z row of J is identically zero on a plane
 #pragma unroll
     for (int j = 0; j < 6; ++j) out.C[sidx(2, j)] = (R)0;
+  } else {
+    // n^T J_pos = 0 on the cylinder, so C- has no variance along the normal
+    // e = (x, y, 0)/r.  Rounding leaves some; at a steep crossing it rivals
+    // sigma_n^2 in S.  Apply P C P^T with P = I - e e^T (an identity in exact
+    // arithmetic): C' = C - e w^T - w e^T + (e^T C e) e e^T, w = C e.
+    const double r1 = sqrt(out.x * out.x + out.y * out.y);
+    const R e0 = (R)(out.x / r1), e1 = (R)(out.y / r1);
+    R w[6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) w[j] = e0 * out.C[sidx(0, j)] + e1 * out.C[sidx(1, j)];
+    const R sg = e0 * w[0] + e1 * w[1];
+    const R ev[6] = {e0, e1, (R)0, (R)0, (R)0, (R)0};
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+#pragma unroll
+      for (int j = 0; j <= i; ++j)
+        if (i < 2 || j < 2) out.C[sidx(i, j)] += -ev[i] * w[j] - w[i] * ev[j] + sg * ev[i] * ev[j];
   }
   // multiple scattering at the destination
   R cinc;
@@ -546,7 +562,7 @@ KFX_HD R kf_update(StateT<R>& st, const FrameT<R>& F, double mx, double my, doub
   st.x += (double)dp[0];
   st.y += (double)dp[1];
   st.z += (double)dp[2];
-  st.k += dp[3];
+  st.k += (double)dp[3];
   st.phi = wrap_pi(st.phi + (double)dp[4]);
   st.th += (double)dp[5];
 #pragma unroll
@@ -583,7 +599,7 @@ KFX_HD void prior_cov(const Prior& pr, StateT<R>& st) {
 #pragma unroll
   for (int i = 0; i < 21; ++i) st.C[i] = (R)0;
   st.C[sidx(0, 0)] = st.C[sidx(1, 1)] = st.C[sidx(2, 2)] = (R)pr.spos * (R)pr.spos;
-  const R sk = (R)pr.sk_rel * mabs(st.k);
+  const R sk = (R)pr.sk_rel * (R)fabs(st.k);
   st.C[sidx(3, 3)] = sk * sk;
   st.C[sidx(4, 4)] = (R)pr.sphi * (R)pr.sphi;
   st.C[sidx(5, 5)] = (R)pr.stheta * (R)pr.stheta;
@@ -621,7 +637,7 @@ KFX_HD void seed_estimate(double bz, const double m1[3], const double m2[3], con
   st.x = m1[0];
   st.y = m1[1];
   st.z = m1[2];
-  st.k = bz == 0.0 ? (R)0 : (R)(-omega / (kHcD * bz));
+  st.k = bz == 0.0 ? 0.0 : -omega / (kHcD * bz);
   // turning angle over the chord 1->2 is 2 asin(omega |P2-P1| / 2)
   const double half12 = asin(fmin(1.0, fmax(-1.0, 0.5 * omega * la)));
   st.phi = wrap_pi(atan2(ay, ax) - half12);

@@ -175,33 +175,32 @@ KFX_HD void bestk_insert(BestK& b, int K, float c, int h) {
 }
 
 // ---- SoA state access ---------------------------------------------------
-// pos: [5][stride] float64 (x, y, z, phi, theta); k: [stride] float32;
-// cov: [21][stride] float32 (packed lower triangle).
+// par: [6][stride] float64 (x, y, z, k, phi, theta); cov: [21][stride]
+// float32 (packed lower triangle).
 struct StateSoA {
-  double* pos;
-  float* k;
+  double* par;
   float* cov;
   long stride;
 };
 
 KFX_HD void load_state(const StateSoA& a, long i, State& s) {
-  s.x = a.pos[i];
-  s.y = a.pos[a.stride + i];
-  s.z = a.pos[2 * a.stride + i];
-  s.phi = a.pos[3 * a.stride + i];
-  s.th = a.pos[4 * a.stride + i];
-  s.k = a.k[i];
+  s.x = a.par[i];
+  s.y = a.par[a.stride + i];
+  s.z = a.par[2 * a.stride + i];
+  s.k = a.par[3 * a.stride + i];
+  s.phi = a.par[4 * a.stride + i];
+  s.th = a.par[5 * a.stride + i];
 #pragma unroll
   for (int j = 0; j < 21; ++j) s.C[j] = a.cov[j * a.stride + i];
 }
 
 KFX_HD void store_state(const StateSoA& a, long i, const State& s) {
-  a.pos[i] = s.x;
-  a.pos[a.stride + i] = s.y;
-  a.pos[2 * a.stride + i] = s.z;
-  a.pos[3 * a.stride + i] = s.phi;
-  a.pos[4 * a.stride + i] = s.th;
-  a.k[i] = s.k;
+  a.par[i] = s.x;
+  a.par[a.stride + i] = s.y;
+  a.par[2 * a.stride + i] = s.z;
+  a.par[3 * a.stride + i] = s.k;
+  a.par[4 * a.stride + i] = s.phi;
+  a.par[5 * a.stride + i] = s.th;
 #pragma unroll
   for (int j = 0; j < 21; ++j) a.cov[j * a.stride + i] = s.C[j];
 }
@@ -276,7 +275,7 @@ KFX_HD bool filter_step(StateT<R>& st, const Layer& Ld, double r_surf, double ka
     add_material(st, Ld);
   } else {
     const double cphi = cos(st.phi), sphi = sin(st.phi);
-    const double s = path_to_layer(st, Ld, r_surf, cphi, sphi, kappa * (double)st.k);
+    const double s = path_to_layer(st, Ld, r_surf, cphi, sphi, kappa * st.k);
     if (!(s > 0.0)) return false;
     StateT<R> nx;
     transport(st, Ld, cphi, sphi, s, kappa, nx);
@@ -358,7 +357,7 @@ KFX_HD void fit_track(const Geometry& G, const HitsView& H, const int* trk_off, 
   double chi2 = 0.0;
   bool ok = n >= 3;
   // checkpoints beyond the caller's capacity: the track is not fitted
-  const bool ckpt_fits = !o.ckpt.pos || (long)b + n <= o.ckpt.stride;
+  const bool ckpt_fits = !o.ckpt.par || (long)b + n <= o.ckpt.stride;
   ok = ok && ckpt_fits;
   for (int i = 0; ok && i < n; ++i) {
     const int h = trk_hits[b + i];
@@ -372,7 +371,11 @@ KFX_HD void fit_track(const Geometry& G, const HitsView& H, const int* trk_off, 
       m0[i][1] = H.y[h];
       m0[i][2] = H.z[h];
     }
-    // the first three hits in FP64 (see seed_state), the rest in FP32
+    // The fit runs the whole filter with an FP64 covariance: a crossing at
+    // angle a to the layer normal scales the covariance terms by 1/cos^2(a),
+    // and over a few steep crossings the FP32 rounding of the covariance
+    // (6e-8 relative per layer) grows to ~1e-3 in chi2; the gradient of the
+    // fit needs the same precision.  The stored states are rounded to FP32.
     StateT<double> sd;
     seed_estimate(G.bz, m0[0], m0[1], m0[2], sd);
     prior_cov(pr, sd);
@@ -385,22 +388,18 @@ KFX_HD void fit_track(const Geometry& G, const HitsView& H, const int* trk_off, 
       double m[3];
       aligned_hit(Ld, H.x[h], H.y[h], H.z[h], a, m);
       const double r_surf = Ld.pos + ((a && Ld.kind == kBarrel) ? (double)a[0] : 0.0);
-      if (i < 3) {
-        double c2 = 0.0;
-        ok = filter_step(sd, Ld, r_surf, kappa_d, i == 0, m, c2);
-        chi2 += c2;
+      double c2 = 0.0;
+      ok = filter_step(sd, Ld, r_surf, kappa_d, i == 0, m, c2);
+      chi2 += c2;
+      if (ok && o.ckpt.par) {
         convert_state(sd, st);
-      } else {
-        float c2 = 0.0f;
-        ok = filter_step(st, Ld, r_surf, kappa_d, false, m, c2);
-        chi2 += (double)c2;
+        store_state(o.ckpt, b + i, st);
       }
-      if (ok && o.ckpt.pos) store_state(o.ckpt, b + i, st);
     }
+    convert_state(sd, st);
   }
   if (!ok) {
-    st.x = st.y = st.z = st.phi = st.th = 0.0;
-    st.k = 0.0f;
+    st.x = st.y = st.z = st.k = st.phi = st.th = 0.0;
     for (int j = 0; j < 21; ++j) st.C[j] = 0.0f;
     chi2 = 0.0;
   }

@@ -32,8 +32,7 @@ EXPORTED = ["kfx_create", "kfx_destroy", "kfx_last_error", "kfx_load_layers", "k
 
 
 class c_states(ctypes.Structure):
-    _fields_ = [("pos", ctypes.c_void_p), ("k", ctypes.c_void_p), ("cov", ctypes.c_void_p),
-                ("stride", ctypes.c_int64)]
+    _fields_ = [("par", ctypes.c_void_p), ("cov", ctypes.c_void_p), ("stride", ctypes.c_int64)]
 
 
 class c_hits(ctypes.Structure):
@@ -117,19 +116,17 @@ class KfxError(RuntimeError):
 
 @dataclass
 class States:
-    """Device SoA states: pos float64 [5, n] (x, y, z, phi, theta), k
-    float32 [n], cov float32 [21, n] (packed lower triangle)."""
+    """Device SoA states: par float64 [6, n] (x, y, z, k, phi, theta), cov
+    float32 [21, n] (packed lower triangle)."""
 
-    pos: object
-    k: object
+    par: object
     cov: object
 
     @staticmethod
     def empty(n, device):
         import torch
         n = max(int(n), 1)
-        return States(torch.zeros((5, n), dtype=torch.float64, device=device),
-                      torch.zeros(n, dtype=torch.float32, device=device),
+        return States(torch.zeros((6, n), dtype=torch.float64, device=device),
                       torch.zeros((21, n), dtype=torch.float32, device=device))
 
     @staticmethod
@@ -141,27 +138,22 @@ class States:
         C = np.asarray(C)
         if C.ndim == 3:
             C = pack_cov(C)
-        pos = np.stack([p[:, 0], p[:, 1], p[:, 2], p[:, 4], p[:, 5]])
-        k = p[:, 3].astype(np.float32)
-        return States(torch.as_tensor(np.ascontiguousarray(pos), device=device),
-                      torch.as_tensor(np.ascontiguousarray(k), device=device),
+        return States(torch.as_tensor(np.ascontiguousarray(p.T), device=device),
                       torch.as_tensor(np.ascontiguousarray(C.T.astype(np.float32)), device=device))
 
     @property
     def n(self):
-        return int(self.pos.shape[1])
+        return int(self.par.shape[1])
 
     def c(self):
-        return c_states(self.pos.data_ptr(), self.k.data_ptr(), self.cov.data_ptr(), self.n)
+        return c_states(self.par.data_ptr(), self.cov.data_ptr(), self.n)
 
     def to_numpy(self, n=None):
         """Returns p [n, 6] (float64) and C [n, 6, 6] (float64)."""
-        pos = self.pos.cpu().numpy()
-        k = self.k.cpu().numpy().astype(np.float64)
+        par = self.par.cpu().numpy()
         cov = self.cov.cpu().numpy().astype(np.float64)
-        n = pos.shape[1] if n is None else n
-        p = np.stack([pos[0], pos[1], pos[2], k, pos[3], pos[4]], axis=1)[:n]
-        return p, unpack_cov(cov.T[:n])
+        n = par.shape[1] if n is None else n
+        return par.T[:n].copy(), unpack_cov(cov.T[:n])
 
 
 def pack_cov(C):

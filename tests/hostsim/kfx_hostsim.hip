@@ -34,7 +34,7 @@ Geometry make_geo(const double* table, int nl, double bz) {
 }
 
 void to_state(const double* p, const float* cov21, State& s) {
-  s.x = p[0]; s.y = p[1]; s.z = p[2]; s.k = (float)p[3]; s.phi = p[4]; s.th = p[5];
+  s.x = p[0]; s.y = p[1]; s.z = p[2]; s.k = p[3]; s.phi = p[4]; s.th = p[5];
   for (int i = 0; i < 21; ++i) s.C[i] = cov21[i];
 }
 
@@ -56,7 +56,7 @@ float hs_predict(const double* table, int nl, double bz, int layer, const double
   const double cphi = cos(st.phi), sphi = sin(st.phi);
   const double kappa = -kHcD * bz;
   const Layer& L = G.L[layer];
-  const double s = path_to_layer(st, L, L.pos, cphi, sphi, kappa * (double)st.k);
+  const double s = path_to_layer(st, L, L.pos, cphi, sphi, kappa * st.k);
   if (!(s > 0.0)) return -1.0f;
   transport(st, L, cphi, sphi, s, kappa, out);
   from_state(out, p_out, cov_out);
@@ -100,14 +100,14 @@ void hs_fit(const double* table, int nl, double bz, const float* x, const float*
   Geometry G = make_geo(table, nl, bz);
   HitsView H{x, y, z, layer, nullptr, nhits, 1};
   Prior pr{prior[0], prior[1], prior[2], prior[3]};
-  std::vector<double> pos(5 * (size_t)nt);
-  std::vector<float> kk((size_t)nt), cov(21 * (size_t)nt);
+  std::vector<double> par(6 * (size_t)nt);
+  std::vector<float> cov(21 * (size_t)nt);
   FitOut o;
-  o.state = StateSoA{pos.data(), kk.data(), cov.data(), nt};
+  o.state = StateSoA{par.data(), cov.data(), nt};
   o.chi2 = chi2;
   o.ndof = ndof;
   o.status = status;
-  o.ckpt = StateSoA{nullptr, nullptr, nullptr, 0};
+  o.ckpt = StateSoA{nullptr, nullptr, 0};
   for (int t = 0; t < nt; ++t) {
     fit_track(G, H, trk_off, trk_hits, t, pr, align, fscale, o);
     State s;
@@ -123,5 +123,5 @@ extern "C" double hs_path_cylinder(const double* p, double bz, double Rc) {
   float c[21] = {0};
   to_state(p, c, st);
   const double cphi = cos(st.phi), sphi = sin(st.phi);
-  return path_to_cylinder(st, cphi, sphi, -kHcD * bz * (double)st.k, Rc);
+  return path_to_cylinder(st, cphi, sphi, -kHcD * bz * st.k, Rc);
 }
