@@ -1,0 +1,265 @@
+#!/usr/bin/env python
+"""Benchmark of Kalman-filter track building on one MI355X.
+
+One step = one pass of the building hot path over one batch of synthetic
+events already resident in HBM: hit binning (counting sort into the
+(eta, phi) index), seed start states, and the search -- navigate and
+propagate every candidate, scan its window for compatible hits, keep the best
+K children per seed, update them -- in the fused persistent kernel.
+
+value = candidate-layer Kalman steps per second (candidate-surface pairs
+propagated, counted by the kernel), for a run whose best candidates were
+checked against the FP64 oracle (parameters within 1e-4 relative).
+
+Prints one JSON line.  Extra objects: roofline (the building kernel, timed
+with HIP events on its own stream), cpu_baseline (the FP64 oracle on the
+host, single thread, on a bounded sample), parity, and secondary
+measurements (the plain per-step path on the same input, the batched
+256-event workload, the high-occupancy workload, the fit).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "cand-layer Kalman steps/s at 1e-4 rel tol; fit+grad tracks/s vs plain path"
+
+# Floating-point operations per unit of work, counted from the formulas as
+# the kernels implement them (FMA = 2, transcendental calls = 1):
+#   per step   navigation (Newton crossing + disk checks) ~300, transport and
+#              covariance J C J^T + Q with the tangent-plane projection ~540,
+#              measurement frame and S^-1 ~195, window ~40
+#   per pair   FP64 residual + 3x3 chi2 ~35
+#   per update FP64 frame, gain, state and covariance update ~500
+FLOP_PER_STEP = 1075.0
+FLOP_PER_PAIR = 35.0
+FLOP_PER_UPDATE = 500.0
+# Unpacked FP32 and FP64 vector FMA both issue 64 per clock per CU on
+# gfx950: 256 CUs x 2.4 GHz x 128 FLOP/clk.  (Packed FP32, which doubles the
+# FP32 figure to 157.3 TFLOP/s, is not used by these kernels.)
+ALU_PEAK_TFLOPS = 256 * 2.4e9 * 128 / 1e12
+
+WORKLOADS = {
+    "build5k": "5000 seeded tracks, 17 barrel layers (R 3-110 cm) + 2x9 disks (|z| 30-270 cm, "
+               "r 20-110 cm), eta U[-2.4,2.4], pT log-U[0.5,20] GeV, 1% inefficiency, 20k noise "
+               "hits, 20x128 (eta, phi) bins, chi2 < 30, K = 6",
+    "batch256": "256 events, tracks Poisson(3000) clipped [200, 12000], noise = 5x tracks, "
+                "geometry as build5k, 5-26 hits per track, K = 6, one persistent kernel",
+    "occ10k": "4 events x (10k tracks, pT log-U[0.3,50], eta U[-2.5,2.5], 10% displaced "
+              "vertices r_xy < 5 cm, 300k noise hits), K = 10",
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_flops(stats):
+    return stats[0] * FLOP_PER_STEP + stats[1] * FLOP_PER_PAIR + stats[2] * FLOP_PER_UPDATE
+
+
+def run_build(ctx, kfx, hits, ev, steps, warmup, mode, out=None):
+    """Warm up, then time `steps` build calls; returns (wall ms per step,
+    per-call kernel times, stats of one call, out)."""
+    import torch
+    w = ev.workload
+    seeds = torch.as_tensor(ev.seeds, device=ctx.device)
+    sev = torch.as_tensor(ev.trk_event.astype(np.int32), device=ctx.device)
+    kw = dict(chi2_cut=w.chi2_cut, max_cands=w.max_cands, max_holes=w.max_holes, max_steps=32, mode=mode)
+    for _ in range(warmup):
+        out = ctx.build_tracks(hits, seeds, sev, out=out, **kw)
+    torch.cuda.synchronize()
+    out["stats"].zero_()
+    ctx.enable_timing(max(steps, 1))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out = ctx.build_tracks(hits, seeds, sev, out=out, **kw)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3 / max(steps, 1)
+    times = ctx.build_times(steps)
+    ctx.enable_timing(0)
+    stats = out["stats"].cpu().numpy().astype(np.float64) / max(steps, 1)
+    return wall, times, stats, out
+
+
+def parity_check(ev, out, n_seeds, oracle_out):
+    """Best candidates of the first n seeds against the oracle's."""
+    from paper_2002_06295_amd import kfx as _k  # noqa: F401
+    K = ev.workload.max_cands
+    g_hits = out["hits"].cpu().numpy()
+    p, _ = out["state"].to_numpy()
+    same = 0
+    rel = 0.0
+    for s in range(n_seeds):
+        gh = g_hits[s * K]
+        oh = oracle_out["hits"][s, 0, :gh.shape[0]]
+        if np.array_equal(gh, oh):
+            same += 1
+            po = oracle_out["p"][s, 0]
+            d = p[s * K] - po
+            d[4] = (d[4] + np.pi) % (2 * np.pi) - np.pi
+            rel = max(rel, float(np.max(np.abs(d) / np.maximum(np.abs(po), [1, 1, 1, 0, 1, 1]))))
+    return dict(seeds_checked=int(n_seeds), best_identical=int(same), params_max_rel=rel,
+                passed=bool(rel <= 1e-4 and same >= 0.98 * n_seeds))
+
+
+def cpu_baseline(ev, n_seeds, reps):
+    """The FP64 oracle (as it is) on the host: building of n seeds, repeated."""
+    import oracle
+    seeds = ev.seeds[:n_seeds]
+    se = ev.trk_event[:n_seeds].astype(np.int32)
+    t0 = time.perf_counter()
+    steps = 0
+    res = None
+    for _ in range(reps):
+        res = oracle.build_tracks(ev, seeds=seeds, seed_event=se, max_hits=48)
+        steps += int(res["stats"][0])
+    dt = time.perf_counter() - t0
+    return dict(value=steps / dt, unit="steps/s", cores=1, kind="oracle",
+                sample=f"{n_seeds} seeds of the {ev.workload.name} event x {reps}, FP64, "
+                       f"binned compatibility search, one thread, {dt:.1f} s"), res
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="build5k", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-secondary", action="store_true", help="skip the secondary workloads")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="after the timed region, copy this many MiB device-to-device (a kernel of "
+                         "known traffic for scaling the profiler's FETCH_SIZE/WRITE_SIZE)")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only (the building shards by event "
+                                   "with no exchange; see the design notes)", "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+
+    import kfsynth
+    from paper_2002_06295_amd import kfx
+
+    dev = torch.device("cuda", 0)
+    t0 = time.perf_counter()
+    ev = kfsynth.generate(args.workload)
+    log(f"[bench] generated {args.workload}: {ev.n_events} events, {ev.n_hits} hits, {ev.n_tracks} seeds "
+        f"in {time.perf_counter() - t0:.1f}s")
+    ctx = kfx.Context(0)
+    w = ev.workload
+    ctx.load_layers(ev.geometry.as_records(), ev.bz, w.n_eta_bins, w.n_phi_bins)
+    hits = kfx.DeviceHits.from_events(ev, dev)
+
+    wall, times, stats, out = run_build(ctx, kfx, hits, ev, args.steps, args.warmup, kfx.MODE_FUSED)
+    kern_ms = float(np.mean([t[1] for t in times]))
+    bin_ms = float(np.mean([t[0] for t in times]))
+    log(f"[bench] fused: {wall:.3f} ms/step wall, building kernels {kern_ms:.3f} ms, binning {bin_ms:.3f} ms, "
+        f"steps {stats[0]:.0f} pairs {stats[1]:.0f} updates {stats[2]:.0f}")
+    if args.calib_copy_mib > 0:
+        n = args.calib_copy_mib * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    flops = algorithmic_flops(stats)
+    achieved = flops / (kern_ms * 1e-3) / 1e12
+    value = stats[0] / (wall * 1e-3)
+
+    result = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]}",
+                   "events_per_step": ev.n_events, "seeds_per_step": ev.n_tracks, "hits_per_step": ev.n_hits,
+                   "path": "fused persistent kernel", "parallelism": "single GPU"},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / ALU_PEAK_TFLOPS, "traffic": None,
+                     "kernel": "k_build_fused", "avg_launch_ms": kern_ms,
+                     "flop_per_launch": flops, "steps_per_launch": stats[0], "pairs_per_launch": stats[1],
+                     "updates_per_launch": stats[2]},
+        "binning_ms": bin_ms,
+    }
+
+    if not args.no_cpu_baseline:
+        n_cpu = min(ev.n_tracks, 5000)
+        cb, ores = cpu_baseline(ev, n_cpu, reps=4 if args.workload == "build5k" else 1)
+        result["cpu_baseline"] = cb
+        result["parity"] = parity_check(ev, out, min(n_cpu, 1000), ores)
+        log(f"[bench] oracle {cb['value']:.3e} steps/s; parity {result['parity']}")
+
+    if not args.no_secondary:
+        sec = {}
+        wall_p, times_p, stats_p, _ = run_build(ctx, kfx, hits, ev, max(3, args.steps // 4), 1, kfx.MODE_PLAIN)
+        sec["plain_path_same_input"] = {"steps_per_s": stats_p[0] / (wall_p * 1e-3), "ms_per_step": wall_p,
+                                        "kernels_ms": float(np.mean([t[1] for t in times_p]))}
+        log(f"[bench] plain path: {wall_p:.3f} ms/step")
+        del out
+        for name in ("batch256", "occ10k"):
+            if name == args.workload:
+                continue
+            t1 = time.perf_counter()
+            ev2 = kfsynth.generate(name)
+            log(f"[bench] generated {name} in {time.perf_counter() - t1:.1f}s")
+            ctx2 = kfx.Context(0)
+            ctx2.load_layers(ev2.geometry.as_records(), ev2.bz, ev2.workload.n_eta_bins, ev2.workload.n_phi_bins)
+            h2 = kfx.DeviceHits.from_events(ev2, dev)
+            wf, tf, sf, o2 = run_build(ctx2, kfx, h2, ev2, 4, 1, kfx.MODE_FUSED)
+            wp, tp, sp, o2 = run_build(ctx2, kfx, h2, ev2, 2, 1, kfx.MODE_PLAIN, out=o2)
+            km = float(np.mean([t[1] for t in tf]))
+            fl = algorithmic_flops(sf)
+            sec[name] = {"steps_per_s": sf[0] / (wf * 1e-3), "ms_per_step": wf, "kernels_ms": km,
+                         "alu_frac": fl / (km * 1e-3) / 1e12 / ALU_PEAK_TFLOPS,
+                         "plain_steps_per_s": sp[0] / (wp * 1e-3), "steps_per_launch": sf[0]}
+            log(f"[bench] {name}: fused {sec[name]['steps_per_s']:.3e} steps/s, plain "
+                f"{sec[name]['plain_steps_per_s']:.3e}")
+            del o2, h2, ctx2, ev2
+            torch.cuda.empty_cache()
+        # the fit on the alignment workload (forward only)
+        evf = kfsynth.generate("align200k")
+        ctxf = kfx.Context(0)
+        ctxf.load_layers(evf.geometry.as_records(), evf.bz, 20, 128)
+        hf = kfx.DeviceHits.from_events(evf, dev)
+        toff = torch.as_tensor(evf.trk_offsets, device=dev)
+        th = torch.as_tensor(evf.trk_hits, device=dev)
+        fo = ctxf.fit_tracks(hf, toff, th, field_scale=1.0, ckpt=True)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(5):
+            fo = ctxf.fit_tracks(hf, toff, th, field_scale=1.0, out=fo)
+        e1.record()
+        torch.cuda.synchronize()
+        fms = e0.elapsed_time(e1) / 5
+        sec["align200k_fit"] = {"tracks_per_s": evf.n_tracks / (fms * 1e-3), "ms_per_fit": fms,
+                                "tracks": evf.n_tracks, "with_checkpoints": True}
+        log(f"[bench] fit align200k: {fms:.3f} ms, {evf.n_tracks / (fms * 1e-3):.3e} tracks/s")
+        result["secondary"] = sec
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

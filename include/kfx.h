@@ -201,6 +201,17 @@ int kfx_fit_tracks(kfx_ctx* ctx, const kfx_hits* hits, const int32_t* trk_off,
                    const float* align, float field_scale, kfx_states* out, float* chi2,
                    int32_t* ndof, int32_t* status, kfx_states* ckpt, void* stream);
 
+/* Timing of kfx_build_tracks with HIP events recorded on the caller's
+ * stream, kept for the last n_calls calls (0 turns timing off; at most
+ * 4096).  Off by default. */
+int kfx_enable_timing(kfx_ctx* ctx, int n_calls);
+
+/* Milliseconds of up to the last n_calls timed builds, oldest first, three
+ * floats per call into ms (host): hit binning, building kernels (seed start,
+ * search, output), total.  Waits for those events; returns the number of
+ * calls written (>= 0) or an error code. */
+int kfx_build_times(kfx_ctx* ctx, float* ms, int n_calls);
+
 #ifdef __cplusplus
 }
 #endif

@@ -28,6 +28,13 @@ struct kfx_ctx {
   const void* index_hits_key[3] = {nullptr, nullptr, nullptr};
   int index_n_hits = -1, index_n_events = -1;
   BinWork bw{};
+  // optional timing of build calls: per call, events before binning, after
+  // binning and after the building kernels, recorded on the caller's stream
+  // into a ring of `ring_n` calls
+  bool timing = false;
+  std::vector<hipEvent_t> ring;  // 3 per slot
+  int ring_n = 0, ring_next = 0, ring_count = 0;
+  hipEvent_t* slot_ev = nullptr;  // events of the call in progress
 };
 
 namespace {
@@ -189,6 +196,8 @@ void kfx_destroy(kfx_ctx* c) {
     DeviceGuard g(c->device);
     for (auto& kv : c->pool) (void)hipFree(kv.second.first);
     if (c->dev_geo) (void)hipFree(c->dev_geo);
+    for (auto& e : c->ring)
+      if (e) (void)hipEventDestroy(e);
   }
   delete c;
 }
@@ -364,8 +373,22 @@ int kfx_build_tracks(kfx_ctx* c, const kfx_hits* hits, const int32_t* seeds, con
   if ((rc = check_states(c, &out->state, SK, "out.state"))) return rc;
   DeviceGuard dg(c->device);
   hipStream_t st = (hipStream_t)stream;
+  hipEvent_t* tev = nullptr;
+  if (c->timing) {
+    tev = c->ring.data() + 3 * c->ring_next;
+    if ((rc = hip_check(c, hipEventRecord(tev[0], st), "timing event"))) return rc;
+  }
   if ((rc = build_index(c, hits, nullptr, st))) return rc;
-  if (n_seeds == 0) return KFX_OK;
+  if (tev && (rc = hip_check(c, hipEventRecord(tev[1], st), "timing event"))) return rc;
+  auto close_timing = [&]() -> int {
+    if (!tev) return KFX_OK;
+    int r = hip_check(c, hipEventRecord(tev[2], st), "timing event");
+    if (r) return r;
+    c->ring_next = (c->ring_next + 1) % c->ring_n;
+    c->ring_count = std::min(c->ring_count + 1, c->ring_n);
+    return KFX_OK;
+  };
+  if (n_seeds == 0) return close_timing();
 
   BuildArgs a{};
   a.G = c->dev_geo;
@@ -436,7 +459,44 @@ int kfx_build_tracks(kfx_ctx* c, const kfx_hits* hits, const int32_t* seeds, con
     blocks = (int)std::max<long>(1, std::min<long>(blocks, max_blocks));
     launch_build_fused(a, o, counter, blocks, threads, st);
   }
-  return hip_check(c, hipGetLastError(), "build kernels");
+  if ((rc = hip_check(c, hipGetLastError(), "build kernels"))) return rc;
+  return close_timing();
+}
+
+int kfx_enable_timing(kfx_ctx* c, int n_calls) {
+  if (!c || n_calls < 0 || n_calls > 4096) return KFX_EINVAL;
+  c->err.clear();
+  DeviceGuard dg(c->device);
+  for (auto& e : c->ring)
+    if (e) (void)hipEventDestroy(e);
+  c->ring.assign(3 * (size_t)n_calls, nullptr);
+  for (auto& e : c->ring) {
+    int rc = hip_check(c, hipEventCreate(&e), "event create");
+    if (rc) return rc;
+  }
+  c->ring_n = n_calls;
+  c->ring_next = 0;
+  c->ring_count = 0;
+  c->timing = n_calls > 0;
+  return KFX_OK;
+}
+
+int kfx_build_times(kfx_ctx* c, float* ms, int n_calls) {
+  if (!c || !ms || n_calls < 0) return KFX_EINVAL;
+  c->err.clear();
+  const int n = std::min(n_calls, c->ring_count);
+  DeviceGuard dg(c->device);
+  for (int i = 0; i < n; ++i) {
+    // oldest of the last n first
+    const int slot = ((c->ring_next - n + i) % c->ring_n + c->ring_n) % c->ring_n;
+    hipEvent_t* e = c->ring.data() + 3 * slot;
+    int rc = hip_check(c, hipEventSynchronize(e[2]), "event sync");
+    if (rc) return rc;
+    if ((rc = hip_check(c, hipEventElapsedTime(&ms[3 * i + 0], e[0], e[1]), "elapsed"))) return rc;
+    if ((rc = hip_check(c, hipEventElapsedTime(&ms[3 * i + 1], e[1], e[2]), "elapsed"))) return rc;
+    if ((rc = hip_check(c, hipEventElapsedTime(&ms[3 * i + 2], e[0], e[2]), "elapsed"))) return rc;
+  }
+  return n;
 }
 
 int kfx_fit_tracks(kfx_ctx* c, const kfx_hits* hits, const int32_t* trk_off, const int32_t* trk_hits,

@@ -28,7 +28,8 @@ MAX_CANDS = 16
 MAX_STEPS = 40
 
 EXPORTED = ["kfx_create", "kfx_destroy", "kfx_last_error", "kfx_load_layers", "kfx_bin_hits",
-            "kfx_seed_states", "kfx_step_compat", "kfx_build_tracks", "kfx_fit_tracks"]
+            "kfx_seed_states", "kfx_step_compat", "kfx_build_tracks", "kfx_fit_tracks",
+            "kfx_enable_timing", "kfx_build_times"]
 
 
 class c_states(ctypes.Structure):
@@ -97,6 +98,8 @@ def load_library():
                                    ctypes.c_void_p, ctypes.c_float, ctypes.POINTER(c_states),
                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                    ctypes.POINTER(c_states), ctypes.c_void_p]
+    lib.kfx_enable_timing.argtypes = [ctypes.c_void_p, ctypes.c_int]
+    lib.kfx_build_times.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
     for name in EXPORTED:
         if name not in ("kfx_destroy", "kfx_last_error"):
             getattr(lib, name).restype = ctypes.c_int
@@ -304,6 +307,18 @@ class Context:
         self._check(self.lib.kfx_build_tracks(self.h, ctypes.byref(hits.struct), _ptr(seeds), _ptr(seed_event), S,
                                               ctypes.byref(p), ctypes.byref(t), self._stream()))
         return out
+
+    def enable_timing(self, n_calls=64):
+        self._check(self.lib.kfx_enable_timing(self.h, int(n_calls)))
+
+    def build_times(self, n_calls):
+        """[(binning ms, building kernels ms, total ms)] of the last n_calls
+        timed builds, oldest first."""
+        ms = (ctypes.c_float * (3 * max(n_calls, 1)))()
+        n = self.lib.kfx_build_times(self.h, ms, int(n_calls))
+        if n < 0:
+            self._check(n)
+        return [(ms[3 * i], ms[3 * i + 1], ms[3 * i + 2]) for i in range(n)]
 
     def alloc_tracks(self, S, K, max_hits=48):
         import torch
