@@ -201,6 +201,25 @@ int kfx_fit_tracks(kfx_ctx* ctx, const kfx_hits* hits, const int32_t* trk_off,
                    const float* align, float field_scale, kfx_states* out, float* chi2,
                    int32_t* ndof, int32_t* status, kfx_states* ckpt, void* stream);
 
+/* Adjoint of the fit (an addition to the paper, whose fit has no
+ * alignment or field parameters): the gradient of L = sum_t w_t chi2_t over
+ * the tracks with status 1 with respect to the alignment of every barrel
+ * layer and the field scale, for the same inputs as a kfx_fit_tracks call
+ * made with a checkpoint.  ckpt: the states that call wrote (read only);
+ * status: its status array.  dchi2: device float32, w_t = dchi2[t] when
+ * dchi2_per_track != 0, else w_t = dchi2[0] for every track.  The sweep
+ * recomputes each step in float64 from the checkpointed state before it and
+ * pulls the adjoint back through the update, the material noise, the
+ * covariance transport, the helix and the path to the surface.  Outputs
+ * (device, float64, overwritten): dalign [3 n_layers] (0 for disks), dfield
+ * [1].  Per-track partial sums are reduced in a fixed order, so the result
+ * is the same on every call. */
+int kfx_fit_tracks_backward(kfx_ctx* ctx, const kfx_hits* hits, const int32_t* trk_off,
+                            const int32_t* trk_hits, int32_t n_tracks, const kfx_prior* prior,
+                            const float* align, float field_scale, const kfx_states* ckpt,
+                            const int32_t* status, const float* dchi2, int32_t dchi2_per_track,
+                            double* dalign, double* dfield, void* stream);
+
 /* Timing of kfx_build_tracks with HIP events recorded on the caller's
  * stream, kept for the last n_calls calls (0 turns timing off; at most
  * 4096).  Off by default. */

@@ -261,9 +261,10 @@ int kfx_load_layers(kfx_ctx* c, const double* table, int n_layers, double bz, in
   G.n_barrel = (int)bar.size();
   G.n_dpos = (int)dp.size();
   G.n_dneg = (int)dn.size();
-  for (int i = 0; i < kMaxLayers; ++i) G.next_barrel[i] = -1;
+  for (int i = 0; i < kMaxLayers; ++i) G.next_barrel[i] = G.brank[i] = -1;
   for (size_t i = 0; i < bar.size(); ++i) {
     G.barrel[i] = bar[i];
+    G.brank[bar[i]] = (int)i;
     G.next_barrel[bar[i]] = (i + 1 < bar.size()) ? bar[i + 1] : -1;
   }
   for (size_t i = 0; i < dp.size(); ++i) G.dpos[i] = dp[i];
@@ -524,6 +525,37 @@ int kfx_fit_tracks(kfx_ctx* c, const kfx_hits* hits, const int32_t* trk_off, con
   else o.ckpt.par = nullptr, o.ckpt.cov = nullptr, o.ckpt.stride = 0;
   launch_fit(c->dev_geo, view(hits), trk_off, trk_hits, n_tracks, prior_of(prior), align, field_scale, o, st);
   return hip_check(c, hipGetLastError(), "fit kernel");
+}
+
+int kfx_fit_tracks_backward(kfx_ctx* c, const kfx_hits* hits, const int32_t* trk_off, const int32_t* trk_hits,
+                            int32_t n_tracks, const kfx_prior* prior, const float* align, float field_scale,
+                            const kfx_states* ckpt, const int32_t* status, const float* dchi2,
+                            int32_t dchi2_per_track, double* dalign, double* dfield, void* stream) {
+  if (!c) return KFX_EINVAL;
+  c->err.clear();
+  if (!c->have_geo) return fail(c, KFX_ESTATE, "kfx_load_layers first");
+  int rc = check_hits(c, hits);
+  if (rc || (rc = check_prior(c, prior))) return rc;
+  if (n_tracks < 0) return fail(c, KFX_EINVAL, "n_tracks < 0");
+  if (!std::isfinite(field_scale)) return fail(c, KFX_EINVAL, "non-finite field scale");
+  if (!dalign || !dfield) return fail(c, KFX_EINVAL, "NULL gradient outputs");
+  if (n_tracks > 0 && (!trk_off || !trk_hits || !status || !dchi2))
+    return fail(c, KFX_EINVAL, "NULL track arrays");
+  if (n_tracks > 0 && (!ckpt || !ckpt->par || !ckpt->cov)) return fail(c, KFX_EINVAL, "ckpt: NULL state arrays");
+  DeviceGuard dg(c->device);
+  hipStream_t st = (hipStream_t)stream;
+  const int nrow = 3 * c->host_geo.n_barrel + 1;
+  const long nblocks = std::max(fit_backward_blocks(n_tracks), 1);
+  double* partial = (double*)ws(c, "g.partial", (size_t)nblocks * nrow * sizeof(double), st, rc);
+  if (rc) return rc;
+  StateSoA ck;
+  if (n_tracks > 0) ck = soa(ckpt);
+  else ck.par = nullptr, ck.cov = nullptr, ck.stride = 0;
+  return hip_check(c,
+                   launch_fit_backward(c->dev_geo, c->host_geo.n_barrel, c->host_geo.n_layers, view(hits), trk_off,
+                                       trk_hits, n_tracks, prior_of(prior), align, field_scale, ck, status, dchi2,
+                                       dchi2_per_track, partial, dalign, dfield, st),
+                   "fit backward kernels");
 }
 
 }  // extern "C"

@@ -116,12 +116,14 @@ KFX_HD int pairs_slot(const BuildArgs& a, long slot, int ev) {
   load_state(a.pred, slot, pr);
   Frame F;
   make_frame(pr, a.G->L[nl], F);
-  BestK b;
+  BestK<kMaxK> b;
   const int found = scan_window(*a.G, a.B, ev, nl, pr, F, a.cut, a.K, b);
-  for (int r = 0; r < b.n; ++r) {
-    a.kid_c[slot * a.K + r] = b.c[r];
-    a.kid_h[slot * a.K + r] = b.h[r];
-  }
+#pragma unroll
+  for (int r = 0; r < kMaxK; ++r)
+    if (r < b.n) {
+      a.kid_c[slot * a.K + r] = b.c[r];
+      a.kid_h[slot * a.K + r] = b.h[r];
+    }
   a.kid_n[slot] = b.n;
   return found;
 }

@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include "kfx_adjoint.h"
 #include "kfx_build.h"
 
 namespace kfx {
@@ -26,6 +27,11 @@ void launch_bin(const Geometry* G, const HitsView& H, int n_layers, int n_bins, 
                 hipStream_t st);
 void launch_fit(const Geometry* G, const HitsView& H, const int* trk_off, const int* trk_hits, int n,
                 const Prior& pr, const float* align, float fscale, const FitOut& o, hipStream_t st);
+int fit_backward_blocks(int n);
+hipError_t launch_fit_backward(const Geometry* G, int n_barrel, int n_layers, const HitsView& H, const int* trk_off,
+                               const int* trk_hits, int n, const Prior& pr, const float* align, float fscale,
+                               const StateSoA& ckpt, const int* status, const float* dchi2, int per_track,
+                               double* partial, double* dalign, double* dfield, hipStream_t st);
 void launch_seed_states(const Geometry* G, const HitsView& H, const int* seeds, int n, const Prior& pr,
                         const StateSoA& out, float* chi2, int* status, hipStream_t st);
 void launch_step_compat(const Geometry* G, const HitsView& H, const BinIndex& B, const int* cand_event,

@@ -177,6 +177,73 @@ __global__ void __launch_bounds__(128) k_fit(const Geometry* __restrict__ G, Hit
   fit_track(*G, H, trk_off, trk_hits, t, pr, align, fscale, o);
 }
 
+// ------------------------------------------------------------ fit adjoint
+// One track per lane.  Each lane adds its track's gradient into its own
+// column of an LDS table (rows: dr, drphi, dz per barrel layer by radius,
+// then the field scale), so no two lanes write one word.  The wave then sums
+// every row over its 64 lanes with a fixed butterfly and writes one partial
+// row per block, and k_grad_reduce sums the partials in block order: the
+// result does not depend on scheduling.
+struct LdsAcc {
+  double* col;  // this lane's column: row q at col[q * 64]
+  const int* brank;
+  int nb;
+  __device__ void add(int l, int c, double v) {
+    const int r = brank[l];
+    if (r >= 0) col[(3 * r + c) * 64] += v;
+  }
+  __device__ void field(double v) { col[(3 * nb) * 64] += v; }
+};
+
+__global__ void __launch_bounds__(64) k_fit_backward(const Geometry* __restrict__ G, HitsView H, const int* trk_off,
+                                                     const int* trk_hits, int n_tracks, Prior pr,
+                                                     const float* align, float fscale, StateSoA ckpt,
+                                                     const int* status, const float* dchi2, int per_track,
+                                                     double* partial) {
+  extern __shared__ double acc_lds[];
+  const int lane = threadIdx.x;
+  const int nb = G->n_barrel;
+  const int nrow = 3 * nb + 1;
+  for (int q = 0; q < nrow; ++q) acc_lds[q * 64 + lane] = 0.0;
+  const int t = blockIdx.x * 64 + lane;
+  if (t < n_tracks && status[t] == 1) {
+    const double w = per_track ? (double)dchi2[t] : (double)dchi2[0];
+    if (w != 0.0) {
+      LdsAcc acc{acc_lds + lane, G->brank, nb};
+      fit_track_backward(*G, H, trk_off, trk_hits, t, pr, align, fscale, ckpt, w, acc);
+    }
+  }
+  __syncthreads();
+  for (int q = 0; q < nrow; ++q) {
+    double v = acc_lds[q * 64 + lane];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (lane == 0) partial[(long)blockIdx.x * nrow + q] = v;
+  }
+}
+
+// dalign[3 l + c] = sum over blocks of the partial rows (0 for disks),
+// dfield = the last row; summed in block order.
+__global__ void k_grad_reduce(const Geometry* __restrict__ G, const double* partial, int nblocks, double* dalign,
+                              double* dfield) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nl = G->n_layers, nrow = 3 * G->n_barrel + 1;
+  if (i > 3 * nl) return;
+  int row = nrow - 1;
+  if (i < 3 * nl) {
+    const int r = G->brank[i / 3];
+    if (r < 0) {
+      dalign[i] = 0.0;
+      return;
+    }
+    row = 3 * r + i % 3;
+  }
+  double s = 0.0;
+  for (int b = 0; b < nblocks; ++b) s += partial[(long)b * nrow + row];
+  if (i < 3 * nl) dalign[i] = s;
+  else *dfield = s;
+}
+
 // ------------------------------------------------------ seeds and step (a2-a6)
 __global__ void k_seed_states(const Geometry* __restrict__ G, HitsView H, const int* seeds, int n, Prior pr,
                               StateSoA out, float* chi2, int* status) {
@@ -329,9 +396,48 @@ struct FusedShared {
   float chi2;
 };
 
+__device__ inline void lds_put(FusedShared& d, const State& s, int layer, int meta, float chi2) {
+  d.par[0] = s.x; d.par[1] = s.y; d.par[2] = s.z; d.par[3] = s.k; d.par[4] = s.phi; d.par[5] = s.th;
+#pragma unroll
+  for (int q = 0; q < 21; ++q) d.cov[q] = s.C[q];
+  d.layer = layer;
+  d.meta = meta;
+  d.chi2 = chi2;
+}
+
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Key of the next child of a lane's stream (see kid_key): the head of its
+// sorted hit list, then the hole, or its single stop child.
+template <int KM>
+__device__ inline uint64_t lane_head(const KidStream& k, const BestK<KM>& b, int popped, bool hole_used,
+                                     int K, float& chi2_out, int& code) {
+  if (!k.live) return ~0ull;
+  if (k.stop) {
+    if (popped > 0) return ~0ull;
+    chi2_out = k.chi2;
+    code = kStop;
+    return child_key(k.nh, k.nho, k.chi2, k.parent, 0);
+  }
+  if (b.n > 0) {
+    chi2_out = k.chi2 + b.c[0];
+    code = b.h[0];
+    return child_key(k.nh + 1, k.nho, chi2_out, k.parent, popped);
+  }
+  if (k.hole && !hole_used) {
+    chi2_out = k.chi2;
+    code = kHole;
+    return child_key(k.nh, k.nho + 1, k.chi2, k.parent, K);
+  }
+  return ~0ull;
+}
+
 template <int G_LANES>
-__global__ void __launch_bounds__(256) k_build_fused(BuildArgs a, int cur_unused, TracksOut o, int* seed_counter) {
-  (void)cur_unused;
+__global__ void __launch_bounds__(256) k_build_fused(BuildArgs a, int* seed_counter) {
   extern __shared__ unsigned char smem_raw[];
   FusedShared* sh = reinterpret_cast<FusedShared*>(smem_raw);
   const Geometry& G = *a.G;
@@ -349,6 +455,7 @@ __global__ void __launch_bounds__(256) k_build_fused(BuildArgs a, int cur_unused
   State st;
   int layer = -1, meta = 0;
   float chi2 = 0.0f;
+  FusedShared& me = sh[threadIdx.x];
 
   while (true) {
     // a group without a seed takes the next one (all lanes take part in
@@ -365,13 +472,13 @@ __global__ void __launch_bounds__(256) k_build_fused(BuildArgs a, int cur_unused
         layer = -1;
         chi2 = 0.0f;
         if (gl == 0) {
-          float c2 = 0.0f;
-          const int* sh3 = a.seeds + 3 * seed;
-          const int ev = a.seed_event[seed];
-          if (ev >= 0 && ev < a.H.n_events && seed_state(G, a.H, sh3, a.prior, st, c2)) {
-            layer = a.H.layer[sh3[2]];
-            chi2 = c2;
-            meta = meta_pack(kSeedHits, 0, 0, kFlagLive);
+          // start state written by the seed kernel into slot 0
+          const long s0 = (long)seed * K;
+          meta = a.meta[0][s0];
+          if (meta_flags(meta) & kFlagLive) {
+            load_state(a.cand[0], s0, st);
+            layer = a.layer[0][s0];
+            chi2 = a.chi2[0][s0];
           }
         }
       } else {
@@ -381,7 +488,9 @@ __global__ void __launch_bounds__(256) k_build_fused(BuildArgs a, int cur_unused
     const bool active = seed >= 0;
     if (__ballot(active) == 0) break;
 
-    // ---- (a) navigate + transport
+    // ---- (a) navigate + transport; the current state goes to LDS now (a
+    // stop child keeps it) and is overwritten by the prediction below when
+    // the lane's children start from the prediction
     int nl = -2;
     State pr;
     const bool live = active && (meta_flags(meta) & kFlagLive) && gl < K;
@@ -398,19 +507,24 @@ __global__ void __launch_bounds__(256) k_build_fused(BuildArgs a, int cur_unused
         }
       }
     }
-    // ---- (b) window scan, best K hit children
-    BestK best;
+    lds_put(me, st, layer, meta, chi2);
+    // ---- (b) window scan, best K hit children in registers
+    BestK<G_LANES> best;
     best.n = 0;
     if (nl >= 0) {
       Frame F;
       make_frame(pr, G.L[nl], F);
       n_pairs += (unsigned long long)scan_window(G, a.B, a.seed_event[seed], nl, pr, F, a.cut, K, best);
     }
-    // ---- (c) selection: K rounds of a segmented minimum over child streams
     const KidStream ks = kid_stream(a, live ? meta : 0, chi2, nl, best.n, gl);
-    int p = 0;
+    if (nl >= 0 && !ks.stop) lds_put(me, pr, nl, meta, chi2);
+    // ---- (c) selection: K rounds of a segmented minimum over the lanes'
+    // child streams; round i fills new slot i (lane gbase + i)
+    int popped = 0;
+    bool hole_used = false;
     float hc = 0.0f;
-    uint64_t head = kid_key(ks, K, 0, best.c, hc);
+    int hcode = kStop;
+    uint64_t head = lane_head(ks, best, popped, hole_used, K, hc, hcode);
     int my_parent = -1, my_code = kStop;
     float my_chi2 = 0.0f;
     for (int i = 0; i < K; ++i) {
@@ -424,11 +538,7 @@ __global__ void __launch_bounds__(256) k_build_fused(BuildArgs a, int cur_unused
       // winner lane in the wave (unique: keys differ by parent slot); a
       // group with no child left reads its own first lane and ignores it
       const int wl = win ? __ffsll((long long)win) - 1 : (lane & ~(G_LANES - 1));
-      int code = kStop;
-      if (ks.stop) code = kStop;
-      else if (p < ks.nkids) code = best.h[p];
-      else code = kHole;
-      const int wcode = __shfl(code, wl, 64);
+      const int wcode = __shfl(hcode, wl, 64);
       const float wchi2 = __shfl(hc, wl, 64);
       if (win && gl == i) {
         my_parent = wl & (G_LANES - 1);
@@ -436,28 +546,14 @@ __global__ void __launch_bounds__(256) k_build_fused(BuildArgs a, int cur_unused
         my_chi2 = wchi2;
       }
       if (win && lane == wl) {
-        ++p;
-        head = kid_key(ks, K, p, best.c, hc);
+        if (hcode >= 0) bestk_pop(best);
+        else if (hcode == kHole) hole_used = true;
+        ++popped;
+        head = lane_head(ks, best, popped, hole_used, K, hc, hcode);
       }
     }
-    // ---- hand states to the children through LDS
-    FusedShared& me = sh[threadIdx.x];
-    {
-      // a stop child keeps its parent's current state; hit and hole
-      // children start from the prediction (a lane with a stop child has
-      // no other child)
-      const State& src = (nl >= 0 && !ks.stop) ? pr : st;
-      me.par[0] = src.x; me.par[1] = src.y; me.par[2] = src.z; me.par[3] = src.k; me.par[4] = src.phi;
-      me.par[5] = src.th;
-#pragma unroll
-      for (int q = 0; q < 21; ++q) me.cov[q] = src.C[q];
-      me.layer = (nl >= 0 && !ks.stop) ? nl : layer;
-      me.meta = meta;
-      me.chi2 = chi2;
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    wave_sync();
+    // ---- (d) children: copy the parent's state from LDS, update hit children
     int new_meta = 0, new_layer = -1;
     if (active && gl < K) {
       if (my_parent >= 0) {
@@ -485,9 +581,7 @@ __global__ void __launch_bounds__(256) k_build_fused(BuildArgs a, int cur_unused
       a.hist_parent[hidx] = (signed char)my_parent;
       a.hist_code[hidx] = my_parent >= 0 ? my_code : kStop;
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    wave_sync();
     if (active) {
       meta = (gl < K) ? new_meta : 0;
       layer = new_layer;
@@ -498,22 +592,15 @@ __global__ void __launch_bounds__(256) k_build_fused(BuildArgs a, int cur_unused
     const bool running = active && (meta_flags(meta) & kFlagLive) && !(meta_flags(meta) & kFlagDone);
     const unsigned long long run_mask = __ballot(running) & gmask;
     if (active && (run_mask == 0 || t >= a.max_steps)) {
+      // final state of each slot into the candidate buffer; the output
+      // (hit lists from the history) is written by the finalize kernel
       if (gl == 0) a.n_steps[seed] = t;
-      // final state of this slot into the candidate buffer, then the output
       const long slot = (long)seed * K + gl;
       if (gl < K) {
         store_state(a.cand[0], slot, st);
         a.meta[0][slot] = meta;
         a.layer[0][slot] = layer;
         a.chi2[0][slot] = chi2;
-      }
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
-      __builtin_amdgcn_wave_barrier();
-      if (gl < K) finalize_slot(a, 0, o, seed, gl);
-      if (gl == 0) {
-        int n = 0;
-        for (int q = 0; q < K; ++q) n += (meta_flags(a.meta[0][(long)seed * K + q]) & kFlagLive) ? 1 : 0;
-        o.n_cands[seed] = n;
       }
       seed = -1;
     }
@@ -552,6 +639,30 @@ void launch_fit(const Geometry* G, const HitsView& H, const int* trk_off, const 
                 const Prior& pr, const float* align, float fscale, const FitOut& o, hipStream_t st) {
   if (n <= 0) return;
   hipLaunchKernelGGL(k_fit, dim3(nblk(n, 128)), dim3(128), 0, st, G, H, trk_off, trk_hits, n, pr, align, fscale, o);
+}
+
+int fit_backward_blocks(int n) { return (n + 63) / 64; }
+
+hipError_t launch_fit_backward(const Geometry* G, int n_barrel, int n_layers, const HitsView& H, const int* trk_off,
+                               const int* trk_hits, int n, const Prior& pr, const float* align, float fscale,
+                               const StateSoA& ckpt, const int* status, const float* dchi2, int per_track,
+                               double* partial, double* dalign, double* dfield, hipStream_t st) {
+  const int nrow = 3 * n_barrel + 1;
+  const int nblocks = fit_backward_blocks(n);
+  const size_t shmem = (size_t)nrow * 64 * sizeof(double);
+  if (n > 0) {
+    if (shmem > 65536) {
+      const hipError_t e = hipFuncSetAttribute((const void*)k_fit_backward,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_fit_backward, dim3(nblocks), dim3(64), shmem, st, G, H, trk_off, trk_hits, n, pr, align,
+                       fscale, ckpt, status, dchi2, per_track, partial);
+  }
+  const int nout = 3 * n_layers + 1;
+  hipLaunchKernelGGL(k_grad_reduce, dim3(nblk(nout, 64)), dim3(64), 0, st, G, partial, n > 0 ? nblocks : 0, dalign,
+                     dfield);
+  return hipGetLastError();
 }
 
 void launch_seed_states(const Geometry* G, const HitsView& H, const int* seeds, int n, const Prior& pr,
@@ -594,19 +705,24 @@ void launch_build_fused(const BuildArgs& a, const TracksOut& o, int* seed_counte
                         hipStream_t st) {
   if (a.n_seeds <= 0) return;
   launch_fill(seed_counter, 1, 0, st);
+  // start states (FP64 seed phase) in their own kernel, so that its FP64
+  // temporaries do not set the register budget of the persistent kernel
+  hipLaunchKernelGGL(k_build_init, dim3(nblk(a.n_seeds, 128)), dim3(128), 0, st, a);
   const size_t shmem = sizeof(FusedShared) * threads;
   const int g = fused_lanes_for(a.K);
   switch (g) {
     case 1: case 2: case 4:
-      hipLaunchKernelGGL(k_build_fused<4>, dim3(blocks), dim3(threads), shmem, st, a, 0, o, seed_counter);
+      hipLaunchKernelGGL(k_build_fused<4>, dim3(blocks), dim3(threads), shmem, st, a, seed_counter);
       break;
     case 8:
-      hipLaunchKernelGGL(k_build_fused<8>, dim3(blocks), dim3(threads), shmem, st, a, 0, o, seed_counter);
+      hipLaunchKernelGGL(k_build_fused<8>, dim3(blocks), dim3(threads), shmem, st, a, seed_counter);
       break;
     default:
-      hipLaunchKernelGGL(k_build_fused<16>, dim3(blocks), dim3(threads), shmem, st, a, 0, o, seed_counter);
+      hipLaunchKernelGGL(k_build_fused<16>, dim3(blocks), dim3(threads), shmem, st, a, seed_counter);
       break;
   }
+  const long nslots = (long)a.n_seeds * a.K;
+  hipLaunchKernelGGL(k_build_finalize, dim3(nblk(nslots, 128)), dim3(128), 0, st, a, 0, o);
 }
 
 }  // namespace kfx

@@ -59,6 +59,7 @@ struct Geometry {
   int dpos[kMaxLayers];     // +z disks, increasing z
   int dneg[kMaxLayers];     // -z disks, decreasing z
   int next_barrel[kMaxLayers];  // for a barrel layer: the next one out (-1)
+  int brank[kMaxLayers];        // rank of a barrel layer by radius (disks: -1)
   double bz;
   int n_eta, n_phi;
 };
@@ -576,16 +577,66 @@ KFX_HD R kf_update(StateT<R>& st, const FrameT<R>& F, double mx, double my, doub
 // The update of an FP32 state carried out in FP64.  C+ = C - K H C keeps
 // the fraction V/(H C H^T + V) of the predicted variance along the measured
 // directions; at a steep crossing that ratio reaches 1e-4 or less, and the
-// FP32 subtraction would keep only a few correct digits.  K, C+ and chi2 are
-// formed in FP64 from the FP32 covariance and rounded once.
+// FP32 subtraction would keep only a few correct digits.  H C, S^-1, the
+// gain and C+ are formed in FP64 from the FP32 covariance and rounded once;
+// the gain is formed one row at a time so that it is never held whole.
 KFX_HD float kf_update_fp64(State& st, const Layer& Ld, double mx, double my, double mz) {
-  StateT<double> sd;
-  convert_state(st, sd);
-  FrameT<double> F;
-  make_frame(sd, Ld, F);
-  const double c2 = kf_update(sd, F, mx, my, mz);
-  convert_state(sd, st);
-  return (float)c2;
+  const double r = sqrt(st.x * st.x + st.y * st.y);
+  const double c = st.x / r, s = st.y / r;
+  const bool disk = Ld.kind == kDisk;
+  // rows of H: u = (-s, c, 0); v = (0, 0, 1) or (c, s, 0); n = (c, s, 0) or (0, 0, 1)
+  double HC[3][6];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    const double cx = st.C[sidx(0, j)], cy = st.C[sidx(1, j)], cz = st.C[sidx(2, j)];
+    const double rad = c * cx + s * cy;
+    HC[0][j] = -s * cx + c * cy;
+    HC[1][j] = disk ? rad : cz;
+    HC[2][j] = disk ? cz : rad;
+  }
+  // S = H C H^T + V: (H C H^T)[a][b] = HC[a] . h_b
+  const double S00 = -s * HC[0][0] + c * HC[0][1] + (double)Ld.v_u;
+  const double S10 = -s * HC[1][0] + c * HC[1][1];
+  const double S20 = -s * HC[2][0] + c * HC[2][1];
+  const double S11 = (disk ? c * HC[1][0] + s * HC[1][1] : HC[1][2]) + (double)Ld.v_v;
+  const double S21 = disk ? c * HC[2][0] + s * HC[2][1] : HC[2][2];
+  const double S22 = (disk ? HC[2][2] : c * HC[2][0] + s * HC[2][1]) + (double)Ld.v_n;
+  const double c00 = S11 * S22 - S21 * S21;
+  const double c01 = S21 * S20 - S10 * S22;
+  const double c02 = S10 * S21 - S11 * S20;
+  const double id = 1.0 / (S00 * c00 + S10 * c01 + S20 * c02);
+  const double Si00 = c00 * id, Si10 = c01 * id, Si20 = c02 * id;
+  const double Si11 = (S00 * S22 - S20 * S20) * id;
+  const double Si21 = (S10 * S20 - S00 * S21) * id;
+  const double Si22 = (S00 * S11 - S10 * S10) * id;
+  // residual
+  const double dx = mx - st.x, dy = my - st.y, dz = mz - st.z;
+  const double ru = -s * dx + c * dy;
+  const double rrad = c * dx + s * dy;
+  const double rv = disk ? rrad : dz, rn = disk ? dz : rrad;
+  const double w0 = Si00 * ru + Si10 * rv + Si20 * rn;
+  const double w1 = Si10 * ru + Si11 * rv + Si21 * rn;
+  const double w2 = Si20 * ru + Si21 * rv + Si22 * rn;
+  const double chi2 = ru * w0 + rv * w1 + rn * w2;
+  // K[i] = HC[.][i]^T S^-1; p_i += K[i] . r; C[i][j] -= K[i] . HC[.][j]
+  double dp[6];
+#pragma unroll
+  for (int i = 5; i >= 0; --i) {
+    const double k0 = HC[0][i] * Si00 + HC[1][i] * Si10 + HC[2][i] * Si20;
+    const double k1 = HC[0][i] * Si10 + HC[1][i] * Si11 + HC[2][i] * Si21;
+    const double k2 = HC[0][i] * Si20 + HC[1][i] * Si21 + HC[2][i] * Si22;
+    dp[i] = k0 * ru + k1 * rv + k2 * rn;
+#pragma unroll
+    for (int j = 0; j <= i; ++j)
+      st.C[sidx(i, j)] = (float)((double)st.C[sidx(i, j)] - (k0 * HC[0][j] + k1 * HC[1][j] + k2 * HC[2][j]));
+  }
+  st.x += dp[0];
+  st.y += dp[1];
+  st.z += dp[2];
+  st.k += dp[3];
+  st.phi = wrap_pi(st.phi + dp[4]);
+  st.th += dp[5];
+  return (float)chi2;
 }
 
 // Prior covariance of the start estimate: diagonal (sigma_pos^2 x3,

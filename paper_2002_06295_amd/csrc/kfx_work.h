@@ -147,31 +147,54 @@ KFX_HD uint64_t child_key(int nhits, int nholes, float chi2, int parent, int ran
 constexpr int kHole = -1;
 constexpr int kStop = -2;
 
-// Sorted best-K list of (chi2, hit) of one candidate's compatible hits.
+// Sorted best-K list of (chi2, hit) of one candidate's compatible hits,
+// held in registers: KM is the compile-time capacity, K <= KM the runtime
+// cap; insert and pop are unrolled over KM so that no element is ever
+// indexed by a runtime value (which would put the list in scratch memory).
+template <int KM>
 struct BestK {
-  float c[kMaxK];
-  int h[kMaxK];
+  float c[KM];
+  int h[KM];
   int n;
 };
 
-KFX_HD void bestk_init(BestK& b) { b.n = 0; }
+template <int KM>
+KFX_HD void bestk_init(BestK<KM>& b) { b.n = 0; }
 
-// insert keeping ascending (chi2, hit); K is the runtime cap (<= kMaxK)
-KFX_HD void bestk_insert(BestK& b, int K, float c, int h) {
-  int n = b.n;
-  if (n == K) {
-    if (c > b.c[K - 1] || (c == b.c[K - 1] && h > b.h[K - 1])) return;
-    n = K - 1;
+// insert keeping ascending (chi2, hit): walk the list carrying the element
+// to place; a smaller pair swaps with the carried one; the carried element
+// lands in the first free slot or falls off the end
+template <int KM>
+KFX_HD void bestk_insert(BestK<KM>& b, int K, float c, int h) {
+  bool carry = true;
+#pragma unroll
+  for (int i = 0; i < KM; ++i) {
+    if (i < K && carry) {
+      if (i >= b.n) {
+        b.c[i] = c;
+        b.h[i] = h;
+        carry = false;
+      } else if (c < b.c[i] || (c == b.c[i] && h < b.h[i])) {
+        const float tc = b.c[i];
+        const int th = b.h[i];
+        b.c[i] = c;
+        b.h[i] = h;
+        c = tc;
+        h = th;
+      }
+    }
   }
-  int i = n;
-  while (i > 0 && (b.c[i - 1] > c || (b.c[i - 1] == c && b.h[i - 1] > h))) {
-    b.c[i] = b.c[i - 1];
-    b.h[i] = b.h[i - 1];
-    --i;
+  b.n = b.n < K ? b.n + 1 : K;
+}
+
+template <int KM>
+KFX_HD void bestk_pop(BestK<KM>& b) {
+#pragma unroll
+  for (int i = 0; i + 1 < KM; ++i) {
+    b.c[i] = b.c[i + 1];
+    b.h[i] = b.h[i + 1];
   }
-  b.c[i] = c;
-  b.h[i] = h;
-  b.n = n + 1;
+  b.n -= 1;
 }
 
 // ---- SoA state access ---------------------------------------------------
@@ -226,19 +249,31 @@ KFX_HD long bin_key(const BinIndex& B, int ev, int layer, int bin) {
 }
 
 // Scan the window's bins and keep the best K compatible hits (chi2 < cut).
+// The phi bins of one eta row are adjacent in the index, so each row is one
+// contiguous range of sorted hits (two when the window wraps at phi = pi).
 // Returns the number of compatible hits found (all of them, not only K).
+template <int KM>
 KFX_HD int scan_window(const Geometry& G, const BinIndex& B, int ev, int layer, const State& pr,
-                       const Frame& F, float cut, int K, BestK& best) {
+                       const Frame& F, float cut, int K, BestK<KM>& best) {
   const Layer& Lr = G.L[layer];
   const Window w = window_bins(G, Lr, pr, F, cut);
   bestk_init(best);
   int found = 0;
+  const long base = bin_key(B, ev, layer, 0);
+  const int wrap = w.pb0 + w.npb - G.n_phi;  // bins past the wrap, if > 0
   for (int eb = w.eb0; eb <= w.eb1; ++eb) {
-    for (int j = 0; j < w.npb; ++j) {
-      int pb = w.pb0 + j;
-      if (pb >= G.n_phi) pb -= G.n_phi;
-      const long key = bin_key(B, ev, layer, eb * G.n_phi + pb);
-      const int a = B.off[key], e = B.off[key + 1];
+    const long row = base + (long)eb * G.n_phi;
+    for (int seg = 0; seg < 2; ++seg) {
+      int b0, b1;  // bins [b0, b1) of this segment
+      if (seg == 0) {
+        b0 = w.pb0;
+        b1 = wrap > 0 ? G.n_phi : w.pb0 + w.npb;
+      } else {
+        if (wrap <= 0) break;
+        b0 = 0;
+        b1 = wrap;
+      }
+      const int a = B.off[row + b0], e = B.off[row + b1];
       for (int q = a; q < e; ++q) {
         const float4 hv = B.sorted[q];
         float r[3];

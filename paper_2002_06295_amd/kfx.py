@@ -29,7 +29,7 @@ MAX_STEPS = 40
 
 EXPORTED = ["kfx_create", "kfx_destroy", "kfx_last_error", "kfx_load_layers", "kfx_bin_hits",
             "kfx_seed_states", "kfx_step_compat", "kfx_build_tracks", "kfx_fit_tracks",
-            "kfx_enable_timing", "kfx_build_times"]
+            "kfx_fit_tracks_backward", "kfx_enable_timing", "kfx_build_times"]
 
 
 class c_states(ctypes.Structure):
@@ -98,6 +98,11 @@ def load_library():
                                    ctypes.c_void_p, ctypes.c_float, ctypes.POINTER(c_states),
                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                    ctypes.POINTER(c_states), ctypes.c_void_p]
+    lib.kfx_fit_tracks_backward.argtypes = [ctypes.c_void_p, ctypes.POINTER(c_hits), ctypes.c_void_p,
+                                            ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(c_prior),
+                                            ctypes.c_void_p, ctypes.c_float, ctypes.POINTER(c_states),
+                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
     lib.kfx_enable_timing.argtypes = [ctypes.c_void_p, ctypes.c_int]
     lib.kfx_build_times.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
     for name in EXPORTED:
@@ -362,3 +367,36 @@ class Context:
                                             _ptr(out["chi2"]), _ptr(out["ndof"]), _ptr(out["status"]),
                                             ctypes.byref(ck) if ck is not None else None, self._stream()))
         return out
+
+    def fit_tracks_backward(self, hits: DeviceHits, trk_off, trk_hits, fit_out, dchi2,
+                            prior=(0.1, 0.5, 0.05, 0.05), align=None, field_scale=1.0):
+        """Gradient of sum_t dchi2[t] chi2_t (dchi2: a device float32 tensor of
+        one element or of n_tracks) with respect to the alignment and the
+        field scale, for the fit that wrote fit_out (made with ckpt=True and
+        the same inputs).  Returns float64 device tensors (dalign [3 L],
+        dfield [1])."""
+        import torch
+        d = self.device
+        if "ckpt" not in fit_out:
+            raise KfxError("fit_tracks_backward needs a fit made with ckpt=True")
+        if not isinstance(trk_off, torch.Tensor):
+            trk_off = torch.as_tensor(np.ascontiguousarray(trk_off, dtype=np.int32), device=d)
+        if not isinstance(trk_hits, torch.Tensor):
+            trk_hits = torch.as_tensor(np.ascontiguousarray(trk_hits, dtype=np.int32), device=d)
+        if align is not None and not isinstance(align, torch.Tensor):
+            align = torch.as_tensor(np.ascontiguousarray(align, dtype=np.float32).reshape(-1), device=d)
+        T = int(trk_off.shape[0] - 1)
+        dchi2 = dchi2.to(device=d, dtype=torch.float32).contiguous().reshape(-1)
+        per_track = 1 if dchi2.numel() > 1 else 0
+        if per_track and dchi2.numel() != T:
+            raise KfxError(f"dchi2 has {dchi2.numel()} entries for {T} tracks")
+        n_layers = self.n_layers
+        dalign = torch.empty(3 * n_layers, dtype=torch.float64, device=d)
+        dfield = torch.empty(1, dtype=torch.float64, device=d)
+        pr = prior_struct(prior)
+        ck = fit_out["ckpt"].c()
+        self._check(self.lib.kfx_fit_tracks_backward(
+            self.h, ctypes.byref(hits.struct), _ptr(trk_off), _ptr(trk_hits), T, ctypes.byref(pr), _ptr(align),
+            float(field_scale), ctypes.byref(ck), _ptr(fit_out["status"]), _ptr(dchi2), per_track, _ptr(dalign),
+            _ptr(dfield), self._stream()))
+        return dalign, dfield

@@ -125,3 +125,48 @@ extern "C" double hs_path_cylinder(const double* p, double bz, double Rc) {
   const double cphi = cos(st.phi), sphi = sin(st.phi);
   return path_to_cylinder(st, cphi, sphi, -kHcD * bz * st.k, Rc);
 }
+
+#include "../../paper_2002_06295_amd/csrc/kfx_adjoint.h"
+
+namespace {
+struct HostAcc {
+  double* g;
+  int nl;
+  KFX_HD void add(int l, int c, double v) { g[3 * l + c] += v; }
+  KFX_HD void field(double v) { g[3 * nl] += v; }
+};
+}  // namespace
+
+extern "C" {
+
+// forward fit with checkpoints, then the reverse sweep of every track that
+// fitted; grad[3 nl + 1] = d(sum_t w_t chi2_t)/d(align, fscale)
+double hs_fit_grad(const double* table, int nl, double bz, const float* x, const float* y, const float* z,
+                   const int* layer, int nhits, const int* trk_off, const int* trk_hits, int nt,
+                   const float* prior, const float* align, float fscale, const double* w, double* grad) {
+  Geometry G = make_geo(table, nl, bz);
+  HitsView H{x, y, z, layer, nullptr, nhits, 1};
+  Prior pr{prior[0], prior[1], prior[2], prior[3]};
+  const long ns = trk_off[nt];
+  std::vector<double> par(6 * (size_t)nt), cpar(6 * (size_t)ns);
+  std::vector<float> cov(21 * (size_t)nt), ccov(21 * (size_t)ns), c2(nt);
+  std::vector<int> ndof(nt), status(nt);
+  FitOut o;
+  o.state = StateSoA{par.data(), cov.data(), nt};
+  o.chi2 = c2.data();
+  o.ndof = ndof.data();
+  o.status = status.data();
+  o.ckpt = StateSoA{cpar.data(), ccov.data(), ns};
+  for (int i = 0; i < 3 * nl + 1; ++i) grad[i] = 0.0;
+  HostAcc acc{grad, nl};
+  double tot = 0.0;
+  for (int t = 0; t < nt; ++t) {
+    fit_track(G, H, trk_off, trk_hits, t, pr, align, fscale, o);
+    if (status[t] != 1) continue;
+    tot += c2[t];
+    fit_track_backward(G, H, trk_off, trk_hits, t, pr, align, fscale, o.ckpt, w ? w[t] : 1.0, acc);
+  }
+  return tot;
+}
+
+}  // extern "C"
