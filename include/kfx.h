@@ -102,6 +102,12 @@ typedef struct {
   int32_t block_threads; /* fused: threads per block, 64..256, multiple of 64;
                             0 = library choice                                */
   int32_t blocks;        /* fused: persistent blocks; 0 = library choice      */
+  int32_t lanes_per_seed;/* fused: lanes of the group that holds one seed's
+                            candidates (one lane per slot): 4, 8 or 16, at
+                            least K; 0 = the smallest that fits K            */
+  int32_t scan_tile;     /* fused: windows holding more hits than this are
+                            scanned by the whole wavefront together; smaller
+                            ones by their own lane; 0 = 64                    */
 } kfx_build_params;
 
 /* Output of building, per seed s and slot j < K, best first (device). */

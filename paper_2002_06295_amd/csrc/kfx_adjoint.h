@@ -167,13 +167,13 @@ KFX_HD bool tape_step(StepTape& T, const StateT<double>& st0, const Layer& Ld, d
   T.R = T.disk ? (double)Ld.pos : R;
   T.kappa = kappa;
   T.omega = kappa * st0.k;
-  const double cphi = cos(st0.phi), sphi = sin(st0.phi);
+  double cphi, sphi;
+  sincos_d(st0.phi, sphi, cphi);
   T.s = path_to_layer(st0, Ld, R, cphi, sphi, T.omega);
   if (!(T.s > 0.0)) return false;
   const double s = T.s;
   T.a = 0.5 * T.omega * s;
-  T.sa = sin(T.a);
-  T.ca = cos(T.a);
+  sincos_d(T.a, T.sa, T.ca);
   sinc_dd(T.a, T.sa, T.ca, T.f, T.f1, T.f2);
   T.cpsi = cphi * T.ca - sphi * T.sa;
   T.spsi = sphi * T.ca + cphi * T.sa;
@@ -185,8 +185,7 @@ KFX_HD bool tape_step(StepTape& T, const StateT<double>& st0, const Layer& Ld, d
   T.Dy = hs2 * (T.f1 * T.spsi + T.f * T.cpsi);
   T.c1 = T.cpsi * T.ca - T.spsi * T.sa;
   T.s1 = T.spsi * T.ca + T.cpsi * T.sa;
-  T.sth = sin(st0.th);
-  T.cth = cos(st0.th);
+  sincos_d(st0.th, T.sth, T.cth);
   const double cot = T.cth / T.sth;
   T.x1 = st0.x + T.dx;
   T.y1 = st0.y + T.dy;

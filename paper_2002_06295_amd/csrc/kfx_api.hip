@@ -361,6 +361,10 @@ int kfx_build_tracks(kfx_ctx* c, const kfx_hits* hits, const int32_t* seeds, con
   if (p->block_threads != 0 && (p->block_threads < 64 || p->block_threads > 256 || p->block_threads % 64))
     return fail(c, KFX_EINVAL, "block_threads must be 0 or a multiple of 64 in [64, 256]");
   if (p->blocks < 0) return fail(c, KFX_EINVAL, "blocks < 0");
+  if (p->scan_tile < 0) return fail(c, KFX_EINVAL, "scan_tile < 0");
+  if (p->lanes_per_seed != 0 && ((p->lanes_per_seed != 4 && p->lanes_per_seed != 8 && p->lanes_per_seed != 16) ||
+                                 p->lanes_per_seed < p->max_cands))
+    return fail(c, KFX_EINVAL, "lanes_per_seed must be 0, or 4, 8 or 16 and at least max_cands");
   const int K = p->max_cands;
   const long SK = (long)n_seeds * K;
   if (out->capacity < SK) {
@@ -403,6 +407,7 @@ int kfx_build_tracks(kfx_ctx* c, const kfx_hits* hits, const int32_t* seeds, con
   a.K = K;
   a.max_holes = p->max_holes;
   a.max_steps = p->max_steps;
+  a.coop_min = p->scan_tile ? p->scan_tile : 64;
   const long N = std::max<long>(SK, 1);
   auto alloc_states = [&](const char* name, StateSoA& s) -> int {
     char* base = (char*)ws(c, name, (size_t)N * (6 * 8 + 21 * 4), st, rc);
@@ -455,10 +460,11 @@ int kfx_build_tracks(kfx_ctx* c, const kfx_hits* hits, const int32_t* seeds, con
       blocks = prop.multiProcessorCount * 4;
     }
     // no more groups than seeds need
-    const int groups_per_block = threads / fused_lanes_for(K) ;
+    const int lanes = p->lanes_per_seed ? p->lanes_per_seed : fused_lanes_for(K);
+    const int groups_per_block = threads / lanes;
     const long max_blocks = (n_seeds + groups_per_block - 1) / groups_per_block;
     blocks = (int)std::max<long>(1, std::min<long>(blocks, max_blocks));
-    launch_build_fused(a, o, counter, blocks, threads, st);
+    launch_build_fused(a, o, counter, blocks, threads, lanes, st);
   }
   if ((rc = hip_check(c, hipGetLastError(), "build kernels"))) return rc;
   return close_timing();

@@ -25,6 +25,7 @@ struct BuildArgs {
   int K;
   int max_holes;
   int max_steps;
+  int coop_min;           // fused: window size scanned by the whole wave
   // candidate slots (S K), two buffers used in turn
   StateSoA cand[2];
   int* layer[2];
@@ -90,7 +91,8 @@ KFX_HD int predict_slot(const BuildArgs& a, int cur, long slot) {
   const Geometry& G = *a.G;
   State st, pr;
   load_state(a.cand[cur], slot, st);
-  const double cphi = cos(st.phi), sphi = sin(st.phi);
+  double cphi, sphi;
+  sincos_d(st.phi, sphi, cphi);
   const double kappa = -kHcD * G.bz;
   double s = 0.0;
   const int nl = navigate(G, a.layer[cur][slot], st, cphi, sphi, kappa * st.k, s);

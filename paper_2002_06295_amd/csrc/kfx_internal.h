@@ -40,7 +40,7 @@ void launch_step_compat(const Geometry* G, const HitsView& H, const BinIndex& B,
                         hipStream_t st);
 void launch_build_plain(const BuildArgs& a, const TracksOut& o, hipStream_t st);
 void launch_build_fused(const BuildArgs& a, const TracksOut& o, int* seed_counter, int blocks, int threads,
-                        hipStream_t st);
+                        int lanes, hipStream_t st);
 int fused_lanes_for(int K);
 
 }  // namespace kfx

@@ -272,7 +272,8 @@ __global__ void k_step_compat(const Geometry* __restrict__ G, HitsView H, BinInd
   if (i >= n) return;
   State st, pr;
   load_state(in, i, st);
-  const double cphi = cos(st.phi), sphi = sin(st.phi);
+  double cphi, sphi;
+  sincos_d(st.phi, sphi, cphi);
   const double kappa = -kHcD * G->bz;
   double s = 0.0;
   const int cl = cand_layer[i], ce = cand_event[i];
@@ -288,37 +289,39 @@ __global__ void k_step_compat(const Geometry* __restrict__ G, HitsView H, BinInd
   Frame F;
   make_frame(pr, G->L[nl], F);
   const Window w = window_bins(*G, G->L[nl], pr, F, cut);
+  const ScanWin sw = scan_win(*G, B, ce, nl, w);
+  PairFrame P;
+  pair_frame(pr, F, G->L[nl].kind == kDisk, P);
   int cnt = 0;
   int* oh = pair_hit + (long)i * max_pairs;
   float* oc = pair_chi2 + (long)i * max_pairs;
-  for (int eb = w.eb0; eb <= w.eb1; ++eb)
-    for (int j = 0; j < w.npb; ++j) {
-      int pb = w.pb0 + j;
-      if (pb >= G->n_phi) pb -= G->n_phi;
-      const long key = bin_key(B, ce, nl, eb * G->n_phi + pb);
-      for (int q = B.off[key]; q < B.off[key + 1]; ++q) {
-        const float4 hv = B.sorted[q];
-        float r[3];
-        residual(pr, F, (double)hv.x, (double)hv.y, (double)hv.z, r);
-        const float c2 = chi2_of(F, r);
-        if (c2 < cut) {
-          int hid;
-          __builtin_memcpy(&hid, &hv.w, 4);
-          if (cnt < max_pairs) {
-            // insertion by hit index
-            int k = cnt;
-            while (k > 0 && oh[k - 1] > hid) {
-              oh[k] = oh[k - 1];
-              oc[k] = oc[k - 1];
-              --k;
-            }
-            oh[k] = hid;
-            oc[k] = c2;
+  const int nr = scan_nranges(sw);
+  for (int r = 0; r < nr; ++r) {
+    int qa, qe;
+    scan_range(sw, B, G->n_phi, r, qa, qe);
+    for (int q = qa; q < qe; ++q) {
+      const float4 hv = B.sorted[q];
+      const float c2 = kfx::pair_chi2(P, hv);
+      if (c2 < cut) {
+        int hid;
+        __builtin_memcpy(&hid, &hv.w, 4);
+        // keep the max_pairs smallest hit indices, ascending
+        int k = cnt < max_pairs ? cnt : max_pairs;
+        if (k == max_pairs && (k == 0 || oh[k - 1] < hid)) k = -1;
+        if (k >= 0) {
+          if (k == max_pairs) --k;  // the largest kept one drops out
+          while (k > 0 && oh[k - 1] > hid) {
+            oh[k] = oh[k - 1];
+            oc[k] = oc[k - 1];
+            --k;
           }
-          ++cnt;
+          oh[k] = hid;
+          oc[k] = c2;
         }
+        ++cnt;
       }
     }
+  }
   pair_count[i] = cnt;
 }
 
@@ -394,6 +397,9 @@ struct FusedShared {
   int layer;
   int meta;
   float chi2;
+  // the child picked for this slot by the selection (written by the winner)
+  int sel_code;
+  float sel_chi2;
 };
 
 __device__ inline void lds_put(FusedShared& d, const State& s, int layer, int meta, float chi2) {
@@ -409,6 +415,188 @@ __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// ---- window scan of a wavefront -----------------------------------------
+// The windows of one step differ wildly in size: a candidate that crosses a
+// layer almost tangentially can cover the whole layer, and a lane-private
+// scan would leave the wave waiting on its largest window.  Each lane first
+// counts the hits of its window.  Windows of at most `coop_min` hits are
+// scanned by their own lane.  The larger ones are flattened: per batch of up
+// to kCoopR ranges per lane, a prefix sum over the lanes of their hit counts
+// gives every hit a flat index, and the 64 lanes walk the flat list
+// together, each finding the owner of its hit by binary search.  A worker
+// keeps a pair only if its chi2 is below the cut and it would enter the
+// owner's best-K list as published at the start of the chunk; the owner then
+// inserts the kept pairs of its stretch of lanes and counts every pair under
+// the cut from a ballot.  The best-K set (ordered by chi2, then hit index)
+// and the count do not depend on the order of insertion, so the result is
+// the lane-private scan's.
+constexpr int kCoopR = 8;
+
+struct CoopShared {
+  PairFrame pf[64];
+  int pre[64];            // exclusive prefix over the lanes of this batch's hits
+  int nrb[64];            // ranges of each lane in this batch
+  int ra[64][kCoopR];     // range starts
+  int rc[64][kCoopR];     // exclusive prefix of the range lengths in the lane
+  float tc[64];           // owner's admission threshold: (chi2, hit) of its
+  int th[64];             // K-th entry, or (inf, max) while the list is short
+  float w_c2[64];         // a worker's kept pair, by lane
+  int w_hit[64];
+};
+
+template <int KM>
+__device__ void publish_threshold(CoopShared& cs, int lane, const BestK<KM>& best, int K) {
+  float c = __builtin_inff();
+  int h = 0x7fffffff;
+#pragma unroll
+  for (int i = 0; i < KM; ++i)
+    if (i == K - 1 && best.n == K) {
+      c = best.c[i];
+      h = best.h[i];
+    }
+  cs.tc[lane] = c;
+  cs.th[lane] = h;
+}
+
+template <int KM>
+__device__ int wave_scan(const BinIndex& B, int n_phi, CoopShared& cs, int lane, bool has, const ScanWin& sw,
+                         const PairFrame& pf, float cut, int K, int coop_min, BestK<KM>& best) {
+  bestk_init(best);
+  int found = 0;
+  const int nr = has ? scan_nranges(sw) : 0;
+  int total_mine = 0;
+  for (int r = 0; r < nr; ++r) {
+    int qa, qe;
+    scan_range(sw, B, n_phi, r, qa, qe);
+    total_mine += qe - qa;
+  }
+  const bool big = total_mine > coop_min;
+  // lane-private scan of the small windows
+  if (has && !big) {
+    for (int r = 0; r < nr; ++r) {
+      int qa, qe;
+      scan_range(sw, B, n_phi, r, qa, qe);
+      for (int q = qa; q < qe; ++q) {
+        const float4 hv = B.sorted[q];
+        const float c2 = pair_chi2(pf, hv);
+        if (c2 < cut) {
+          int hid;
+          __builtin_memcpy(&hid, &hv.w, 4);
+          ++found;
+          bestk_insert(best, K, c2, hid);
+        }
+      }
+    }
+  }
+  if (__ballot(big) == 0) return found;
+  // cooperative scan of the large windows
+  if (big) cs.pf[lane] = pf;
+  const int nrc = big ? nr : 0;
+  for (int rb = 0;; rb += kCoopR) {
+    if (__ballot(rb < nrc) == 0) break;
+    const int nb = nrc - rb <= 0 ? 0 : (nrc - rb < kCoopR ? nrc - rb : kCoopR);
+    int cnt = 0;
+    for (int i = 0; i < nb; ++i) {
+      int qa, qe;
+      scan_range(sw, B, n_phi, rb + i, qa, qe);
+      cs.ra[lane][i] = qa;
+      cs.rc[lane][i] = cnt;
+      cnt += qe - qa;
+    }
+    cs.nrb[lane] = nb;
+    int incl = cnt;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int v = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += v;
+    }
+    const int total = __shfl(incl, 63, 64);
+    const int pre = incl - cnt;
+    cs.pre[lane] = pre;
+    if (big) publish_threshold(cs, lane, best, K);
+    wave_sync();
+    for (int base = 0; base < total; base += 64) {
+      const int j = base + lane;
+      bool under = false, keep = false;
+      if (j < total) {
+        // owner: the last lane whose prefix is <= j (it has hits: j < total)
+        int lo = 0, hi = 63;
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (cs.pre[mid] <= j) lo = mid;
+          else hi = mid - 1;
+        }
+        const int owner = lo;
+        const int k = j - cs.pre[owner];
+        int ri = cs.nrb[owner] - 1;
+        while (ri > 0 && cs.rc[owner][ri] > k) --ri;
+        const float4 hv = B.sorted[cs.ra[owner][ri] + (k - cs.rc[owner][ri])];
+        const float c2 = pair_chi2(cs.pf[owner], hv);
+        int hid;
+        __builtin_memcpy(&hid, &hv.w, 4);
+        under = c2 < cut;
+        const float tc = cs.tc[owner];
+        keep = under && (c2 < tc || (c2 == tc && hid < cs.th[owner]));
+        if (keep) {
+          cs.w_c2[lane] = c2;
+          cs.w_hit[lane] = hid;
+        }
+      }
+      const unsigned long long m_under = __ballot(under);
+      const unsigned long long m_keep = __ballot(keep);
+      if (m_under) {
+        // this owner's stretch of the chunk: flat [pre, pre + cnt) within
+        // [base, base + 64)
+        unsigned long long mine = 0;
+        if (cnt > 0 && pre < base + 64 && pre + cnt > base) {
+          const int f = pre > base ? pre - base : 0;
+          const int l = pre + cnt - base < 64 ? pre + cnt - base : 64;  // exclusive
+          const unsigned long long hi_mask = l == 64 ? ~0ull : ((1ull << l) - 1ull);
+          mine = hi_mask & ~((1ull << f) - 1ull);
+        }
+        found += __popcll(m_under & mine);
+        if (m_keep) {
+          wave_sync();
+          unsigned long long take = m_keep & mine;
+          while (take) {
+            const int b = __ffsll((long long)take) - 1;
+            take &= take - 1ull;
+            bestk_insert(best, K, cs.w_c2[b], cs.w_hit[b]);
+          }
+          wave_sync();
+          if (big) publish_threshold(cs, lane, best, K);
+          wave_sync();
+        }
+      }
+    }
+    wave_sync();
+  }
+  return found;
+}
+
+// Minimum of a 64-bit key over aligned groups of G lanes (G = 4, 8, 16)
+// with DPP lane moves: a mirror within the row of 16, a mirror within the
+// half row of 8, then the two quad exchanges.  Each step pairs every lane
+// with one whose partial set is disjoint from its own, so after the steps
+// every lane of a group holds the group's minimum.
+template <int CTRL>
+__device__ inline uint64_t dpp_min_step(uint64_t v) {
+  const int lo = __builtin_amdgcn_mov_dpp((int)(uint32_t)v, CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(uint32_t)(v >> 32), CTRL, 0xf, 0xf, false);
+  const uint64_t o = ((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo;
+  return o < v ? o : v;
+}
+
+template <int G>
+__device__ inline uint64_t group_min(uint64_t v) {
+  static_assert(G == 4 || G == 8 || G == 16, "group of 4, 8 or 16 lanes");
+  if (G >= 16) v = dpp_min_step<0x140>(v);  // row_mirror
+  if (G >= 8) v = dpp_min_step<0x141>(v);   // row_half_mirror
+  v = dpp_min_step<0x4E>(v);                // quad_perm [2, 3, 0, 1]
+  v = dpp_min_step<0xB1>(v);                // quad_perm [1, 0, 3, 2]
+  return v;
 }
 
 // Key of the next child of a lane's stream (see kid_key): the head of its
@@ -440,7 +628,17 @@ template <int G_LANES>
 __global__ void __launch_bounds__(256) k_build_fused(BuildArgs a, int* seed_counter) {
   extern __shared__ unsigned char smem_raw[];
   FusedShared* sh = reinterpret_cast<FusedShared*>(smem_raw);
-  const Geometry& G = *a.G;
+  CoopShared* coop = reinterpret_cast<CoopShared*>(smem_raw + sizeof(FusedShared) * blockDim.x);
+  // the layer table is read at every step with lane-dependent indices: keep
+  // a copy in LDS
+  __shared__ Geometry g_lds;
+  {
+    const int* src = reinterpret_cast<const int*>(a.G);
+    int* dst = reinterpret_cast<int*>(&g_lds);
+    for (int i = threadIdx.x; i < (int)(sizeof(Geometry) / 4); i += blockDim.x) dst[i] = src[i];
+    __syncthreads();
+  }
+  const Geometry& G = g_lds;
   const int lane = threadIdx.x & 63;
   const int gl = lane & (G_LANES - 1);          // slot within the seed
   const int gbase = threadIdx.x & ~(G_LANES - 1);
@@ -498,7 +696,8 @@ __global__ void __launch_bounds__(256) k_build_fused(BuildArgs a, int* seed_coun
       if (meta_flags(meta) & kFlagDone) {
         nl = -1;
       } else {
-        const double cphi = cos(st.phi), sphi = sin(st.phi);
+        double cphi, sphi;
+        sincos_d(st.phi, sphi, cphi);
         double s = 0.0;
         nl = navigate(G, layer, st, cphi, sphi, kappa * st.k, s);
         if (nl >= 0) {
@@ -510,11 +709,18 @@ __global__ void __launch_bounds__(256) k_build_fused(BuildArgs a, int* seed_coun
     lds_put(me, st, layer, meta, chi2);
     // ---- (b) window scan, best K hit children in registers
     BestK<G_LANES> best;
-    best.n = 0;
-    if (nl >= 0) {
-      Frame F;
-      make_frame(pr, G.L[nl], F);
-      n_pairs += (unsigned long long)scan_window(G, a.B, a.seed_event[seed], nl, pr, F, a.cut, K, best);
+    {
+      ScanWin sw;
+      PairFrame pf;
+      if (nl >= 0) {
+        Frame F;
+        const Layer& Ln = G.L[nl];
+        make_frame(pr, Ln, F);
+        sw = scan_win(G, a.B, a.seed_event[seed], nl, window_bins(G, Ln, pr, F, a.cut));
+        pair_frame(pr, F, Ln.kind == kDisk, pf);
+      }
+      n_pairs += (unsigned long long)wave_scan(a.B, G.n_phi, coop[threadIdx.x >> 6], lane, nl >= 0, sw, pf,
+                                               a.cut, K, a.coop_min, best);
     }
     const KidStream ks = kid_stream(a, live ? meta : 0, chi2, nl, best.n, gl);
     if (nl >= 0 && !ks.stop) lds_put(me, pr, nl, meta, chi2);
@@ -528,24 +734,15 @@ __global__ void __launch_bounds__(256) k_build_fused(BuildArgs a, int* seed_coun
     int my_parent = -1, my_code = kStop;
     float my_chi2 = 0.0f;
     for (int i = 0; i < K; ++i) {
-      uint64_t m = head;
-#pragma unroll
-      for (int off = G_LANES / 2; off >= 1; off >>= 1) {
-        const uint64_t o2 = __shfl_xor(m, off, 64);
-        m = o2 < m ? o2 : m;
-      }
+      const uint64_t m = group_min<G_LANES>(head);
       const unsigned long long win = __ballot(head == m && m != ~0ull) & gmask;
-      // winner lane in the wave (unique: keys differ by parent slot); a
-      // group with no child left reads its own first lane and ignores it
-      const int wl = win ? __ffsll((long long)win) - 1 : (lane & ~(G_LANES - 1));
-      const int wcode = __shfl(hcode, wl, 64);
-      const float wchi2 = __shfl(hc, wl, 64);
-      if (win && gl == i) {
-        my_parent = wl & (G_LANES - 1);
-        my_code = wcode;
-        my_chi2 = wchi2;
-      }
+      // winner lane in the wave (unique: keys differ by parent slot); it
+      // hands its child to the lane of new slot i through LDS
+      const int wl = win ? __ffsll((long long)win) - 1 : 0;
+      if (win && gl == i) my_parent = wl & (G_LANES - 1);
       if (win && lane == wl) {
+        sh[gbase + i].sel_code = hcode;
+        sh[gbase + i].sel_chi2 = hc;
         if (hcode >= 0) bestk_pop(best);
         else if (hcode == kHole) hole_used = true;
         ++popped;
@@ -553,6 +750,10 @@ __global__ void __launch_bounds__(256) k_build_fused(BuildArgs a, int* seed_coun
       }
     }
     wave_sync();
+    if (my_parent >= 0) {
+      my_code = me.sel_code;
+      my_chi2 = me.sel_chi2;
+    }
     // ---- (d) children: copy the parent's state from LDS, update hit children
     int new_meta = 0, new_layer = -1;
     if (active && gl < K) {
@@ -696,22 +897,21 @@ void launch_build_plain(const BuildArgs& a, const TracksOut& o, hipStream_t st) 
 }
 
 int fused_lanes_for(int K) {
-  int g = 1;
+  int g = 4;
   while (g < K) g <<= 1;
   return g;
 }
 
 void launch_build_fused(const BuildArgs& a, const TracksOut& o, int* seed_counter, int blocks, int threads,
-                        hipStream_t st) {
+                        int lanes, hipStream_t st) {
   if (a.n_seeds <= 0) return;
   launch_fill(seed_counter, 1, 0, st);
   // start states (FP64 seed phase) in their own kernel, so that its FP64
   // temporaries do not set the register budget of the persistent kernel
   hipLaunchKernelGGL(k_build_init, dim3(nblk(a.n_seeds, 128)), dim3(128), 0, st, a);
-  const size_t shmem = sizeof(FusedShared) * threads;
-  const int g = fused_lanes_for(a.K);
-  switch (g) {
-    case 1: case 2: case 4:
+  const size_t shmem = sizeof(FusedShared) * threads + sizeof(CoopShared) * (threads / 64);
+  switch (lanes) {
+    case 4:
       hipLaunchKernelGGL(k_build_fused<4>, dim3(blocks), dim3(threads), shmem, st, a, seed_counter);
       break;
     case 8:

@@ -96,6 +96,50 @@ KFX_HD double mmax(double a, double b) { return fmax(a, b); }
 // apart; the FP64 steps that follow finish the convergence)
 template <class R> KFX_HD constexpr R newton_tol() { return sizeof(R) == 4 ? (R)2e-6 : (R)1e-13; }
 
+// sin and cos of an FP64 angle of moderate size (the azimuth, the polar
+// angle and the turning angle of a step are all below 8 in magnitude).
+// Cody-Waite reduction by pi/2 with a two-part constant (fma keeps
+// x - q pi/2_hi exact to one rounding; |q| <= 5), then the Taylor series of
+// sin and cos on [-pi/4, pi/4] to the terms r^17 and r^16, whose truncation
+// error (< 1e-17) is below FP64 rounding.  Larger or non-finite arguments
+// take the library functions.
+KFX_HD void sincos_d(double x, double& s, double& c) {
+  if (!(fabs(x) <= 8.0)) {
+    s = sin(x);
+    c = cos(x);
+    return;
+  }
+  constexpr double kPio2Hi = 1.5707963267948966;      // nearest double to pi/2
+  constexpr double kPio2Lo = 6.123233995736766e-17;   // pi/2 - kPio2Hi
+  constexpr double k2Opi = 0.6366197723675814;        // 2/pi
+  const double q = rint(x * k2Opi);
+  const double r = fma(-q, kPio2Lo, fma(-q, kPio2Hi, x));
+  const double r2 = r * r;
+  // sin r = r (1 - r^2/3! + r^4/5! - ... + r^16/17!)
+  double ps = 1.0 / 355687428096000.0;                // 1/17!
+  ps = fma(ps, r2, -1.0 / 1307674368000.0);           // 1/15!
+  ps = fma(ps, r2, 1.0 / 6227020800.0);               // 1/13!
+  ps = fma(ps, r2, -1.0 / 39916800.0);                // 1/11!
+  ps = fma(ps, r2, 1.0 / 362880.0);                   // 1/9!
+  ps = fma(ps, r2, -1.0 / 5040.0);                    // 1/7!
+  ps = fma(ps, r2, 1.0 / 120.0);                      // 1/5!
+  ps = fma(ps, r2, -1.0 / 6.0);                       // 1/3!
+  const double sr = fma(ps * r2, r, r);
+  // cos r = 1 - r^2/2! + r^4/4! - ... + r^16/16!
+  double pc = 1.0 / 20922789888000.0;                 // 1/16!
+  pc = fma(pc, r2, -1.0 / 87178291200.0);             // 1/14!
+  pc = fma(pc, r2, 1.0 / 479001600.0);                // 1/12!
+  pc = fma(pc, r2, -1.0 / 3628800.0);                 // 1/10!
+  pc = fma(pc, r2, 1.0 / 40320.0);                    // 1/8!
+  pc = fma(pc, r2, -1.0 / 720.0);                     // 1/6!
+  pc = fma(pc, r2, 1.0 / 24.0);                       // 1/4!
+  pc = fma(pc, r2, -0.5);                             // 1/2!
+  const double cr = fma(pc, r2, 1.0);
+  const int qi = ((int)q) & 3;
+  s = qi == 0 ? sr : (qi == 1 ? cr : (qi == 2 ? -sr : -cr));
+  c = qi == 0 ? cr : (qi == 1 ? -sr : (qi == 2 ? -cr : sr));
+}
+
 KFX_HD double wrap_pi(double a) {  // to (-pi, pi]
   if (a > kPi) a -= 2.0 * kPi;
   if (a <= -kPi) a += 2.0 * kPi;
@@ -158,8 +202,7 @@ struct ChordD {
 KFX_HD ChordD chord_d(double s, double omega, double cphi, double sphi) {
   ChordD c;
   c.a = 0.5 * omega * s;
-  c.sa = sin(c.a);
-  c.ca = cos(c.a);
+  sincos_d(c.a, c.sa, c.ca);
   double sinc;
   if (fabs(c.a) < 1e-4) {
     const double a2 = c.a * c.a;
@@ -246,11 +289,17 @@ KFX_HD double path_to_cylinder(const StateT<R>& st, double cphi, double sphi, do
 
 // Plane z = Z: s = (Z - z0) tan(theta), ahead of the track (FP64).
 template <class R>
-KFX_HD double path_to_disk(const StateT<R>& st, double Z) {
-  const double sth = sin(st.th), cth = cos(st.th);
+KFX_HD double path_to_disk(const StateT<R>& st, double Z, double sth, double cth) {
   if (fabs(cth) < 1e-12) return -1.0;
   const double s = (Z - st.z) * (sth / cth);
   return s > 1e-12 ? s : -1.0;
+}
+
+template <class R>
+KFX_HD double path_to_disk(const StateT<R>& st, double Z) {
+  double sth, cth;
+  sincos_d(st.th, sth, cth);
+  return path_to_disk(st, Z, sth, cth);
 }
 
 // Path to the surface of a layer (barrel radius r_surf, possibly aligned).
@@ -274,6 +323,8 @@ KFX_HD int navigate(const Geometry& G, int cur, const State& st, double cphi, do
   if (!isfinite(st.x) || !isfinite(st.y) || !isfinite(st.z) || !isfinite(st.phi) || !isfinite(st.th) ||
       !isfinite(st.k) || !isfinite(omega_d))
     return -1;
+  double sth, cth;
+  sincos_d(st.th, sth, cth);
   const Layer& Lc = G.L[cur];
   if (Lc.kind == kBarrel) {
     nb = G.next_barrel[cur];
@@ -288,14 +339,13 @@ KFX_HD int navigate(const Geometry& G, int cur, const State& st, double cphi, do
   if (nb >= 0) {
     const double s = path_to_cylinder(st, cphi, sphi, omega_d, G.L[nb].pos);
     if (s > 0.0) {
-      const double z = st.z + s * (cos(st.th) / sin(st.th));
+      const double z = st.z + s * (cth / sth);
       if (fabs(z) <= G.L[nb].hi) {
         best = s;
         bl = nb;
       }
     }
   }
-  const double cth = cos(st.th);
   if (fabs(cth) > 1e-12) {
     const bool fwd = cth > 0.0;
     const int n = fwd ? G.n_dpos : G.n_dneg;
@@ -305,7 +355,7 @@ KFX_HD int navigate(const Geometry& G, int cur, const State& st, double cphi, do
       if (id == cur) continue;
       const double Z = G.L[id].pos;
       if (fwd ? (Z <= st.z) : (Z >= st.z)) continue;
-      const double s = path_to_disk(st, Z);
+      const double s = path_to_disk(st, Z, sth, cth);
       if (!(s > 0.0)) continue;
       const ChordD c = chord_d(s, omega_d, cphi, sphi);
       const double x = st.x + c.dx, y = st.y + c.dy;
@@ -354,7 +404,8 @@ KFX_HD void transport(const StateT<R>& in, const Layer& Ld, double cphi, double 
                       double kappa_d, StateT<R>& out) {
   const double omega_d = kappa_d * in.k;
   const ChordD cd = chord_d(s_d, omega_d, cphi, sphi);
-  const double sth_d = sin(in.th), cth_d = cos(in.th);
+  double sth_d, cth_d;
+  sincos_d(in.th, sth_d, cth_d);
   const bool disk = Ld.kind == kDisk;
   out.x = in.x + cd.dx;
   out.y = in.y + cd.dy;
@@ -660,13 +711,16 @@ KFX_HD void prior_cov(const Prior& pr, StateT<R>& st) {
 // where there is no transport).
 template <class R>
 KFX_HD void add_material(StateT<R>& st, const Layer& Ld) {
-  const R sth = (R)sin(st.th), cth = (R)cos(st.th);
+  double sth_d, cth_d, sphi_d, cphi_d;
+  sincos_d(st.th, sth_d, cth_d);
+  sincos_d(st.phi, sphi_d, cphi_d);
+  const R sth = (R)sth_d, cth = (R)cth_d;
   R cinc;
   if (Ld.kind == kDisk) {
     cinc = mabs(cth);
   } else {
     const double r = sqrt(st.x * st.x + st.y * st.y);
-    cinc = mabs(sth * (R)((st.x * cos(st.phi) + st.y * sin(st.phi)) / r));
+    cinc = mabs(sth * (R)((st.x * cphi_d + st.y * sphi_d) / r));
   }
   add_noise(st, Ld, sth, cth, cinc);
 }

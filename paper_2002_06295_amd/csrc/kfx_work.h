@@ -71,8 +71,9 @@ KFX_HD Window window_bins(const Geometry& G, const Layer& Lr, const State& pr, c
   const float wu = sqrtf(cut * F.S[0]) * infl + 1e-5f;
   const float wv = sqrtf(cut * F.S[2]) * infl + 1e-5f;
   const float wn = sqrtf(cut * F.S[5]) * infl + 1e-5f;
-  const float rp = (float)sqrt(pr.x * pr.x + pr.y * pr.y);
-  const float php = (float)atan2(pr.y, pr.x);
+  const float px = (float)pr.x, py = (float)pr.y;
+  const float rp = sqrtf(px * px + py * py);
+  const float php = atan2f(py, px);
   Window w;
   if (!isfinite(wu) || !isfinite(wv) || !isfinite(wn) || !isfinite(rp) || !isfinite(php) ||
       !isfinite((float)pr.z)) {
@@ -248,43 +249,105 @@ KFX_HD long bin_key(const BinIndex& B, int ev, int layer, int bin) {
   return ((long)ev * B.n_layers + layer) * B.n_bins + bin;
 }
 
-// Scan the window's bins and keep the best K compatible hits (chi2 < cut).
-// The phi bins of one eta row are adjacent in the index, so each row is one
-// contiguous range of sorted hits (two when the window wraps at phi = pi).
-// Returns the number of compatible hits found (all of them, not only K).
+// ---- window scan ---------------------------------------------------------
+// The window's bins as contiguous ranges of the sorted hits: the phi bins of
+// one eta row are adjacent in the index, so a row is one range (two when the
+// phi range wraps at pi).  Range r of nrows * nseg: row r / nseg, segment
+// r % nseg.
+struct ScanWin {
+  long row0;      // key of (event, layer, first eta row, phi bin 0)
+  int nrows, nseg;
+  int b0, b1;     // first segment: phi bins [b0, b1)
+  int w1;         // second segment (wrap): phi bins [0, w1)
+};
+
+KFX_HD ScanWin scan_win(const Geometry& G, const BinIndex& B, int ev, int layer, const Window& w) {
+  ScanWin s;
+  const int wrap = w.pb0 + w.npb - G.n_phi;
+  s.row0 = bin_key(B, ev, layer, 0) + (long)w.eb0 * G.n_phi;
+  s.nrows = (w.eb1 >= w.eb0 && w.npb > 0) ? w.eb1 - w.eb0 + 1 : 0;
+  s.nseg = wrap > 0 ? 2 : 1;
+  s.b0 = w.pb0;
+  s.b1 = wrap > 0 ? G.n_phi : w.pb0 + w.npb;
+  s.w1 = wrap;
+  return s;
+}
+
+KFX_HD int scan_nranges(const ScanWin& s) { return s.nrows * s.nseg; }
+
+// sorted hits [a, e) of range r
+KFX_HD void scan_range(const ScanWin& s, const BinIndex& B, int n_phi, int r, int& a, int& e) {
+  const bool two = s.nseg == 2;
+  const int row = two ? (r >> 1) : r;
+  const bool second = two && (r & 1);
+  const long k = s.row0 + (long)row * n_phi;
+  a = B.off[k + (second ? 0 : s.b0)];
+  e = B.off[k + (second ? s.w1 : s.b1)];
+}
+
+// What the chi2 of a candidate-hit pair needs: the predicted position, the
+// azimuth (cos, sin) that defines the measurement frame, and S^-1.
+struct PairFrame {
+  double x, y, z;
+  float c, s;
+  int disk;
+  float Si[6];
+};
+
+KFX_HD void pair_frame(const State& pr, const Frame& F, bool disk, PairFrame& P) {
+  P.x = pr.x;
+  P.y = pr.y;
+  P.z = pr.z;
+  P.c = F.h[0][1];
+  P.s = -F.h[0][0];
+  P.disk = disk ? 1 : 0;
+#pragma unroll
+  for (int i = 0; i < 6; ++i) P.Si[i] = F.Si[i];
+}
+
+// chi2 of the pair: residual r = H (m - x) with the difference taken in
+// FP64, then r^T S^-1 r (the same arithmetic as residual() and chi2_of()
+// on the full frame).
+KFX_HD float pair_chi2(const PairFrame& P, const float4& hv) {
+  const float dx = (float)((double)hv.x - P.x), dy = (float)((double)hv.y - P.y);
+  const float dz = (float)((double)hv.z - P.z);
+  const bool disk = P.disk != 0;
+  const float z0 = 0.0f, o1 = 1.0f;
+  const float h[3][3] = {{-P.s, P.c, z0},
+                         {disk ? P.c : z0, disk ? P.s : z0, disk ? z0 : o1},
+                         {disk ? z0 : P.c, disk ? z0 : P.s, disk ? o1 : z0}};
+  float r[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) r[a] = h[a][0] * dx + h[a][1] * dy + h[a][2] * dz;
+  return r[0] * r[0] * P.Si[0] + r[1] * r[1] * P.Si[2] + r[2] * r[2] * P.Si[5] +
+         2.0f * (r[0] * r[1] * P.Si[1] + r[0] * r[2] * P.Si[3] + r[1] * r[2] * P.Si[4]);
+}
+
+// Scan the window of one candidate and keep the best K compatible hits
+// (chi2 < cut).  Returns the number of compatible hits found (all of them,
+// not only K).
 template <int KM>
 KFX_HD int scan_window(const Geometry& G, const BinIndex& B, int ev, int layer, const State& pr,
                        const Frame& F, float cut, int K, BestK<KM>& best) {
   const Layer& Lr = G.L[layer];
   const Window w = window_bins(G, Lr, pr, F, cut);
+  const ScanWin sw = scan_win(G, B, ev, layer, w);
+  PairFrame P;
+  pair_frame(pr, F, Lr.kind == kDisk, P);
   bestk_init(best);
   int found = 0;
-  const long base = bin_key(B, ev, layer, 0);
-  const int wrap = w.pb0 + w.npb - G.n_phi;  // bins past the wrap, if > 0
-  for (int eb = w.eb0; eb <= w.eb1; ++eb) {
-    const long row = base + (long)eb * G.n_phi;
-    for (int seg = 0; seg < 2; ++seg) {
-      int b0, b1;  // bins [b0, b1) of this segment
-      if (seg == 0) {
-        b0 = w.pb0;
-        b1 = wrap > 0 ? G.n_phi : w.pb0 + w.npb;
-      } else {
-        if (wrap <= 0) break;
-        b0 = 0;
-        b1 = wrap;
-      }
-      const int a = B.off[row + b0], e = B.off[row + b1];
-      for (int q = a; q < e; ++q) {
-        const float4 hv = B.sorted[q];
-        float r[3];
-        residual(pr, F, (double)hv.x, (double)hv.y, (double)hv.z, r);
-        const float c2 = chi2_of(F, r);
-        if (c2 < cut) {
-          int hid;
-          __builtin_memcpy(&hid, &hv.w, 4);
-          ++found;
-          bestk_insert(best, K, c2, hid);
-        }
+  const int nr = scan_nranges(sw);
+  for (int r = 0; r < nr; ++r) {
+    int a, e;
+    scan_range(sw, B, G.n_phi, r, a, e);
+    for (int q = a; q < e; ++q) {
+      const float4 hv = B.sorted[q];
+      const float c2 = pair_chi2(P, hv);
+      if (c2 < cut) {
+        int hid;
+        __builtin_memcpy(&hid, &hv.w, 4);
+        ++found;
+        bestk_insert(best, K, c2, hid);
       }
     }
   }
@@ -309,7 +372,8 @@ KFX_HD bool filter_step(StateT<R>& st, const Layer& Ld, double r_surf, double ka
   if (first) {
     add_material(st, Ld);
   } else {
-    const double cphi = cos(st.phi), sphi = sin(st.phi);
+    double cphi, sphi;
+    sincos_d(st.phi, sphi, cphi);
     const double s = path_to_layer(st, Ld, r_surf, cphi, sphi, kappa * st.k);
     if (!(s > 0.0)) return false;
     StateT<R> nx;
@@ -365,7 +429,8 @@ KFX_HD void aligned_hit(const Layer& Ld, float hx, float hy, float hz, const flo
     const double r = sqrt(x * x + y * y);
     const double c = x / r, s = y / r;
     const double d = drphi / Ld.pos;
-    const double cd = cos(d), sd = sin(d);
+    double cd, sd;
+    sincos_d(d, sd, cd);
     const double R = Ld.pos + dr;
     m[0] = R * (c * cd - s * sd);
     m[1] = R * (s * cd + c * sd);

@@ -51,7 +51,7 @@ class c_build_params(ctypes.Structure):
     _fields_ = [("chi2_cut", ctypes.c_float), ("max_cands", ctypes.c_int32),
                 ("max_holes", ctypes.c_int32), ("max_steps", ctypes.c_int32),
                 ("prior", c_prior), ("mode", ctypes.c_int32), ("block_threads", ctypes.c_int32),
-                ("blocks", ctypes.c_int32)]
+                ("blocks", ctypes.c_int32), ("lanes_per_seed", ctypes.c_int32), ("scan_tile", ctypes.c_int32)]
 
 
 class c_tracks(ctypes.Structure):
@@ -294,7 +294,7 @@ class Context:
 
     def build_tracks(self, hits: DeviceHits, seeds, seed_event, chi2_cut=30.0, max_cands=6, max_holes=3,
                      max_steps=32, prior=(0.1, 0.5, 0.05, 0.05), mode=MODE_FUSED, block_threads=0,
-                     blocks=0, max_hits=48, out=None):
+                     blocks=0, lanes_per_seed=0, scan_tile=0, max_hits=48, out=None):
         """Returns a dict of device tensors (see kfx_tracks in kfx.h)."""
         import torch
         d = self.device
@@ -307,7 +307,7 @@ class Context:
         if out is None:
             out = self.alloc_tracks(S, K, max_hits)
         p = c_build_params(float(chi2_cut), K, int(max_holes), int(max_steps), prior_struct(prior), int(mode),
-                           int(block_threads), int(blocks))
+                           int(block_threads), int(blocks), int(lanes_per_seed), int(scan_tile))
         t = out["_struct"]
         self._check(self.lib.kfx_build_tracks(self.h, ctypes.byref(hits.struct), _ptr(seeds), _ptr(seed_event), S,
                                               ctypes.byref(p), ctypes.byref(t), self._stream()))
@@ -378,7 +378,7 @@ class Context:
         import torch
         d = self.device
         if "ckpt" not in fit_out:
-            raise KfxError("fit_tracks_backward needs a fit made with ckpt=True")
+            raise KfxError(KFX_EINVAL, "fit_tracks_backward needs a fit made with ckpt=True")
         if not isinstance(trk_off, torch.Tensor):
             trk_off = torch.as_tensor(np.ascontiguousarray(trk_off, dtype=np.int32), device=d)
         if not isinstance(trk_hits, torch.Tensor):
@@ -389,7 +389,7 @@ class Context:
         dchi2 = dchi2.to(device=d, dtype=torch.float32).contiguous().reshape(-1)
         per_track = 1 if dchi2.numel() > 1 else 0
         if per_track and dchi2.numel() != T:
-            raise KfxError(f"dchi2 has {dchi2.numel()} entries for {T} tracks")
+            raise KfxError(KFX_EINVAL, f"dchi2 has {dchi2.numel()} entries for {T} tracks")
         n_layers = self.n_layers
         dalign = torch.empty(3 * n_layers, dtype=torch.float64, device=d)
         dfield = torch.empty(1, dtype=torch.float64, device=d)
