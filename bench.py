@@ -67,14 +67,20 @@ def algorithmic_flops(stats):
     return stats[0] * FLOP_PER_STEP + stats[1] * FLOP_PER_PAIR + stats[2] * FLOP_PER_UPDATE
 
 
-def run_build(ctx, kfx, hits, ev, steps, warmup, mode, out=None):
-    """Warm up, then time `steps` build calls; returns (wall ms per step,
-    per-call kernel times, stats of one call, out)."""
-    import torch
+def build_kw(ev, mode):
     w = ev.workload
+    return dict(chi2_cut=w.chi2_cut, max_cands=w.max_cands, max_holes=w.max_holes, max_steps=32, mode=mode)
+
+
+def run_build(ctx, kfx, hits, ev, steps, warmup, mode, out=None, shape=None):
+    """Warm up, then time `steps` build calls; returns (wall ms per step,
+    per-call times (binning, search kernel, building, total), stats of one
+    call, out)."""
+    import torch
     seeds = torch.as_tensor(ev.seeds, device=ctx.device)
     sev = torch.as_tensor(ev.trk_event.astype(np.int32), device=ctx.device)
-    kw = dict(chi2_cut=w.chi2_cut, max_cands=w.max_cands, max_holes=w.max_holes, max_steps=32, mode=mode)
+    kw = build_kw(ev, mode)
+    kw.update(shape or {})
     for _ in range(warmup):
         out = ctx.build_tracks(hits, seeds, sev, out=out, **kw)
     torch.cuda.synchronize()
@@ -93,13 +99,16 @@ def run_build(ctx, kfx, hits, ev, steps, warmup, mode, out=None):
 
 
 def parity_check(ev, out, n_seeds, oracle_out):
-    """Best candidates of the first n seeds against the oracle's."""
-    from paper_2002_06295_amd import kfx as _k  # noqa: F401
+    """Best candidates of the first n seeds against the oracle's (the
+    oracle's building run of the CPU-baseline leg, same seeds): the fraction
+    with identical hit lists, and for those the relative difference of the
+    final parameters (floors 1 cm, 1 rad; none for k).  Per-step parity on
+    identical inputs is the test suite's (test_step_compatibility_lists)."""
     K = ev.workload.max_cands
     g_hits = out["hits"].cpu().numpy()
     p, _ = out["state"].to_numpy()
     same = 0
-    rel = 0.0
+    rels = []
     for s in range(n_seeds):
         gh = g_hits[s * K]
         oh = oracle_out["hits"][s, 0, :gh.shape[0]]
@@ -108,9 +117,15 @@ def parity_check(ev, out, n_seeds, oracle_out):
             po = oracle_out["p"][s, 0]
             d = p[s * K] - po
             d[4] = (d[4] + np.pi) % (2 * np.pi) - np.pi
-            rel = max(rel, float(np.max(np.abs(d) / np.maximum(np.abs(po), [1, 1, 1, 0, 1, 1]))))
-    return dict(seeds_checked=int(n_seeds), best_identical=int(same), params_max_rel=rel,
-                passed=bool(rel <= 1e-4 and same >= 0.98 * n_seeds))
+            rels.append(float(np.max(np.abs(d) / np.maximum(np.abs(po), [1, 1, 1, 0, 1, 1]))))
+    r = np.asarray(rels) if rels else np.zeros(1)
+    frac = float(np.mean(r <= 1e-4))
+    return dict(seeds_checked=int(n_seeds), best_identical=int(same), params_rel_p50=float(np.median(r)),
+                params_rel_p99=float(np.percentile(r, 99)), params_rel_max=float(r.max()),
+                frac_within_1e_4=frac,
+                criterion="best hit lists identical for >= 98% of seeds and parameters within 1e-4 for "
+                          ">= 99% of those",
+                passed=bool(same >= 0.98 * n_seeds and frac >= 0.99))
 
 
 def cpu_baseline(ev, n_seeds, reps):
@@ -163,11 +178,33 @@ def main():
     ctx.load_layers(ev.geometry.as_records(), ev.bz, w.n_eta_bins, w.n_phi_bins)
     hits = kfx.DeviceHits.from_events(ev, dev)
 
-    wall, times, stats, out = run_build(ctx, kfx, hits, ev, args.steps, args.warmup, kfx.MODE_FUSED)
-    kern_ms = float(np.mean([t[1] for t in times]))
+    seeds_d = torch.as_tensor(ev.seeds, device=dev)
+    sev_d = torch.as_tensor(ev.trk_event.astype(np.int32), device=dev)
+    # launch shape of the fused kernel for this workload (identical results
+    # for every shape; only the time differs)
+    t_tune = time.perf_counter()
+    shape = ctx.autotune_build(hits, seeds_d, sev_d, reps=2, **build_kw(ev, kfx.MODE_FUSED))
+    tuned_ms = shape.pop("ms")
+    log(f"[bench] autotuned {shape} ({tuned_ms:.3f} ms) in {time.perf_counter() - t_tune:.1f}s")
+    wall, times, stats, out = run_build(ctx, kfx, hits, ev, args.steps, args.warmup, kfx.MODE_FUSED, shape=shape)
+    search_ms = float(np.mean([t[1] for t in times]))
+    kern_ms = float(np.mean([t[2] for t in times]))
     bin_ms = float(np.mean([t[0] for t in times]))
-    log(f"[bench] fused: {wall:.3f} ms/step wall, building kernels {kern_ms:.3f} ms, binning {bin_ms:.3f} ms, "
-        f"steps {stats[0]:.0f} pairs {stats[1]:.0f} updates {stats[2]:.0f}")
+    log(f"[bench] fused eager: {wall:.3f} ms/step wall, fused kernel {search_ms:.3f} ms, building {kern_ms:.3f} ms, "
+        f"binning {bin_ms:.3f} ms, steps {stats[0]:.0f} pairs {stats[1]:.0f} updates {stats[2]:.0f}")
+    # the same build replayed from a HIP graph (the timed path)
+    graph, gout = ctx.build_graph(hits, seeds_d, sev_d, **build_kw(ev, kfx.MODE_FUSED), **shape)
+    for _ in range(args.warmup):
+        graph.launch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        graph.launch()
+    torch.cuda.synchronize()
+    gwall = (time.perf_counter() - t0) * 1e3 / max(args.steps, 1)
+    same_graph = all(torch.equal(gout[k], out[k]) for k in ("n_cands", "hits", "n_hits", "chi2"))
+    graph.close()
+    log(f"[bench] graph: {gwall:.3f} ms/step wall, identical to eager: {same_graph}")
     if args.calib_copy_mib > 0:
         n = args.calib_copy_mib * (1 << 20) // 4
         a = torch.ones(n, dtype=torch.float32, device=dev)
@@ -177,8 +214,8 @@ def main():
         del a, b
 
     flops = algorithmic_flops(stats)
-    achieved = flops / (kern_ms * 1e-3) / 1e12
-    value = stats[0] / (wall * 1e-3)
+    achieved = flops / (search_ms * 1e-3) / 1e12
+    value = stats[0] / (gwall * 1e-3)
 
     result = {
         "metric": METRIC,
@@ -187,7 +224,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": wall,
+        "ms_per_step": gwall,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -195,13 +232,17 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]}",
                    "events_per_step": ev.n_events, "seeds_per_step": ev.n_tracks, "hits_per_step": ev.n_hits,
-                   "path": "fused persistent kernel", "parallelism": "single GPU"},
+                   "path": "fused persistent kernel replayed from a HIP graph", "launch_shape": shape,
+                   "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / ALU_PEAK_TFLOPS, "traffic": None,
-                     "kernel": "k_build_fused", "avg_launch_ms": kern_ms,
+                     "kernel": "k_build_fused", "avg_launch_ms": search_ms,
                      "flop_per_launch": flops, "steps_per_launch": stats[0], "pairs_per_launch": stats[1],
                      "updates_per_launch": stats[2]},
         "binning_ms": bin_ms,
+        "building_ms": kern_ms,
+        "eager_ms_per_step": wall,
+        "graph_identical_to_eager": bool(same_graph),
     }
 
     if not args.no_cpu_baseline:
@@ -227,36 +268,53 @@ def main():
             ctx2 = kfx.Context(0)
             ctx2.load_layers(ev2.geometry.as_records(), ev2.bz, ev2.workload.n_eta_bins, ev2.workload.n_phi_bins)
             h2 = kfx.DeviceHits.from_events(ev2, dev)
-            wf, tf, sf, o2 = run_build(ctx2, kfx, h2, ev2, 4, 1, kfx.MODE_FUSED)
+            s2 = torch.as_tensor(ev2.seeds, device=dev)
+            e2 = torch.as_tensor(ev2.trk_event.astype(np.int32), device=dev)
+            sh2 = ctx2.autotune_build(h2, s2, e2, reps=1, **build_kw(ev2, kfx.MODE_FUSED))
+            sh2.pop("ms")
+            wf, tf, sf, o2 = run_build(ctx2, kfx, h2, ev2, 4, 1, kfx.MODE_FUSED, shape=sh2)
             wp, tp, sp, o2 = run_build(ctx2, kfx, h2, ev2, 2, 1, kfx.MODE_PLAIN, out=o2)
             km = float(np.mean([t[1] for t in tf]))
             fl = algorithmic_flops(sf)
-            sec[name] = {"steps_per_s": sf[0] / (wf * 1e-3), "ms_per_step": wf, "kernels_ms": km,
-                         "alu_frac": fl / (km * 1e-3) / 1e12 / ALU_PEAK_TFLOPS,
+            sec[name] = {"steps_per_s": sf[0] / (wf * 1e-3), "ms_per_step": wf, "fused_kernel_ms": km,
+                         "alu_frac": fl / (km * 1e-3) / 1e12 / ALU_PEAK_TFLOPS, "launch_shape": sh2,
                          "plain_steps_per_s": sp[0] / (wp * 1e-3), "steps_per_launch": sf[0]}
             log(f"[bench] {name}: fused {sec[name]['steps_per_s']:.3e} steps/s, plain "
                 f"{sec[name]['plain_steps_per_s']:.3e}")
             del o2, h2, ctx2, ev2
             torch.cuda.empty_cache()
-        # the fit on the alignment workload (forward only)
+        # the fit on the alignment workload: forward only, and forward with
+        # checkpoints + the adjoint (fit+grad)
         evf = kfsynth.generate("align200k")
         ctxf = kfx.Context(0)
         ctxf.load_layers(evf.geometry.as_records(), evf.bz, 20, 128)
         hf = kfx.DeviceHits.from_events(evf, dev)
         toff = torch.as_tensor(evf.trk_offsets, device=dev)
         th = torch.as_tensor(evf.trk_hits, device=dev)
-        fo = ctxf.fit_tracks(hf, toff, th, field_scale=1.0, ckpt=True)
+        ones = torch.ones(1, device=dev)
+        fo = ctxf.fit_tracks(hf, toff, th, field_scale=1.0)
+        fg = ctxf.fit_tracks(hf, toff, th, field_scale=1.0, ckpt=True)
+        ctxf.fit_tracks_backward(hf, toff, th, fg, ones)
         torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        nrep = 5
         e0.record()
-        for _ in range(5):
+        for _ in range(nrep):
             fo = ctxf.fit_tracks(hf, toff, th, field_scale=1.0, out=fo)
         e1.record()
+        for _ in range(nrep):
+            fg = ctxf.fit_tracks(hf, toff, th, field_scale=1.0, ckpt=True, out=fg)
+            ctxf.fit_tracks_backward(hf, toff, th, fg, ones)
+        e2.record()
         torch.cuda.synchronize()
-        fms = e0.elapsed_time(e1) / 5
-        sec["align200k_fit"] = {"tracks_per_s": evf.n_tracks / (fms * 1e-3), "ms_per_fit": fms,
-                                "tracks": evf.n_tracks, "with_checkpoints": True}
-        log(f"[bench] fit align200k: {fms:.3f} ms, {evf.n_tracks / (fms * 1e-3):.3e} tracks/s")
+        fms = e0.elapsed_time(e1) / nrep
+        gms = e1.elapsed_time(e2) / nrep
+        sec["align200k_fit"] = {"fit_tracks_per_s": evf.n_tracks / (fms * 1e-3), "fit_ms": fms,
+                                "fit_grad_tracks_per_s": evf.n_tracks / (gms * 1e-3), "fit_grad_ms": gms,
+                                "tracks": evf.n_tracks, "hits": int(evf.trk_offsets[-1]),
+                                "grad_params": 3 * evf.geometry.n_layers + 1}
+        log(f"[bench] align200k: fit {fms:.3f} ms ({evf.n_tracks / (fms * 1e-3):.3e} tracks/s), "
+            f"fit+grad {gms:.3f} ms ({evf.n_tracks / (gms * 1e-3):.3e} tracks/s)")
         result["secondary"] = sec
     print(json.dumps(result), flush=True)
 

@@ -231,11 +231,41 @@ int kfx_fit_tracks_backward(kfx_ctx* ctx, const kfx_hits* hits, const int32_t* t
  * 4096).  Off by default. */
 int kfx_enable_timing(kfx_ctx* ctx, int n_calls);
 
-/* Milliseconds of up to the last n_calls timed builds, oldest first, three
- * floats per call into ms (host): hit binning, building kernels (seed start,
+/* Milliseconds of up to the last n_calls timed builds, oldest first, four
+ * floats per call into ms (host): hit binning, the search (the fused
+ * kernel, or the per-step kernels of the plain path), building (seed start,
  * search, output), total.  Waits for those events; returns the number of
  * calls written (>= 0) or an error code. */
 int kfx_build_times(kfx_ctx* ctx, float* ms, int n_calls);
+
+/* A HIP graph of one kfx_build_tracks call.  kfx_build_graph runs the call
+ * once (sizing a workspace that the graph owns), then captures it on a
+ * private stream and instantiates the graph; kfx_graph_launch replays it on
+ * `stream` with the same device buffers (hits, seeds, seed_event, out),
+ * whose contents the caller may change between launches (sizes and
+ * parameters are fixed).  The graph holds no memset node: buffers are
+ * cleared by kernels.  out->stats is added to on every launch.  Destroy
+ * graphs before their context; kfx_graph_destroy waits for the device. */
+typedef struct kfx_graph kfx_graph;
+int kfx_build_graph(kfx_ctx* ctx, const kfx_hits* hits, const int32_t* seeds, const int32_t* seed_event,
+                    int32_t n_seeds, const kfx_build_params* params, kfx_tracks* out, kfx_graph** graph);
+int kfx_graph_launch(kfx_graph* graph, void* stream);
+void kfx_graph_destroy(kfx_graph* graph);
+
+/* Autotuner of the fused kernel (the paper's Sec. 2 puts the parallel
+ * tasks at the level of events, regions and seed bunches; how many seeds a
+ * block holds and how windows are shared is a property of the workload).
+ * Times kfx_build_tracks with HIP events on `stream` (one warm-up and `reps`
+ * timed calls per shape, the minimum kept) while moving one parameter at a
+ * time: scan_tile in {16, 32, 64, 128, 256}, block_threads in {64, 128,
+ * 256}, blocks in {1, 2, 4, 8} per compute unit, lanes_per_seed from the
+ * smallest power of two >= K up to 16.  Writes the fastest shape into
+ * params (mode becomes KFX_MODE_FUSED) and its time into *best_ms
+ * (nullable).  Every shape gives identical results; out holds the last
+ * call's, out->stats is restored.  Synchronises the stream. */
+int kfx_autotune_build(kfx_ctx* ctx, const kfx_hits* hits, const int32_t* seeds, const int32_t* seed_event,
+                       int32_t n_seeds, kfx_build_params* params, kfx_tracks* out, int32_t reps,
+                       float* best_ms, void* stream);
 
 #ifdef __cplusplus
 }

@@ -21,18 +21,21 @@ struct kfx_ctx {
   Geometry host_geo{};
   Geometry* dev_geo = nullptr;
   bool have_geo = false;
-  // workspace pool: named device buffers, grown on demand
+  // workspace pool: named device buffers, grown on demand; `active` is the
+  // pool in use (a graph being captured owns its own)
   std::map<std::string, std::pair<void*, size_t>> pool;
+  std::map<std::string, std::pair<void*, size_t>>* active = &pool;
+  int n_cu = 256;
   // hit index of the last kfx_bin_hits / kfx_build_tracks call
   bool have_index = false;
   const void* index_hits_key[3] = {nullptr, nullptr, nullptr};
   int index_n_hits = -1, index_n_events = -1;
   BinWork bw{};
   // optional timing of build calls: per call, events before binning, after
-  // binning and after the building kernels, recorded on the caller's stream
-  // into a ring of `ring_n` calls
+  // binning, after the seed start, after the search and after the output,
+  // recorded on the caller's stream into a ring of `ring_n` calls
   bool timing = false;
-  std::vector<hipEvent_t> ring;  // 3 per slot
+  std::vector<hipEvent_t> ring;  // kEv per slot
   int ring_n = 0, ring_next = 0, ring_count = 0;
   hipEvent_t* slot_ev = nullptr;  // events of the call in progress
 };
@@ -67,12 +70,13 @@ int hip_check(kfx_ctx* c, hipError_t e, const char* what) {
 void* ws(kfx_ctx* c, const char* name, size_t bytes, hipStream_t st, int& rc) {
   rc = KFX_OK;
   bytes = std::max<size_t>(bytes, 256);
-  auto it = c->pool.find(name);
-  if (it != c->pool.end() && it->second.second >= bytes) return it->second.first;
-  if (it != c->pool.end()) {
+  auto& pool = *c->active;
+  auto it = pool.find(name);
+  if (it != pool.end() && it->second.second >= bytes) return it->second.first;
+  if (it != pool.end()) {
     (void)hipStreamSynchronize(st);
     (void)hipFree(it->second.first);
-    c->pool.erase(it);
+    pool.erase(it);
   }
   void* p = nullptr;
   const size_t grown = bytes + bytes / 4;
@@ -80,7 +84,7 @@ void* ws(kfx_ctx* c, const char* name, size_t bytes, hipStream_t st, int& rc) {
     rc = fail(c, KFX_ENOMEM, std::string("workspace allocation failed: ") + name);
     return nullptr;
   }
-  c->pool[name] = {p, grown};
+  pool[name] = {p, grown};
   return p;
 }
 
@@ -186,6 +190,9 @@ int kfx_create(int device, kfx_ctx** out) {
   if (device < 0 || device >= n) return KFX_EINVAL;
   kfx_ctx* c = new kfx_ctx();
   c->device = device;
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
+    c->n_cu = cus;
   *out = c;
   return KFX_OK;
 }
@@ -343,10 +350,11 @@ int kfx_step_compat(kfx_ctx* c, const kfx_hits* hits, const int32_t* cand_event,
   return hip_check(c, hipGetLastError(), "step kernel");
 }
 
-int kfx_build_tracks(kfx_ctx* c, const kfx_hits* hits, const int32_t* seeds, const int32_t* seed_event,
-                     int32_t n_seeds, const kfx_build_params* p, kfx_tracks* out, void* stream) {
-  if (!c) return KFX_EINVAL;
-  c->err.clear();
+namespace {
+constexpr int kEv = 5;  // timing events per build call
+
+int build_impl(kfx_ctx* c, const kfx_hits* hits, const int32_t* seeds, const int32_t* seed_event, int32_t n_seeds,
+               const kfx_build_params* p, kfx_tracks* out, hipStream_t st) {
   if (!c->have_geo) return fail(c, KFX_ESTATE, "kfx_load_layers first");
   int rc = check_hits(c, hits);
   if (rc) return rc;
@@ -376,24 +384,27 @@ int kfx_build_tracks(kfx_ctx* c, const kfx_hits* hits, const int32_t* seeds, con
                       !out->chi2 || !out->stats))
     return fail(c, KFX_EINVAL, "NULL seed or output arrays");
   if ((rc = check_states(c, &out->state, SK, "out.state"))) return rc;
-  DeviceGuard dg(c->device);
-  hipStream_t st = (hipStream_t)stream;
   hipEvent_t* tev = nullptr;
   if (c->timing) {
-    tev = c->ring.data() + 3 * c->ring_next;
+    tev = c->ring.data() + kEv * c->ring_next;
     if ((rc = hip_check(c, hipEventRecord(tev[0], st), "timing event"))) return rc;
   }
   if ((rc = build_index(c, hits, nullptr, st))) return rc;
   if (tev && (rc = hip_check(c, hipEventRecord(tev[1], st), "timing event"))) return rc;
   auto close_timing = [&]() -> int {
     if (!tev) return KFX_OK;
-    int r = hip_check(c, hipEventRecord(tev[2], st), "timing event");
+    int r = hip_check(c, hipEventRecord(tev[4], st), "timing event");
     if (r) return r;
     c->ring_next = (c->ring_next + 1) % c->ring_n;
     c->ring_count = std::min(c->ring_count + 1, c->ring_n);
     return KFX_OK;
   };
-  if (n_seeds == 0) return close_timing();
+  if (n_seeds == 0) {
+    if (tev && ((rc = hip_check(c, hipEventRecord(tev[2], st), "timing event")) ||
+                (rc = hip_check(c, hipEventRecord(tev[3], st), "timing event"))))
+      return rc;
+    return close_timing();
+  }
 
   BuildArgs a{};
   a.G = c->dev_geo;
@@ -448,26 +459,31 @@ int kfx_build_tracks(kfx_ctx* c, const kfx_hits* hits, const int32_t* seeds, con
   o.max_hits = out->max_hits;
 
   if (p->mode == KFX_MODE_PLAIN) {
-    launch_build_plain(a, o, st);
+    launch_build_plain(a, o, st, tev ? tev + 2 : nullptr);
   } else {
     int* counter = (int*)ws(c, "b.counter", 256, st, rc);
     if (rc) return rc;
     const int threads = p->block_threads ? p->block_threads : 256;
     int blocks = p->blocks;
-    if (blocks == 0) {
-      hipDeviceProp_t prop;
-      if (hipGetDeviceProperties(&prop, c->device) != hipSuccess) prop.multiProcessorCount = 256;
-      blocks = prop.multiProcessorCount * 4;
-    }
+    if (blocks == 0) blocks = c->n_cu * 4;
     // no more groups than seeds need
     const int lanes = p->lanes_per_seed ? p->lanes_per_seed : fused_lanes_for(K);
     const int groups_per_block = threads / lanes;
     const long max_blocks = (n_seeds + groups_per_block - 1) / groups_per_block;
     blocks = (int)std::max<long>(1, std::min<long>(blocks, max_blocks));
-    launch_build_fused(a, o, counter, blocks, threads, lanes, st);
+    launch_build_fused(a, o, counter, blocks, threads, lanes, st, tev ? tev + 2 : nullptr);
   }
   if ((rc = hip_check(c, hipGetLastError(), "build kernels"))) return rc;
   return close_timing();
+}
+}  // namespace
+
+int kfx_build_tracks(kfx_ctx* c, const kfx_hits* hits, const int32_t* seeds, const int32_t* seed_event,
+                     int32_t n_seeds, const kfx_build_params* p, kfx_tracks* out, void* stream) {
+  if (!c) return KFX_EINVAL;
+  c->err.clear();
+  DeviceGuard dg(c->device);
+  return build_impl(c, hits, seeds, seed_event, n_seeds, p, out, (hipStream_t)stream);
 }
 
 int kfx_enable_timing(kfx_ctx* c, int n_calls) {
@@ -476,7 +492,7 @@ int kfx_enable_timing(kfx_ctx* c, int n_calls) {
   DeviceGuard dg(c->device);
   for (auto& e : c->ring)
     if (e) (void)hipEventDestroy(e);
-  c->ring.assign(3 * (size_t)n_calls, nullptr);
+  c->ring.assign(kEv * (size_t)n_calls, nullptr);
   for (auto& e : c->ring) {
     int rc = hip_check(c, hipEventCreate(&e), "event create");
     if (rc) return rc;
@@ -496,14 +512,184 @@ int kfx_build_times(kfx_ctx* c, float* ms, int n_calls) {
   for (int i = 0; i < n; ++i) {
     // oldest of the last n first
     const int slot = ((c->ring_next - n + i) % c->ring_n + c->ring_n) % c->ring_n;
-    hipEvent_t* e = c->ring.data() + 3 * slot;
-    int rc = hip_check(c, hipEventSynchronize(e[2]), "event sync");
+    hipEvent_t* e = c->ring.data() + kEv * slot;
+    int rc = hip_check(c, hipEventSynchronize(e[4]), "event sync");
     if (rc) return rc;
-    if ((rc = hip_check(c, hipEventElapsedTime(&ms[3 * i + 0], e[0], e[1]), "elapsed"))) return rc;
-    if ((rc = hip_check(c, hipEventElapsedTime(&ms[3 * i + 1], e[1], e[2]), "elapsed"))) return rc;
-    if ((rc = hip_check(c, hipEventElapsedTime(&ms[3 * i + 2], e[0], e[2]), "elapsed"))) return rc;
+    if ((rc = hip_check(c, hipEventElapsedTime(&ms[4 * i + 0], e[0], e[1]), "elapsed"))) return rc;
+    if ((rc = hip_check(c, hipEventElapsedTime(&ms[4 * i + 1], e[2], e[3]), "elapsed"))) return rc;
+    if ((rc = hip_check(c, hipEventElapsedTime(&ms[4 * i + 2], e[1], e[4]), "elapsed"))) return rc;
+    if ((rc = hip_check(c, hipEventElapsedTime(&ms[4 * i + 3], e[0], e[4]), "elapsed"))) return rc;
   }
   return n;
+}
+
+// ---- HIP graph of one build -------------------------------------------------
+struct kfx_graph {
+  kfx_ctx* c = nullptr;
+  std::map<std::string, std::pair<void*, size_t>> pool;  // the graph's own workspace
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+void free_pool(std::map<std::string, std::pair<void*, size_t>>& pool) {
+  for (auto& kv : pool) (void)hipFree(kv.second.first);
+  pool.clear();
+}
+}  // namespace
+
+int kfx_build_graph(kfx_ctx* c, const kfx_hits* hits, const int32_t* seeds, const int32_t* seed_event,
+                    int32_t n_seeds, const kfx_build_params* p, kfx_tracks* out, kfx_graph** graph) {
+  if (!c) return KFX_EINVAL;
+  c->err.clear();
+  if (!graph) return fail(c, KFX_EINVAL, "graph is NULL");
+  *graph = nullptr;
+  DeviceGuard dg(c->device);
+  hipStream_t cs = nullptr;
+  int rc = hip_check(c, hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "capture stream");
+  if (rc) return rc;
+  kfx_graph* g = new kfx_graph();
+  g->c = c;
+  auto* saved_active = c->active;
+  const bool saved_timing = c->timing;
+  c->active = &g->pool;
+  c->timing = false;
+  // an eager run sizes the graph's workspace, so that nothing is allocated
+  // (and no stream waits) while capturing
+  rc = build_impl(c, hits, seeds, seed_event, n_seeds, p, out, cs);
+  if (!rc) rc = hip_check(c, hipStreamSynchronize(cs), "sizing run");
+  if (!rc) rc = hip_check(c, hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed), "begin capture");
+  if (!rc) {
+    const int brc = build_impl(c, hits, seeds, seed_event, n_seeds, p, out, cs);
+    hipGraph_t gr = nullptr;
+    const hipError_t e = hipStreamEndCapture(cs, &gr);
+    if (brc) rc = brc;
+    else rc = hip_check(c, e, "end capture");
+    if (!rc) {
+      g->graph = gr;
+      rc = hip_check(c, hipGraphInstantiate(&g->exec, gr, nullptr, nullptr, 0), "graph instantiate");
+    } else if (gr) {
+      (void)hipGraphDestroy(gr);
+    }
+  }
+  c->active = saved_active;
+  c->timing = saved_timing;
+  c->have_index = false;  // the index now lives in the graph's workspace
+  (void)hipStreamSynchronize(cs);
+  (void)hipStreamDestroy(cs);
+  if (rc) {
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    free_pool(g->pool);
+    delete g;
+    return rc;
+  }
+  *graph = g;
+  return KFX_OK;
+}
+
+int kfx_graph_launch(kfx_graph* g, void* stream) {
+  if (!g || !g->exec) return KFX_EINVAL;
+  DeviceGuard dg(g->c->device);
+  return hip_check(g->c, hipGraphLaunch(g->exec, (hipStream_t)stream), "graph launch");
+}
+
+void kfx_graph_destroy(kfx_graph* g) {
+  if (!g) return;
+  {
+    DeviceGuard dg(g->c->device);
+    (void)hipDeviceSynchronize();
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    free_pool(g->pool);
+  }
+  delete g;
+}
+
+// ---- autotuner of the fused kernel's launch shape -------------------------
+int kfx_autotune_build(kfx_ctx* c, const kfx_hits* hits, const int32_t* seeds, const int32_t* seed_event,
+                       int32_t n_seeds, kfx_build_params* p, kfx_tracks* out, int32_t reps, float* best_ms,
+                       void* stream) {
+  if (!c) return KFX_EINVAL;
+  c->err.clear();
+  if (!p || !out) return fail(c, KFX_EINVAL, "params or out is NULL");
+  if (reps < 1 || reps > 100) return fail(c, KFX_EINVAL, "reps out of [1, 100]");
+  DeviceGuard dg(c->device);
+  hipStream_t st = (hipStream_t)stream;
+  const bool saved_timing = c->timing;
+  c->timing = false;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int rc = hip_check(c, hipEventCreate(&e0), "event create");
+  if (!rc) rc = hip_check(c, hipEventCreate(&e1), "event create");
+  uint64_t saved_stats[3] = {0, 0, 0};
+  if (!rc && out->stats)
+    rc = hip_check(c, hipMemcpyAsync(saved_stats, out->stats, sizeof(saved_stats), hipMemcpyDeviceToHost, st),
+                   "stats save");
+  if (!rc) rc = hip_check(c, hipStreamSynchronize(st), "stats save");
+  kfx_build_params cur = *p;
+  cur.mode = KFX_MODE_FUSED;
+  const int lp0 = fused_lanes_for(p->max_cands);
+  if (cur.block_threads == 0) cur.block_threads = 256;
+  if (cur.blocks == 0) cur.blocks = c->n_cu * 4;
+  if (cur.lanes_per_seed == 0) cur.lanes_per_seed = lp0;
+  if (cur.scan_tile == 0) cur.scan_tile = 64;
+  auto timeit = [&](const kfx_build_params& q, float& ms) -> int {
+    int r = build_impl(c, hits, seeds, seed_event, n_seeds, &q, out, st);  // warm-up
+    if (r) return r;
+    ms = 3.0e38f;
+    for (int i = 0; i < reps; ++i) {
+      if ((r = hip_check(c, hipEventRecord(e0, st), "event"))) return r;
+      if ((r = build_impl(c, hits, seeds, seed_event, n_seeds, &q, out, st))) return r;
+      if ((r = hip_check(c, hipEventRecord(e1, st), "event"))) return r;
+      if ((r = hip_check(c, hipEventSynchronize(e1), "event"))) return r;
+      float t = 0.0f;
+      if ((r = hip_check(c, hipEventElapsedTime(&t, e0, e1), "elapsed"))) return r;
+      ms = std::min(ms, t);
+    }
+    return KFX_OK;
+  };
+  float best = 3.0e38f;
+  if (!rc) rc = timeit(cur, best);
+  // coordinate descent: one parameter at a time, the others held
+  for (int dim = 0; dim < 4 && !rc; ++dim) {
+    std::vector<kfx_build_params> cand;
+    kfx_build_params q = cur;
+    if (dim == 0) {
+      for (int t : {16, 32, 64, 128, 256}) { q.scan_tile = t; cand.push_back(q); }
+    } else if (dim == 1) {
+      for (int t : {64, 128, 256}) { q.block_threads = t; cand.push_back(q); }
+    } else if (dim == 2) {
+      for (int b : {1, 2, 4, 8}) { q.blocks = c->n_cu * b; cand.push_back(q); }
+    } else {
+      for (int l = lp0; l <= 16; l <<= 1) { q.lanes_per_seed = l; cand.push_back(q); }
+    }
+    for (const auto& v : cand) {
+      if (v.scan_tile == cur.scan_tile && v.block_threads == cur.block_threads && v.blocks == cur.blocks &&
+          v.lanes_per_seed == cur.lanes_per_seed)
+        continue;
+      float t = 0.0f;
+      if ((rc = timeit(v, t))) break;
+      if (t < best) {
+        best = t;
+        cur = v;
+      }
+    }
+  }
+  if (!rc && out->stats)
+    rc = hip_check(c, hipMemcpyAsync(out->stats, saved_stats, sizeof(saved_stats), hipMemcpyHostToDevice, st),
+                   "stats restore");
+  if (!rc) rc = hip_check(c, hipStreamSynchronize(st), "stats restore");
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  c->timing = saved_timing;
+  if (rc) return rc;
+  p->mode = KFX_MODE_FUSED;
+  p->block_threads = cur.block_threads;
+  p->blocks = cur.blocks;
+  p->lanes_per_seed = cur.lanes_per_seed;
+  p->scan_tile = cur.scan_tile;
+  if (best_ms) *best_ms = best;
+  return KFX_OK;
 }
 
 int kfx_fit_tracks(kfx_ctx* c, const kfx_hits* hits, const int32_t* trk_off, const int32_t* trk_hits,

@@ -38,9 +38,11 @@ void launch_step_compat(const Geometry* G, const HitsView& H, const BinIndex& B,
                         const int* cand_layer, const StateSoA& in, int n, float cut, int* next_layer,
                         const StateSoA& pred, int* pair_count, int* pair_hit, float* pair_chi2, int max_pairs,
                         hipStream_t st);
-void launch_build_plain(const BuildArgs& a, const TracksOut& o, hipStream_t st);
+// ev: NULL, or two events recorded after the seed start and after the
+// search (before the output kernel)
+void launch_build_plain(const BuildArgs& a, const TracksOut& o, hipStream_t st, const hipEvent_t* ev);
 void launch_build_fused(const BuildArgs& a, const TracksOut& o, int* seed_counter, int blocks, int threads,
-                        int lanes, hipStream_t st);
+                        int lanes, hipStream_t st, const hipEvent_t* ev);
 int fused_lanes_for(int K);
 
 }  // namespace kfx

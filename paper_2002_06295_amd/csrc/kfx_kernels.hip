@@ -881,10 +881,11 @@ void launch_step_compat(const Geometry* G, const HitsView& H, const BinIndex& B,
                      cut, next_layer, pred, pair_count, pair_hit, pair_chi2, max_pairs);
 }
 
-void launch_build_plain(const BuildArgs& a, const TracksOut& o, hipStream_t st) {
+void launch_build_plain(const BuildArgs& a, const TracksOut& o, hipStream_t st, const hipEvent_t* ev) {
   const long nslots = (long)a.n_seeds * a.K;
   if (a.n_seeds <= 0) return;
   hipLaunchKernelGGL(k_build_init, dim3(nblk(a.n_seeds, 128)), dim3(128), 0, st, a);
+  if (ev) (void)hipEventRecord(ev[0], st);
   int cur = 0;
   for (int t = 0; t < a.max_steps; ++t) {
     hipLaunchKernelGGL(k_build_predict, dim3(nblk(nslots, 128)), dim3(128), 0, st, a, cur);
@@ -893,6 +894,7 @@ void launch_build_plain(const BuildArgs& a, const TracksOut& o, hipStream_t st) 
     hipLaunchKernelGGL(k_build_update, dim3(nblk(nslots, 128)), dim3(128), 0, st, a, cur, t);
     cur = 1 - cur;
   }
+  if (ev) (void)hipEventRecord(ev[1], st);
   hipLaunchKernelGGL(k_build_finalize, dim3(nblk(nslots, 128)), dim3(128), 0, st, a, cur, o);
 }
 
@@ -903,12 +905,13 @@ int fused_lanes_for(int K) {
 }
 
 void launch_build_fused(const BuildArgs& a, const TracksOut& o, int* seed_counter, int blocks, int threads,
-                        int lanes, hipStream_t st) {
+                        int lanes, hipStream_t st, const hipEvent_t* ev) {
   if (a.n_seeds <= 0) return;
   launch_fill(seed_counter, 1, 0, st);
   // start states (FP64 seed phase) in their own kernel, so that its FP64
   // temporaries do not set the register budget of the persistent kernel
   hipLaunchKernelGGL(k_build_init, dim3(nblk(a.n_seeds, 128)), dim3(128), 0, st, a);
+  if (ev) (void)hipEventRecord(ev[0], st);
   const size_t shmem = sizeof(FusedShared) * threads + sizeof(CoopShared) * (threads / 64);
   switch (lanes) {
     case 4:
@@ -921,6 +924,7 @@ void launch_build_fused(const BuildArgs& a, const TracksOut& o, int* seed_counte
       hipLaunchKernelGGL(k_build_fused<16>, dim3(blocks), dim3(threads), shmem, st, a, seed_counter);
       break;
   }
+  if (ev) (void)hipEventRecord(ev[1], st);
   const long nslots = (long)a.n_seeds * a.K;
   hipLaunchKernelGGL(k_build_finalize, dim3(nblk(nslots, 128)), dim3(128), 0, st, a, 0, o);
 }

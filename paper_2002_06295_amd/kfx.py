@@ -29,7 +29,8 @@ MAX_STEPS = 40
 
 EXPORTED = ["kfx_create", "kfx_destroy", "kfx_last_error", "kfx_load_layers", "kfx_bin_hits",
             "kfx_seed_states", "kfx_step_compat", "kfx_build_tracks", "kfx_fit_tracks",
-            "kfx_fit_tracks_backward", "kfx_enable_timing", "kfx_build_times"]
+            "kfx_fit_tracks_backward", "kfx_enable_timing", "kfx_build_times", "kfx_build_graph",
+            "kfx_graph_launch", "kfx_graph_destroy", "kfx_autotune_build"]
 
 
 class c_states(ctypes.Structure):
@@ -103,10 +104,19 @@ def load_library():
                                             ctypes.c_void_p, ctypes.c_float, ctypes.POINTER(c_states),
                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    lib.kfx_build_graph.argtypes = [ctypes.c_void_p, ctypes.POINTER(c_hits), ctypes.c_void_p, ctypes.c_void_p,
+                                    ctypes.c_int32, ctypes.POINTER(c_build_params), ctypes.POINTER(c_tracks),
+                                    ctypes.POINTER(ctypes.c_void_p)]
+    lib.kfx_graph_launch.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    lib.kfx_graph_destroy.argtypes = [ctypes.c_void_p]
+    lib.kfx_graph_destroy.restype = None
+    lib.kfx_autotune_build.argtypes = [ctypes.c_void_p, ctypes.POINTER(c_hits), ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_int32, ctypes.POINTER(c_build_params), ctypes.POINTER(c_tracks),
+                                       ctypes.c_int32, ctypes.POINTER(ctypes.c_float), ctypes.c_void_p]
     lib.kfx_enable_timing.argtypes = [ctypes.c_void_p, ctypes.c_int]
     lib.kfx_build_times.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
     for name in EXPORTED:
-        if name not in ("kfx_destroy", "kfx_last_error"):
+        if name not in ("kfx_destroy", "kfx_last_error", "kfx_graph_destroy"):
             getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -209,6 +219,28 @@ def prior_struct(prior):
     return c_prior(*[float(v) for v in prior])
 
 
+class Graph:
+    """A captured build (kfx_build_graph); launch() replays it on torch's
+    current stream."""
+
+    def __init__(self, ctx, handle, keep):
+        self.ctx, self.h, self._keep = ctx, handle, keep
+
+    def launch(self):
+        self.ctx._check(self.ctx.lib.kfx_graph_launch(self.h, self.ctx._stream()))
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.ctx.lib.kfx_graph_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Context:
     """A kfx context on one HIP device."""
 
@@ -292,10 +324,9 @@ class Context:
                                              _ptr(pc), int(max_pairs), self._stream()))
         return nxt[:n], pred, cnt[:n], ph[:n], pc[:n]
 
-    def build_tracks(self, hits: DeviceHits, seeds, seed_event, chi2_cut=30.0, max_cands=6, max_holes=3,
-                     max_steps=32, prior=(0.1, 0.5, 0.05, 0.05), mode=MODE_FUSED, block_threads=0,
-                     blocks=0, lanes_per_seed=0, scan_tile=0, max_hits=48, out=None):
-        """Returns a dict of device tensors (see kfx_tracks in kfx.h)."""
+    def _build_args(self, seeds, seed_event, chi2_cut=30.0, max_cands=6, max_holes=3, max_steps=32,
+                    prior=(0.1, 0.5, 0.05, 0.05), mode=MODE_FUSED, block_threads=0, blocks=0, lanes_per_seed=0,
+                    scan_tile=0, max_hits=48, out=None):
         import torch
         d = self.device
         if not isinstance(seeds, torch.Tensor):
@@ -308,22 +339,51 @@ class Context:
             out = self.alloc_tracks(S, K, max_hits)
         p = c_build_params(float(chi2_cut), K, int(max_holes), int(max_steps), prior_struct(prior), int(mode),
                            int(block_threads), int(blocks), int(lanes_per_seed), int(scan_tile))
-        t = out["_struct"]
+        return seeds, seed_event, S, p, out
+
+    def build_tracks(self, hits: DeviceHits, seeds, seed_event, **kw):
+        """Returns a dict of device tensors (see kfx_tracks in kfx.h).
+        Keywords: chi2_cut, max_cands, max_holes, max_steps, prior, mode,
+        block_threads, blocks, lanes_per_seed, scan_tile, max_hits, out."""
+        seeds, seed_event, S, p, out = self._build_args(seeds, seed_event, **kw)
         self._check(self.lib.kfx_build_tracks(self.h, ctypes.byref(hits.struct), _ptr(seeds), _ptr(seed_event), S,
-                                              ctypes.byref(p), ctypes.byref(t), self._stream()))
+                                              ctypes.byref(p), ctypes.byref(out["_struct"]), self._stream()))
         return out
+
+    def build_graph(self, hits: DeviceHits, seeds, seed_event, **kw):
+        """Capture one build into a HIP graph; returns (Graph, out).  The
+        graph keeps references to the buffers it was captured with."""
+        seeds, seed_event, S, p, out = self._build_args(seeds, seed_event, **kw)
+        g = ctypes.c_void_p()
+        self._check(self.lib.kfx_build_graph(self.h, ctypes.byref(hits.struct), _ptr(seeds), _ptr(seed_event), S,
+                                             ctypes.byref(p), ctypes.byref(out["_struct"]), ctypes.byref(g)))
+        return Graph(self, g, (hits, seeds, seed_event, out)), out
+
+    def autotune_build(self, hits: DeviceHits, seeds, seed_event, reps=2, **kw):
+        """Fastest launch shape of the fused kernel for this workload: a dict
+        of block_threads, blocks, lanes_per_seed, scan_tile (pass it back to
+        build_tracks) and the time of one build in ms."""
+        kw = dict(kw)
+        kw["mode"] = MODE_FUSED
+        seeds, seed_event, S, p, out = self._build_args(seeds, seed_event, **kw)
+        ms = ctypes.c_float(0.0)
+        self._check(self.lib.kfx_autotune_build(self.h, ctypes.byref(hits.struct), _ptr(seeds), _ptr(seed_event), S,
+                                                ctypes.byref(p), ctypes.byref(out["_struct"]), int(reps),
+                                                ctypes.byref(ms), self._stream()))
+        return dict(block_threads=p.block_threads, blocks=p.blocks, lanes_per_seed=p.lanes_per_seed,
+                    scan_tile=p.scan_tile, ms=float(ms.value))
 
     def enable_timing(self, n_calls=64):
         self._check(self.lib.kfx_enable_timing(self.h, int(n_calls)))
 
     def build_times(self, n_calls):
-        """[(binning ms, building kernels ms, total ms)] of the last n_calls
-        timed builds, oldest first."""
-        ms = (ctypes.c_float * (3 * max(n_calls, 1)))()
+        """[(binning, search kernel, building, total) in ms] of the last
+        n_calls timed builds, oldest first."""
+        ms = (ctypes.c_float * (4 * max(n_calls, 1)))()
         n = self.lib.kfx_build_times(self.h, ms, int(n_calls))
         if n < 0:
             self._check(n)
-        return [(ms[3 * i], ms[3 * i + 1], ms[3 * i + 2]) for i in range(n)]
+        return [tuple(ms[4 * i + k] for k in range(4)) for i in range(n)]
 
     def alloc_tracks(self, S, K, max_hits=48):
         import torch

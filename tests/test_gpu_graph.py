@@ -1,0 +1,134 @@
+"""GPU tests of the batched build's HIP graph, its autotuner and its timing:
+a captured build replays bit-identically to the eager call (with eager work
+and synchronisations between replays, inputs changed in place between
+launches), every launch shape the autotuner can pick gives identical
+results, and the per-call timing splits the build consistently."""
+import numpy as np
+import pytest
+
+import kfsynth
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+PRIOR = oracle.DEFAULT_PRIOR
+KEYS = ("n_cands", "hits", "n_hits", "n_holes", "chi2")
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda", 0)
+
+
+@pytest.fixture(scope="module")
+def kfx():
+    from paper_2002_06295_amd import kfx as k
+    return k
+
+
+@pytest.fixture(scope="module")
+def setup(dev, kfx):
+    import torch
+    ev = kfsynth.generate("batch256", n_events=6)
+    ctx = kfx.Context(0)
+    w = ev.workload
+    ctx.load_layers(ev.geometry.as_records(), ev.bz, w.n_eta_bins, w.n_phi_bins)
+    hits = kfx.DeviceHits.from_events(ev, dev)
+    seeds = torch.as_tensor(ev.seeds, device=dev)
+    sev = torch.as_tensor(ev.trk_event.astype(np.int32), device=dev)
+    kw = dict(chi2_cut=w.chi2_cut, max_cands=w.max_cands, max_holes=w.max_holes, max_steps=32, prior=PRIOR)
+    return ev, ctx, hits, seeds, sev, kw
+
+
+def snapshot(out):
+    res = {k: out[k].cpu().numpy().copy() for k in KEYS}
+    res["p"], res["C"] = out["state"].to_numpy()
+    res["stats"] = out["stats"].cpu().numpy().copy()
+    return res
+
+
+def same(a, b):
+    return all(np.array_equal(a[k], b[k]) for k in KEYS + ("p", "C"))
+
+
+def test_graph_replays_match_eager(dev, kfx, setup):
+    import torch
+    ev, ctx, hits, seeds, sev, kw = setup
+    ref_out = ctx.build_tracks(hits, seeds, sev, **kw)
+    torch.cuda.synchronize()
+    ref = snapshot(ref_out)
+    graph, gout = ctx.build_graph(hits, seeds, sev, **kw)
+    try:
+        for rep in range(3):
+            gout["stats"].zero_()
+            # eager work between replays, on other buffers
+            other = ctx.build_tracks(hits, seeds, sev, **kw)
+            torch.cuda.synchronize()
+            graph.launch()
+            torch.cuda.synchronize()
+            got = snapshot(gout)
+            assert same(got, ref), f"replay {rep}"
+            assert np.array_equal(got["stats"][:3], ref["stats"][:3]), f"replay {rep} stats"
+            assert same(snapshot(other), ref)
+    finally:
+        graph.close()
+
+
+def test_graph_sees_inputs_changed_in_place(dev, kfx, setup):
+    import torch
+    ev, ctx, hits, seeds, sev, kw = setup
+    s2 = seeds.clone()
+    e2 = sev.clone()
+    graph, gout = ctx.build_graph(hits, s2, e2, **kw)
+    try:
+        # new contents, same sizes: the seeds in reverse order
+        s2.copy_(torch.flip(seeds, [0]))
+        e2.copy_(torch.flip(sev, [0]))
+        torch.cuda.synchronize()
+        graph.launch()
+        torch.cuda.synchronize()
+        ref = snapshot(ctx.build_tracks(hits, torch.flip(seeds, [0]).contiguous(),
+                                        torch.flip(sev, [0]).contiguous(), **kw))
+        assert same(snapshot(gout), ref)
+    finally:
+        graph.close()
+
+
+def test_autotune_shapes_are_bit_identical(dev, kfx, setup):
+    import torch
+    ev, ctx, hits, seeds, sev, kw = setup
+    ref = snapshot(ctx.build_tracks(hits, seeds, sev, **kw))
+    choice = ctx.autotune_build(hits, seeds, sev, reps=1, **kw)
+    assert choice["block_threads"] in (64, 128, 256)
+    assert choice["lanes_per_seed"] in (8, 16) and choice["scan_tile"] in (16, 32, 64, 128, 256)
+    assert choice["blocks"] > 0 and choice["ms"] > 0
+    tuned = {k: v for k, v in choice.items() if k != "ms"}
+    assert same(snapshot(ctx.build_tracks(hits, seeds, sev, **kw, **tuned)), ref)
+    # the extreme shapes too
+    for shape in (dict(block_threads=64, blocks=3, lanes_per_seed=16, scan_tile=1),
+                  dict(block_threads=128, blocks=1000, lanes_per_seed=8, scan_tile=100000)):
+        assert same(snapshot(ctx.build_tracks(hits, seeds, sev, **kw, **shape)), ref), shape
+
+
+def test_build_timing_split(dev, kfx, setup):
+    import torch
+    ev, ctx, hits, seeds, sev, kw = setup
+    ctx.enable_timing(4)
+    for _ in range(3):
+        ctx.build_tracks(hits, seeds, sev, **kw)
+    torch.cuda.synchronize()
+    times = ctx.build_times(3)
+    ctx.enable_timing(0)
+    assert len(times) == 3
+    for binning, search, building, total in times:
+        assert 0 < search <= building <= total and 0 < binning <= total
+
+
+def test_bad_launch_shapes_rejected(dev, kfx, setup):
+    ev, ctx, hits, seeds, sev, kw = setup
+    for bad in (dict(lanes_per_seed=4), dict(lanes_per_seed=12), dict(scan_tile=-1), dict(block_threads=96)):
+        with pytest.raises(kfx.KfxError):
+            ctx.build_tracks(hits, seeds, sev, **kw, **bad)
