@@ -108,6 +108,9 @@ typedef struct {
   int32_t scan_tile;     /* fused: windows holding more hits than this are
                             scanned by the whole wavefront together; smaller
                             ones by their own lane; 0 = 64                    */
+  int32_t waves_per_simd;/* fused: register budget of the kernel, 1 (all 512
+                            registers of a lane) or 2 (half, the rest spilled
+                            to scratch, two waves resident per SIMD); 0 = 1  */
 } kfx_build_params;
 
 /* Output of building, per seed s and slot j < K, best first (device). */
@@ -259,7 +262,7 @@ void kfx_graph_destroy(kfx_graph* graph);
  * timed calls per shape, the minimum kept) while moving one parameter at a
  * time: scan_tile in {16, 32, 64, 128, 256}, block_threads in {64, 128,
  * 256}, blocks in {1, 2, 4, 8} per compute unit, lanes_per_seed from the
- * smallest power of two >= K up to 16.  Writes the fastest shape into
+ * smallest power of two >= K up to 16, waves_per_simd in {1, 2}.  Writes the fastest shape into
  * params (mode becomes KFX_MODE_FUSED) and its time into *best_ms
  * (nullable).  Every shape gives identical results; out holds the last
  * call's, out->stats is restored.  Synchronises the stream. */

@@ -370,6 +370,7 @@ int build_impl(kfx_ctx* c, const kfx_hits* hits, const int32_t* seeds, const int
     return fail(c, KFX_EINVAL, "block_threads must be 0 or a multiple of 64 in [64, 256]");
   if (p->blocks < 0) return fail(c, KFX_EINVAL, "blocks < 0");
   if (p->scan_tile < 0) return fail(c, KFX_EINVAL, "scan_tile < 0");
+  if (p->waves_per_simd < 0 || p->waves_per_simd > 2) return fail(c, KFX_EINVAL, "waves_per_simd must be 0, 1 or 2");
   if (p->lanes_per_seed != 0 && ((p->lanes_per_seed != 4 && p->lanes_per_seed != 8 && p->lanes_per_seed != 16) ||
                                  p->lanes_per_seed < p->max_cands))
     return fail(c, KFX_EINVAL, "lanes_per_seed must be 0, or 4, 8 or 16 and at least max_cands");
@@ -471,7 +472,8 @@ int build_impl(kfx_ctx* c, const kfx_hits* hits, const int32_t* seeds, const int
     const int groups_per_block = threads / lanes;
     const long max_blocks = (n_seeds + groups_per_block - 1) / groups_per_block;
     blocks = (int)std::max<long>(1, std::min<long>(blocks, max_blocks));
-    launch_build_fused(a, o, counter, blocks, threads, lanes, st, tev ? tev + 2 : nullptr);
+    launch_build_fused(a, o, counter, blocks, threads, lanes, p->waves_per_simd == 2 ? 2 : 1, st,
+                       tev ? tev + 2 : nullptr);
   }
   if ((rc = hip_check(c, hipGetLastError(), "build kernels"))) return rc;
   return close_timing();
@@ -633,6 +635,7 @@ int kfx_autotune_build(kfx_ctx* c, const kfx_hits* hits, const int32_t* seeds, c
   if (cur.blocks == 0) cur.blocks = c->n_cu * 4;
   if (cur.lanes_per_seed == 0) cur.lanes_per_seed = lp0;
   if (cur.scan_tile == 0) cur.scan_tile = 64;
+  if (cur.waves_per_simd == 0) cur.waves_per_simd = 1;
   auto timeit = [&](const kfx_build_params& q, float& ms) -> int {
     int r = build_impl(c, hits, seeds, seed_event, n_seeds, &q, out, st);  // warm-up
     if (r) return r;
@@ -651,7 +654,7 @@ int kfx_autotune_build(kfx_ctx* c, const kfx_hits* hits, const int32_t* seeds, c
   float best = 3.0e38f;
   if (!rc) rc = timeit(cur, best);
   // coordinate descent: one parameter at a time, the others held
-  for (int dim = 0; dim < 4 && !rc; ++dim) {
+  for (int dim = 0; dim < 5 && !rc; ++dim) {
     std::vector<kfx_build_params> cand;
     kfx_build_params q = cur;
     if (dim == 0) {
@@ -660,12 +663,14 @@ int kfx_autotune_build(kfx_ctx* c, const kfx_hits* hits, const int32_t* seeds, c
       for (int t : {64, 128, 256}) { q.block_threads = t; cand.push_back(q); }
     } else if (dim == 2) {
       for (int b : {1, 2, 4, 8}) { q.blocks = c->n_cu * b; cand.push_back(q); }
-    } else {
+    } else if (dim == 3) {
       for (int l = lp0; l <= 16; l <<= 1) { q.lanes_per_seed = l; cand.push_back(q); }
+    } else {
+      for (int w : {1, 2}) { q.waves_per_simd = w; cand.push_back(q); }
     }
     for (const auto& v : cand) {
       if (v.scan_tile == cur.scan_tile && v.block_threads == cur.block_threads && v.blocks == cur.blocks &&
-          v.lanes_per_seed == cur.lanes_per_seed)
+          v.lanes_per_seed == cur.lanes_per_seed && v.waves_per_simd == cur.waves_per_simd)
         continue;
       float t = 0.0f;
       if ((rc = timeit(v, t))) break;
@@ -688,6 +693,7 @@ int kfx_autotune_build(kfx_ctx* c, const kfx_hits* hits, const int32_t* seeds, c
   p->blocks = cur.blocks;
   p->lanes_per_seed = cur.lanes_per_seed;
   p->scan_tile = cur.scan_tile;
+  p->waves_per_simd = cur.waves_per_simd;
   if (best_ms) *best_ms = best;
   return KFX_OK;
 }

@@ -42,7 +42,7 @@ void launch_step_compat(const Geometry* G, const HitsView& H, const BinIndex& B,
 // search (before the output kernel)
 void launch_build_plain(const BuildArgs& a, const TracksOut& o, hipStream_t st, const hipEvent_t* ev);
 void launch_build_fused(const BuildArgs& a, const TracksOut& o, int* seed_counter, int blocks, int threads,
-                        int lanes, hipStream_t st, const hipEvent_t* ev);
+                        int lanes, int waves_per_simd, hipStream_t st, const hipEvent_t* ev);
 int fused_lanes_for(int K);
 
 }  // namespace kfx

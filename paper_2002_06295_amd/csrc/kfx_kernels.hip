@@ -390,8 +390,9 @@ __global__ void k_build_finalize(BuildArgs a, int fin, TracksOut o) {
 // segmented wavefront minimum over the lanes' child streams) and update;
 // states move between lanes through LDS.
 struct FusedShared {
-  // per lane: state to hand to the children (predicted, or current for a
-  // stop child), its layer, meta and chi2
+  // per lane: the state its children start from -- the prediction on the
+  // next surface, or the current state when its child is a stop child --
+  // with its layer, and the candidate's meta and chi2
   double par[6];
   float cov[21];
   int layer;
@@ -402,13 +403,19 @@ struct FusedShared {
   float sel_chi2;
 };
 
-__device__ inline void lds_put(FusedShared& d, const State& s, int layer, int meta, float chi2) {
-  d.par[0] = s.x; d.par[1] = s.y; d.par[2] = s.z; d.par[3] = s.k; d.par[4] = s.phi; d.par[5] = s.th;
+__device__ inline void lds_put(FusedShared& d, const State& s, int layer) {
+  double* p = d.par;
+  p[0] = s.x; p[1] = s.y; p[2] = s.z; p[3] = s.k; p[4] = s.phi; p[5] = s.th;
 #pragma unroll
   for (int q = 0; q < 21; ++q) d.cov[q] = s.C[q];
   d.layer = layer;
-  d.meta = meta;
-  d.chi2 = chi2;
+}
+
+__device__ inline void lds_get(const FusedShared& d, State& s) {
+  const double* p = d.par;
+  s.x = p[0]; s.y = p[1]; s.z = p[2]; s.k = p[3]; s.phi = p[4]; s.th = p[5];
+#pragma unroll
+  for (int q = 0; q < 21; ++q) s.C[q] = d.cov[q];
 }
 
 __device__ inline void wave_sync() {
@@ -432,7 +439,7 @@ __device__ inline void wave_sync() {
 // the cut from a ballot.  The best-K set (ordered by chi2, then hit index)
 // and the count do not depend on the order of insertion, so the result is
 // the lane-private scan's.
-constexpr int kCoopR = 8;
+constexpr int kCoopR = 4;
 
 struct CoopShared {
   PairFrame pf[64];
@@ -624,8 +631,9 @@ __device__ inline uint64_t lane_head(const KidStream& k, const BestK<KM>& b, int
   return ~0ull;
 }
 
-template <int G_LANES>
-__global__ void __launch_bounds__(256) k_build_fused(BuildArgs a, int* seed_counter) {
+template <int G_LANES, int OCC>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC, OCC)))
+k_build_fused(BuildArgs a, int* seed_counter) {
   extern __shared__ unsigned char smem_raw[];
   FusedShared* sh = reinterpret_cast<FusedShared*>(smem_raw);
   CoopShared* coop = reinterpret_cast<CoopShared*>(smem_raw + sizeof(FusedShared) * blockDim.x);
@@ -686,9 +694,9 @@ __global__ void __launch_bounds__(256) k_build_fused(BuildArgs a, int* seed_coun
     const bool active = seed >= 0;
     if (__ballot(active) == 0) break;
 
-    // ---- (a) navigate + transport; the current state goes to LDS now (a
-    // stop child keeps it) and is overwritten by the prediction below when
-    // the lane's children start from the prediction
+    // ---- (a) navigate + transport; the prediction goes to LDS at once (the
+    // lane's children start from it, unless its child is a stop child, which
+    // keeps the current state and overwrites it after the scan)
     int nl = -2;
     State pr;
     const bool live = active && (meta_flags(meta) & kFlagLive) && gl < K;
@@ -706,13 +714,16 @@ __global__ void __launch_bounds__(256) k_build_fused(BuildArgs a, int* seed_coun
         }
       }
     }
-    lds_put(me, st, layer, meta, chi2);
+    me.meta = meta;
+    me.chi2 = chi2;
+    if (nl < 0) lds_put(me, st, layer);
     // ---- (b) window scan, best K hit children in registers
     BestK<G_LANES> best;
     {
       ScanWin sw;
       PairFrame pf;
       if (nl >= 0) {
+        lds_put(me, pr, nl);
         Frame F;
         const Layer& Ln = G.L[nl];
         make_frame(pr, Ln, F);
@@ -723,7 +734,7 @@ __global__ void __launch_bounds__(256) k_build_fused(BuildArgs a, int* seed_coun
                                                a.cut, K, a.coop_min, best);
     }
     const KidStream ks = kid_stream(a, live ? meta : 0, chi2, nl, best.n, gl);
-    if (nl >= 0 && !ks.stop) lds_put(me, pr, nl, meta, chi2);
+    if (nl >= 0 && ks.stop) lds_put(me, st, layer);
     // ---- (c) selection: K rounds of a segmented minimum over the lanes'
     // child streams; round i fills new slot i (lane gbase + i)
     int popped = 0;
@@ -760,10 +771,7 @@ __global__ void __launch_bounds__(256) k_build_fused(BuildArgs a, int* seed_coun
       if (my_parent >= 0) {
         const FusedShared& par = sh[gbase + my_parent];
         State ns;
-        ns.x = par.par[0]; ns.y = par.par[1]; ns.z = par.par[2]; ns.k = par.par[3]; ns.phi = par.par[4];
-        ns.th = par.par[5];
-#pragma unroll
-        for (int q = 0; q < 21; ++q) ns.C[q] = par.cov[q];
+        lds_get(par, ns);
         const int pm = par.meta;
         new_layer = par.layer;
         if (my_code == kStop) {
@@ -905,7 +913,7 @@ int fused_lanes_for(int K) {
 }
 
 void launch_build_fused(const BuildArgs& a, const TracksOut& o, int* seed_counter, int blocks, int threads,
-                        int lanes, hipStream_t st, const hipEvent_t* ev) {
+                        int lanes, int waves_per_simd, hipStream_t st, const hipEvent_t* ev) {
   if (a.n_seeds <= 0) return;
   launch_fill(seed_counter, 1, 0, st);
   // start states (FP64 seed phase) in their own kernel, so that its FP64
@@ -913,17 +921,21 @@ void launch_build_fused(const BuildArgs& a, const TracksOut& o, int* seed_counte
   hipLaunchKernelGGL(k_build_init, dim3(nblk(a.n_seeds, 128)), dim3(128), 0, st, a);
   if (ev) (void)hipEventRecord(ev[0], st);
   const size_t shmem = sizeof(FusedShared) * threads + sizeof(CoopShared) * (threads / 64);
+#define KFX_FUSED(GL, OC) \
+  hipLaunchKernelGGL((k_build_fused<GL, OC>), dim3(blocks), dim3(threads), shmem, st, a, seed_counter)
+  const bool two = waves_per_simd == 2;
   switch (lanes) {
     case 4:
-      hipLaunchKernelGGL(k_build_fused<4>, dim3(blocks), dim3(threads), shmem, st, a, seed_counter);
+      if (two) KFX_FUSED(4, 2); else KFX_FUSED(4, 1);
       break;
     case 8:
-      hipLaunchKernelGGL(k_build_fused<8>, dim3(blocks), dim3(threads), shmem, st, a, seed_counter);
+      if (two) KFX_FUSED(8, 2); else KFX_FUSED(8, 1);
       break;
     default:
-      hipLaunchKernelGGL(k_build_fused<16>, dim3(blocks), dim3(threads), shmem, st, a, seed_counter);
+      if (two) KFX_FUSED(16, 2); else KFX_FUSED(16, 1);
       break;
   }
+#undef KFX_FUSED
   if (ev) (void)hipEventRecord(ev[1], st);
   const long nslots = (long)a.n_seeds * a.K;
   hipLaunchKernelGGL(k_build_finalize, dim3(nblk(nslots, 128)), dim3(128), 0, st, a, 0, o);

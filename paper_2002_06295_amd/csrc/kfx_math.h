@@ -92,9 +92,6 @@ KFX_HD float mlog(float x) { return logf(x); }
 KFX_HD double mlog(double x) { return log(x); }
 KFX_HD float mmax(float a, float b) { return fmaxf(a, b); }
 KFX_HD double mmax(double a, double b) { return fmax(a, b); }
-// stopping test of the Newton phase in R (FP32 iterates can cycle a few ulps
-// apart; the FP64 steps that follow finish the convergence)
-template <class R> KFX_HD constexpr R newton_tol() { return sizeof(R) == 4 ? (R)2e-6 : (R)1e-13; }
 
 // sin and cos of an FP64 angle of moderate size (the azimuth, the polar
 // angle and the turning angle of a step are all below 8 in magnitude).
@@ -160,39 +157,19 @@ KFX_HD void sinc_d(R a, R sa, R ca, R& sinc, R& dsinc) {
   }
 }
 
-// Displacement after a transverse path s on a helix that starts with
-// direction (cphi, sphi) and turns at omega = d(phi)/ds: a chord of length
-// s sinc(a) at angle phi0 + a, a = omega s / 2.  Stable at omega -> 0.
+// Half turning angle a = omega s / 2 of a step with its sine, cosine, sinc
+// and sinc derivative in R (the Jacobian's precision).
 template <class R>
 struct ChordT {
   R a, sa, ca, sinc, dsinc;
   double dx, dy;
 };
 
-template <class R>
-KFX_HD ChordT<R> chord(R s, R omega, double cphi, double sphi) {
-  ChordT<R> c;
-  c.a = (R)0.5 * omega * s;
-  c.sa = msin(c.a);
-  c.ca = mcos(c.a);
-  sinc_d(c.a, c.sa, c.ca, c.sinc, c.dsinc);
-  const R L = s * c.sinc;
-  const double dpar = (double)(L * c.ca), dperp = (double)(L * c.sa);
-  c.dx = cphi * dpar - sphi * dperp;
-  c.dy = sphi * dpar + cphi * dperp;
-  return c;
-}
-
-// direction (cos, sin) at the end of a chord: phi0 + 2a
-template <class R>
-KFX_HD void chord_end_dir(const ChordT<R>& c, double cphi, double sphi, double& c1, double& s1) {
-  const R c2a = c.ca * c.ca - c.sa * c.sa, s2a = (R)2 * c.sa * c.ca;
-  c1 = cphi * (double)c2a - sphi * (double)s2a;
-  s1 = sphi * (double)c2a + cphi * (double)s2a;
-}
-
-// The same chord in FP64 (positions and the direction at the end): the
-// crossing point and the residuals are computed from it.
+// Displacement after a transverse path s on a helix that starts with
+// direction (cphi, sphi) and turns at omega = d(phi)/ds: a chord of length
+// s sinc(a) at angle phi0 + a, a = omega s / 2, stable at omega -> 0; in
+// FP64 with the direction at the end.  The crossing point and the residuals
+// are computed from it.
 struct ChordD {
   double a, sa, ca;   // half turning angle and its sine/cosine
   double dx, dy;      // displacement
@@ -220,71 +197,40 @@ KFX_HD ChordD chord_d(double s, double omega, double cphi, double sphi) {
   return c;
 }
 
-// Outgoing crossing of the cylinder of radius Rc.  The start must lie
-// inside it and move outward; the crossing must come before the turning
-// point (the maximum radius of the transverse circle).  Newton on
-// g(s) = |P(s)|^2 - Rc^2 (g taken relative to the start) from the
-// straight-line root, first in R, then two FP64 steps on the FP64 chord.
-// When the cylinder lies near the maximum radius the iteration keeps a
-// bracket [0, s_turn] and falls back to bisection whenever a Newton step
-// leaves it.  Returns the transverse path, or a negative value when there
-// is no outgoing crossing.
+// Outgoing crossing of the cylinder of radius Rc in closed form (FP64).
+// With the half turning angle a = omega s / 2, the helix point is
+// P(a) = P0 + (2 sin a / omega) (cos(phi0 + a), sin(phi0 + a)); writing
+// t = tan a = k tau with k = omega / 2 turns |P|^2 = Rc^2 into
+//   alpha tau^2 + 2 D tau + c0 = 0,
+//   c0 = |P0|^2 - Rc^2 < 0, D = P0 . u, E = P0 . u_perp,
+//   alpha = 1 + 2 k E + k^2 c0,
+// (u the start direction, u_perp it turned by +90 degrees; alpha = 1 is the
+// straight line).  The crossing on the outgoing arc, before the turning
+// point, is the smallest positive root, tau = c0 / (-D - sqrt(D^2 -
+// alpha c0)) in cancellation-free form, and s = atan(k tau) / k.  |a| stays
+// below pi/2 on that arc, so a single branch of atan covers it.  Returns
+// the transverse path, or a negative value when the track moves inward or
+// never reaches the cylinder.
 template <class R>
-KFX_HD double path_to_cylinder(const StateT<R>& st, double cphi, double sphi, double omega_d, double Rc) {
-  const double c0 = st.x * st.x + st.y * st.y - Rc * Rc;
-  const double Dd = st.x * cphi + st.y * sphi;
-  if (!(c0 < 0.0) || Dd < 0.0) return -1.0;
-  double lo = 0.0, hi = 1e30;
-  bool guarded = false;
-  if (fabs(omega_d) > 1e-12) {
-    const double ir = 1.0 / omega_d;
-    const double cx = st.x - sphi * ir, cy = st.y + cphi * ir;
-    const double d = sqrt(cx * cx + cy * cy), rho = fabs(ir);
-    if (d + rho < Rc) return -1.0;  // the circle never reaches the cylinder
-    if (d + rho < 1.5 * Rc) {
-      guarded = true;
-      const double b0 = atan2(st.y - cy, st.x - cx), gam = atan2(cy, cx);
-      double db = fmod((gam - b0) * (omega_d > 0.0 ? 1.0 : -1.0), 2.0 * kPi);
-      if (db < 0.0) db += 2.0 * kPi;
-      hi = db * rho;  // path to the turning point
-    }
+KFX_HD double path_to_cylinder(const StateT<R>& st, double cphi, double sphi, double omega, double Rc) {
+  const double c0 = fma(st.x, st.x, fma(st.y, st.y, -Rc * Rc));
+  const double D = st.x * cphi + st.y * sphi;
+  if (!(c0 < 0.0) || !(D >= 0.0)) return -1.0;
+  const double E = st.y * cphi - st.x * sphi;
+  const double k = 0.5 * omega;
+  const double alpha = fma(k, fma(k, c0, 2.0 * E), 1.0);
+  const double disc = fma(D, D, -alpha * c0);
+  if (!(disc >= 0.0)) return -1.0;
+  const double tau = c0 / (-D - sqrt(disc));
+  const double x = k * tau;
+  double s;
+  if (fabs(x) < 1e-4) {
+    const double x2 = x * x;
+    s = tau * fma(x2, fma(x2, 0.2, -1.0 / 3.0), 1.0);  // atan(x)/x to x^4
+  } else {
+    s = atan(x) / k;
   }
-  const R D = (R)Dd;
-  const R omega = (R)omega_d;
-  R s = (R)(-c0) / (D + msqrt(D * D - (R)c0));
-  if (guarded && !((double)s < hi)) s = (R)(0.5 * (lo + hi));
-  bool conv = false;
-  for (int it = 0; it < 48; ++it) {
-    const ChordT<R> c = chord(s, omega, cphi, sphi);
-    const double g = c0 + 2.0 * (st.x * c.dx + st.y * c.dy) + (c.dx * c.dx + c.dy * c.dy);
-    double c1, s1;
-    chord_end_dir(c, cphi, sphi, c1, s1);
-    const R gp = (R)2 * (R)((st.x + c.dx) * c1 + (st.y + c.dy) * s1);
-    if (guarded) {
-      if (g < 0.0) lo = (double)s; else hi = (double)s;
-    }
-    R sn = s - (R)g / gp;
-    if (!(gp > (R)0) || (guarded && !((double)sn > lo && (double)sn < hi))) {
-      if (!guarded) return -1.0;
-      sn = (R)(0.5 * (lo + hi));
-    }
-    const R ds = sn - s;
-    s = sn;
-    if (mabs(ds) <= newton_tol<R>() * mabs(s) + (R)1e-9) {
-      conv = true;
-      break;
-    }
-  }
-  if (!conv || !(s > (R)0)) return -1.0;
-  double sd = (double)s;
-  for (int it = 0; it < 2; ++it) {
-    const ChordD c = chord_d(sd, omega_d, cphi, sphi);
-    const double g = c0 + 2.0 * (st.x * c.dx + st.y * c.dy) + (c.dx * c.dx + c.dy * c.dy);
-    const double gp = 2.0 * ((st.x + c.dx) * c.c1 + (st.y + c.dy) * c.s1);
-    if (!(gp > 0.0)) return -1.0;  // at the turning point: tangent, no crossing
-    sd -= g / gp;
-  }
-  return sd > 0.0 ? sd : -1.0;
+  return s > 0.0 ? s : -1.0;
 }
 
 // Plane z = Z: s = (Z - z0) tan(theta), ahead of the track (FP64).

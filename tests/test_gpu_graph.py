@@ -109,7 +109,8 @@ def test_autotune_shapes_are_bit_identical(dev, kfx, setup):
     assert same(snapshot(ctx.build_tracks(hits, seeds, sev, **kw, **tuned)), ref)
     # the extreme shapes too
     for shape in (dict(block_threads=64, blocks=3, lanes_per_seed=16, scan_tile=1),
-                  dict(block_threads=128, blocks=1000, lanes_per_seed=8, scan_tile=100000)):
+                  dict(block_threads=128, blocks=1000, lanes_per_seed=8, scan_tile=100000),
+                  dict(block_threads=256, waves_per_simd=2, scan_tile=8)):
         assert same(snapshot(ctx.build_tracks(hits, seeds, sev, **kw, **shape)), ref), shape
 
 
@@ -129,6 +130,7 @@ def test_build_timing_split(dev, kfx, setup):
 
 def test_bad_launch_shapes_rejected(dev, kfx, setup):
     ev, ctx, hits, seeds, sev, kw = setup
-    for bad in (dict(lanes_per_seed=4), dict(lanes_per_seed=12), dict(scan_tile=-1), dict(block_threads=96)):
+    for bad in (dict(lanes_per_seed=4), dict(lanes_per_seed=12), dict(scan_tile=-1), dict(block_threads=96),
+                dict(waves_per_simd=3)):
         with pytest.raises(kfx.KfxError):
             ctx.build_tracks(hits, seeds, sev, **kw, **bad)
