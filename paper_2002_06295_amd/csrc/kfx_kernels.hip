@@ -424,165 +424,6 @@ __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// ---- window scan of a wavefront -----------------------------------------
-// The windows of one step differ wildly in size: a candidate that crosses a
-// layer almost tangentially can cover the whole layer, and a lane-private
-// scan would leave the wave waiting on its largest window.  Each lane first
-// counts the hits of its window.  Windows of at most `coop_min` hits are
-// scanned by their own lane.  The larger ones are flattened: per batch of up
-// to kCoopR ranges per lane, a prefix sum over the lanes of their hit counts
-// gives every hit a flat index, and the 64 lanes walk the flat list
-// together, each finding the owner of its hit by binary search.  A worker
-// keeps a pair only if its chi2 is below the cut and it would enter the
-// owner's best-K list as published at the start of the chunk; the owner then
-// inserts the kept pairs of its stretch of lanes and counts every pair under
-// the cut from a ballot.  The best-K set (ordered by chi2, then hit index)
-// and the count do not depend on the order of insertion, so the result is
-// the lane-private scan's.
-constexpr int kCoopR = 4;
-
-struct CoopShared {
-  PairFrame pf[64];
-  int pre[64];            // exclusive prefix over the lanes of this batch's hits
-  int nrb[64];            // ranges of each lane in this batch
-  int ra[64][kCoopR];     // range starts
-  int rc[64][kCoopR];     // exclusive prefix of the range lengths in the lane
-  float tc[64];           // owner's admission threshold: (chi2, hit) of its
-  int th[64];             // K-th entry, or (inf, max) while the list is short
-  float w_c2[64];         // a worker's kept pair, by lane
-  int w_hit[64];
-};
-
-template <int KM>
-__device__ void publish_threshold(CoopShared& cs, int lane, const BestK<KM>& best, int K) {
-  float c = __builtin_inff();
-  int h = 0x7fffffff;
-#pragma unroll
-  for (int i = 0; i < KM; ++i)
-    if (i == K - 1 && best.n == K) {
-      c = best.c[i];
-      h = best.h[i];
-    }
-  cs.tc[lane] = c;
-  cs.th[lane] = h;
-}
-
-template <int KM>
-__device__ int wave_scan(const BinIndex& B, int n_phi, CoopShared& cs, int lane, bool has, const ScanWin& sw,
-                         const PairFrame& pf, float cut, int K, int coop_min, BestK<KM>& best) {
-  bestk_init(best);
-  int found = 0;
-  const int nr = has ? scan_nranges(sw) : 0;
-  int total_mine = 0;
-  for (int r = 0; r < nr; ++r) {
-    int qa, qe;
-    scan_range(sw, B, n_phi, r, qa, qe);
-    total_mine += qe - qa;
-  }
-  const bool big = total_mine > coop_min;
-  // lane-private scan of the small windows
-  if (has && !big) {
-    for (int r = 0; r < nr; ++r) {
-      int qa, qe;
-      scan_range(sw, B, n_phi, r, qa, qe);
-      for (int q = qa; q < qe; ++q) {
-        const float4 hv = B.sorted[q];
-        const float c2 = pair_chi2(pf, hv);
-        if (c2 < cut) {
-          int hid;
-          __builtin_memcpy(&hid, &hv.w, 4);
-          ++found;
-          bestk_insert(best, K, c2, hid);
-        }
-      }
-    }
-  }
-  if (__ballot(big) == 0) return found;
-  // cooperative scan of the large windows
-  if (big) cs.pf[lane] = pf;
-  const int nrc = big ? nr : 0;
-  for (int rb = 0;; rb += kCoopR) {
-    if (__ballot(rb < nrc) == 0) break;
-    const int nb = nrc - rb <= 0 ? 0 : (nrc - rb < kCoopR ? nrc - rb : kCoopR);
-    int cnt = 0;
-    for (int i = 0; i < nb; ++i) {
-      int qa, qe;
-      scan_range(sw, B, n_phi, rb + i, qa, qe);
-      cs.ra[lane][i] = qa;
-      cs.rc[lane][i] = cnt;
-      cnt += qe - qa;
-    }
-    cs.nrb[lane] = nb;
-    int incl = cnt;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const int v = __shfl_up(incl, o, 64);
-      if (lane >= o) incl += v;
-    }
-    const int total = __shfl(incl, 63, 64);
-    const int pre = incl - cnt;
-    cs.pre[lane] = pre;
-    if (big) publish_threshold(cs, lane, best, K);
-    wave_sync();
-    for (int base = 0; base < total; base += 64) {
-      const int j = base + lane;
-      bool under = false, keep = false;
-      if (j < total) {
-        // owner: the last lane whose prefix is <= j (it has hits: j < total)
-        int lo = 0, hi = 63;
-        while (lo < hi) {
-          const int mid = (lo + hi + 1) >> 1;
-          if (cs.pre[mid] <= j) lo = mid;
-          else hi = mid - 1;
-        }
-        const int owner = lo;
-        const int k = j - cs.pre[owner];
-        int ri = cs.nrb[owner] - 1;
-        while (ri > 0 && cs.rc[owner][ri] > k) --ri;
-        const float4 hv = B.sorted[cs.ra[owner][ri] + (k - cs.rc[owner][ri])];
-        const float c2 = pair_chi2(cs.pf[owner], hv);
-        int hid;
-        __builtin_memcpy(&hid, &hv.w, 4);
-        under = c2 < cut;
-        const float tc = cs.tc[owner];
-        keep = under && (c2 < tc || (c2 == tc && hid < cs.th[owner]));
-        if (keep) {
-          cs.w_c2[lane] = c2;
-          cs.w_hit[lane] = hid;
-        }
-      }
-      const unsigned long long m_under = __ballot(under);
-      const unsigned long long m_keep = __ballot(keep);
-      if (m_under) {
-        // this owner's stretch of the chunk: flat [pre, pre + cnt) within
-        // [base, base + 64)
-        unsigned long long mine = 0;
-        if (cnt > 0 && pre < base + 64 && pre + cnt > base) {
-          const int f = pre > base ? pre - base : 0;
-          const int l = pre + cnt - base < 64 ? pre + cnt - base : 64;  // exclusive
-          const unsigned long long hi_mask = l == 64 ? ~0ull : ((1ull << l) - 1ull);
-          mine = hi_mask & ~((1ull << f) - 1ull);
-        }
-        found += __popcll(m_under & mine);
-        if (m_keep) {
-          wave_sync();
-          unsigned long long take = m_keep & mine;
-          while (take) {
-            const int b = __ffsll((long long)take) - 1;
-            take &= take - 1ull;
-            bestk_insert(best, K, cs.w_c2[b], cs.w_hit[b]);
-          }
-          wave_sync();
-          if (big) publish_threshold(cs, lane, best, K);
-          wave_sync();
-        }
-      }
-    }
-    wave_sync();
-  }
-  return found;
-}
-
 // Minimum of a 64-bit key over aligned groups of G lanes (G = 4, 8, 16)
 // with DPP lane moves: a mirror within the row of 16, a mirror within the
 // half row of 8, then the two quad exchanges.  Each step pairs every lane
@@ -604,6 +445,196 @@ __device__ inline uint64_t group_min(uint64_t v) {
   v = dpp_min_step<0x4E>(v);                // quad_perm [2, 3, 0, 1]
   v = dpp_min_step<0xB1>(v);                // quad_perm [1, 0, 3, 2]
   return v;
+}
+
+// ---- window scan of a wavefront -----------------------------------------
+// The windows of one step differ wildly in size: a candidate that crosses a
+// layer almost tangentially can cover the whole layer, and a lane-private
+// scan would leave the wave waiting on its largest window.  Each lane first
+// counts the hits of its window.  Windows of at most `coop_min` hits are
+// scanned by their own lane.  Each larger one is then scanned by the whole
+// wave in turn: its owner's frame, window and admission threshold are
+// broadcast with readlane, the 64 lanes read 64 consecutive hits of a range
+// at a time (one coalesced load), and a lane keeps a pair only if its chi2 is
+// below the cut and it would enter the owner's best-K list (ordered by chi2,
+// then hit index) as it stood at the start of the chunk.  The kept pairs are
+// handed to the owner through readlane, in ballot order, and the owner counts
+// every pair under the cut from a ballot.  The best-K set and the count do
+// not depend on the order of insertion, so the result is the lane-private
+// scan's.
+__device__ inline double rl_d(double v, int l) {
+  uint64_t b;
+  __builtin_memcpy(&b, &v, 8);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), l);
+  const uint64_t r = ((uint64_t)hi << 32) | lo;
+  double d;
+  __builtin_memcpy(&d, &r, 8);
+  return d;
+}
+__device__ inline float rl_f(float v, int l) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l)); }
+__device__ inline int rl_i(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+__device__ inline long rl_l(long v, int l) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(uint64_t)v, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), l);
+  return (long)(((uint64_t)hi << 32) | lo);
+}
+
+// (chi2, hit) of the K-th entry of a full list, (inf, max) otherwise
+template <int KM>
+__device__ inline void bestk_threshold(const BestK<KM>& best, int K, float& c, int& h) {
+  c = __builtin_inff();
+  h = 0x7fffffff;
+#pragma unroll
+  for (int i = 0; i < KM; ++i)
+    if (i == K - 1 && best.n == K) {
+      c = best.c[i];
+      h = best.h[i];
+    }
+}
+
+template <int KM>
+__device__ int wave_scan(const BinIndex& B, int n_phi, int lane, bool has, const ScanWin& sw, const PairFrame& pf,
+                         float cut, int K, int coop_min, BestK<KM>& best) {
+  bestk_init(best);
+  int found = 0;
+  const int nr = has ? scan_nranges(sw) : 0;
+  int total_mine = 0;
+  for (int r = 0; r < nr; ++r) {
+    int qa, qe;
+    scan_range(sw, B, n_phi, r, qa, qe);
+    total_mine += qe - qa;
+  }
+  const bool big = total_mine > coop_min;
+  // lane-private scan of the small windows, four loads in flight
+  if (has && !big) {
+    for (int r = 0; r < nr; ++r) {
+      int qa, qe;
+      scan_range(sw, B, n_phi, r, qa, qe);
+      for (int q = qa; q < qe; q += 4) {
+        float4 hv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) hv[u] = q + u < qe ? B.sorted[q + u] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const float c2 = pair_chi2(pf, hv[u]);
+          if (q + u < qe && c2 < cut) {
+            int hid;
+            __builtin_memcpy(&hid, &hv[u].w, 4);
+            ++found;
+            bestk_insert(best, K, c2, hid);
+          }
+        }
+      }
+    }
+  }
+  // the large windows, one owner at a time, by the whole wave
+  unsigned long long owners = __ballot(big);
+  while (owners) {
+    const int o = __ffsll((long long)owners) - 1;
+    owners &= owners - 1ull;
+    PairFrame P;
+    P.x = rl_d(pf.x, o);
+    P.y = rl_d(pf.y, o);
+    P.z = rl_d(pf.z, o);
+    P.c = rl_f(pf.c, o);
+    P.s = rl_f(pf.s, o);
+    P.disk = rl_i(pf.disk, o);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) P.Si[i] = rl_f(pf.Si[i], o);
+    ScanWin W;
+    W.row0 = rl_l(sw.row0, o);
+    W.nrows = rl_i(sw.nrows, o);
+    W.nseg = rl_i(sw.nseg, o);
+    W.b0 = rl_i(sw.b0, o);
+    W.b1 = rl_i(sw.b1, o);
+    W.w1 = rl_i(sw.w1, o);
+    float tc;
+    int th;
+    bestk_threshold(best, K, tc, th);
+    tc = rl_f(tc, o);
+    th = rl_i(th, o);
+    const int nro = W.nrows * W.nseg;
+    for (int r = 0; r < nro; ++r) {
+      int qa, qe;
+      scan_range(W, B, n_phi, r, qa, qe);
+      // four loads of 64 consecutive hits in flight per pass
+      for (int base = qa; base < qe; base += 256) {
+        float c2[4];
+        int hid[4];
+        bool under[4];
+        float4 hv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int q = base + 64 * u + lane;
+          hv[u] = q < qe ? B.sorted[q] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        }
+        unsigned long long m_keep[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const bool in = base + 64 * u + lane < qe;
+          c2[u] = pair_chi2(P, hv[u]);
+          __builtin_memcpy(&hid[u], &hv[u].w, 4);
+          under[u] = in && c2[u] < cut;
+          const bool keep = under[u] && (c2[u] < tc || (c2[u] == tc && hid[u] < th));
+          const unsigned long long m_under = __ballot(under[u]);
+          m_keep[u] = __ballot(keep);
+          if (lane == o) found += __popcll(m_under);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          unsigned long long mk = m_keep[u];
+          if (!mk) continue;
+          if (__popcll(mk) <= 3) {
+            // few: hand them over one by one
+            while (mk) {
+              const int b = __ffsll((long long)mk) - 1;
+              mk &= mk - 1ull;
+              const float kc = rl_f(c2[u], b);
+              const int kh = rl_i(hid[u], b);
+              if (lane == o) bestk_insert(best, K, kc, kh);
+            }
+          } else {
+            // many (hits sorted by phi approach the window centre with
+            // falling chi2): extract them smallest first, at most K, and
+            // stop at the first that no longer enters the list
+            // order-preserving integer image of the float (a chi2 rounded
+            // below zero, or -0, must still sort first)
+            const uint32_t fb = __float_as_uint(c2[u] + 0.0f);  // -0 -> +0
+            const uint32_t fk = (fb & 0x80000000u) ? ~fb : (fb | 0x80000000u);
+            uint64_t key = (m_keep[u] >> lane) & 1ull ? ((uint64_t)fk << 32) | (uint32_t)hid[u] : ~0ull;
+            for (int i = 0; i < K; ++i) {
+              const uint64_t m = group_min<16>(key);
+              const uint64_t r0 = (uint64_t)(uint32_t)rl_i((int)(uint32_t)m, 0) |
+                                  ((uint64_t)(uint32_t)rl_i((int)(uint32_t)(m >> 32), 0) << 32);
+              const uint64_t r1 = (uint64_t)(uint32_t)rl_i((int)(uint32_t)m, 16) |
+                                  ((uint64_t)(uint32_t)rl_i((int)(uint32_t)(m >> 32), 16) << 32);
+              const uint64_t r2 = (uint64_t)(uint32_t)rl_i((int)(uint32_t)m, 32) |
+                                  ((uint64_t)(uint32_t)rl_i((int)(uint32_t)(m >> 32), 32) << 32);
+              const uint64_t r3 = (uint64_t)(uint32_t)rl_i((int)(uint32_t)m, 48) |
+                                  ((uint64_t)(uint32_t)rl_i((int)(uint32_t)(m >> 32), 48) << 32);
+              const uint64_t a01 = r0 < r1 ? r0 : r1, a23 = r2 < r3 ? r2 : r3;
+              const uint64_t mn = a01 < a23 ? a01 : a23;
+              if (mn == ~0ull) break;
+              const uint32_t kk = (uint32_t)(mn >> 32);
+              const float kc = __uint_as_float((kk & 0x80000000u) ? (kk & 0x7fffffffu) : ~kk);
+              const int kh = (int)(uint32_t)mn;
+              if (!(kc < tc || (kc == tc && kh < th))) break;
+              if (lane == o) bestk_insert(best, K, kc, kh);
+              bestk_threshold(best, K, tc, th);
+              tc = rl_f(tc, o);
+              th = rl_i(th, o);
+              if (key == mn) key = ~0ull;
+            }
+          }
+          bestk_threshold(best, K, tc, th);
+          tc = rl_f(tc, o);
+          th = rl_i(th, o);
+        }
+      }
+    }
+  }
+  return found;
 }
 
 // Key of the next child of a lane's stream (see kid_key): the head of its
@@ -636,7 +667,6 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC, O
 k_build_fused(BuildArgs a, int* seed_counter) {
   extern __shared__ unsigned char smem_raw[];
   FusedShared* sh = reinterpret_cast<FusedShared*>(smem_raw);
-  CoopShared* coop = reinterpret_cast<CoopShared*>(smem_raw + sizeof(FusedShared) * blockDim.x);
   // the layer table is read at every step with lane-dependent indices: keep
   // a copy in LDS
   __shared__ Geometry g_lds;
@@ -730,8 +760,7 @@ k_build_fused(BuildArgs a, int* seed_counter) {
         sw = scan_win(G, a.B, a.seed_event[seed], nl, window_bins(G, Ln, pr, F, a.cut));
         pair_frame(pr, F, Ln.kind == kDisk, pf);
       }
-      n_pairs += (unsigned long long)wave_scan(a.B, G.n_phi, coop[threadIdx.x >> 6], lane, nl >= 0, sw, pf,
-                                               a.cut, K, a.coop_min, best);
+      n_pairs += (unsigned long long)wave_scan(a.B, G.n_phi, lane, nl >= 0, sw, pf, a.cut, K, a.coop_min, best);
     }
     const KidStream ks = kid_stream(a, live ? meta : 0, chi2, nl, best.n, gl);
     if (nl >= 0 && ks.stop) lds_put(me, st, layer);
@@ -920,7 +949,7 @@ void launch_build_fused(const BuildArgs& a, const TracksOut& o, int* seed_counte
   // temporaries do not set the register budget of the persistent kernel
   hipLaunchKernelGGL(k_build_init, dim3(nblk(a.n_seeds, 128)), dim3(128), 0, st, a);
   if (ev) (void)hipEventRecord(ev[0], st);
-  const size_t shmem = sizeof(FusedShared) * threads + sizeof(CoopShared) * (threads / 64);
+  const size_t shmem = sizeof(FusedShared) * threads;
 #define KFX_FUSED(GL, OC) \
   hipLaunchKernelGGL((k_build_fused<GL, OC>), dim3(blocks), dim3(threads), shmem, st, a, seed_counter)
   const bool two = waves_per_simd == 2;
