@@ -59,6 +59,32 @@ WORKLOADS = {
 }
 
 
+def source_sha256():
+    """Hash of the HIP sources (names and contents), to tell whether stored
+    profiler counters still describe the kernels that run."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2002_06295_amd", "csrc")
+    for f in sorted(glob.glob(os.path.join(csrc, "*.h")) + glob.glob(os.path.join(csrc, "*.hip"))):
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def stored_traffic(name="k_build_fused_build5k_traffic.json"):
+    """HBM bytes per launch of the fused kernel from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary (calibrated against a copy of known
+    size), or None when the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    return t["hbm_bytes_per_launch"] if t.get("source_sha256") == source_sha256() else None
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -235,7 +261,8 @@ def main():
                    "path": "fused persistent kernel replayed from a HIP graph", "launch_shape": shape,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / ALU_PEAK_TFLOPS, "traffic": None,
+                     "frac": achieved / ALU_PEAK_TFLOPS, "traffic": stored_traffic(),
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
                      "kernel": "k_build_fused", "avg_launch_ms": search_ms,
                      "flop_per_launch": flops, "steps_per_launch": stats[0], "pairs_per_launch": stats[1],
                      "updates_per_launch": stats[2]},
