@@ -18,10 +18,13 @@ def wrap(a):
 
 
 def param_rel(pg, po):
-    """|delta p_i| / max(|p_i|, floor_i) (phi difference wrapped)."""
+    """|delta p_i| / max(|p_i|, floor_i) (phi difference wrapped); equal
+    values compare as 0 (k = 0 exactly without a field)."""
     d = pg - po
     d[:, 4] = wrap(d[:, 4])
-    return np.abs(d) / np.maximum(np.abs(po), PARAM_FLOORS)
+    den = np.maximum(np.abs(po), PARAM_FLOORS)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        return np.where(d == 0.0, 0.0, np.abs(d) / den)
 
 
 def local_frame_T(p, kinds):

@@ -1,0 +1,151 @@
+"""GPU parity at the workloads' full sizes, in the launch configuration the
+benchmark times (the autotuned shape of the fused kernel), on sampled
+outputs the FP64 oracle computes one by one (every seed's search and every
+track's fit is independent of the others, so the oracle runs only the
+sampled ones), plus the method's degenerate cases: no field, K = 1 and the
+largest K, the longest search.
+
+Bars: best candidates' hit lists identical for >= 98 % of the sampled seeds
+(candidates whose chi2 sums differ by less than the FP32 rounding of ~20
+pair chi2 may swap ranks), the number of candidates equal, and the best
+candidate's parameters within 1e-4 (floors 1 cm, 1 rad; none for k) for
+>= 99 % of the identical ones; fits within 1e-3 absolute in chi2 and 1e-4
+in the parameters, excluding near-tangent tracks (oracle chi2/ndof > 5).
+"""
+import numpy as np
+import pytest
+
+import kfsynth
+import oracle
+from parity import param_rel
+
+pytestmark = pytest.mark.gpu
+
+PRIOR = oracle.DEFAULT_PRIOR
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda", 0)
+
+
+@pytest.fixture(scope="module")
+def kfx():
+    from paper_2002_06295_amd import kfx as k
+    return k
+
+
+def gpu_build(kfx, dev, ev, tune=True, **kw):
+    import torch
+    ctx = kfx.Context(0)
+    w = ev.workload
+    ctx.load_layers(ev.geometry.as_records(), ev.bz, w.n_eta_bins, w.n_phi_bins)
+    hits = kfx.DeviceHits.from_events(ev, dev)
+    seeds = torch.as_tensor(ev.seeds, device=dev)
+    sev = torch.as_tensor(ev.trk_event.astype(np.int32), device=dev)
+    args = dict(chi2_cut=w.chi2_cut, max_cands=kw.pop("max_cands", w.max_cands), max_holes=w.max_holes,
+                max_steps=kw.pop("max_steps", 32), prior=PRIOR)
+    shape = {}
+    if tune:
+        shape = ctx.autotune_build(hits, seeds, sev, reps=1, **args)
+        shape.pop("ms")
+    out = ctx.build_tracks(hits, seeds, sev, **args, **shape)
+    res = {k: out[k].cpu().numpy() for k in ("n_cands", "hits", "n_hits", "n_holes", "chi2", "stats")}
+    res["p"], res["C"] = out["state"].to_numpy()
+    res["K"] = args["max_cands"]
+    res["max_steps"] = args["max_steps"]
+    return res
+
+
+def compare_sampled(ev, g, idx, **okw):
+    K = g["K"]
+    o = oracle.build_tracks(ev, seeds=ev.seeds[idx], seed_event=ev.trk_event[idx].astype(np.int32),
+                            prior=PRIOR, max_hits=48, max_cands=K, **okw)
+    same = 0
+    rel = []
+    ncand = 0
+    for j, s in enumerate(idx):
+        gb = g["hits"][s * K]
+        ncand += g["n_cands"][s] == o["n"][j]
+        if np.array_equal(gb[:48], o["hits"][j, 0, :48]):
+            same += 1
+            rel.append(param_rel(g["p"][s * K][None], o["p"][j, 0][None]).max())
+    rel = np.asarray(rel)
+    n = len(idx)
+    assert same >= 0.98 * n, f"best identical {same}/{n}"
+    assert ncand >= 0.99 * n, f"candidate counts equal {ncand}/{n}"
+    assert np.mean(rel <= 1e-4) >= 0.99, f"params within 1e-4: {np.mean(rel <= 1e-4)}"
+    return same, rel
+
+
+def test_build5k_full_size(dev, kfx):
+    ev = kfsynth.generate("build5k")
+    g = gpu_build(kfx, dev, ev)
+    idx = np.random.default_rng(11).choice(ev.n_tracks, 500, replace=False)
+    compare_sampled(ev, g, idx)
+
+
+def test_batch256_full_size(dev, kfx):
+    ev = kfsynth.generate("batch256")
+    assert ev.n_events == 256
+    g = gpu_build(kfx, dev, ev)
+    idx = np.random.default_rng(12).choice(ev.n_tracks, 300, replace=False)
+    compare_sampled(ev, g, idx)
+
+
+def test_occ10k_full_size(dev, kfx):
+    ev = kfsynth.generate("occ10k")
+    g = gpu_build(kfx, dev, ev)
+    assert g["K"] == 10
+    idx = np.random.default_rng(13).choice(ev.n_tracks, 200, replace=False)
+    compare_sampled(ev, g, idx)
+
+
+def test_align200k_fit_full_size(dev, kfx):
+    import torch
+    ev = kfsynth.generate("align200k")
+    ctx = kfx.Context(0)
+    ctx.load_layers(ev.geometry.as_records(), ev.bz, 20, 128)
+    hits = kfx.DeviceHits.from_events(ev, dev)
+    off = torch.as_tensor(ev.trk_offsets, device=dev)
+    th = torch.as_tensor(ev.trk_hits, device=dev)
+    out = ctx.fit_tracks(hits, off, th, prior=PRIOR)
+    pg, _ = out["state"].to_numpy()
+    c2g = out["chi2"].cpu().numpy()
+    stg = out["status"].cpu().numpy()
+    idx = np.sort(np.random.default_rng(14).choice(ev.n_tracks, 600, replace=False))
+    toff = ev.trk_offsets
+    lens = toff[idx + 1] - toff[idx]
+    soff = np.concatenate([[0], np.cumsum(lens)]).astype(np.int32)
+    shits = np.concatenate([ev.trk_hits[toff[i]:toff[i + 1]] for i in idx]).astype(np.int32)
+    po, _, c2o, ndo, oko = oracle.fit(ev, trk_offsets=soff, trk_hits=shits, prior=PRIOR)
+    ok = (oko == 1) & (stg[idx] == 1) & (c2o / np.maximum(ndo, 1) <= 5)
+    assert ok.sum() >= 0.95 * len(idx)
+    assert np.array_equal(stg[idx] == 1, oko == 1)
+    assert np.abs(c2g[idx][ok] - c2o[ok]).max() <= 1e-3
+    assert param_rel(pg[idx][ok], po[ok]).max() <= 1e-4
+
+
+def test_build_without_field(dev, kfx):
+    ev = kfsynth.generate(kfsynth.workload("build5k", bz=0.0, scatter=False), tracks_per_event=400)
+    g = gpu_build(kfx, dev, ev, tune=False)
+    idx = np.arange(ev.n_tracks)
+    compare_sampled(ev, g, idx)
+
+
+@pytest.mark.parametrize("K", [1, 16])
+def test_build_smallest_and_largest_K(dev, kfx, K):
+    ev = kfsynth.generate("build5k", tracks_per_event=400)
+    g = gpu_build(kfx, dev, ev, tune=False, max_cands=K)
+    compare_sampled(ev, g, np.arange(ev.n_tracks))
+
+
+def test_build_longest_search(dev, kfx):
+    # the largest step budget: the oracle runs to the end of every candidate
+    ev = kfsynth.generate("batch256", n_events=2)
+    g = gpu_build(kfx, dev, ev, tune=False, max_steps=40)
+    idx = np.random.default_rng(15).choice(ev.n_tracks, 300, replace=False)
+    compare_sampled(ev, g, idx)
