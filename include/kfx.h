@@ -202,9 +202,10 @@ int kfx_build_tracks(kfx_ctx* ctx, const kfx_hits* hits, const int32_t* seeds,
  * Outputs (device): state at hit N, chi2 [n] (float32, accumulated in
  * float64), ndof [n] = 2N - 5, status [n]: 1 ok, 0 failed (fewer than 3
  * hits, a hit off the geometry, a surface not reached), -1 checkpoint
- * capacity too small for this track.  ckpt: NULL, or states with stride
- * >= trk_off[n_tracks] receiving the filtered state after every hit
- * (entry trk_off[t] + i). */
+ * capacity too small for this track.  ckpt: NULL, or states receiving the
+ * filtered state after every hit, hit i of track t at entry
+ * i * n_tracks + t (one row per hit number, so that the writes of one
+ * step are coalesced); stride >= n_tracks * (longest track). */
 int kfx_fit_tracks(kfx_ctx* ctx, const kfx_hits* hits, const int32_t* trk_off,
                    const int32_t* trk_hits, int32_t n_tracks, const kfx_prior* prior,
                    const float* align, float field_scale, kfx_states* out, float* chi2,

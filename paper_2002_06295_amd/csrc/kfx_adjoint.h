@@ -15,11 +15,15 @@
 //   helix    p- = F(p, s, omega) along the chord form of the helix
 //   path     s from the surface equation (implicit-function derivative)
 //
-// The adjoints of symmetric matrices are held as full symmetric matrices G
-// with dL = sum_ij G_ij dC_ij.  The tangent-plane projection that the forward
-// transport applies (and the zeroed z row on disks) is an identity on the
-// values that exact arithmetic produces, so its derivative is the identity
-// and the sweep leaves it out.
+// The adjoint of a symmetric matrix C is the symmetric G with dL =
+// sum_ij G_ij dC_ij, stored packed like C.  J = A + b c^T with A the unit
+// matrix plus six entries, so J^T G J and the parts of the adjoint of J
+// that matter (its entries in A, J_bar c and J_bar^T b) reduce to products
+// of packed symmetric matrices with vectors; no 6x6 temporary is formed.
+// The tangent-plane projection that the forward transport applies is an
+// identity on the values that exact arithmetic produces, so its derivative
+// is the identity and the sweep leaves it out; on a disk the z row of J is
+// identically zero and is treated as the constant it is.
 //
 // Paper: arXiv 2002.06295, Sec. 1 (the Kalman filter: propagation with
 // material effects, then the update with the hit position; the fit applies
@@ -46,11 +50,15 @@ KFX_HD void sinc_dd(double a, double sa, double ca, double& f, double& f1, doubl
   }
 }
 
-KFX_HD void sym_unpack(const double* Cp, double C[6][6]) {
+// y = C x for a packed symmetric 6x6 C
+KFX_HD void symv6(const double* C, const double x[6], double y[6]) {
 #pragma unroll
-  for (int i = 0; i < 6; ++i)
+  for (int i = 0; i < 6; ++i) {
+    double acc = 0.0;
 #pragma unroll
-    for (int j = 0; j <= i; ++j) C[i][j] = C[j][i] = Cp[sidx(i, j)];
+    for (int j = 0; j < 6; ++j) acc += C[sidx(i, j)] * x[j];
+    y[i] = acc;
+  }
 }
 
 // What the reverse sweep of one step needs from its forward recompute.
@@ -58,46 +66,72 @@ struct StepTape {
   bool disk;
   double R;                       // surface radius (barrel) or z (disk)
   double kappa, omega, s;
-  double a, sa, ca, f, f1, f2;    // half turning angle, sinc and derivatives
+  double f, f1, f2;               // sinc and its derivatives at a = omega s / 2
   double cpsi, spsi;              // direction at the middle of the chord
   double dx, dy, Dx, Dy;          // chord and d(chord)/d(omega)
   double c1, s1;                  // direction at the crossing
   double sth, cth;
   double x1, y1, Dn;              // crossing point, (x1, y1) . (c1, s1)
-  double A[6];                    // Axk Ayk Axp Ayp Azt Apk
-  double cv[6], bv[6];            // J = A + b c^T
+  double A[6];                    // Axk Ayk Axp Ayp Azt Apk (the entries of A beyond the unit matrix)
+  double cv[6];                   // c = ds/dp
+  double be[6];                   // b = dF/ds as used in J (z entry 0 on a disk)
+  double d22;                     // A_zz: 1, or 0 on a disk
   // noise
   bool noise, clamped;
   double cinc, t, th0, var;
   // update
   double p1[6];
-  double C1[6][6];
   double hc, hs, r1;              // frame: (cos, sin) of the crossing's azimuth
-  double H[3][3];
-  double d[3], r[3], P[6][3], W[3][3], z[3];
+  double d[3], r[3], P[6][3], W[6], z[3];  // W = S^-1 packed (00 10 11 20 21 22)
   double chi2;
 };
 
-// J = A + b c^T as a dense 6x6.
-KFX_HD void tape_J(const StepTape& T, double J[6][6]) {
+KFX_HD int s3(int a, int b) { return a >= b ? a * (a + 1) / 2 + b : b * (b + 1) / 2 + a; }
+
+// rows u, v, n of the measurement frame
+KFX_HD void frame_rows(const StepTape& T, double H[3][3]) {
+  H[0][0] = -T.hs; H[0][1] = T.hc; H[0][2] = 0.0;
+  H[1][0] = T.disk ? T.hc : 0.0; H[1][1] = T.disk ? T.hs : 0.0; H[1][2] = T.disk ? 0.0 : 1.0;
+  H[2][0] = T.disk ? 0.0 : T.hc; H[2][1] = T.disk ? 0.0 : T.hs; H[2][2] = T.disk ? 1.0 : 0.0;
+}
+
+// y = A x and y = A^T x (A: unit matrix, z diagonal d22, plus six entries)
+KFX_HD void amul(const StepTape& T, const double x[6], double y[6]) {
+  y[0] = x[0] + T.A[0] * x[3] + T.A[2] * x[4];
+  y[1] = x[1] + T.A[1] * x[3] + T.A[3] * x[4];
+  y[2] = T.d22 * x[2] + T.d22 * T.A[4] * x[5];
+  y[3] = x[3];
+  y[4] = x[4] + T.A[5] * x[3];
+  y[5] = x[5];
+}
+KFX_HD void atmul(const StepTape& T, const double x[6], double y[6]) {
+  y[0] = x[0];
+  y[1] = x[1];
+  y[2] = T.d22 * x[2];
+  y[3] = x[3] + T.A[0] * x[0] + T.A[1] * x[1] + T.A[5] * x[4];
+  y[4] = x[4] + T.A[2] * x[0] + T.A[3] * x[1];
+  y[5] = x[5] + T.d22 * T.A[4] * x[2];
+}
+// y = J x and y = J^T x, J = A + b c^T
+KFX_HD void jmul(const StepTape& T, const double x[6], double y[6]) {
+  amul(T, x, y);
+  double cx = 0.0;
 #pragma unroll
-  for (int i = 0; i < 6; ++i)
+  for (int j = 0; j < 6; ++j) cx += T.cv[j] * x[j];
 #pragma unroll
-    for (int j = 0; j < 6; ++j) J[i][j] = (i == j ? 1.0 : 0.0) + T.bv[i] * T.cv[j];
-  J[0][3] += T.A[0];
-  J[1][3] += T.A[1];
-  J[0][4] += T.A[2];
-  J[1][4] += T.A[3];
-  J[2][5] += T.A[4];
-  J[4][3] += T.A[5];
-  if (T.disk) {
+  for (int i = 0; i < 6; ++i) y[i] += T.be[i] * cx;
+}
+KFX_HD void jtmul(const StepTape& T, const double x[6], double y[6]) {
+  atmul(T, x, y);
+  double bx = 0.0;
 #pragma unroll
-    for (int j = 0; j < 6; ++j) J[2][j] = 0.0;
-  }
+  for (int i = 0; i < 6; ++i) bx += T.be[i] * x[i];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) y[j] += T.cv[j] * bx;
 }
 
 // Multiple-scattering noise at a crossing, with what its adjoint needs.
-KFX_HD void tape_noise(StepTape& T, const Layer& Ld, double k, double sth, double cth, double cinc_raw) {
+KFX_HD void tape_noise(StepTape& T, const Layer& Ld, double k, double sth, double cth, double cinc_raw, double* C1) {
   T.noise = Ld.x0 > 0.0f;
   if (!T.noise) return;
   T.clamped = !(cinc_raw > 1e-3);
@@ -106,55 +140,50 @@ KFX_HD void tape_noise(StepTape& T, const Layer& Ld, double k, double sth, doubl
   T.th0 = 0.0136 * fabs(k) * sth * sqrt(T.t) * (1.0 + 0.038 * log(T.t));
   T.var = T.th0 * T.th0;
   const double cot = cth / sth;
-  T.C1[4][4] += T.var / (sth * sth);
-  T.C1[5][5] += T.var;
-  T.C1[3][3] += k * k * cot * cot * T.var;
-  T.C1[5][3] += -k * cot * T.var;
-  T.C1[3][5] = T.C1[5][3];
+  C1[sidx(4, 4)] += T.var / (sth * sth);
+  C1[sidx(5, 5)] += T.var;
+  C1[sidx(3, 3)] += k * k * cot * cot * T.var;
+  C1[sidx(5, 3)] += -k * cot * T.var;
 }
 
-// Update at hit m of the state (T.p1, T.C1); fills the update part of T.
-KFX_HD void tape_update(StepTape& T, const Layer& Ld, const double m[3]) {
+// Update at hit m of the state (T.p1, C1); fills the update part of T.
+KFX_HD void tape_update(StepTape& T, const Layer& Ld, const double* C1, const double m[3]) {
   T.r1 = sqrt(T.p1[0] * T.p1[0] + T.p1[1] * T.p1[1]);
   T.hc = T.p1[0] / T.r1;
   T.hs = T.p1[1] / T.r1;
-  const bool disk = Ld.kind == kDisk;
-  const double h[3][3] = {{-T.hs, T.hc, 0.0},
-                          {disk ? T.hc : 0.0, disk ? T.hs : 0.0, disk ? 0.0 : 1.0},
-                          {disk ? 0.0 : T.hc, disk ? 0.0 : T.hs, disk ? 1.0 : 0.0}};
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int j = 0; j < 3; ++j) T.H[a][j] = h[a][j];
+  T.disk = Ld.kind == kDisk;
+  double H[3][3];
+  frame_rows(T, H);
 #pragma unroll
   for (int j = 0; j < 3; ++j) T.d[j] = m[j] - T.p1[j];
 #pragma unroll
-  for (int a = 0; a < 3; ++a) T.r[a] = T.H[a][0] * T.d[0] + T.H[a][1] * T.d[1] + T.H[a][2] * T.d[2];
+  for (int a = 0; a < 3; ++a) T.r[a] = H[a][0] * T.d[0] + H[a][1] * T.d[1] + H[a][2] * T.d[2];
 #pragma unroll
   for (int i = 0; i < 6; ++i)
 #pragma unroll
     for (int a = 0; a < 3; ++a)
-      T.P[i][a] = T.C1[i][0] * T.H[a][0] + T.C1[i][1] * T.H[a][1] + T.C1[i][2] * T.H[a][2];
+      T.P[i][a] = C1[sidx(i, 0)] * H[a][0] + C1[sidx(i, 1)] * H[a][1] + C1[sidx(i, 2)] * H[a][2];
   const double V[3] = {(double)Ld.v_u, (double)Ld.v_v, (double)Ld.v_n};
   double S[3][3];
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
     for (int b = 0; b < 3; ++b)
-      S[a][b] = T.H[a][0] * T.P[0][b] + T.H[a][1] * T.P[1][b] + T.H[a][2] * T.P[2][b] + (a == b ? V[a] : 0.0);
+      S[a][b] = H[a][0] * T.P[0][b] + H[a][1] * T.P[1][b] + H[a][2] * T.P[2][b] + (a == b ? V[a] : 0.0);
   // symmetric 3x3 inverse by cofactors
   const double c00 = S[1][1] * S[2][2] - S[1][2] * S[2][1];
   const double c01 = S[1][2] * S[2][0] - S[1][0] * S[2][2];
   const double c02 = S[1][0] * S[2][1] - S[1][1] * S[2][0];
   const double id = 1.0 / (S[0][0] * c00 + S[0][1] * c01 + S[0][2] * c02);
-  T.W[0][0] = c00 * id;
-  T.W[1][0] = T.W[0][1] = c01 * id;
-  T.W[2][0] = T.W[0][2] = c02 * id;
-  T.W[1][1] = (S[0][0] * S[2][2] - S[0][2] * S[2][0]) * id;
-  T.W[2][1] = T.W[1][2] = (S[0][1] * S[2][0] - S[0][0] * S[2][1]) * id;
-  T.W[2][2] = (S[0][0] * S[1][1] - S[0][1] * S[1][0]) * id;
+  T.W[s3(0, 0)] = c00 * id;
+  T.W[s3(1, 0)] = c01 * id;
+  T.W[s3(2, 0)] = c02 * id;
+  T.W[s3(1, 1)] = (S[0][0] * S[2][2] - S[0][2] * S[2][0]) * id;
+  T.W[s3(2, 1)] = (S[0][1] * S[2][0] - S[0][0] * S[2][1]) * id;
+  T.W[s3(2, 2)] = (S[0][0] * S[1][1] - S[0][1] * S[1][0]) * id;
 #pragma unroll
-  for (int a = 0; a < 3; ++a) T.z[a] = T.W[a][0] * T.r[0] + T.W[a][1] * T.r[1] + T.W[a][2] * T.r[2];
+  for (int a = 0; a < 3; ++a)
+    T.z[a] = T.W[s3(a, 0)] * T.r[0] + T.W[s3(a, 1)] * T.r[1] + T.W[s3(a, 2)] * T.r[2];
   T.chi2 = T.r[0] * T.z[0] + T.r[1] * T.z[1] + T.r[2] * T.z[2];
 }
 
@@ -172,19 +201,20 @@ KFX_HD bool tape_step(StepTape& T, const StateT<double>& st0, const Layer& Ld, d
   T.s = path_to_layer(st0, Ld, R, cphi, sphi, T.omega);
   if (!(T.s > 0.0)) return false;
   const double s = T.s;
-  T.a = 0.5 * T.omega * s;
-  sincos_d(T.a, T.sa, T.ca);
-  sinc_dd(T.a, T.sa, T.ca, T.f, T.f1, T.f2);
-  T.cpsi = cphi * T.ca - sphi * T.sa;
-  T.spsi = sphi * T.ca + cphi * T.sa;
+  const double a = 0.5 * T.omega * s;
+  double sa, ca;
+  sincos_d(a, sa, ca);
+  sinc_dd(a, sa, ca, T.f, T.f1, T.f2);
+  T.cpsi = cphi * ca - sphi * sa;
+  T.spsi = sphi * ca + cphi * sa;
   const double L = s * T.f;
   T.dx = L * T.cpsi;
   T.dy = L * T.spsi;
   const double hs2 = 0.5 * s * s;
   T.Dx = hs2 * (T.f1 * T.cpsi - T.f * T.spsi);
   T.Dy = hs2 * (T.f1 * T.spsi + T.f * T.cpsi);
-  T.c1 = T.cpsi * T.ca - T.spsi * T.sa;
-  T.s1 = T.spsi * T.ca + T.cpsi * T.sa;
+  T.c1 = T.cpsi * ca - T.spsi * sa;
+  T.s1 = T.spsi * ca + T.cpsi * sa;
   sincos_d(st0.th, T.sth, T.cth);
   const double cot = T.cth / T.sth;
   T.x1 = st0.x + T.dx;
@@ -193,7 +223,7 @@ KFX_HD bool tape_step(StepTape& T, const StateT<double>& st0, const Layer& Ld, d
   T.p1[1] = T.y1;
   T.p1[2] = T.disk ? (double)Ld.pos : st0.z + s * cot;
   T.p1[3] = st0.k;
-  T.p1[4] = wrap_pi(st0.phi + 2.0 * T.a);
+  T.p1[4] = wrap_pi(st0.phi + 2.0 * a);
   T.p1[5] = st0.th;
   T.A[0] = kappa * T.Dx;
   T.A[1] = kappa * T.Dy;
@@ -201,6 +231,7 @@ KFX_HD bool tape_step(StepTape& T, const StateT<double>& st0, const Layer& Ld, d
   T.A[3] = T.dx;
   T.A[4] = -s / (T.sth * T.sth);
   T.A[5] = kappa * s;
+  T.d22 = T.disk ? 0.0 : 1.0;
   T.Dn = T.x1 * T.c1 + T.y1 * T.s1;
   if (T.disk) {
     T.cv[0] = T.cv[1] = T.cv[3] = T.cv[4] = 0.0;
@@ -215,46 +246,40 @@ KFX_HD bool tape_step(StepTape& T, const StateT<double>& st0, const Layer& Ld, d
     T.cv[4] = (T.x1 * T.A[2] + T.y1 * T.A[3]) * iDn;
     T.cv[5] = 0.0;
   }
-  T.bv[0] = T.c1;
-  T.bv[1] = T.s1;
-  T.bv[2] = cot;
-  T.bv[3] = 0.0;
-  T.bv[4] = T.omega;
-  T.bv[5] = 0.0;
-  double J[6][6], C0[6][6], M[6][6];
-  tape_J(T, J);
-  sym_unpack(st0.C, C0);
+  T.be[0] = T.c1;
+  T.be[1] = T.s1;
+  T.be[2] = T.disk ? 0.0 : cot;
+  T.be[3] = 0.0;
+  T.be[4] = T.omega;
+  T.be[5] = 0.0;
+  // C1 = J C0 J^T, one column at a time: column j is J (C0 J^T e_j)
+  double C1[21];
 #pragma unroll
-  for (int i = 0; i < 6; ++i)
+  for (int j = 0; j < 6; ++j) {
+    double e[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    e[j] = 1.0;
+    double rj[6], zj[6], wj[6];
+    jtmul(T, e, rj);
+    symv6(st0.C, rj, zj);
+    jmul(T, zj, wj);
 #pragma unroll
-    for (int j = 0; j < 6; ++j) {
-      double acc = 0.0;
-#pragma unroll
-      for (int q = 0; q < 6; ++q) acc += J[i][q] * C0[q][j];
-      M[i][j] = acc;
-    }
-#pragma unroll
-  for (int i = 0; i < 6; ++i)
-#pragma unroll
-    for (int j = 0; j <= i; ++j) {
-      double acc = 0.0;
-#pragma unroll
-      for (int q = 0; q < 6; ++q) acc += M[i][q] * J[j][q];
-      T.C1[i][j] = T.C1[j][i] = acc;
-    }
+    for (int i = j; i < 6; ++i) C1[sidx(i, j)] = wj[i];
+  }
   const double cinc_raw = T.disk ? fabs(T.cth) : fabs(T.sth * T.Dn / sqrt(T.x1 * T.x1 + T.y1 * T.y1));
-  tape_noise(T, Ld, st0.k, T.sth, T.cth, cinc_raw);
-  tape_update(T, Ld, m);
+  tape_noise(T, Ld, st0.k, T.sth, T.cth, cinc_raw, C1);
+  tape_update(T, Ld, C1, m);
   return true;
 }
 
-// Adjoint of the update.  In: pb (adjoint of p+), G (adjoint of C+), w (the
-// weight of this step's chi2).  Out: pb and G become the adjoints of p- and
-// C- (update part only: the frame's dependence on x- is included), mb the
+// Adjoint of the update.  In: pb (adjoint of p+), G (adjoint of C+,
+// packed), w (the weight of this step's chi2).  Out: pb and G become the
+// adjoints of p- and C- (the frame's dependence on x- included), mb the
 // adjoint of the measurement.
-KFX_HD void adj_update(const StepTape& T, double pb[6], double G[6][6], double w, double mb[3]) {
-  double zb[3], Pb[6][3], Wb[3][3], rb[3], Hb[3][3], X[6][6];
-  // p+ = p- + P z
+KFX_HD void adj_update(const StepTape& T, double pb[6], double* G, double w, double mb[3]) {
+  double H[3][3];
+  frame_rows(T, H);
+  // p+ = p- + P z:  zb = P^T pb
+  double zb[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     double acc = 0.0;
@@ -262,23 +287,24 @@ KFX_HD void adj_update(const StepTape& T, double pb[6], double G[6][6], double w
     for (int i = 0; i < 6; ++i) acc += T.P[i][a] * pb[i];
     zb[a] = acc;
   }
-  // GP = G P, then Pb = pb z^T - 2 G P W
+  // GP = G P
   double GP[6][3];
 #pragma unroll
-  for (int i = 0; i < 6; ++i)
+  for (int a = 0; a < 3; ++a) {
+    const double pa[6] = {T.P[0][a], T.P[1][a], T.P[2][a], T.P[3][a], T.P[4][a], T.P[5][a]};
+    double y[6];
+    symv6(G, pa, y);
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      double acc = 0.0;
-#pragma unroll
-      for (int q = 0; q < 6; ++q) acc += G[i][q] * T.P[q][a];
-      GP[i][a] = acc;
-    }
+    for (int i = 0; i < 6; ++i) GP[i][a] = y[i];
+  }
+  // C+ = C- - P W P^T:  Pb = pb z^T - 2 G P W;  Wb = -P^T G P + w r r^T + zb r^T
+  double Pb[6][3], Wb[3][3];
 #pragma unroll
   for (int i = 0; i < 6; ++i)
 #pragma unroll
     for (int a = 0; a < 3; ++a)
-      Pb[i][a] = pb[i] * T.z[a] - 2.0 * (GP[i][0] * T.W[0][a] + GP[i][1] * T.W[1][a] + GP[i][2] * T.W[2][a]);
-  // Wb = -P^T G P + w r r^T + zb r^T
+      Pb[i][a] = pb[i] * T.z[a] -
+                 2.0 * (GP[i][0] * T.W[s3(0, a)] + GP[i][1] * T.W[s3(1, a)] + GP[i][2] * T.W[s3(2, a)]);
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
@@ -288,59 +314,70 @@ KFX_HD void adj_update(const StepTape& T, double pb[6], double G[6][6], double w
       for (int i = 0; i < 6; ++i) acc += T.P[i][a] * GP[i][b];
       Wb[a][b] = -acc + w * T.r[a] * T.r[b] + zb[a] * T.r[b];
     }
-  // rb = 2 w z + W zb
+  // chi2 = r^T z, z = W r:  rb = 2 w z + W zb
+  double rb[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a)
-    rb[a] = 2.0 * w * T.z[a] + T.W[a][0] * zb[0] + T.W[a][1] * zb[1] + T.W[a][2] * zb[2];
-  // Sb = -W Wb W, symmetrised
+    rb[a] = 2.0 * w * T.z[a] + T.W[s3(a, 0)] * zb[0] + T.W[s3(a, 1)] * zb[1] + T.W[s3(a, 2)] * zb[2];
+  // W = S^-1:  Sb = -W Wb W, symmetrised
   double WW[3][3], Sb[3][3];
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
-    for (int b = 0; b < 3; ++b) WW[a][b] = Wb[a][0] * T.W[0][b] + Wb[a][1] * T.W[1][b] + Wb[a][2] * T.W[2][b];
+    for (int b = 0; b < 3; ++b)
+      WW[a][b] = Wb[a][0] * T.W[s3(0, b)] + Wb[a][1] * T.W[s3(1, b)] + Wb[a][2] * T.W[s3(2, b)];
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
-    for (int b = 0; b < 3; ++b) Sb[a][b] = -(T.W[a][0] * WW[0][b] + T.W[a][1] * WW[1][b] + T.W[a][2] * WW[2][b]);
+    for (int b = 0; b < 3; ++b)
+      Sb[a][b] = -(T.W[s3(a, 0)] * WW[0][b] + T.W[s3(a, 1)] * WW[1][b] + T.W[s3(a, 2)] * WW[2][b]);
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
     for (int b = 0; b < a; ++b) Sb[a][b] = Sb[b][a] = 0.5 * (Sb[a][b] + Sb[b][a]);
-  // X collects the (unsymmetrised) adjoint of C-: G, H^T Sb H on the
-  // position block, and Pb H on the position columns
+  // the position columns of C-: CP = P H (H is orthonormal)
+  double CP[6][3];
 #pragma unroll
   for (int i = 0; i < 6; ++i)
 #pragma unroll
-    for (int j = 0; j < 6; ++j) X[i][j] = G[i][j];
-  double SbH[3][3];
+    for (int j = 0; j < 3; ++j) CP[i][j] = T.P[i][0] * H[0][j] + T.P[i][1] * H[1][j] + T.P[i][2] * H[2][j];
+  // S = H C_pp H^T + V and P = C[:, pos] H^T:  the adjoint of C- gains
+  // H^T Sb H on the position block and Pb H on the position columns; H gains
+  // 2 Sb H C_pp + Pb^T C[:, pos] + rb d^T
+  double SbH[3][3], PbH[6][3], Hb[3][3];
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
-    for (int j = 0; j < 3; ++j) SbH[a][j] = Sb[a][0] * T.H[0][j] + Sb[a][1] * T.H[1][j] + Sb[a][2] * T.H[2][j];
-#pragma unroll
-  for (int i = 0; i < 3; ++i)
-#pragma unroll
-    for (int j = 0; j < 3; ++j) X[i][j] += T.H[0][i] * SbH[0][j] + T.H[1][i] * SbH[1][j] + T.H[2][i] * SbH[2][j];
+    for (int j = 0; j < 3; ++j) SbH[a][j] = Sb[a][0] * H[0][j] + Sb[a][1] * H[1][j] + Sb[a][2] * H[2][j];
 #pragma unroll
   for (int i = 0; i < 6; ++i)
 #pragma unroll
-    for (int j = 0; j < 3; ++j) X[i][j] += Pb[i][0] * T.H[0][j] + Pb[i][1] * T.H[1][j] + Pb[i][2] * T.H[2][j];
-  // Hb = 2 Sb H C_pp + Pb^T C[:, pos] + rb d^T
+    for (int j = 0; j < 3; ++j) PbH[i][j] = Pb[i][0] * H[0][j] + Pb[i][1] * H[1][j] + Pb[i][2] * H[2][j];
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
       double acc = rb[a] * T.d[j];
 #pragma unroll
-      for (int q = 0; q < 3; ++q) acc += 2.0 * SbH[a][q] * T.C1[q][j];
+      for (int q = 0; q < 3; ++q) acc += 2.0 * SbH[a][q] * CP[q][j];
 #pragma unroll
-      for (int i = 0; i < 6; ++i) acc += Pb[i][a] * T.C1[i][j];
+      for (int i = 0; i < 6; ++i) acc += Pb[i][a] * CP[i][j];
       Hb[a][j] = acc;
     }
-  // d = m - x-: mb = H^T rb, pb_pos -= mb
+#pragma unroll
+  for (int i = 0; i < 6; ++i)
+#pragma unroll
+    for (int j = 0; j <= i; ++j) {
+      double add = 0.0;
+      if (i < 3) add += H[0][i] * SbH[0][j] + H[1][i] * SbH[1][j] + H[2][i] * SbH[2][j];  // j <= i < 3
+      if (j < 3) add += 0.5 * PbH[i][j];
+      if (i < 3) add += 0.5 * PbH[j][i];
+      G[sidx(i, j)] += add;
+    }
+  // d = m - x-:  mb = H^T rb, pb_pos -= mb
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
-    mb[j] = T.H[0][j] * rb[0] + T.H[1][j] * rb[1] + T.H[2][j] * rb[2];
+    mb[j] = H[0][j] * rb[0] + H[1][j] * rb[1] + H[2][j] * rb[2];
     pb[j] -= mb[j];
   }
   // frame: H from (hc, hs) = (x, y) / r
@@ -355,18 +392,13 @@ KFX_HD void adj_update(const StepTape& T, double pb[6], double G[6][6], double w
   const double ir = 1.0 / T.r1;
   pb[0] += (hcb * T.hs * T.hs - hsb * T.hc * T.hs) * ir;
   pb[1] += (-hcb * T.hc * T.hs + hsb * T.hc * T.hc) * ir;
-#pragma unroll
-  for (int i = 0; i < 6; ++i)
-#pragma unroll
-    for (int j = 0; j <= i; ++j) G[i][j] = G[j][i] = 0.5 * (X[i][j] + X[j][i]);
 }
 
 // Adjoint of the transport + noise.  In: pb, G = adjoints of (p-, C-) after
-// the noise; C0 the covariance the step started from.  Out: pb, G become
-// the adjoints of (p0, C0); Rb and kb the adjoints of the surface radius and
-// of kappa.
-KFX_HD void adj_transport(const StepTape& T, const double C0[6][6], double pb[6], double G[6][6], double& Rb,
-                          double& kb) {
+// the noise (G packed); C0 the covariance the step started from (packed).
+// Out: pb, G become the adjoints of (p0, C0); Rb and kb the adjoints of the
+// surface radius and of kappa.
+KFX_HD void adj_transport(const StepTape& T, const double* C0, double pb[6], double* G, double& Rb, double& kb) {
   const double s = T.s, sth = T.sth, cth = T.cth;
   const double cot = cth / sth;
   const double k0 = T.p1[3];
@@ -377,10 +409,11 @@ KFX_HD void adj_transport(const StepTape& T, const double C0[6][6], double pb[6]
   Rb = 0.0;
   // ---- noise
   if (T.noise) {
-    const double vb = G[4][4] / (sth * sth) + G[5][5] + G[3][3] * k0 * k0 * cot * cot - 2.0 * G[5][3] * k0 * cot;
-    kb0 += G[3][3] * 2.0 * k0 * cot * cot * T.var - 2.0 * G[5][3] * cot * T.var;
-    cotb += G[3][3] * k0 * k0 * 2.0 * cot * T.var - 2.0 * G[5][3] * k0 * T.var;
-    sthb += -2.0 * G[4][4] * T.var / (sth * sth * sth);
+    const double G33 = G[sidx(3, 3)], G44 = G[sidx(4, 4)], G55 = G[sidx(5, 5)], G53 = G[sidx(5, 3)];
+    const double vb = G44 / (sth * sth) + G55 + G33 * k0 * k0 * cot * cot - 2.0 * G53 * k0 * cot;
+    kb0 += G33 * 2.0 * k0 * cot * cot * T.var - 2.0 * G53 * cot * T.var;
+    cotb += G33 * k0 * k0 * 2.0 * cot * T.var - 2.0 * G53 * k0 * T.var;
+    sthb += -2.0 * G44 * T.var / (sth * sth * sth);
     const double th0b = 2.0 * T.th0 * vb;
     if (k0 != 0.0) kb0 += th0b * T.th0 / k0;
     sthb += th0b * T.th0 / sth;
@@ -402,64 +435,73 @@ KFX_HD void adj_transport(const StepTape& T, const double C0[6][6], double pb[6]
       }
     }
   }
-  // ---- covariance: C- = J C0 J^T
-  double J[6][6], JC[6][6], Jb[6][6], GJ[6][6];
-  tape_J(T, J);
+  // ---- covariance C- = J C0 J^T with J = A + b c^T.
+  // The parts of J_bar = 2 G J C0 that reach the parameters:
+  //   J_bar c = 2 G J (C0 c),   J_bar^T b = 2 C0 J^T (G b),
+  //   its entries in A (columns 3, 4, 5: 2 G J (C0 e_j)).
+  double u[6];
+  symv6(G, T.be, u);
+  double bb[6], cb[6], Ab[6];
+  {
+    double v[6], jv[6];
+    symv6(C0, T.cv, v);
+    jmul(T, v, jv);
+    symv6(G, jv, bb);
 #pragma unroll
-  for (int i = 0; i < 6; ++i)
+    for (int i = 0; i < 6; ++i) bb[i] *= 2.0;
+    double jtu[6];
+    jtmul(T, u, jtu);
+    symv6(C0, jtu, cb);
 #pragma unroll
-    for (int j = 0; j < 6; ++j) {
-      double acc = 0.0;
+    for (int i = 0; i < 6; ++i) cb[i] *= 2.0;
+    double col[6], y[6], gy[6];
 #pragma unroll
-      for (int q = 0; q < 6; ++q) acc += G[i][q] * J[q][j];
-      GJ[i][j] = acc;
-    }
-  // Jb = 2 G J C0
+    for (int q = 0; q < 6; ++q) col[q] = C0[sidx(q, 3)];
+    jmul(T, col, y);
+    symv6(G, y, gy);
+    Ab[0] = 2.0 * gy[0];
+    Ab[1] = 2.0 * gy[1];
+    Ab[5] = 2.0 * gy[4];
 #pragma unroll
-  for (int i = 0; i < 6; ++i)
+    for (int q = 0; q < 6; ++q) col[q] = C0[sidx(q, 4)];
+    jmul(T, col, y);
+    symv6(G, y, gy);
+    Ab[2] = 2.0 * gy[0];
+    Ab[3] = 2.0 * gy[1];
 #pragma unroll
-    for (int j = 0; j < 6; ++j) {
-      double acc = 0.0;
-#pragma unroll
-      for (int q = 0; q < 6; ++q) acc += GJ[i][q] * C0[q][j];
-      Jb[i][j] = 2.0 * acc;
-    }
-  // G0 = J^T G J
-#pragma unroll
-  for (int i = 0; i < 6; ++i)
-#pragma unroll
-    for (int j = 0; j < 6; ++j) {
-      double acc = 0.0;
-#pragma unroll
-      for (int q = 0; q < 6; ++q) acc += J[q][i] * GJ[q][j];
-      JC[i][j] = acc;
-    }
-#pragma unroll
-  for (int i = 0; i < 6; ++i)
-#pragma unroll
-    for (int j = 0; j <= i; ++j) G[i][j] = G[j][i] = 0.5 * (JC[i][j] + JC[j][i]);
-  if (T.disk) {
-#pragma unroll
-    for (int j = 0; j < 6; ++j) Jb[2][j] = 0.0;
+    for (int q = 0; q < 6; ++q) col[q] = C0[sidx(q, 5)];
+    jmul(T, col, y);
+    symv6(G, y, gy);
+    Ab[4] = T.disk ? 0.0 : 2.0 * gy[2];
   }
-  // J = A + b c^T
-  double cb[6], bb[6];
+  // G0 = J^T G J = A^T G A + w c^T + c w^T + sigma c c^T, w = A^T G b,
+  // sigma = b^T G b; A^T G A column by column
+  {
+    double wv[6];
+    atmul(T, u, wv);
+    double sig = 0.0;
 #pragma unroll
-  for (int i = 0; i < 6; ++i) {
-    double a1 = 0.0, a2 = 0.0;
+    for (int i = 0; i < 6; ++i) sig += T.be[i] * u[i];
+    double G0[21];
 #pragma unroll
-    for (int q = 0; q < 6; ++q) {
-      a1 += Jb[i][q] * T.cv[q];
-      a2 += Jb[q][i] * T.bv[q];
+    for (int j = 0; j < 6; ++j) {
+      double e[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+      e[j] = 1.0;
+      double aj[6], nj[6], mj[6];
+      amul(T, e, aj);
+      symv6(G, aj, nj);
+      atmul(T, nj, mj);
+#pragma unroll
+      for (int i = j; i < 6; ++i)
+        G0[sidx(i, j)] = mj[i] + wv[i] * T.cv[j] + T.cv[i] * wv[j] + sig * T.cv[i] * T.cv[j];
     }
-    bb[i] = a1;
-    cb[i] = a2;
+#pragma unroll
+    for (int q = 0; q < 21; ++q) G[q] = G0[q];
   }
-  double Ab[6] = {Jb[0][3], Jb[1][3], Jb[0][4], Jb[1][4], Jb[2][5], Jb[4][3]};
-  // b = (c1, s1, cot, 0, omega, 0)
+  // b = (c1, s1, cot, 0, omega, 0); on a disk the z entry is the constant 0
   c1b += bb[0];
   s1b += bb[1];
-  cotb += bb[2];
+  if (!T.disk) cotb += bb[2];
   ob += bb[4];
   // c
   if (T.disk) {
@@ -494,7 +536,7 @@ KFX_HD void adj_transport(const StepTape& T, const double C0[6][6], double pb[6]
   sthb += Ab[4] * 2.0 * s / (sth * sth * sth);
   sb += Ab[5] * T.kappa;
   kb += Ab[5] * s;
-  double Dxb = T.kappa * Ab[0], Dyb = T.kappa * Ab[1];
+  const double Dxb = T.kappa * Ab[0], Dyb = T.kappa * Ab[1];
   kb += Ab[0] * T.Dx + Ab[1] * T.Dy;
   // ---- parameters p- = F(p0, s, omega)
   double pb0[6] = {x1b, y1b, 0.0, kb0, 0.0, thb};
@@ -569,22 +611,21 @@ KFX_HD void hit_grad(const Layer& Ld, int l, const double m[3], const double mb[
 
 // Reverse sweep of one fitted track: adds w * d(chi2 of the track) /
 // d(alignment, field scale) to acc.  ckpt holds the filtered state after
-// each hit (as written by fit_track).  Returns false for a track that the
+// each hit (as written by fit_track: hit i of track t at i * n_tracks + t).  Returns false for a track that the
 // forward fit did not fit.
 template <class Acc>
 KFX_HD bool fit_track_backward(const Geometry& G, const HitsView& H, const int* trk_off, const int* trk_hits, int t,
-                               const Prior& pr, const float* align, float fscale, const StateSoA& ckpt, double w,
+                               const Prior& pr, const float* align, float fscale, const StateSoA& ckpt,
+                               int n_tracks, double w,
                                Acc& acc) {
   const int b = trk_off[t], n = trk_off[t + 1] - trk_off[t];
   if (n < 3) return false;
   const double kappa0 = -kHcD * G.bz;
   const double kappa = kappa0 * (double)fscale;
   double pb[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  double Gb[6][6];
+  double Gb[21];
 #pragma unroll
-  for (int i = 0; i < 6; ++i)
-#pragma unroll
-    for (int j = 0; j < 6; ++j) Gb[i][j] = 0.0;
+  for (int q = 0; q < 21; ++q) Gb[q] = 0.0;
   double fb = 0.0;
   for (int i = n - 1; i >= 0; --i) {
     const int h = trk_hits[b + i];
@@ -598,15 +639,13 @@ KFX_HD bool fit_track_backward(const Geometry& G, const HitsView& H, const int* 
     if (i > 0) {
       const double r_surf = Ld.pos + ((a && Ld.kind == kBarrel) ? (double)a[0] : 0.0);
       State c;
-      load_state(ckpt, b + i - 1, c);
+      load_state(ckpt, (long)(i - 1) * n_tracks + t, c);
       StateT<double> s0;
       convert_state(c, s0);
       if (!tape_step(T, s0, Ld, r_surf, kappa, m)) return false;
       adj_update(T, pb, Gb, w, mb);
-      double C0[6][6];
-      sym_unpack(s0.C, C0);
       double kb = 0.0;
-      adj_transport(T, C0, pb, Gb, Rb, kb);
+      adj_transport(T, s0.C, pb, Gb, Rb, kb);
       fb += kb * kappa0;
     } else {
       // the start estimate from the first three hits as recorded, with the
@@ -622,10 +661,8 @@ KFX_HD bool fit_track_backward(const Geometry& G, const HitsView& H, const int* 
       seed_estimate(G.bz, m0[0], m0[1], m0[2], sd);
       prior_cov(pr, sd);
       add_material(sd, Ld);
-      T.disk = Ld.kind == kDisk;
       T.p1[0] = sd.x; T.p1[1] = sd.y; T.p1[2] = sd.z; T.p1[3] = sd.k; T.p1[4] = sd.phi; T.p1[5] = sd.th;
-      sym_unpack(sd.C, T.C1);
-      tape_update(T, Ld, m);
+      tape_update(T, Ld, sd.C, m);
       adj_update(T, pb, Gb, w, mb);
     }
     hit_grad(Ld, l, m, mb, Rb, acc);

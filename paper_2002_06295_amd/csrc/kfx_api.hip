@@ -721,6 +721,7 @@ int kfx_fit_tracks(kfx_ctx* c, const kfx_hits* hits, const int32_t* trk_off, con
   o.status = status;
   if (ckpt) o.ckpt = soa(ckpt);
   else o.ckpt.par = nullptr, o.ckpt.cov = nullptr, o.ckpt.stride = 0;
+  o.n_tracks = n_tracks;
   launch_fit(c->dev_geo, view(hits), trk_off, trk_hits, n_tracks, prior_of(prior), align, field_scale, o, st);
   return hip_check(c, hipGetLastError(), "fit kernel");
 }

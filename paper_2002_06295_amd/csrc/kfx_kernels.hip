@@ -210,7 +210,7 @@ __global__ void __launch_bounds__(64) k_fit_backward(const Geometry* __restrict_
     const double w = per_track ? (double)dchi2[t] : (double)dchi2[0];
     if (w != 0.0) {
       LdsAcc acc{acc_lds + lane, G->brank, nb};
-      fit_track_backward(*G, H, trk_off, trk_hits, t, pr, align, fscale, ckpt, w, acc);
+      fit_track_backward(*G, H, trk_off, trk_hits, t, pr, align, fscale, ckpt, n_tracks, w, acc);
     }
   }
   __syncthreads();

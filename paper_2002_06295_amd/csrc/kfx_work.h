@@ -447,7 +447,8 @@ struct FitOut {
   float* chi2;
   int* ndof;
   int* status;        // 1 ok, 0 failed
-  StateSoA ckpt;      // per hit slot (pos == nullptr: none)
+  StateSoA ckpt;      // after hit i of track t: entry i * n_tracks + t (par == nullptr: none)
+  int n_tracks;
 };
 
 KFX_HD void fit_track(const Geometry& G, const HitsView& H, const int* trk_off, const int* trk_hits,
@@ -457,7 +458,7 @@ KFX_HD void fit_track(const Geometry& G, const HitsView& H, const int* trk_off, 
   double chi2 = 0.0;
   bool ok = n >= 3;
   // checkpoints beyond the caller's capacity: the track is not fitted
-  const bool ckpt_fits = !o.ckpt.par || (long)b + n <= o.ckpt.stride;
+  const bool ckpt_fits = !o.ckpt.par || (long)(n - 1) * o.n_tracks + t < o.ckpt.stride;
   ok = ok && ckpt_fits;
   for (int i = 0; ok && i < n; ++i) {
     const int h = trk_hits[b + i];
@@ -493,7 +494,7 @@ KFX_HD void fit_track(const Geometry& G, const HitsView& H, const int* trk_off, 
       chi2 += c2;
       if (ok && o.ckpt.par) {
         convert_state(sd, st);
-        store_state(o.ckpt, b + i, st);
+        store_state(o.ckpt, (long)i * o.n_tracks + t, st);
       }
     }
     convert_state(sd, st);

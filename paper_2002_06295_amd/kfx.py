@@ -420,7 +420,9 @@ class Context:
                        ndof=torch.zeros(max(T, 1), dtype=torch.int32, device=d),
                        status=torch.zeros(max(T, 1), dtype=torch.int32, device=d))
             if ckpt:
-                out["ckpt"] = States.empty(int(trk_hits.shape[0]), d)
+                lens = torch.diff(trk_off.to(torch.int64))
+                longest = int(lens.max().item()) if T > 0 else 0
+                out["ckpt"] = States.empty(max(T * longest, 1), d)
         pr = prior_struct(prior)
         so = out["state"].c()
         ck = out["ckpt"].c() if "ckpt" in out else None

@@ -4,6 +4,7 @@
 // library never loads this; only tests/ do.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstring>
 #include <vector>
 
@@ -108,6 +109,7 @@ void hs_fit(const double* table, int nl, double bz, const float* x, const float*
   o.ndof = ndof;
   o.status = status;
   o.ckpt = StateSoA{nullptr, nullptr, 0};
+  o.n_tracks = nt;
   for (int t = 0; t < nt; ++t) {
     fit_track(G, H, trk_off, trk_hits, t, pr, align, fscale, o);
     State s;
@@ -147,7 +149,9 @@ double hs_fit_grad(const double* table, int nl, double bz, const float* x, const
   Geometry G = make_geo(table, nl, bz);
   HitsView H{x, y, z, layer, nullptr, nhits, 1};
   Prior pr{prior[0], prior[1], prior[2], prior[3]};
-  const long ns = trk_off[nt];
+  long longest = 0;
+  for (int t = 0; t < nt; ++t) longest = std::max<long>(longest, trk_off[t + 1] - trk_off[t]);
+  const long ns = std::max<long>((long)nt * longest, 1);
   std::vector<double> par(6 * (size_t)nt), cpar(6 * (size_t)ns);
   std::vector<float> cov(21 * (size_t)nt), ccov(21 * (size_t)ns), c2(nt);
   std::vector<int> ndof(nt), status(nt);
@@ -157,6 +161,7 @@ double hs_fit_grad(const double* table, int nl, double bz, const float* x, const
   o.ndof = ndof.data();
   o.status = status.data();
   o.ckpt = StateSoA{cpar.data(), ccov.data(), ns};
+  o.n_tracks = nt;
   for (int i = 0; i < 3 * nl + 1; ++i) grad[i] = 0.0;
   HostAcc acc{grad, nl};
   double tot = 0.0;
@@ -164,7 +169,7 @@ double hs_fit_grad(const double* table, int nl, double bz, const float* x, const
     fit_track(G, H, trk_off, trk_hits, t, pr, align, fscale, o);
     if (status[t] != 1) continue;
     tot += c2[t];
-    fit_track_backward(G, H, trk_off, trk_hits, t, pr, align, fscale, o.ckpt, w ? w[t] : 1.0, acc);
+    fit_track_backward(G, H, trk_off, trk_hits, t, pr, align, fscale, o.ckpt, nt, w ? w[t] : 1.0, acc);
   }
   return tot;
 }

@@ -250,7 +250,9 @@ def test_fit_checkpoints_match_forward(dev, kfx):
     out = ctx.fit_tracks(hits, ev.trk_offsets, ev.trk_hits, prior=PRIOR, ckpt=True)
     pc, Cc = out["ckpt"].to_numpy()
     pf, Cf = out["state"].to_numpy()
-    last = ev.trk_offsets[1:] - 1
+    # hit i of track t at i * n_tracks + t
+    T = ev.n_tracks
+    last = (np.diff(ev.trk_offsets) - 1) * T + np.arange(T)
     ok = out["status"].cpu().numpy() == 1
     assert np.array_equal(pc[last][ok], pf[ok]) and np.array_equal(Cc[last][ok], Cf[ok])
 
