@@ -389,6 +389,7 @@ __global__ void k_build_finalize(BuildArgs a, int fin, TracksOut o) {
 // path: navigate + transport, window scan, selection (here K rounds of a
 // segmented wavefront minimum over the lanes' child streams) and update;
 // states move between lanes through LDS.
+template <int G_LANES>
 struct FusedShared {
   // per lane: the state its children start from -- the prediction on the
   // next surface, or the current state when its child is a stop child --
@@ -398,12 +399,17 @@ struct FusedShared {
   int layer;
   int meta;
   float chi2;
+  // the lane's children in stream order (keys, codes, chi2 totals)
+  uint64_t ekey[G_LANES + 1];
+  int ecode[G_LANES + 1];
+  float echi2[G_LANES + 1];
   // the child picked for this slot by the selection (written by the winner)
   int sel_code;
   float sel_chi2;
 };
 
-__device__ inline void lds_put(FusedShared& d, const State& s, int layer) {
+template <class FS>
+__device__ inline void lds_put(FS& d, const State& s, int layer) {
   double* p = d.par;
   p[0] = s.x; p[1] = s.y; p[2] = s.z; p[3] = s.k; p[4] = s.phi; p[5] = s.th;
 #pragma unroll
@@ -411,7 +417,8 @@ __device__ inline void lds_put(FusedShared& d, const State& s, int layer) {
   d.layer = layer;
 }
 
-__device__ inline void lds_get(const FusedShared& d, State& s) {
+template <class FS>
+__device__ inline void lds_get(const FS& d, State& s) {
   const double* p = d.par;
   s.x = p[0]; s.y = p[1]; s.z = p[2]; s.k = p[3]; s.phi = p[4]; s.th = p[5];
 #pragma unroll
@@ -637,36 +644,12 @@ __device__ int wave_scan(const BinIndex& B, int n_phi, int lane, bool has, const
   return found;
 }
 
-// Key of the next child of a lane's stream (see kid_key): the head of its
-// sorted hit list, then the hole, or its single stop child.
-template <int KM>
-__device__ inline uint64_t lane_head(const KidStream& k, const BestK<KM>& b, int popped, bool hole_used,
-                                     int K, float& chi2_out, int& code) {
-  if (!k.live) return ~0ull;
-  if (k.stop) {
-    if (popped > 0) return ~0ull;
-    chi2_out = k.chi2;
-    code = kStop;
-    return child_key(k.nh, k.nho, k.chi2, k.parent, 0);
-  }
-  if (b.n > 0) {
-    chi2_out = k.chi2 + b.c[0];
-    code = b.h[0];
-    return child_key(k.nh + 1, k.nho, chi2_out, k.parent, popped);
-  }
-  if (k.hole && !hole_used) {
-    chi2_out = k.chi2;
-    code = kHole;
-    return child_key(k.nh, k.nho + 1, k.chi2, k.parent, K);
-  }
-  return ~0ull;
-}
-
 template <int G_LANES, int OCC>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC, OCC)))
 k_build_fused(BuildArgs a, int* seed_counter) {
   extern __shared__ unsigned char smem_raw[];
-  FusedShared* sh = reinterpret_cast<FusedShared*>(smem_raw);
+  using FS = FusedShared<G_LANES>;
+  FS* sh = reinterpret_cast<FS*>(smem_raw);
   // the layer table is read at every step with lane-dependent indices: keep
   // a copy in LDS
   __shared__ Geometry g_lds;
@@ -691,7 +674,7 @@ k_build_fused(BuildArgs a, int* seed_counter) {
   State st;
   int layer = -1, meta = 0;
   float chi2 = 0.0f;
-  FusedShared& me = sh[threadIdx.x];
+  FS& me = sh[threadIdx.x];
 
   while (true) {
     // a group without a seed takes the next one (all lanes take part in
@@ -764,29 +747,51 @@ k_build_fused(BuildArgs a, int* seed_counter) {
     }
     const KidStream ks = kid_stream(a, live ? meta : 0, chi2, nl, best.n, gl);
     if (nl >= 0 && ks.stop) lds_put(me, st, layer);
-    // ---- (c) selection: K rounds of a segmented minimum over the lanes'
-    // child streams; round i fills new slot i (lane gbase + i)
-    int popped = 0;
-    bool hole_used = false;
-    float hc = 0.0f;
-    int hcode = kStop;
-    uint64_t head = lane_head(ks, best, popped, hole_used, K, hc, hcode);
+    // ---- (c) selection: each lane lists its children in stream order in
+    // LDS (hit children by (chi2, hit), then the hole; or its stop child),
+    // then K rounds of a segmented minimum over the lanes' stream heads;
+    // round i fills new slot i (lane gbase + i)
+    int m = 0;
+    if (ks.live) {
+      if (ks.stop) {
+        me.ekey[0] = child_key(ks.nh, ks.nho, ks.chi2, ks.parent, 0);
+        me.ecode[0] = kStop;
+        me.echi2[0] = ks.chi2;
+        m = 1;
+      } else {
+#pragma unroll
+        for (int p = 0; p < G_LANES; ++p)
+          if (p < best.n) {
+            const float tot = ks.chi2 + best.c[p];
+            me.ekey[p] = child_key(ks.nh + 1, ks.nho, tot, ks.parent, p);
+            me.ecode[p] = best.h[p];
+            me.echi2[p] = tot;
+          }
+        m = best.n;
+        if (ks.hole) {
+          me.ekey[m] = child_key(ks.nh, ks.nho + 1, ks.chi2, ks.parent, K);
+          me.ecode[m] = kHole;
+          me.echi2[m] = ks.chi2;
+          ++m;
+        }
+      }
+    }
+    int idx = 0;
+    uint64_t head = m > 0 ? me.ekey[0] : ~0ull;
     int my_parent = -1, my_code = kStop;
     float my_chi2 = 0.0f;
     for (int i = 0; i < K; ++i) {
-      const uint64_t m = group_min<G_LANES>(head);
-      const unsigned long long win = __ballot(head == m && m != ~0ull) & gmask;
+      const uint64_t mn = group_min<G_LANES>(head);
+      const unsigned long long win = __ballot(head == mn && mn != ~0ull) & gmask;
       // winner lane in the wave (unique: keys differ by parent slot); it
       // hands its child to the lane of new slot i through LDS
       const int wl = win ? __ffsll((long long)win) - 1 : 0;
       if (win && gl == i) my_parent = wl & (G_LANES - 1);
       if (win && lane == wl) {
-        sh[gbase + i].sel_code = hcode;
-        sh[gbase + i].sel_chi2 = hc;
-        if (hcode >= 0) bestk_pop(best);
-        else if (hcode == kHole) hole_used = true;
-        ++popped;
-        head = lane_head(ks, best, popped, hole_used, K, hc, hcode);
+        sh[gbase + i].sel_code = me.ecode[idx];
+        sh[gbase + i].sel_chi2 = me.echi2[idx];
+        ++idx;
+        head = idx < m ? me.ekey[idx] : ~0ull;
       }
     }
     wave_sync();
@@ -798,7 +803,7 @@ k_build_fused(BuildArgs a, int* seed_counter) {
     int new_meta = 0, new_layer = -1;
     if (active && gl < K) {
       if (my_parent >= 0) {
-        const FusedShared& par = sh[gbase + my_parent];
+        const FS& par = sh[gbase + my_parent];
         State ns;
         lds_get(par, ns);
         const int pm = par.meta;
@@ -949,7 +954,8 @@ void launch_build_fused(const BuildArgs& a, const TracksOut& o, int* seed_counte
   // temporaries do not set the register budget of the persistent kernel
   hipLaunchKernelGGL(k_build_init, dim3(nblk(a.n_seeds, 128)), dim3(128), 0, st, a);
   if (ev) (void)hipEventRecord(ev[0], st);
-  const size_t shmem = sizeof(FusedShared) * threads;
+  const size_t shmem = (lanes == 4 ? sizeof(FusedShared<4>) : lanes == 8 ? sizeof(FusedShared<8>)
+                                                                         : sizeof(FusedShared<16>)) * threads;
 #define KFX_FUSED(GL, OC) \
   hipLaunchKernelGGL((k_build_fused<GL, OC>), dim3(blocks), dim3(threads), shmem, st, a, seed_counter)
   const bool two = waves_per_simd == 2;

@@ -266,8 +266,8 @@ KFX_HD int navigate(const Geometry& G, int cur, const State& st, double cphi, do
   int nb = -1;
   s_out = best;
   // a state that is not finite goes nowhere (comparisons with NaN are false)
-  if (!isfinite(st.x) || !isfinite(st.y) || !isfinite(st.z) || !isfinite(st.phi) || !isfinite(st.th) ||
-      !isfinite(st.k) || !isfinite(omega_d))
+  if (!__builtin_isfinite(st.x) || !__builtin_isfinite(st.y) || !__builtin_isfinite(st.z) || !__builtin_isfinite(st.phi) || !__builtin_isfinite(st.th) ||
+      !__builtin_isfinite(st.k) || !__builtin_isfinite(omega_d))
     return -1;
   double sth, cth;
   sincos_d(st.th, sth, cth);
@@ -296,13 +296,17 @@ KFX_HD int navigate(const Geometry& G, int cur, const State& st, double cphi, do
     const bool fwd = cth > 0.0;
     const int n = fwd ? G.n_dpos : G.n_dneg;
     const int* dl = fwd ? G.dpos : G.dneg;
+    const double tanth = sth / cth;
     for (int i = 0; i < n; ++i) {
       const int id = dl[i];
       if (id == cur) continue;
       const double Z = G.L[id].pos;
       if (fwd ? (Z <= st.z) : (Z >= st.z)) continue;
-      const double s = path_to_disk(st, Z, sth, cth);
-      if (!(s > 0.0)) continue;
+      const double s = (Z - st.z) * tanth;  // as path_to_disk
+      if (!(s > 1e-12)) continue;
+      // the disks ahead come in order of path length: once one is no nearer
+      // than the barrel crossing, none after it can be either
+      if (!(s < best)) break;
       const ChordD c = chord_d(s, omega_d, cphi, sphi);
       const double x = st.x + c.dx, y = st.y + c.dy;
       if (x * c.c1 + y * c.s1 < 0.0) break;  // turned before reaching it

@@ -75,8 +75,8 @@ KFX_HD Window window_bins(const Geometry& G, const Layer& Lr, const State& pr, c
   const float rp = sqrtf(px * px + py * py);
   const float php = atan2f(py, px);
   Window w;
-  if (!isfinite(wu) || !isfinite(wv) || !isfinite(wn) || !isfinite(rp) || !isfinite(php) ||
-      !isfinite((float)pr.z)) {
+  if (!__builtin_isfinite(wu) || !__builtin_isfinite(wv) || !__builtin_isfinite(wn) || !__builtin_isfinite(rp) || !__builtin_isfinite(php) ||
+      !__builtin_isfinite((float)pr.z)) {
     w.eb0 = 1;  // empty window
     w.eb1 = 0;
     w.pb0 = 0;

@@ -120,6 +120,36 @@ void hs_fit(const double* table, int nl, double bz, const float* x, const float*
 
 }  // extern "C"
 
+// navigation from layer `cur`: next layer (-1 none) and its path
+extern "C" int hs_navigate(const double* table, int nl, double bz, int cur, const double* p, double* s_out) {
+  Geometry G = make_geo(table, nl, bz);
+  std::vector<int> bar, dp, dn;
+  for (int i = 0; i < nl; ++i) {
+    if (G.L[i].kind == kBarrel) bar.push_back(i);
+    else if (G.L[i].pos > 0) dp.push_back(i);
+    else dn.push_back(i);
+  }
+  std::sort(bar.begin(), bar.end(), [&](int a, int b) { return G.L[a].pos < G.L[b].pos; });
+  std::sort(dp.begin(), dp.end(), [&](int a, int b) { return G.L[a].pos < G.L[b].pos; });
+  std::sort(dn.begin(), dn.end(), [&](int a, int b) { return G.L[a].pos > G.L[b].pos; });
+  G.n_barrel = (int)bar.size();
+  G.n_dpos = (int)dp.size();
+  G.n_dneg = (int)dn.size();
+  for (int i = 0; i < kMaxLayers; ++i) G.next_barrel[i] = -1;
+  for (size_t i = 0; i < bar.size(); ++i) {
+    G.barrel[i] = bar[i];
+    G.next_barrel[bar[i]] = (i + 1 < bar.size()) ? bar[i + 1] : -1;
+  }
+  for (size_t i = 0; i < dp.size(); ++i) G.dpos[i] = dp[i];
+  for (size_t i = 0; i < dn.size(); ++i) G.dneg[i] = dn[i];
+  State st;
+  float c[21] = {0};
+  to_state(p, c, st);
+  double cphi, sphi;
+  sincos_d(st.phi, sphi, cphi);
+  return navigate(G, cur, st, cphi, sphi, -kHcD * bz * st.k, *s_out);
+}
+
 extern "C" double hs_path_cylinder(const double* p, double bz, double Rc) {
   State st;
   float c[21] = {0};
