@@ -307,6 +307,31 @@ KFX_HD int navigate(const Geometry& G, int cur, const State& st, double cphi, do
       // the disks ahead come in order of path length: once one is no nearer
       // than the barrel crossing, none after it can be either
       if (!(s < best)) break;
+      const float lo = (float)G.L[id].lo, hi = (float)G.L[id].hi;
+      {
+        // FP32 estimate of the crossing: a disk that the track clearly
+        // leaves radially, or clearly passes inside of while still moving
+        // outward, is decided without the FP64 chord; anything within the
+        // margin (far above the FP32 error) takes the exact path below
+        const float s32 = (float)s;
+        const float a32 = 0.5f * (float)omega_d * s32;
+        if (fabsf(a32) < 0.5f) {
+          // Taylor series on |a| < 0.5 (truncation below 1e-8)
+          const float a2 = a32 * a32;
+          const float sinc = 1.0f + a2 * (-1.0f / 6.0f + a2 * (1.0f / 120.0f + a2 * (-1.0f / 5040.0f)));
+          const float sa = a32 * sinc;
+          const float ca = 1.0f + a2 * (-0.5f + a2 * (1.0f / 24.0f + a2 * (-1.0f / 720.0f + a2 * (1.0f / 40320.0f))));
+          const float L = s32 * sinc;
+          const float cp = (float)cphi, sp = (float)sphi;
+          const float cps = cp * ca - sp * sa, sps = sp * ca + cp * sa;
+          const float x = (float)st.x + L * cps, y = (float)st.y + L * sps;
+          const float c1 = cps * ca - sps * sa, s1 = sps * ca + cps * sa;
+          const float r = sqrtf(x * x + y * y);
+          const float tol = 1e-3f * s32 + 1e-2f;
+          if (r > hi + tol) break;                                         // left radially
+          if (r < lo - tol && x * c1 + y * s1 > tol * (r + 1.0f)) continue;  // passes inside
+        }
+      }
       const ChordD c = chord_d(s, omega_d, cphi, sphi);
       const double x = st.x + c.dx, y = st.y + c.dy;
       if (x * c.c1 + y * c.s1 < 0.0) break;  // turned before reaching it

@@ -65,6 +65,11 @@ KFX_HD int eta_bin_f(const Geometry& G, const Layer& Lr, float eta) {
   return (int)f;
 }
 
+// An upper bound of asin(w / r) for 0 <= w < r: tan(asin(x)) >= asin(x),
+// i.e. w / sqrt(r^2 - w^2), wider by a relative (w/r)^2/3 when w/r is
+// small; a superset window is all the scan needs.
+KFX_HD float asin_upper(float w, float r) { return w / sqrtf((r - w) * (r + w)); }
+
 KFX_HD Window window_bins(const Geometry& G, const Layer& Lr, const State& pr, const Frame& F,
                           float cut) {
   const float infl = 1.0f + 1e-4f;
@@ -86,14 +91,14 @@ KFX_HD Window window_bins(const Geometry& G, const Layer& Lr, const State& pr, c
   float dphi, elo, ehi;
   if (Lr.kind == kBarrel) {
     const float rmin = rp - wn;
-    dphi = (rmin <= 0.0f || wu >= rmin) ? 4.0f : asinf(wu / rmin) + 1e-5f;
+    dphi = (rmin <= 0.0f || wu >= rmin) ? 4.0f : asin_upper(wu, rmin) + 1e-5f;
     const float R = (float)Lr.pos;
     elo = asinhf(((float)pr.z - wv) / R) - 1e-5f;
     ehi = asinhf(((float)pr.z + wv) / R) + 1e-5f;
   } else {
     const float rmin = rp - wv;
     const float rmax = sqrtf(wu * wu + (rp + wv) * (rp + wv));
-    dphi = (rmin <= 0.0f || wu >= rmin) ? 4.0f : asinf(wu / rmin) + 1e-5f;
+    dphi = (rmin <= 0.0f || wu >= rmin) ? 4.0f : asin_upper(wu, rmin) + 1e-5f;
     const float Z = (float)Lr.pos;
     const float a = asinhf(Z / rmax);
     const float b = rmin > 0.0f ? asinhf(Z / rmin) : (Z > 0.0f ? 1e30f : -1e30f);
