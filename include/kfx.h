@@ -111,6 +111,10 @@ typedef struct {
   int32_t waves_per_simd;/* fused: register budget of the kernel, 1 (all 512
                             registers of a lane) or 2 (half, the rest spilled
                             to scratch, two waves resident per SIMD); 0 = 1  */
+  int32_t seeds_per_wave;/* fused: seeds a wavefront works on at once, 1 ..
+                            64 / lanes_per_seed (the rest of its lanes idle):
+                            fewer seeds per wavefront spread a small event
+                            over more SIMDs; 0 = 64 / lanes_per_seed         */
 } kfx_build_params;
 
 /* Output of building, per seed s and slot j < K, best first (device). */
@@ -263,7 +267,8 @@ void kfx_graph_destroy(kfx_graph* graph);
  * timed calls per shape, the minimum kept) while moving one parameter at a
  * time: scan_tile in {16, 32, 64, 128, 256}, block_threads in {64, 128,
  * 256}, blocks in {1, 2, 4, 8} per compute unit, lanes_per_seed from the
- * smallest power of two >= K up to 16, waves_per_simd in {1, 2}.  Writes the fastest shape into
+ * smallest power of two >= K up to 16, waves_per_simd in {1, 2},
+ * seeds_per_wave from 2 up to 64 / lanes_per_seed.  Writes the fastest shape into
  * params (mode becomes KFX_MODE_FUSED) and its time into *best_ms
  * (nullable).  Every shape gives identical results; out holds the last
  * call's, out->stats is restored.  Synchronises the stream. */

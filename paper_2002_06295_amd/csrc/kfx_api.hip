@@ -276,6 +276,7 @@ int kfx_load_layers(kfx_ctx* c, const double* table, int n_layers, double bz, in
   }
   for (size_t i = 0; i < dp.size(); ++i) G.dpos[i] = dp[i];
   for (size_t i = 0; i < dn.size(); ++i) G.dneg[i] = dn[i];
+  nav_tables(G);
   DeviceGuard dg(c->device);
   if (!c->dev_geo) {
     if (hipMalloc(&c->dev_geo, sizeof(Geometry)) != hipSuccess) return fail(c, KFX_ENOMEM, "geometry allocation");
@@ -374,6 +375,11 @@ int build_impl(kfx_ctx* c, const kfx_hits* hits, const int32_t* seeds, const int
   if (p->lanes_per_seed != 0 && ((p->lanes_per_seed != 4 && p->lanes_per_seed != 8 && p->lanes_per_seed != 16) ||
                                  p->lanes_per_seed < p->max_cands))
     return fail(c, KFX_EINVAL, "lanes_per_seed must be 0, or 4, 8 or 16 and at least max_cands");
+  {
+    const int lanes = p->lanes_per_seed ? p->lanes_per_seed : fused_lanes_for(p->max_cands);
+    if (p->seeds_per_wave < 0 || p->seeds_per_wave > 64 / lanes)
+      return fail(c, KFX_EINVAL, "seeds_per_wave must be 0 or in [1, 64 / lanes_per_seed]");
+  }
   const int K = p->max_cands;
   const long SK = (long)n_seeds * K;
   if (out->capacity < SK) {
@@ -420,6 +426,10 @@ int build_impl(kfx_ctx* c, const kfx_hits* hits, const int32_t* seeds, const int
   a.max_holes = p->max_holes;
   a.max_steps = p->max_steps;
   a.coop_min = p->scan_tile ? p->scan_tile : 64;
+  {
+    const int lanes = p->lanes_per_seed ? p->lanes_per_seed : fused_lanes_for(K);
+    a.groups_per_wave = p->seeds_per_wave ? p->seeds_per_wave : 64 / lanes;
+  }
   const long N = std::max<long>(SK, 1);
   auto alloc_states = [&](const char* name, StateSoA& s) -> int {
     char* base = (char*)ws(c, name, (size_t)N * (6 * 8 + 21 * 4), st, rc);
@@ -469,7 +479,7 @@ int build_impl(kfx_ctx* c, const kfx_hits* hits, const int32_t* seeds, const int
     if (blocks == 0) blocks = c->n_cu * 4;
     // no more groups than seeds need
     const int lanes = p->lanes_per_seed ? p->lanes_per_seed : fused_lanes_for(K);
-    const int groups_per_block = threads / lanes;
+    const int groups_per_block = (threads / 64) * a.groups_per_wave;
     const long max_blocks = (n_seeds + groups_per_block - 1) / groups_per_block;
     blocks = (int)std::max<long>(1, std::min<long>(blocks, max_blocks));
     launch_build_fused(a, o, counter, blocks, threads, lanes, p->waves_per_simd == 2 ? 2 : 1, st,
@@ -636,6 +646,7 @@ int kfx_autotune_build(kfx_ctx* c, const kfx_hits* hits, const int32_t* seeds, c
   if (cur.lanes_per_seed == 0) cur.lanes_per_seed = lp0;
   if (cur.scan_tile == 0) cur.scan_tile = 64;
   if (cur.waves_per_simd == 0) cur.waves_per_simd = 1;
+  if (cur.seeds_per_wave == 0) cur.seeds_per_wave = 64 / cur.lanes_per_seed;
   auto timeit = [&](const kfx_build_params& q, float& ms) -> int {
     int r = build_impl(c, hits, seeds, seed_event, n_seeds, &q, out, st);  // warm-up
     if (r) return r;
@@ -654,7 +665,7 @@ int kfx_autotune_build(kfx_ctx* c, const kfx_hits* hits, const int32_t* seeds, c
   float best = 3.0e38f;
   if (!rc) rc = timeit(cur, best);
   // coordinate descent: one parameter at a time, the others held
-  for (int dim = 0; dim < 5 && !rc; ++dim) {
+  for (int dim = 0; dim < 6 && !rc; ++dim) {
     std::vector<kfx_build_params> cand;
     kfx_build_params q = cur;
     if (dim == 0) {
@@ -664,13 +675,21 @@ int kfx_autotune_build(kfx_ctx* c, const kfx_hits* hits, const int32_t* seeds, c
     } else if (dim == 2) {
       for (int b : {1, 2, 4, 8}) { q.blocks = c->n_cu * b; cand.push_back(q); }
     } else if (dim == 3) {
-      for (int l = lp0; l <= 16; l <<= 1) { q.lanes_per_seed = l; cand.push_back(q); }
-    } else {
+      // a full wavefront of seeds for each lane count
+      for (int l = lp0; l <= 16; l <<= 1) {
+        q.lanes_per_seed = l;
+        q.seeds_per_wave = 64 / l;
+        cand.push_back(q);
+      }
+    } else if (dim == 4) {
       for (int w : {1, 2}) { q.waves_per_simd = w; cand.push_back(q); }
+    } else {
+      for (int g = 2; g <= 64 / cur.lanes_per_seed; ++g) { q.seeds_per_wave = g; cand.push_back(q); }
     }
     for (const auto& v : cand) {
       if (v.scan_tile == cur.scan_tile && v.block_threads == cur.block_threads && v.blocks == cur.blocks &&
-          v.lanes_per_seed == cur.lanes_per_seed && v.waves_per_simd == cur.waves_per_simd)
+          v.lanes_per_seed == cur.lanes_per_seed && v.waves_per_simd == cur.waves_per_simd &&
+          v.seeds_per_wave == cur.seeds_per_wave)
         continue;
       float t = 0.0f;
       if ((rc = timeit(v, t))) break;
@@ -694,6 +713,7 @@ int kfx_autotune_build(kfx_ctx* c, const kfx_hits* hits, const int32_t* seeds, c
   p->lanes_per_seed = cur.lanes_per_seed;
   p->scan_tile = cur.scan_tile;
   p->waves_per_simd = cur.waves_per_simd;
+  p->seeds_per_wave = cur.seeds_per_wave;
   if (best_ms) *best_ms = best;
   return KFX_OK;
 }

@@ -26,6 +26,7 @@ struct BuildArgs {
   int max_holes;
   int max_steps;
   int coop_min;           // fused: window size scanned by the whole wave
+  int groups_per_wave;    // fused: seed groups of a wavefront that take seeds
   // candidate slots (S K), two buffers used in turn
   StateSoA cand[2];
   int* layer[2];
@@ -123,8 +124,8 @@ KFX_HD int pairs_slot(const BuildArgs& a, long slot, int ev) {
 #pragma unroll
   for (int r = 0; r < kMaxK; ++r)
     if (r < b.n) {
-      a.kid_c[slot * a.K + r] = b.c[r];
-      a.kid_h[slot * a.K + r] = b.h[r];
+      a.kid_c[slot * a.K + r] = pair_key_chi2(b.k[r]);
+      a.kid_h[slot * a.K + r] = pair_key_hit(b.k[r]);
     }
   a.kid_n[slot] = b.n;
   return found;

@@ -487,19 +487,6 @@ __device__ inline long rl_l(long v, int l) {
   return (long)(((uint64_t)hi << 32) | lo);
 }
 
-// (chi2, hit) of the K-th entry of a full list, (inf, max) otherwise
-template <int KM>
-__device__ inline void bestk_threshold(const BestK<KM>& best, int K, float& c, int& h) {
-  c = __builtin_inff();
-  h = 0x7fffffff;
-#pragma unroll
-  for (int i = 0; i < KM; ++i)
-    if (i == K - 1 && best.n == K) {
-      c = best.c[i];
-      h = best.h[i];
-    }
-}
-
 template <int KM>
 __device__ int wave_scan(const BinIndex& B, int n_phi, int lane, bool has, const ScanWin& sw, const PairFrame& pf,
                          float cut, int K, int coop_min, BestK<KM>& best) {
@@ -556,11 +543,8 @@ __device__ int wave_scan(const BinIndex& B, int n_phi, int lane, bool has, const
     W.b0 = rl_i(sw.b0, o);
     W.b1 = rl_i(sw.b1, o);
     W.w1 = rl_i(sw.w1, o);
-    float tc;
-    int th;
-    bestk_threshold(best, K, tc, th);
-    tc = rl_f(tc, o);
-    th = rl_i(th, o);
+    // the owner's admission threshold: a pair must have a smaller key
+    uint64_t thr = rl_l((long)bestk_threshold(best, K), o);
     const int nro = W.nrows * W.nseg;
     for (int r = 0; r < nro; ++r) {
       int qa, qe;
@@ -568,7 +552,7 @@ __device__ int wave_scan(const BinIndex& B, int n_phi, int lane, bool has, const
       // four loads of 64 consecutive hits in flight per pass
       for (int base = qa; base < qe; base += 256) {
         float c2[4];
-        int hid[4];
+        uint64_t pk[4];
         bool under[4];
         float4 hv[4];
 #pragma unroll
@@ -581,9 +565,11 @@ __device__ int wave_scan(const BinIndex& B, int n_phi, int lane, bool has, const
         for (int u = 0; u < 4; ++u) {
           const bool in = base + 64 * u + lane < qe;
           c2[u] = pair_chi2(P, hv[u]);
-          __builtin_memcpy(&hid[u], &hv[u].w, 4);
+          int hid;
+          __builtin_memcpy(&hid, &hv[u].w, 4);
+          pk[u] = pair_key(c2[u], hid);
           under[u] = in && c2[u] < cut;
-          const bool keep = under[u] && (c2[u] < tc || (c2[u] == tc && hid[u] < th));
+          const bool keep = under[u] && pk[u] < thr;
           const unsigned long long m_under = __ballot(under[u]);
           m_keep[u] = __ballot(keep);
           if (lane == o) found += __popcll(m_under);
@@ -597,46 +583,27 @@ __device__ int wave_scan(const BinIndex& B, int n_phi, int lane, bool has, const
             while (mk) {
               const int b = __ffsll((long long)mk) - 1;
               mk &= mk - 1ull;
-              const float kc = rl_f(c2[u], b);
-              const int kh = rl_i(hid[u], b);
-              if (lane == o) bestk_insert(best, K, kc, kh);
+              const uint64_t kk = (uint64_t)rl_l((long)pk[u], b);
+              if (lane == o) bestk_insert_key(best, K, kk);
             }
           } else {
             // many (hits sorted by phi approach the window centre with
             // falling chi2): extract them smallest first, at most K, and
             // stop at the first that no longer enters the list
-            // order-preserving integer image of the float (a chi2 rounded
-            // below zero, or -0, must still sort first)
-            const uint32_t fb = __float_as_uint(c2[u] + 0.0f);  // -0 -> +0
-            const uint32_t fk = (fb & 0x80000000u) ? ~fb : (fb | 0x80000000u);
-            uint64_t key = (m_keep[u] >> lane) & 1ull ? ((uint64_t)fk << 32) | (uint32_t)hid[u] : ~0ull;
+            uint64_t key = (m_keep[u] >> lane) & 1ull ? pk[u] : kNoKey;
             for (int i = 0; i < K; ++i) {
               const uint64_t m = group_min<16>(key);
-              const uint64_t r0 = (uint64_t)(uint32_t)rl_i((int)(uint32_t)m, 0) |
-                                  ((uint64_t)(uint32_t)rl_i((int)(uint32_t)(m >> 32), 0) << 32);
-              const uint64_t r1 = (uint64_t)(uint32_t)rl_i((int)(uint32_t)m, 16) |
-                                  ((uint64_t)(uint32_t)rl_i((int)(uint32_t)(m >> 32), 16) << 32);
-              const uint64_t r2 = (uint64_t)(uint32_t)rl_i((int)(uint32_t)m, 32) |
-                                  ((uint64_t)(uint32_t)rl_i((int)(uint32_t)(m >> 32), 32) << 32);
-              const uint64_t r3 = (uint64_t)(uint32_t)rl_i((int)(uint32_t)m, 48) |
-                                  ((uint64_t)(uint32_t)rl_i((int)(uint32_t)(m >> 32), 48) << 32);
+              const uint64_t r0 = (uint64_t)rl_l((long)m, 0), r1 = (uint64_t)rl_l((long)m, 16);
+              const uint64_t r2 = (uint64_t)rl_l((long)m, 32), r3 = (uint64_t)rl_l((long)m, 48);
               const uint64_t a01 = r0 < r1 ? r0 : r1, a23 = r2 < r3 ? r2 : r3;
               const uint64_t mn = a01 < a23 ? a01 : a23;
-              if (mn == ~0ull) break;
-              const uint32_t kk = (uint32_t)(mn >> 32);
-              const float kc = __uint_as_float((kk & 0x80000000u) ? (kk & 0x7fffffffu) : ~kk);
-              const int kh = (int)(uint32_t)mn;
-              if (!(kc < tc || (kc == tc && kh < th))) break;
-              if (lane == o) bestk_insert(best, K, kc, kh);
-              bestk_threshold(best, K, tc, th);
-              tc = rl_f(tc, o);
-              th = rl_i(th, o);
-              if (key == mn) key = ~0ull;
+              if (!(mn < thr)) break;  // none left (kNoKey), or no longer enters
+              if (lane == o) bestk_insert_key(best, K, mn);
+              thr = rl_l((long)bestk_threshold(best, K), o);
+              if (key == mn) key = kNoKey;
             }
           }
-          bestk_threshold(best, K, tc, th);
-          tc = rl_f(tc, o);
-          th = rl_i(th, o);
+          thr = rl_l((long)bestk_threshold(best, K), o);
         }
       }
     }
@@ -668,7 +635,8 @@ k_build_fused(BuildArgs a, int* seed_counter) {
   const unsigned long long gmask = ((G_LANES == 64) ? ~0ull : ((1ull << G_LANES) - 1ull)) << (lane & ~(G_LANES - 1));
 
   unsigned long long n_steps = 0, n_pairs = 0, n_upd = 0;
-  int seed = -1;
+  // groups beyond the wave's quota never take a seed
+  int seed = (lane / G_LANES) < a.groups_per_wave ? -1 : -2;
   int t = 0;
   // register state of this lane's slot
   State st;
@@ -762,9 +730,9 @@ k_build_fused(BuildArgs a, int* seed_counter) {
 #pragma unroll
         for (int p = 0; p < G_LANES; ++p)
           if (p < best.n) {
-            const float tot = ks.chi2 + best.c[p];
+            const float tot = ks.chi2 + pair_key_chi2(best.k[p]);
             me.ekey[p] = child_key(ks.nh + 1, ks.nho, tot, ks.parent, p);
-            me.ecode[p] = best.h[p];
+            me.ecode[p] = pair_key_hit(best.k[p]);
             me.echi2[p] = tot;
           }
         m = best.n;

@@ -36,6 +36,7 @@ constexpr float kHc = (float)kHcD;
 constexpr int kBarrel = 0;
 constexpr int kDisk = 1;
 constexpr int kMaxLayers = 64;
+constexpr int kNavGrid = 256;  // cells of the navigation lookup grids
 
 // Packed symmetric 6x6: element (i, j), i >= j, lives at i(i+1)/2 + j.
 KFX_HD constexpr int sidx(int i, int j) { return i >= j ? i * (i + 1) / 2 + j : j * (j + 1) / 2 + i; }
@@ -60,9 +61,57 @@ struct Geometry {
   int dneg[kMaxLayers];     // -z disks, decreasing z
   int next_barrel[kMaxLayers];  // for a barrel layer: the next one out (-1)
   int brank[kMaxLayers];        // rank of a barrel layer by radius (disks: -1)
+  int drank[kMaxLayers];        // rank of a disk within its side (barrel: -1)
   double bz;
   int n_eta, n_phi;
+  // navigation tables (filled by nav_tables from the lists above): barrel
+  // radii by rank, |Z| of the disks of each side (0: +z, 1: -z) by rank, and
+  // for each a coarse grid giving, per cell of width 1 / ginv, the number of
+  // entries at or below the cell's start (a first guess for nav_count)
+  double bR[kMaxLayers];
+  double dA[2][kMaxLayers];
+  float ginv[3];
+  unsigned char grid[3][kNavGrid];
 };
+
+// The lookup tables of the navigation, from the sorted barrel and disk
+// lists (host side, once per geometry).
+inline void nav_tables(Geometry& G) {
+  const int n[3] = {G.n_barrel, G.n_dpos, G.n_dneg};
+  for (int i = 0; i < kMaxLayers; ++i) G.drank[i] = -1;
+  for (int i = 0; i < G.n_barrel; ++i) G.bR[i] = G.L[G.barrel[i]].pos;
+  for (int i = 0; i < G.n_dpos; ++i) {
+    G.dA[0][i] = G.L[G.dpos[i]].pos;
+    G.drank[G.dpos[i]] = i;
+  }
+  for (int i = 0; i < G.n_dneg; ++i) {
+    G.dA[1][i] = -G.L[G.dneg[i]].pos;
+    G.drank[G.dneg[i]] = i;
+  }
+  for (int t = 0; t < 3; ++t) {
+    const double* a = t == 0 ? G.bR : G.dA[t - 1];
+    const double top = n[t] > 0 ? a[n[t] - 1] : 1.0;
+    G.ginv[t] = (float)((kNavGrid - 1) / (top > 0.0 ? 1.01 * top : 1.0));
+    for (int b = 0; b < kNavGrid; ++b) {
+      const double w = b / (double)G.ginv[t];
+      int c = 0;
+      while (c < n[t] && a[c] <= w) ++c;
+      G.grid[t][b] = (unsigned char)c;
+    }
+  }
+}
+
+// Number of entries of the ascending table a[0..n) that are <= w, exactly:
+// the grid cell gives a first guess, which is then moved up or down.
+KFX_HD int nav_count(const Geometry& G, int t, const double* a, int n, double w) {
+  const float f = (float)w * G.ginv[t];
+  const int b = f > 0.0f ? (f < (float)(kNavGrid - 1) ? (int)f : kNavGrid - 1) : 0;
+  int c = G.grid[t][b];
+  c = c < n ? c : n;
+  while (c < n && a[c] <= w) ++c;
+  while (c > 0 && a[c - 1] > w) --c;
+  return c;
+}
 
 // Track parameters in FP64, covariance in R (FP32 on the hot path).
 template <class R>
@@ -80,10 +129,6 @@ KFX_HD void convert_state(const StateT<A>& a, StateT<B>& b) {
 }
 
 // scalar math for float and double
-KFX_HD float msin(float x) { return sinf(x); }
-KFX_HD double msin(double x) { return sin(x); }
-KFX_HD float mcos(float x) { return cosf(x); }
-KFX_HD double mcos(double x) { return cos(x); }
 KFX_HD float msqrt(float x) { return sqrtf(x); }
 KFX_HD double msqrt(double x) { return sqrt(x); }
 KFX_HD float mabs(float x) { return fabsf(x); }
@@ -93,19 +138,14 @@ KFX_HD double mlog(double x) { return log(x); }
 KFX_HD float mmax(float a, float b) { return fmaxf(a, b); }
 KFX_HD double mmax(double a, double b) { return fmax(a, b); }
 
-// sin and cos of an FP64 angle of moderate size (the azimuth, the polar
-// angle and the turning angle of a step are all below 8 in magnitude).
-// Cody-Waite reduction by pi/2 with a two-part constant (fma keeps
-// x - q pi/2_hi exact to one rounding; |q| <= 5), then the Taylor series of
+// sin and cos of an FP64 angle (the azimuth, the polar angle and the
+// turning angle of a step are all below 8 in magnitude).  Cody-Waite
+// reduction by pi/2 with a two-part constant: the fma rounds x - q pi/2_hi
+// once, and the constant's missing part (~1e-33 q) stays far below FP64
+// rounding of the reduced argument for |x| < 1e9.  Then the Taylor series of
 // sin and cos on [-pi/4, pi/4] to the terms r^17 and r^16, whose truncation
-// error (< 1e-17) is below FP64 rounding.  Larger or non-finite arguments
-// take the library functions.
+// error (< 1e-17) is below FP64 rounding.  A non-finite argument gives NaN.
 KFX_HD void sincos_d(double x, double& s, double& c) {
-  if (!(fabs(x) <= 8.0)) {
-    s = sin(x);
-    c = cos(x);
-    return;
-  }
   constexpr double kPio2Hi = 1.5707963267948966;      // nearest double to pi/2
   constexpr double kPio2Lo = 6.123233995736766e-17;   // pi/2 - kPio2Hi
   constexpr double k2Opi = 0.6366197723675814;        // 2/pi
@@ -132,7 +172,7 @@ KFX_HD void sincos_d(double x, double& s, double& c) {
   pc = fma(pc, r2, 1.0 / 24.0);                       // 1/4!
   pc = fma(pc, r2, -0.5);                             // 1/2!
   const double cr = fma(pc, r2, 1.0);
-  const int qi = ((int)q) & 3;
+  const int qi = (int)(q - 4.0 * floor(0.25 * q));  // q mod 4, exact
   s = qi == 0 ? sr : (qi == 1 ? cr : (qi == 2 ? -sr : -cr));
   c = qi == 0 ? cr : (qi == 1 ? -sr : (qi == 2 ? -cr : sr));
 }
@@ -275,12 +315,10 @@ KFX_HD int navigate(const Geometry& G, int cur, const State& st, double cphi, do
   if (Lc.kind == kBarrel) {
     nb = G.next_barrel[cur];
   } else {
+    // the first barrel layer with a radius above the state's
     const double r = sqrt(st.x * st.x + st.y * st.y);
-    for (int i = 0; i < G.n_barrel; ++i)
-      if (G.L[G.barrel[i]].pos > r) {
-        nb = G.barrel[i];
-        break;
-      }
+    const int rk = nav_count(G, 0, G.bR, G.n_barrel, r);
+    nb = rk < G.n_barrel ? G.barrel[rk] : -1;
   }
   if (nb >= 0) {
     const double s = path_to_cylinder(st, cphi, sphi, omega_d, G.L[nb].pos);
@@ -296,17 +334,20 @@ KFX_HD int navigate(const Geometry& G, int cur, const State& st, double cphi, do
     const bool fwd = cth > 0.0;
     const int n = fwd ? G.n_dpos : G.n_dneg;
     const int* dl = fwd ? G.dpos : G.dneg;
+    const double* dA = G.dA[fwd ? 0 : 1];
     const double tanth = sth / cth;
-    for (int i = 0; i < n; ++i) {
-      const int id = dl[i];
-      if (id == cur) continue;
-      const double Z = G.L[id].pos;
-      if (fwd ? (Z <= st.z) : (Z >= st.z)) continue;
+    // the disks of this side ordered along the motion; the ones at or
+    // behind the state's z are skipped at once, and so is the current disk
+    const int crank = (Lc.kind == kDisk && (Lc.pos > 0.0) == fwd) ? G.drank[cur] : -1;
+    for (int i = nav_count(G, fwd ? 1 : 2, dA, n, fwd ? st.z : -st.z); i < n; ++i) {
+      if (i == crank) continue;
+      const double Z = fwd ? dA[i] : -dA[i];
       const double s = (Z - st.z) * tanth;  // as path_to_disk
       if (!(s > 1e-12)) continue;
       // the disks ahead come in order of path length: once one is no nearer
       // than the barrel crossing, none after it can be either
       if (!(s < best)) break;
+      const int id = dl[i];
       const float lo = (float)G.L[id].lo, hi = (float)G.L[id].hi;
       {
         // FP32 estimate of the crossing: a disk that the track clearly

@@ -153,54 +153,70 @@ KFX_HD uint64_t child_key(int nhits, int nholes, float chi2, int parent, int ran
 constexpr int kHole = -1;
 constexpr int kStop = -2;
 
-// Sorted best-K list of (chi2, hit) of one candidate's compatible hits,
-// held in registers: KM is the compile-time capacity, K <= KM the runtime
-// cap; insert and pop are unrolled over KM so that no element is ever
-// indexed by a runtime value (which would put the list in scratch memory).
+// Order-preserving integer image of a chi2 (a value rounded below zero, or
+// -0, still sorts first; -0 and +0 map to the same image) and its inverse.
+KFX_HD uint32_t chi2_image(float c) {
+  uint32_t b;
+  const float cz = c + 0.0f;  // -0 -> +0
+  __builtin_memcpy(&b, &cz, 4);
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+KFX_HD float chi2_from_image(uint32_t k) {
+  const uint32_t b = (k & 0x80000000u) ? (k & 0x7fffffffu) : ~k;
+  float c;
+  __builtin_memcpy(&c, &b, 4);
+  return c;
+}
+// (chi2, hit index) as one key, ascending in chi2 then in hit index
+KFX_HD uint64_t pair_key(float c, int h) { return ((uint64_t)chi2_image(c) << 32) | (uint32_t)h; }
+KFX_HD float pair_key_chi2(uint64_t k) { return chi2_from_image((uint32_t)(k >> 32)); }
+KFX_HD int pair_key_hit(uint64_t k) { return (int)(uint32_t)k; }
+constexpr uint64_t kNoKey = ~0ull;
+
+// Best-K list of one candidate's compatible hits: the KM smallest
+// (chi2, hit) keys in ascending order (empty entries kNoKey), held in
+// registers; n = the number of valid entries, capped at the runtime K <= KM
+// (entries from n on are not read).  Insertion is one compare-exchange
+// pass over the unrolled list: no branches, and no element is indexed by a
+// runtime value (which would put the list in scratch memory).
 template <int KM>
 struct BestK {
-  float c[KM];
-  int h[KM];
+  uint64_t k[KM];
   int n;
 };
 
 template <int KM>
-KFX_HD void bestk_init(BestK<KM>& b) { b.n = 0; }
+KFX_HD void bestk_init(BestK<KM>& b) {
+#pragma unroll
+  for (int i = 0; i < KM; ++i) b.k[i] = kNoKey;
+  b.n = 0;
+}
 
-// insert keeping ascending (chi2, hit): walk the list carrying the element
-// to place; a smaller pair swaps with the carried one; the carried element
-// lands in the first free slot or falls off the end
 template <int KM>
-KFX_HD void bestk_insert(BestK<KM>& b, int K, float c, int h) {
-  bool carry = true;
+KFX_HD void bestk_insert_key(BestK<KM>& b, int K, uint64_t key) {
 #pragma unroll
   for (int i = 0; i < KM; ++i) {
-    if (i < K && carry) {
-      if (i >= b.n) {
-        b.c[i] = c;
-        b.h[i] = h;
-        carry = false;
-      } else if (c < b.c[i] || (c == b.c[i] && h < b.h[i])) {
-        const float tc = b.c[i];
-        const int th = b.h[i];
-        b.c[i] = c;
-        b.h[i] = h;
-        c = tc;
-        h = th;
-      }
-    }
+    const uint64_t e = b.k[i];
+    b.k[i] = key < e ? key : e;
+    key = key < e ? e : key;
   }
   b.n = b.n < K ? b.n + 1 : K;
 }
 
 template <int KM>
-KFX_HD void bestk_pop(BestK<KM>& b) {
+KFX_HD void bestk_insert(BestK<KM>& b, int K, float c, int h) {
+  bestk_insert_key(b, K, pair_key(c, h));
+}
+
+// key of the K-th entry of a full list (kNoKey otherwise): a pair enters
+// the list only with a smaller key
+template <int KM>
+KFX_HD uint64_t bestk_threshold(const BestK<KM>& b, int K) {
+  uint64_t t = kNoKey;
 #pragma unroll
-  for (int i = 0; i + 1 < KM; ++i) {
-    b.c[i] = b.c[i + 1];
-    b.h[i] = b.h[i + 1];
-  }
-  b.n -= 1;
+  for (int i = 0; i < KM; ++i)
+    if (i == K - 1) t = b.k[i];
+  return b.n == K ? t : kNoKey;
 }
 
 // ---- SoA state access ---------------------------------------------------

@@ -142,6 +142,7 @@ extern "C" int hs_navigate(const double* table, int nl, double bz, int cur, cons
   }
   for (size_t i = 0; i < dp.size(); ++i) G.dpos[i] = dp[i];
   for (size_t i = 0; i < dn.size(); ++i) G.dneg[i] = dn[i];
+  nav_tables(G);
   State st;
   float c[21] = {0};
   to_state(p, c, st);
