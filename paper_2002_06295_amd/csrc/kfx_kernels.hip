@@ -551,60 +551,73 @@ __device__ int wave_scan(const BinIndex& B, int n_phi, int lane, bool has, const
       scan_range(W, B, n_phi, r, qa, qe);
       // four loads of 64 consecutive hits in flight per pass
       for (int base = qa; base < qe; base += 256) {
-        float c2[4];
-        uint64_t pk[4];
-        bool under[4];
         float4 hv[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const int q = base + 64 * u + lane;
           hv[u] = q < qe ? B.sorted[q] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         }
-        unsigned long long m_keep[4];
+        // keys of the pairs under the cut that would enter the owner's list
+        uint64_t kk[4];
+        int n_under = 0, n_keep = 0;
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-          const bool in = base + 64 * u + lane < qe;
-          c2[u] = pair_chi2(P, hv[u]);
+          const float c2 = pair_chi2(P, hv[u]);
           int hid;
           __builtin_memcpy(&hid, &hv[u].w, 4);
-          pk[u] = pair_key(c2[u], hid);
-          under[u] = in && c2[u] < cut;
-          const bool keep = under[u] && pk[u] < thr;
-          const unsigned long long m_under = __ballot(under[u]);
-          m_keep[u] = __ballot(keep);
-          if (lane == o) found += __popcll(m_under);
+          const uint64_t pk = pair_key(c2, hid);
+          const bool under = base + 64 * u + lane < qe && c2 < cut;
+          const bool keep = under && pk < thr;
+          kk[u] = keep ? pk : kNoKey;
+          n_under += __popcll(__ballot(under));
+          n_keep += __popcll(__ballot(keep));
         }
+        if (lane == o) found += n_under;
+        if (n_keep == 0) continue;
+        if (n_keep <= 3) {
+          // few: hand them over one by one
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          unsigned long long mk = m_keep[u];
-          if (!mk) continue;
-          if (__popcll(mk) <= 3) {
-            // few: hand them over one by one
+          for (int u = 0; u < 4; ++u) {
+            unsigned long long mk = __ballot(kk[u] != kNoKey);
             while (mk) {
               const int b = __ffsll((long long)mk) - 1;
               mk &= mk - 1ull;
-              const uint64_t kk = (uint64_t)rl_l((long)pk[u], b);
-              if (lane == o) bestk_insert_key(best, K, kk);
-            }
-          } else {
-            // many (hits sorted by phi approach the window centre with
-            // falling chi2): extract them smallest first, at most K, and
-            // stop at the first that no longer enters the list
-            uint64_t key = (m_keep[u] >> lane) & 1ull ? pk[u] : kNoKey;
-            for (int i = 0; i < K; ++i) {
-              const uint64_t m = group_min<16>(key);
-              const uint64_t r0 = (uint64_t)rl_l((long)m, 0), r1 = (uint64_t)rl_l((long)m, 16);
-              const uint64_t r2 = (uint64_t)rl_l((long)m, 32), r3 = (uint64_t)rl_l((long)m, 48);
-              const uint64_t a01 = r0 < r1 ? r0 : r1, a23 = r2 < r3 ? r2 : r3;
-              const uint64_t mn = a01 < a23 ? a01 : a23;
-              if (!(mn < thr)) break;  // none left (kNoKey), or no longer enters
-              if (lane == o) bestk_insert_key(best, K, mn);
-              thr = rl_l((long)bestk_threshold(best, K), o);
-              if (key == mn) key = kNoKey;
+              const uint64_t k1 = (uint64_t)rl_l((long)kk[u], b);
+              if (lane == o) bestk_insert_key(best, K, k1);
             }
           }
-          thr = rl_l((long)bestk_threshold(best, K), o);
+        } else {
+          // many (hits sorted by phi approach the window centre with
+          // falling chi2): each lane sorts its four keys, then rounds of a
+          // wave minimum over the lanes' smallest remaining keys hand the
+          // pass's keys to the owner smallest first, at most K of them,
+          // stopping at the first that no longer enters the list
+#define KFX_CX(a, b)                                  \
+  {                                                   \
+    const uint64_t lo_ = kk[a] < kk[b] ? kk[a] : kk[b]; \
+    kk[b] = kk[a] < kk[b] ? kk[b] : kk[a];            \
+    kk[a] = lo_;                                      \
+  }
+          KFX_CX(0, 1) KFX_CX(2, 3) KFX_CX(0, 2) KFX_CX(1, 3) KFX_CX(1, 2)
+#undef KFX_CX
+          for (int i = 0; i < K; ++i) {
+            const uint64_t m = group_min<16>(kk[0]);
+            const uint64_t r0 = (uint64_t)rl_l((long)m, 0), r1 = (uint64_t)rl_l((long)m, 16);
+            const uint64_t r2 = (uint64_t)rl_l((long)m, 32), r3 = (uint64_t)rl_l((long)m, 48);
+            const uint64_t a01 = r0 < r1 ? r0 : r1, a23 = r2 < r3 ? r2 : r3;
+            const uint64_t mn = a01 < a23 ? a01 : a23;
+            if (!(mn < thr)) break;  // none left (kNoKey), or no longer enters
+            if (lane == o) bestk_insert_key(best, K, mn);
+            thr = rl_l((long)bestk_threshold(best, K), o);
+            if (kk[0] == mn) {  // keys are unique (hit index): one lane advances
+              kk[0] = kk[1];
+              kk[1] = kk[2];
+              kk[2] = kk[3];
+              kk[3] = kNoKey;
+            }
+          }
         }
+        thr = rl_l((long)bestk_threshold(best, K), o);
       }
     }
   }

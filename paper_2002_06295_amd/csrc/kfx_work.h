@@ -65,6 +65,36 @@ KFX_HD int eta_bin_f(const Geometry& G, const Layer& Lr, float eta) {
   return (int)f;
 }
 
+// Short FP32 forms of asinh and atan2 for the window bounds, whose margins
+// (1e-5 absolute and more) cover their errors: asinh(x) = log(|x| +
+// sqrt(x^2 + 1)) with the sign of x, within 1e-6 absolute for the
+// arguments the geometry gives (|x| < 1e4); atan2 by octant reduction to
+// atan on [0, 1], there an odd polynomial of degree 15 fitted to atan
+// (Lawson-weighted least squares; 1.5e-7 in FP32), within 1e-6 overall.
+KFX_HD float asinh_win(float x) {
+  const float ax = fabsf(x);
+  const float v = __builtin_log2f(ax + __builtin_sqrtf(fmaf(ax, ax, 1.0f))) * 0.6931471805599453f;
+  return x < 0.0f ? -v : v;
+}
+KFX_HD float atan2_win(float y, float x) {
+  const float ax = fabsf(x), ay = fabsf(y);
+  const float hi = fmaxf(ax, ay), lo = fminf(ax, ay);
+  const float t = hi > 0.0f ? lo / hi : 0.0f;
+  const float t2 = t * t;
+  float p = -0.004054567310959101f;
+  p = fmaf(p, t2, 0.021862957626581192f);
+  p = fmaf(p, t2, -0.0559123270213604f);
+  p = fmaf(p, t2, 0.0964219719171524f);
+  p = fmaf(p, t2, -0.1390862911939621f);
+  p = fmaf(p, t2, 0.19946566224098206f);
+  p = fmaf(p, t2, -0.33329859375953674f);
+  p = fmaf(p, t2, 0.9999993443489075f);
+  float a = t * p;
+  if (ay > ax) a = 1.5707963267948966f - a;
+  if (x < 0.0f) a = 3.141592653589793f - a;
+  return y < 0.0f ? -a : a;
+}
+
 // An upper bound of asin(w / r) for 0 <= w < r: tan(asin(x)) >= asin(x),
 // i.e. w / sqrt(r^2 - w^2), wider by a relative (w/r)^2/3 when w/r is
 // small; a superset window is all the scan needs.
@@ -78,7 +108,7 @@ KFX_HD Window window_bins(const Geometry& G, const Layer& Lr, const State& pr, c
   const float wn = sqrtf(cut * F.S[5]) * infl + 1e-5f;
   const float px = (float)pr.x, py = (float)pr.y;
   const float rp = sqrtf(px * px + py * py);
-  const float php = atan2f(py, px);
+  const float php = atan2_win(py, px);
   Window w;
   if (!__builtin_isfinite(wu) || !__builtin_isfinite(wv) || !__builtin_isfinite(wn) || !__builtin_isfinite(rp) || !__builtin_isfinite(php) ||
       !__builtin_isfinite((float)pr.z)) {
@@ -93,15 +123,15 @@ KFX_HD Window window_bins(const Geometry& G, const Layer& Lr, const State& pr, c
     const float rmin = rp - wn;
     dphi = (rmin <= 0.0f || wu >= rmin) ? 4.0f : asin_upper(wu, rmin) + 1e-5f;
     const float R = (float)Lr.pos;
-    elo = asinhf(((float)pr.z - wv) / R) - 1e-5f;
-    ehi = asinhf(((float)pr.z + wv) / R) + 1e-5f;
+    elo = asinh_win(((float)pr.z - wv) / R) - 1e-5f;
+    ehi = asinh_win(((float)pr.z + wv) / R) + 1e-5f;
   } else {
     const float rmin = rp - wv;
     const float rmax = sqrtf(wu * wu + (rp + wv) * (rp + wv));
     dphi = (rmin <= 0.0f || wu >= rmin) ? 4.0f : asin_upper(wu, rmin) + 1e-5f;
     const float Z = (float)Lr.pos;
-    const float a = asinhf(Z / rmax);
-    const float b = rmin > 0.0f ? asinhf(Z / rmin) : (Z > 0.0f ? 1e30f : -1e30f);
+    const float a = asinh_win(Z / rmax);
+    const float b = rmin > 0.0f ? asinh_win(Z / rmin) : (Z > 0.0f ? 1e30f : -1e30f);
     elo = fminf(a, b) - 1e-5f;
     ehi = fmaxf(a, b) + 1e-5f;
   }
@@ -291,6 +321,15 @@ KFX_HD ScanWin scan_win(const Geometry& G, const BinIndex& B, int ev, int layer,
   s.b0 = w.pb0;
   s.b1 = wrap > 0 ? G.n_phi : w.pb0 + w.npb;
   s.w1 = wrap;
+  if (s.nrows > 0 && 2 * w.npb > G.n_phi) {
+    // more than half of phi: the whole rows instead (still a superset), and
+    // consecutive whole rows are one contiguous range of the sorted hits
+    s.b0 = 0;
+    s.b1 = s.nrows * G.n_phi;
+    s.nrows = 1;
+    s.nseg = 1;
+    s.w1 = 0;
+  }
   return s;
 }
 
