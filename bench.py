@@ -182,6 +182,9 @@ def main():
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the timed region, copy this many MiB device-to-device (a kernel of "
                          "known traffic for scaling the profiler's FETCH_SIZE/WRITE_SIZE)")
+    ap.add_argument("--shape", default="",
+                    help="launch shape of the fused kernel as JSON (as the autotuner reports it); "
+                         "skips the autotuner, e.g. to profile the tuned shape alone")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -209,9 +212,13 @@ def main():
     # launch shape of the fused kernel for this workload (identical results
     # for every shape; only the time differs)
     t_tune = time.perf_counter()
-    shape = ctx.autotune_build(hits, seeds_d, sev_d, reps=2, **build_kw(ev, kfx.MODE_FUSED))
-    tuned_ms = shape.pop("ms")
-    log(f"[bench] autotuned {shape} ({tuned_ms:.3f} ms) in {time.perf_counter() - t_tune:.1f}s")
+    if args.shape:
+        shape = {k: int(v) for k, v in json.loads(args.shape).items() if k != "ms"}
+        log(f"[bench] launch shape given: {shape}")
+    else:
+        shape = ctx.autotune_build(hits, seeds_d, sev_d, reps=2, **build_kw(ev, kfx.MODE_FUSED))
+        tuned_ms = shape.pop("ms")
+        log(f"[bench] autotuned {shape} ({tuned_ms:.3f} ms) in {time.perf_counter() - t_tune:.1f}s")
     wall, times, stats, out = run_build(ctx, kfx, hits, ev, args.steps, args.warmup, kfx.MODE_FUSED, shape=shape)
     search_ms = float(np.mean([t[1] for t in times]))
     kern_ms = float(np.mean([t[2] for t in times]))

@@ -38,6 +38,10 @@ struct kfx_ctx {
   std::vector<hipEvent_t> ring;  // kEv per slot
   int ring_n = 0, ring_next = 0, ring_count = 0;
   hipEvent_t* slot_ev = nullptr;  // events of the call in progress
+  // a second stream of the context: the fused build forks the seed start
+  // onto it while the caller's stream bins the hits, then joins
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
 
 namespace {
@@ -86,6 +90,15 @@ void* ws(kfx_ctx* c, const char* name, size_t bytes, hipStream_t st, int& rc) {
   }
   pool[name] = {p, grown};
   return p;
+}
+
+// the context's second stream and its fork / join events (created once)
+int side_stream(kfx_ctx* c) {
+  if (c->side) return KFX_OK;
+  int rc = hip_check(c, hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming), "fork event");
+  if (!rc) rc = hip_check(c, hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming), "join event");
+  if (!rc) rc = hip_check(c, hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking), "second stream");
+  return rc;
 }
 
 bool is_finite(double v) { return std::isfinite(v); }
@@ -205,6 +218,12 @@ void kfx_destroy(kfx_ctx* c) {
     if (c->dev_geo) (void)hipFree(c->dev_geo);
     for (auto& e : c->ring)
       if (e) (void)hipEventDestroy(e);
+    if (c->side) {
+      (void)hipStreamSynchronize(c->side);
+      (void)hipStreamDestroy(c->side);
+    }
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
   }
   delete c;
 }
@@ -396,8 +415,6 @@ int build_impl(kfx_ctx* c, const kfx_hits* hits, const int32_t* seeds, const int
     tev = c->ring.data() + kEv * c->ring_next;
     if ((rc = hip_check(c, hipEventRecord(tev[0], st), "timing event"))) return rc;
   }
-  if ((rc = build_index(c, hits, nullptr, st))) return rc;
-  if (tev && (rc = hip_check(c, hipEventRecord(tev[1], st), "timing event"))) return rc;
   auto close_timing = [&]() -> int {
     if (!tev) return KFX_OK;
     int r = hip_check(c, hipEventRecord(tev[4], st), "timing event");
@@ -406,7 +423,13 @@ int build_impl(kfx_ctx* c, const kfx_hits* hits, const int32_t* seeds, const int
     c->ring_count = std::min(c->ring_count + 1, c->ring_n);
     return KFX_OK;
   };
+  auto bin = [&]() -> int {
+    int r = build_index(c, hits, nullptr, st);
+    if (!r && tev) r = hip_check(c, hipEventRecord(tev[1], st), "timing event");
+    return r;
+  };
   if (n_seeds == 0) {
+    if ((rc = bin())) return rc;
     if (tev && ((rc = hip_check(c, hipEventRecord(tev[2], st), "timing event")) ||
                 (rc = hip_check(c, hipEventRecord(tev[3], st), "timing event"))))
       return rc;
@@ -416,7 +439,6 @@ int build_impl(kfx_ctx* c, const kfx_hits* hits, const int32_t* seeds, const int
   BuildArgs a{};
   a.G = c->dev_geo;
   a.H = view(hits);
-  a.B = index_view(c);
   a.seeds = seeds;
   a.seed_event = seed_event;
   a.n_seeds = n_seeds;
@@ -470,10 +492,22 @@ int build_impl(kfx_ctx* c, const kfx_hits* hits, const int32_t* seeds, const int
   o.max_hits = out->max_hits;
 
   if (p->mode == KFX_MODE_PLAIN) {
+    if ((rc = bin())) return rc;
+    a.B = index_view(c);
     launch_build_plain(a, o, st, tev ? tev + 2 : nullptr);
   } else {
     int* counter = (int*)ws(c, "b.counter", 256, st, rc);
     if (rc) return rc;
+    // the seed start reads only the hits: it runs on the second stream
+    // while this one bins them
+    if ((rc = side_stream(c)) || (rc = hip_check(c, hipEventRecord(c->ev_fork, st), "fork")) ||
+        (rc = hip_check(c, hipStreamWaitEvent(c->side, c->ev_fork, 0), "fork")))
+      return rc;
+    launch_build_init(a, c->side);
+    if ((rc = hip_check(c, hipEventRecord(c->ev_join, c->side), "join"))) return rc;
+    if ((rc = bin())) return rc;
+    a.B = index_view(c);
+    if ((rc = hip_check(c, hipStreamWaitEvent(st, c->ev_join, 0), "join"))) return rc;
     const int threads = p->block_threads ? p->block_threads : 256;
     int blocks = p->blocks;
     if (blocks == 0) blocks = c->n_cu * 4;

@@ -284,13 +284,19 @@ struct TracksOut {
   int max_hits;
 };
 
-// Rebuild the hit list of one final slot from the per-step history.
-KFX_HD void finalize_slot(const BuildArgs& a, int fin, const TracksOut& o, int s, int j) {
+// Output of one final slot (m its meta word, T the seed's step count): the
+// hit list rebuilt from the per-step history by one backward walk over the
+// parent pointers (the seed hits, then one entry per step with a hit or a
+// hole, n_hits + n_holes entries in all; stop entries add none), the
+// counts, the chi2 sum and the state.
+KFX_HD void write_slot_output(const BuildArgs& a, const TracksOut& o, int s, int j, int T, int m, float chi2,
+                              const State& st) {
   const long slot = (long)s * a.K + j;
-  const int m = a.meta[fin][slot];
   int* out = o.hits + slot * o.max_hits;
-  for (int q = 0; q < o.max_hits; ++q) out[q] = -3;
-  if (!(meta_flags(m) & kFlagLive)) {
+  const bool live = (meta_flags(m) & kFlagLive) != 0;
+  const int total = live ? meta_nhits(m) + meta_nholes(m) : 0;
+  for (int q = total < o.max_hits ? total : o.max_hits; q < o.max_hits; ++q) out[q] = -3;
+  if (!live) {
     o.n_hits[slot] = 0;
     o.n_holes[slot] = 0;
     o.chi2[slot] = 0.0f;
@@ -300,18 +306,8 @@ KFX_HD void finalize_slot(const BuildArgs& a, int fin, const TracksOut& o, int s
     store_state(o.state, slot, z);
     return;
   }
-  // count the entries first (stop entries add nothing)
-  const int T = a.n_steps[s];
-  int n = 0, cj = j;
-  for (int t = T - 1; t >= 0; --t) {
-    const long h = hist_index(a, s, t, cj);
-    if (a.hist_code[h] != kStop) ++n;
-    cj = a.hist_parent[h];
-  }
-  const int total = kSeedHits + n;
   for (int q = 0; q < kSeedHits && q < o.max_hits; ++q) out[q] = a.seeds[3 * s + q];
-  int w = total - 1;
-  cj = j;
+  int w = total - 1, cj = j;
   for (int t = T - 1; t >= 0; --t) {
     const long h = hist_index(a, s, t, cj);
     const int code = a.hist_code[h];
@@ -323,10 +319,16 @@ KFX_HD void finalize_slot(const BuildArgs& a, int fin, const TracksOut& o, int s
   }
   o.n_hits[slot] = meta_nhits(m);
   o.n_holes[slot] = meta_nholes(m);
-  o.chi2[slot] = a.chi2[fin][slot];
+  o.chi2[slot] = chi2;
+  store_state(o.state, slot, st);
+}
+
+// The same for a slot of the plain path's final candidate buffer.
+KFX_HD void finalize_slot(const BuildArgs& a, int fin, const TracksOut& o, int s, int j) {
+  const long slot = (long)s * a.K + j;
   State st;
   load_state(a.cand[fin], slot, st);
-  store_state(o.state, slot, st);
+  write_slot_output(a, o, s, j, a.n_steps[s], a.meta[fin][slot], a.chi2[fin][slot], st);
 }
 
 }  // namespace kfx

@@ -41,6 +41,7 @@ void launch_step_compat(const Geometry* G, const HitsView& H, const BinIndex& B,
 // ev: NULL, or two events recorded after the seed start and after the
 // search (before the output kernel)
 void launch_build_plain(const BuildArgs& a, const TracksOut& o, hipStream_t st, const hipEvent_t* ev);
+void launch_build_init(const BuildArgs& a, hipStream_t st);
 void launch_build_fused(const BuildArgs& a, const TracksOut& o, int* seed_counter, int blocks, int threads,
                         int lanes, int waves_per_simd, hipStream_t st, const hipEvent_t* ev);
 int fused_lanes_for(int K);

@@ -927,13 +927,18 @@ int fused_lanes_for(int K) {
   return g;
 }
 
+// Start states of the fused build (FP64 seed phase) in their own kernel, so
+// that its FP64 temporaries do not set the register budget of the
+// persistent kernel; it needs only the hits, not their bin index.
+void launch_build_init(const BuildArgs& a, hipStream_t st) {
+  if (a.n_seeds <= 0) return;
+  hipLaunchKernelGGL(k_build_init, dim3(nblk(a.n_seeds, 128)), dim3(128), 0, st, a);
+}
+
 void launch_build_fused(const BuildArgs& a, const TracksOut& o, int* seed_counter, int blocks, int threads,
                         int lanes, int waves_per_simd, hipStream_t st, const hipEvent_t* ev) {
   if (a.n_seeds <= 0) return;
   launch_fill(seed_counter, 1, 0, st);
-  // start states (FP64 seed phase) in their own kernel, so that its FP64
-  // temporaries do not set the register budget of the persistent kernel
-  hipLaunchKernelGGL(k_build_init, dim3(nblk(a.n_seeds, 128)), dim3(128), 0, st, a);
   if (ev) (void)hipEventRecord(ev[0], st);
   const size_t shmem = (lanes == 4 ? sizeof(FusedShared<4>) : lanes == 8 ? sizeof(FusedShared<8>)
                                                                          : sizeof(FusedShared<16>)) * threads;
