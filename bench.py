@@ -35,12 +35,13 @@ METRIC = "cand-layer Kalman steps/s at 1e-4 rel tol; fit+grad tracks/s vs plain 
 
 # Floating-point operations per unit of work, counted from the formulas as
 # the kernels implement them (FMA = 2, transcendental calls = 1):
-#   per step   navigation (Newton crossing + disk checks) ~300, transport and
+#   per step   navigation (closed-form cylinder crossing ~25, its z check
+#              and the polar angle ~5, one disk check ~25) ~55, transport and
 #              covariance J C J^T + Q with the tangent-plane projection ~540,
 #              measurement frame and S^-1 ~195, window ~40
 #   per pair   FP64 residual + 3x3 chi2 ~35
 #   per update FP64 frame, gain, state and covariance update ~500
-FLOP_PER_STEP = 1075.0
+FLOP_PER_STEP = 830.0
 FLOP_PER_PAIR = 35.0
 FLOP_PER_UPDATE = 500.0
 # Unpacked FP32 and FP64 vector FMA both issue 64 per clock per CU on
