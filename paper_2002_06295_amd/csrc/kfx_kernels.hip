@@ -493,8 +493,20 @@ __device__ int wave_scan(const BinIndex& B, int n_phi, int lane, bool has, const
   bestk_init(best);
   int found = 0;
   const int nr = has ? scan_nranges(sw) : 0;
+  // bounds of the first kR ranges, loaded together and kept for the scan
+  // (a window rarely has more); the others are loaded where needed
+  constexpr int kR = 4;
+  int ra[kR], re[kR];
+#pragma unroll
+  for (int r = 0; r < kR; ++r) {
+    ra[r] = 0;
+    re[r] = 0;
+    if (r < nr) scan_range(sw, B, n_phi, r, ra[r], re[r]);
+  }
   int total_mine = 0;
-  for (int r = 0; r < nr; ++r) {
+#pragma unroll
+  for (int r = 0; r < kR; ++r) total_mine += re[r] - ra[r];
+  for (int r = kR; r < nr; ++r) {
     int qa, qe;
     scan_range(sw, B, n_phi, r, qa, qe);
     total_mine += qe - qa;
@@ -503,8 +515,14 @@ __device__ int wave_scan(const BinIndex& B, int n_phi, int lane, bool has, const
   // lane-private scan of the small windows, four loads in flight
   if (has && !big) {
     for (int r = 0; r < nr; ++r) {
-      int qa, qe;
-      scan_range(sw, B, n_phi, r, qa, qe);
+      int qa = ra[0], qe = re[0];
+#pragma unroll
+      for (int i = 1; i < kR; ++i)
+        if (r == i) {
+          qa = ra[i];
+          qe = re[i];
+        }
+      if (r >= kR) scan_range(sw, B, n_phi, r, qa, qe);
       for (int q = qa; q < qe; q += 4) {
         float4 hv[4];
 #pragma unroll
@@ -757,8 +775,13 @@ k_build_fused(BuildArgs a, int* seed_counter) {
         }
       }
     }
+    // the stream's head and the entry after it are held in registers, so
+    // that a winning lane's next key is at hand in the next round
     int idx = 0;
     uint64_t head = m > 0 ? me.ekey[0] : ~0ull;
+    uint64_t next = m > 1 ? me.ekey[1] : ~0ull;
+    int hcode = m > 0 ? me.ecode[0] : kStop;
+    float hchi2 = m > 0 ? me.echi2[0] : 0.0f;
     int my_parent = -1, my_code = kStop;
     float my_chi2 = 0.0f;
     for (int i = 0; i < K; ++i) {
@@ -769,10 +792,14 @@ k_build_fused(BuildArgs a, int* seed_counter) {
       const int wl = win ? __ffsll((long long)win) - 1 : 0;
       if (win && gl == i) my_parent = wl & (G_LANES - 1);
       if (win && lane == wl) {
-        sh[gbase + i].sel_code = me.ecode[idx];
-        sh[gbase + i].sel_chi2 = me.echi2[idx];
+        sh[gbase + i].sel_code = hcode;
+        sh[gbase + i].sel_chi2 = hchi2;
         ++idx;
-        head = idx < m ? me.ekey[idx] : ~0ull;
+        head = next;
+        const bool more = idx < m;
+        hcode = more ? me.ecode[idx] : kStop;
+        hchi2 = more ? me.echi2[idx] : 0.0f;
+        next = idx + 1 < m ? me.ekey[idx + 1] : ~0ull;
       }
     }
     wave_sync();
