@@ -44,6 +44,11 @@ METRIC = "cand-layer Kalman steps/s at 1e-4 rel tol; fit+grad tracks/s vs plain 
 FLOP_PER_STEP = 830.0
 FLOP_PER_PAIR = 35.0
 FLOP_PER_UPDATE = 500.0
+# The fit (FP64 throughout): per hit the surface crossing, J C J^T + Q and
+# the projection, the update ~1700; its adjoint per hit (recompute of the
+# step from its checkpoint and the reverse sweep) ~6000.
+FIT_FLOP_PER_HIT = 1700.0
+ADJ_FLOP_PER_HIT = 6000.0
 # Unpacked FP32 and FP64 vector FMA both issue 64 per clock per CU on
 # gfx950: 256 CUs x 2.4 GHz x 128 FLOP/clk.  (Packed FP32, which doubles the
 # FP32 figure to 157.3 TFLOP/s, is not used by these kernels.)
@@ -331,7 +336,7 @@ def main():
         fg = ctxf.fit_tracks(hf, toff, th, field_scale=1.0, ckpt=True)
         ctxf.fit_tracks_backward(hf, toff, th, fg, ones)
         torch.cuda.synchronize()
-        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        e0, e1, e2, e3 = (torch.cuda.Event(enable_timing=True) for _ in range(4))
         nrep = 5
         e0.record()
         for _ in range(nrep):
@@ -341,12 +346,21 @@ def main():
             fg = ctxf.fit_tracks(hf, toff, th, field_scale=1.0, ckpt=True, out=fg)
             ctxf.fit_tracks_backward(hf, toff, th, fg, ones)
         e2.record()
+        for _ in range(nrep):
+            ctxf.fit_tracks_backward(hf, toff, th, fg, ones)
+        e3.record()
         torch.cuda.synchronize()
         fms = e0.elapsed_time(e1) / nrep
         gms = e1.elapsed_time(e2) / nrep
+        bms = e2.elapsed_time(e3) / nrep
+        nh = int(evf.trk_offsets[-1])
         sec["align200k_fit"] = {"fit_tracks_per_s": evf.n_tracks / (fms * 1e-3), "fit_ms": fms,
                                 "fit_grad_tracks_per_s": evf.n_tracks / (gms * 1e-3), "fit_grad_ms": gms,
-                                "tracks": evf.n_tracks, "hits": int(evf.trk_offsets[-1]),
+                                "backward_ms": bms,
+                                # the fit is the propagate + update chain alone (FP64)
+                                "fit_alu_frac": nh * FIT_FLOP_PER_HIT / (fms * 1e-3) / 1e12 / ALU_PEAK_TFLOPS,
+                                "backward_alu_frac": nh * ADJ_FLOP_PER_HIT / (bms * 1e-3) / 1e12 / ALU_PEAK_TFLOPS,
+                                "tracks": evf.n_tracks, "hits": nh,
                                 "grad_params": 3 * evf.geometry.n_layers + 1}
         log(f"[bench] align200k: fit {fms:.3f} ms ({evf.n_tracks / (fms * 1e-3):.3e} tracks/s), "
             f"fit+grad {gms:.3f} ms ({evf.n_tracks / (gms * 1e-3):.3e} tracks/s)")

@@ -169,7 +169,11 @@ __global__ void k_bin_gather(HitsView H, const int* perm, const int* n_valid, fl
 }
 
 // ---------------------------------------------------------------- fit (a10)
-__global__ void __launch_bounds__(128) k_fit(const Geometry* __restrict__ G, HitsView H, const int* trk_off,
+// Two wavefronts per SIMD (at most 256 registers a lane; the FP64 filter
+// step needs about that many): 200k tracks are ~3 wavefronts per SIMD, and
+// two resident at a time hide part of each other's latency.
+__global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2, 2)))
+k_fit(const Geometry* __restrict__ G, HitsView H, const int* trk_off,
                                              const int* trk_hits, int n_tracks, Prior pr,
                                              const float* align, float fscale, FitOut o) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
