@@ -275,6 +275,7 @@ int kfx_load_layers(kfx_ctx* c, const double* table, int n_layers, double bz, in
       (L.pos > 0 ? dp : dn).push_back(i);
     }
   }
+  for (int i = 0; i < n_layers; ++i) G.L[i].eta_scale = (float)(n_eta / (G.L[i].eta_hi - G.L[i].eta_lo));
   std::sort(bar.begin(), bar.end(), [&](int a, int b) { return G.L[a].pos < G.L[b].pos; });
   std::sort(dp.begin(), dp.end(), [&](int a, int b) { return G.L[a].pos < G.L[b].pos; });
   std::sort(dn.begin(), dn.end(), [&](int a, int b) { return G.L[a].pos > G.L[b].pos; });

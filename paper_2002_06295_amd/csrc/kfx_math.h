@@ -47,6 +47,7 @@ struct Layer {
   double pos;      // R (barrel) or Z (disk)
   double lo, hi;   // z bounds (barrel) or r bounds (disk)
   double eta_lo, eta_hi;  // pseudorapidity range of the layer's hit bins
+  float eta_scale;        // eta bins per unit of eta (n_eta / range)
   float x0;        // thickness in radiation lengths
   float v_u, v_v, v_n;    // hit variances along the local u, v, n axes
 };
@@ -401,8 +402,9 @@ KFX_HD void add_noise(StateT<R>& st, const Layer& Ld, R sth, R cth, R cinc) {
   const R k = (R)st.k;
   const R th0 = (R)0.0136 * mabs(k) * sth * msqrt(t) * ((R)1 + (R)0.038 * mlog(t));
   const R var = th0 * th0;
-  const R cot = cth / sth;
-  st.C[sidx(4, 4)] += var / (sth * sth);
+  const R isth = (R)1 / sth;
+  const R cot = cth * isth;
+  st.C[sidx(4, 4)] += var * (isth * isth);
   st.C[sidx(5, 5)] += var;
   st.C[sidx(3, 3)] += k * k * cot * cot * var;
   st.C[sidx(5, 3)] += -k * cot * var;
@@ -432,7 +434,8 @@ KFX_HD void transport(const StateT<R>& in, const Layer& Ld, double cphi, double 
   // Jacobian and noise in R from the rounded geometry
   const R s = (R)s_d, kappa = (R)kappa_d, omega = (R)omega_d;
   const R sth = (R)sth_d, cth = (R)cth_d;
-  const R cot = cth / sth;
+  const R isth = (R)1 / sth;
+  const R cot = cth * isth;
   ChordT<R> c;
   c.a = (R)cd.a;
   c.sa = (R)cd.sa;
@@ -448,14 +451,15 @@ KFX_HD void transport(const StateT<R>& in, const Layer& Ld, double cphi, double 
   const R Axk = hs2 * (c.dsinc * cpsi - c.sinc * spsi);
   const R Ayk = hs2 * (c.dsinc * spsi + c.sinc * cpsi);
   const R Axp = -dyf, Ayp = dxf;
-  const R Azt = -s / (sth * sth);
+  const R Azt = -s * (isth * isth);
   const R Apk = kappa * s;
   // c = ds/dp from the surface equation
   R cv[6];
   if (disk) {
     cv[0] = (R)0; cv[1] = (R)0; cv[3] = (R)0; cv[4] = (R)0;
-    cv[2] = -sth / cth;
-    cv[5] = s / (sth * cth);
+    const R icth = (R)1 / cth;
+    cv[2] = -sth * icth;
+    cv[5] = s * (isth * icth);
   } else {
     const R x1 = (R)out.x, y1 = (R)out.y;
     const R iDn = (R)-1 / (x1 * c1 + y1 * s1);
@@ -516,6 +520,8 @@ KFX_HD void transport(const StateT<R>& in, const Layer& Ld, double cphi, double 
 #pragma unroll
     for (int j = 0; j <= i; ++j)
       out.C[sidx(i, j)] = N[i][j] + bv[i] * u[j] + u[i] * bv[j] + sig * bv[i] * bv[j];
+  // unit radius vector at the destination (barrel: the surface normal)
+  R e0_n = (R)0, e1_n = (R)0;
   if (disk) {
     // the z row of J is identically zero on a plane
 #pragma unroll
@@ -525,8 +531,10 @@ KFX_HD void transport(const StateT<R>& in, const Layer& Ld, double cphi, double 
     // e = (x, y, 0)/r.  Rounding leaves some; at a steep crossing it rivals
     // sigma_n^2 in S.  Apply P C P^T with P = I - e e^T (an identity in exact
     // arithmetic): C' = C - e w^T - w e^T + (e^T C e) e e^T, w = C e.
-    const double r1 = sqrt(out.x * out.x + out.y * out.y);
-    const R e0 = (R)(out.x / r1), e1 = (R)(out.y / r1);
+    const double ir1 = 1.0 / sqrt(out.x * out.x + out.y * out.y);
+    const R e0 = (R)(out.x * ir1), e1 = (R)(out.y * ir1);
+    e0_n = e0;
+    e1_n = e1;
     R w[6];
 #pragma unroll
     for (int j = 0; j < 6; ++j) w[j] = e0 * out.C[sidx(0, j)] + e1 * out.C[sidx(1, j)];
@@ -543,8 +551,9 @@ KFX_HD void transport(const StateT<R>& in, const Layer& Ld, double cphi, double 
   if (disk) {
     cinc = mabs(cth);
   } else {
-    const R x1 = (R)out.x, y1 = (R)out.y;
-    cinc = mabs(sth * (x1 * c1 + y1 * s1) / msqrt(x1 * x1 + y1 * y1));
+    // cosine of the incidence angle: sin(theta) times the transverse
+    // direction's component along the radius (e0, e1)
+    cinc = mabs(sth * (e0_n * c1 + e1_n * s1));
   }
   add_noise(out, Ld, sth, cth, cinc);
 }
@@ -562,8 +571,8 @@ using Frame = FrameT<float>;
 
 template <class R>
 KFX_HD void make_frame(const StateT<R>& st, const Layer& Ld, FrameT<R>& F) {
-  const double r = sqrt(st.x * st.x + st.y * st.y);
-  const R c = (R)(st.x / r), s = (R)(st.y / r);
+  const double ir = 1.0 / sqrt(st.x * st.x + st.y * st.y);
+  const R c = (R)(st.x * ir), s = (R)(st.y * ir);
   const bool disk = Ld.kind == kDisk;
   const R z0 = (R)0, o1 = (R)1;
   F.h[0][0] = -s; F.h[0][1] = c; F.h[0][2] = z0;

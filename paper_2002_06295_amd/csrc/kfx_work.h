@@ -60,7 +60,7 @@ struct Window {
 };
 
 KFX_HD int eta_bin_f(const Geometry& G, const Layer& Lr, float eta) {
-  float f = floorf((eta - (float)Lr.eta_lo) / (float)(Lr.eta_hi - Lr.eta_lo) * (float)G.n_eta);
+  float f = floorf((eta - (float)Lr.eta_lo) * Lr.eta_scale);
   f = fminf(fmaxf(f, 0.0f), (float)(G.n_eta - 1));
   return (int)f;
 }
@@ -122,9 +122,9 @@ KFX_HD Window window_bins(const Geometry& G, const Layer& Lr, const State& pr, c
   if (Lr.kind == kBarrel) {
     const float rmin = rp - wn;
     dphi = (rmin <= 0.0f || wu >= rmin) ? 4.0f : asin_upper(wu, rmin) + 1e-5f;
-    const float R = (float)Lr.pos;
-    elo = asinh_win(((float)pr.z - wv) / R) - 1e-5f;
-    ehi = asinh_win(((float)pr.z + wv) / R) + 1e-5f;
+    const float iR = 1.0f / (float)Lr.pos;
+    elo = asinh_win(((float)pr.z - wv) * iR) - 1e-5f;
+    ehi = asinh_win(((float)pr.z + wv) * iR) + 1e-5f;
   } else {
     const float rmin = rp - wv;
     const float rmax = sqrtf(wu * wu + (rp + wv) * (rp + wv));
@@ -141,10 +141,10 @@ KFX_HD Window window_bins(const Geometry& G, const Layer& Lr, const State& pr, c
     w.pb0 = 0;
     w.npb = G.n_phi;
   } else {
-    const float bw = (float)(2.0 * kPi) / (float)G.n_phi;
+    const float ibw = (float)G.n_phi * (float)(0.5 / kPi);  // phi bins per radian
     const float pi = (float)kPi;
-    int b0 = (int)floorf((php - dphi + pi) / bw);
-    int b1 = (int)floorf((php + dphi + pi) / bw);
+    int b0 = (int)floorf((php - dphi + pi) * ibw);
+    int b1 = (int)floorf((php + dphi + pi) * ibw);
     int n = b1 - b0 + 1;
     if (n > G.n_phi) n = G.n_phi;
     b0 %= G.n_phi;
