@@ -265,9 +265,23 @@ KFX_HD double path_to_cylinder(const StateT<R>& st, double cphi, double sphi, do
   const double tau = c0 / (-D - sqrt(disc));
   const double x = k * tau;
   double s;
-  if (fabs(x) < 1e-4) {
+  if (fabs(x) < 0.25) {
+    // atan(x)/x = sum (-1)^n x^2n / (2n + 1), to the x^24 term: the
+    // truncation (< 1e-17 for |x| < 0.25) is below FP64 rounding
     const double x2 = x * x;
-    s = tau * fma(x2, fma(x2, 0.2, -1.0 / 3.0), 1.0);  // atan(x)/x to x^4
+    double p = 1.0 / 25.0;
+    p = fma(p, x2, -1.0 / 23.0);
+    p = fma(p, x2, 1.0 / 21.0);
+    p = fma(p, x2, -1.0 / 19.0);
+    p = fma(p, x2, 1.0 / 17.0);
+    p = fma(p, x2, -1.0 / 15.0);
+    p = fma(p, x2, 1.0 / 13.0);
+    p = fma(p, x2, -1.0 / 11.0);
+    p = fma(p, x2, 1.0 / 9.0);
+    p = fma(p, x2, -1.0 / 7.0);
+    p = fma(p, x2, 1.0 / 5.0);
+    p = fma(p, x2, -1.0 / 3.0);
+    s = tau * fma(p, x2, 1.0);
   } else {
     s = atan(x) / k;
   }
