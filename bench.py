@@ -317,6 +317,8 @@ def main():
             km = float(np.mean([t[1] for t in tf]))
             fl = algorithmic_flops(sf)
             sec[name] = {"steps_per_s": sf[0] / (wf * 1e-3), "ms_per_step": wf, "fused_kernel_ms": km,
+                         "binning_ms": float(np.mean([t[0] for t in tf])),
+                         "building_ms": float(np.mean([t[2] for t in tf])),
                          "alu_frac": fl / (km * 1e-3) / 1e12 / ALU_PEAK_TFLOPS, "launch_shape": sh2,
                          "plain_steps_per_s": sp[0] / (wp * 1e-3), "steps_per_launch": sf[0]}
             log(f"[bench] {name}: fused {sec[name]['steps_per_s']:.3e} steps/s, plain "
