@@ -190,7 +190,10 @@ int kfx_step_compat(kfx_ctx* ctx, const kfx_hits* hits, const int32_t* cand_even
 /* Track building (Sec. 1-3).  seeds: device int32 [n_seeds][3];
  * seed_event: device int32 [n_seeds].  Bins the hits, starts every seed,
  * then per step keeps the best K children of each seed.  KFX_EOVERFLOW
- * (with out->needed) when out->capacity < n_seeds * K. */
+ * (with out->needed) when out->capacity < n_seeds * K.  KFX_MODE_FUSED
+ * takes at most 2^27 - 3 hits (its per-step history words hold the hit
+ * index in 27 bits) and a launch shape whose LDS fits in a block
+ * (KFX_EINVAL otherwise). */
 int kfx_build_tracks(kfx_ctx* ctx, const kfx_hits* hits, const int32_t* seeds,
                      const int32_t* seed_event, int32_t n_seeds, const kfx_build_params* params,
                      kfx_tracks* out, void* stream);

@@ -26,6 +26,7 @@ struct kfx_ctx {
   std::map<std::string, std::pair<void*, size_t>> pool;
   std::map<std::string, std::pair<void*, size_t>>* active = &pool;
   int n_cu = 256;
+  size_t max_lds = 65536;  // LDS a block may use
   // hit index of the last kfx_bin_hits / kfx_build_tracks call
   bool have_index = false;
   const void* index_hits_key[3] = {nullptr, nullptr, nullptr};
@@ -206,6 +207,9 @@ int kfx_create(int device, kfx_ctx** out) {
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
     c->n_cu = cus;
+  int lds = 0;
+  if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess && lds > 0)
+    c->max_lds = (size_t)lds;
   *out = c;
   return KFX_OK;
 }
@@ -373,6 +377,16 @@ int kfx_step_compat(kfx_ctx* c, const kfx_hits* hits, const int32_t* cand_event,
 
 namespace {
 constexpr int kEv = 5;  // timing events per build call
+// hit indices of the fused kernel's history words (27 bits for code + 2)
+constexpr long kFusedMaxHits = (1L << 27) - 3;
+
+// whether a fused launch shape's LDS (state slots, history, layer table)
+// fits in a block
+bool fused_shape_fits(const kfx_ctx* c, const kfx_build_params* p) {
+  const int lanes = p->lanes_per_seed ? p->lanes_per_seed : fused_lanes_for(p->max_cands);
+  const int threads = p->block_threads ? p->block_threads : 256;
+  return fused_lds_bytes(lanes, threads, p->max_steps) + fused_static_lds_bytes() <= c->max_lds;
+}
 
 int build_impl(kfx_ctx* c, const kfx_hits* hits, const int32_t* seeds, const int32_t* seed_event, int32_t n_seeds,
                const kfx_build_params* p, kfx_tracks* out, hipStream_t st) {
@@ -399,6 +413,10 @@ int build_impl(kfx_ctx* c, const kfx_hits* hits, const int32_t* seeds, const int
     const int lanes = p->lanes_per_seed ? p->lanes_per_seed : fused_lanes_for(p->max_cands);
     if (p->seeds_per_wave < 0 || p->seeds_per_wave > 64 / lanes)
       return fail(c, KFX_EINVAL, "seeds_per_wave must be 0 or in [1, 64 / lanes_per_seed]");
+    if (p->mode == KFX_MODE_FUSED) {
+      if (!fused_shape_fits(c, p)) return fail(c, KFX_EINVAL, "launch shape needs more LDS than a block may use");
+      if (hits->n_hits > kFusedMaxHits) return fail(c, KFX_EINVAL, "fused building takes at most 2^27 - 3 hits");
+    }
   }
   const int K = p->max_cands;
   const long SK = (long)n_seeds * K;
@@ -478,9 +496,12 @@ int build_impl(kfx_ctx* c, const kfx_hits* hits, const int32_t* seeds, const int
   a.sel_parent = (int*)ws(c, "b.selp", N * 4, st, rc); if (rc) return rc;
   a.sel_code = (int*)ws(c, "b.selc", N * 4, st, rc); if (rc) return rc;
   a.sel_chi2 = (float*)ws(c, "b.selx", N * 4, st, rc); if (rc) return rc;
-  a.hist_parent = (signed char*)ws(c, "b.histp", (size_t)N * p->max_steps, st, rc); if (rc) return rc;
-  a.hist_code = (int*)ws(c, "b.histc", (size_t)N * p->max_steps * 4, st, rc); if (rc) return rc;
-  a.n_steps = (int*)ws(c, "b.nsteps", (size_t)std::max(n_seeds, 1) * 4, st, rc); if (rc) return rc;
+  if (p->mode == KFX_MODE_PLAIN) {
+    // the per-step history in HBM (the fused kernel keeps it in LDS)
+    a.hist_parent = (signed char*)ws(c, "b.histp", (size_t)N * p->max_steps, st, rc); if (rc) return rc;
+    a.hist_code = (int*)ws(c, "b.histc", (size_t)N * p->max_steps * 4, st, rc); if (rc) return rc;
+    a.n_steps = (int*)ws(c, "b.nsteps", (size_t)std::max(n_seeds, 1) * 4, st, rc); if (rc) return rc;
+  }
   a.stats = (unsigned long long*)out->stats;
 
   TracksOut o;
@@ -726,6 +747,7 @@ int kfx_autotune_build(kfx_ctx* c, const kfx_hits* hits, const int32_t* seeds, c
           v.lanes_per_seed == cur.lanes_per_seed && v.waves_per_simd == cur.waves_per_simd &&
           v.seeds_per_wave == cur.seeds_per_wave)
         continue;
+      if (!fused_shape_fits(c, &v)) continue;
       float t = 0.0f;
       if ((rc = timeit(v, t))) break;
       if (t < best) {

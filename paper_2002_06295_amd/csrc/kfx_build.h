@@ -74,7 +74,7 @@ KFX_HD void init_seed_slots(const BuildArgs& a, int s) {
       a.chi2[0][slot] = 0.0f;
     }
   }
-  a.n_steps[s] = 0;
+  if (a.n_steps) a.n_steps[s] = 0;  // the plain path's step count
 }
 
 // (a) navigate + transport (+ material) of one slot.  Returns 1 when a
@@ -288,9 +288,11 @@ struct TracksOut {
 // hit list rebuilt from the per-step history by one backward walk over the
 // parent pointers (the seed hits, then one entry per step with a hit or a
 // hole, n_hits + n_holes entries in all; stop entries add none), the
-// counts, the chi2 sum and the state.
+// counts, the chi2 sum and the state.  hist(t, slot, code, parent) reads
+// the history entry of step t and slot.
+template <class Hist>
 KFX_HD void write_slot_output(const BuildArgs& a, const TracksOut& o, int s, int j, int T, int m, float chi2,
-                              const State& st) {
+                              const State& st, const Hist& hist) {
   const long slot = (long)s * a.K + j;
   int* out = o.hits + slot * o.max_hits;
   const bool live = (meta_flags(m) & kFlagLive) != 0;
@@ -309,13 +311,13 @@ KFX_HD void write_slot_output(const BuildArgs& a, const TracksOut& o, int s, int
   for (int q = 0; q < kSeedHits && q < o.max_hits; ++q) out[q] = a.seeds[3 * s + q];
   int w = total - 1, cj = j;
   for (int t = T - 1; t >= 0; --t) {
-    const long h = hist_index(a, s, t, cj);
-    const int code = a.hist_code[h];
+    int code, parent;
+    hist(t, cj, code, parent);
     if (code != kStop) {
       if (w < o.max_hits) out[w] = code >= 0 ? code : -1;
       --w;
     }
-    cj = a.hist_parent[h];
+    cj = parent;
   }
   o.n_hits[slot] = meta_nhits(m);
   o.n_holes[slot] = meta_nholes(m);
@@ -323,12 +325,23 @@ KFX_HD void write_slot_output(const BuildArgs& a, const TracksOut& o, int s, int
   store_state(o.state, slot, st);
 }
 
+// History entries of the plain path (HBM, per seed, step and slot).
+struct HbmHist {
+  const BuildArgs* a;
+  int s;
+  KFX_HD void operator()(int t, int j, int& code, int& parent) const {
+    const long h = hist_index(*a, s, t, j);
+    code = a->hist_code[h];
+    parent = a->hist_parent[h];
+  }
+};
+
 // The same for a slot of the plain path's final candidate buffer.
 KFX_HD void finalize_slot(const BuildArgs& a, int fin, const TracksOut& o, int s, int j) {
   const long slot = (long)s * a.K + j;
   State st;
   load_state(a.cand[fin], slot, st);
-  write_slot_output(a, o, s, j, a.n_steps[s], a.meta[fin][slot], a.chi2[fin][slot], st);
+  write_slot_output(a, o, s, j, a.n_steps[s], a.meta[fin][slot], a.chi2[fin][slot], st, HbmHist{&a, s});
 }
 
 }  // namespace kfx

@@ -41,6 +41,8 @@ void launch_step_compat(const Geometry* G, const HitsView& H, const BinIndex& B,
 // ev: NULL, or two events recorded after the seed start and after the
 // search (before the output kernel)
 void launch_build_plain(const BuildArgs& a, const TracksOut& o, hipStream_t st, const hipEvent_t* ev);
+size_t fused_lds_bytes(int lanes, int threads, int max_steps);
+size_t fused_static_lds_bytes();
 void launch_build_init(const BuildArgs& a, hipStream_t st);
 void launch_build_fused(const BuildArgs& a, const TracksOut& o, int* seed_counter, int blocks, int threads,
                         int lanes, int waves_per_simd, hipStream_t st, const hipEvent_t* ev);

@@ -646,12 +646,29 @@ __device__ int wave_scan(const BinIndex& B, int n_phi, int lane, bool has, const
   return found;
 }
 
+// History of the fused kernel in LDS: one word per lane and step, the
+// child's code + 2 in bits 0-26 (hit indices below 2^27 - 2) and its parent
+// slot + 1 in bits 27-31; column = the lane in the block.
+__device__ inline unsigned int hist_pack(int code, int parent) {
+  return (unsigned int)(code + 2) | ((unsigned int)(parent + 1) << 27);
+}
+struct LdsHist {
+  const unsigned int* h;
+  int stride, base;
+  __device__ void operator()(int t, int j, int& code, int& parent) const {
+    const unsigned int e = h[t * stride + base + j];
+    code = (int)(e & 0x7ffffffu) - 2;
+    parent = (int)(e >> 27) - 1;
+  }
+};
+
 template <int G_LANES, int OCC>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC, OCC)))
-k_build_fused(BuildArgs a, int* seed_counter) {
+k_build_fused(BuildArgs a, TracksOut o, int* seed_counter) {
   extern __shared__ unsigned char smem_raw[];
   using FS = FusedShared<G_LANES>;
   FS* sh = reinterpret_cast<FS*>(smem_raw);
+  unsigned int* hl = reinterpret_cast<unsigned int*>(smem_raw + sizeof(FS) * blockDim.x);
   // the layer table is read at every step with lane-dependent indices: keep
   // a copy in LDS
   __shared__ Geometry g_lds;
@@ -832,9 +849,7 @@ k_build_fused(BuildArgs a, int* seed_counter) {
         }
         st = ns;
       }
-      const long hidx = hist_index(a, seed, t, gl);
-      a.hist_parent[hidx] = (signed char)my_parent;
-      a.hist_code[hidx] = my_parent >= 0 ? my_code : kStop;
+      hl[t * blockDim.x + threadIdx.x] = hist_pack(my_parent >= 0 ? my_code : kStop, my_parent);
     }
     wave_sync();
     if (active) {
@@ -847,16 +862,11 @@ k_build_fused(BuildArgs a, int* seed_counter) {
     const bool running = active && (meta_flags(meta) & kFlagLive) && !(meta_flags(meta) & kFlagDone);
     const unsigned long long run_mask = __ballot(running) & gmask;
     if (active && (run_mask == 0 || t >= a.max_steps)) {
-      // final state of each slot into the candidate buffer; the output
-      // (hit lists from the history) is written by the finalize kernel
-      if (gl == 0) a.n_steps[seed] = t;
-      const long slot = (long)seed * K + gl;
-      if (gl < K) {
-        store_state(a.cand[0], slot, st);
-        a.meta[0][slot] = meta;
-        a.layer[0][slot] = layer;
-        a.chi2[0][slot] = chi2;
-      }
+      // the seed's output: each lane rebuilds its slot's hit list from the
+      // group's history in LDS (written before the wave sync above)
+      const unsigned long long live_mask = __ballot(gl < K && (meta_flags(meta) & kFlagLive)) & gmask;
+      if (gl == 0) o.n_cands[seed] = __popcll(live_mask);
+      if (gl < K) write_slot_output(a, o, seed, gl, t, meta, chi2, st, LdsHist{hl, (int)blockDim.x, gbase});
       seed = -1;
     }
   }
@@ -971,10 +981,9 @@ void launch_build_fused(const BuildArgs& a, const TracksOut& o, int* seed_counte
   if (a.n_seeds <= 0) return;
   launch_fill(seed_counter, 1, 0, st);
   if (ev) (void)hipEventRecord(ev[0], st);
-  const size_t shmem = (lanes == 4 ? sizeof(FusedShared<4>) : lanes == 8 ? sizeof(FusedShared<8>)
-                                                                         : sizeof(FusedShared<16>)) * threads;
+  const size_t shmem = fused_lds_bytes(lanes, threads, a.max_steps);
 #define KFX_FUSED(GL, OC) \
-  hipLaunchKernelGGL((k_build_fused<GL, OC>), dim3(blocks), dim3(threads), shmem, st, a, seed_counter)
+  hipLaunchKernelGGL((k_build_fused<GL, OC>), dim3(blocks), dim3(threads), shmem, st, a, o, seed_counter)
   const bool two = waves_per_simd == 2;
   switch (lanes) {
     case 4:
@@ -989,8 +998,15 @@ void launch_build_fused(const BuildArgs& a, const TracksOut& o, int* seed_counte
   }
 #undef KFX_FUSED
   if (ev) (void)hipEventRecord(ev[1], st);
-  const long nslots = (long)a.n_seeds * a.K;
-  hipLaunchKernelGGL(k_build_finalize, dim3(nblk(nslots, 128)), dim3(128), 0, st, a, 0, o);
 }
+
+// Dynamic LDS of a fused launch: the lanes' state slots and their history
+// words (one per step); the layer table comes on top of it.
+size_t fused_lds_bytes(int lanes, int threads, int max_steps) {
+  const size_t fs = lanes == 4 ? sizeof(FusedShared<4>) : lanes == 8 ? sizeof(FusedShared<8>)
+                                                                     : sizeof(FusedShared<16>);
+  return (fs + 4 * (size_t)max_steps) * threads;
+}
+size_t fused_static_lds_bytes() { return sizeof(Geometry); }
 
 }  // namespace kfx
