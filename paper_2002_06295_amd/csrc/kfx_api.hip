@@ -167,7 +167,7 @@ int build_index(kfx_ctx* c, const kfx_hits* h, int32_t* bin_out, hipStream_t st)
   const long nh = std::max<long>(h->n_hits, 1);
   w.key = (int*)ws(c, "bin.key", nh * 4, st, rc); if (rc) return rc;
   w.counts = (int*)ws(c, "bin.counts", (n_keys + 1) * 4, st, rc); if (rc) return rc;
-  w.fill = (int*)ws(c, "bin.fill", (n_keys + 1) * 4, st, rc); if (rc) return rc;
+  w.rank = (int*)ws(c, "bin.rank", nh * 4, st, rc); if (rc) return rc;
   w.off = (int*)ws(c, "bin.off", (n_keys + 2) * 4, st, rc); if (rc) return rc;
   w.perm = (int*)ws(c, "bin.perm", nh * 4, st, rc); if (rc) return rc;
   w.sorted = (float4*)ws(c, "bin.sorted", nh * 16, st, rc); if (rc) return rc;

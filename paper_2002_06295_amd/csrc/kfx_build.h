@@ -297,7 +297,16 @@ KFX_HD void write_slot_output(const BuildArgs& a, const TracksOut& o, int s, int
   int* out = o.hits + slot * o.max_hits;
   const bool live = (meta_flags(m) & kFlagLive) != 0;
   const int total = live ? meta_nhits(m) + meta_nholes(m) : 0;
-  for (int q = total < o.max_hits ? total : o.max_hits; q < o.max_hits; ++q) out[q] = -3;
+  {
+    // unused entries: one by one up to a 16-byte boundary, then four at a
+    // time (when the row is 16-byte aligned), then the rest
+    int q = total < o.max_hits ? total : o.max_hits;
+    if ((reinterpret_cast<uintptr_t>(out) & 15) == 0) {
+      for (; q < o.max_hits && (q & 3); ++q) out[q] = -3;
+      for (; q + 4 <= o.max_hits; q += 4) *reinterpret_cast<int4*>(out + q) = make_int4(-3, -3, -3, -3);
+    }
+    for (; q < o.max_hits; ++q) out[q] = -3;
+  }
   if (!live) {
     o.n_hits[slot] = 0;
     o.n_holes[slot] = 0;

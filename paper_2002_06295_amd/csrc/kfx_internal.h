@@ -14,7 +14,7 @@ namespace kfx {
 struct BinWork {
   int* key;       // [n_hits]
   int* counts;    // [n_keys + 1]
-  int* fill;      // [n_keys]
+  int* rank;      // [n_hits]: place of a hit among its bin's hits
   int* off;       // [n_keys + 1]
   int* perm;      // [n_hits]
   float4* sorted; // [n_hits]

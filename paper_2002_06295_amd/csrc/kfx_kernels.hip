@@ -17,6 +17,17 @@ namespace kfx {
 __global__ void k_fill_i32(int* p, long n, int v) {
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) p[i] = v;
 }
+// the same with 16-byte stores (p 16-byte aligned), the last n % 4 by the
+// first threads
+__global__ void k_fill_i32x4(int* p, long n, int v) {
+  const long n4 = n >> 2;
+  int4* q = reinterpret_cast<int4*>(p);
+  const int4 v4 = make_int4(v, v, v, v);
+  const long stride = (long)gridDim.x * blockDim.x;
+  const long i0 = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  for (long i = i0; i < n4; i += stride) q[i] = v4;
+  if (i0 < (n & 3)) p[(n4 << 2) + i0] = v;
+}
 
 // Exclusive scan of int32 in three passes: block sums, scan of the sums,
 // block-local scan plus offset.  Each block covers kScanTile elements.
@@ -114,7 +125,7 @@ __device__ inline int event_of(const int* ev_off, int n_events, int hit) {
 }
 
 __global__ void k_bin_keys(const Geometry* __restrict__ G, HitsView H, int* key_out, int* bin_out,
-                           int* counts) {
+                           int* counts, int* rank) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= H.n_hits) return;
   const int l = H.layer[i];
@@ -125,19 +136,20 @@ __global__ void k_bin_keys(const Geometry* __restrict__ G, HitsView H, int* key_
     bin = hit_bin(*G, l, H.x[i], H.y[i], H.z[i]);
     const int e = event_of(H.ev_off, H.n_events, i);
     key = ((long)e * G->n_layers + l) * nb + bin;
-    atomicAdd(counts + key, 1);
+    // the hit's place among its bin's hits (arrival order; the per-bin sort
+    // restores ascending hit index)
+    rank[i] = atomicAdd(counts + key, 1);
   }
   key_out[i] = (int)key;
   if (bin_out) bin_out[i] = bin;
 }
 
-__global__ void k_bin_scatter(HitsView H, const int* key, const int* off, int* fill, int* perm) {
+__global__ void k_bin_scatter(HitsView H, const int* key, const int* off, const int* rank, int* perm) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= H.n_hits) return;
   const int k = key[i];
   if (k < 0) return;
-  const int p = off[k] + atomicAdd(fill + k, 1);
-  perm[p] = i;
+  perm[off[k] + rank[i]] = i;
 }
 
 // bins hold a handful of hits: insertion sort by hit index gives the same
@@ -880,6 +892,11 @@ static inline unsigned nblk(long n, int b) { return (unsigned)((n + b - 1) / b);
 
 void launch_fill(int* p, long n, int v, hipStream_t st) {
   if (n <= 0) return;
+  if ((reinterpret_cast<uintptr_t>(p) & 15) == 0 && n >= 1024) {
+    const long blocks = std::min<long>(nblk(n >> 2, 256), 8192);
+    hipLaunchKernelGGL(k_fill_i32x4, dim3((unsigned)blocks), dim3(256), 0, st, p, n, v);
+    return;
+  }
   const long blocks = std::min<long>(nblk(n, 256), 65536);
   hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)blocks), dim3(256), 0, st, p, n, v);
 }
@@ -888,12 +905,12 @@ void launch_bin(const Geometry* G, const HitsView& H, int n_layers, int n_bins, 
                 int* bin_out, hipStream_t st) {
   const long n_keys = (long)H.n_events * n_layers * n_bins;
   launch_fill(w.counts, n_keys + 1, 0, st);
-  launch_fill(w.fill, n_keys, 0, st);
   if (H.n_hits > 0)
-    hipLaunchKernelGGL(k_bin_keys, dim3(nblk(H.n_hits, 256)), dim3(256), 0, st, G, H, w.key, bin_out, w.counts);
+    hipLaunchKernelGGL(k_bin_keys, dim3(nblk(H.n_hits, 256)), dim3(256), 0, st, G, H, w.key, bin_out, w.counts,
+                       w.rank);
   exclusive_scan(w.counts, n_keys, w.off, w.scan_scratch, st);
   if (H.n_hits > 0)
-    hipLaunchKernelGGL(k_bin_scatter, dim3(nblk(H.n_hits, 256)), dim3(256), 0, st, H, w.key, w.off, w.fill, w.perm);
+    hipLaunchKernelGGL(k_bin_scatter, dim3(nblk(H.n_hits, 256)), dim3(256), 0, st, H, w.key, w.off, w.rank, w.perm);
   hipLaunchKernelGGL(k_bin_sort, dim3(nblk(n_keys, 256)), dim3(256), 0, st, w.off, n_keys, w.perm);
   if (H.n_hits > 0)
     hipLaunchKernelGGL(k_bin_gather, dim3(nblk(H.n_hits, 256)), dim3(256), 0, st, H, w.perm, w.off + n_keys,
