@@ -157,7 +157,7 @@ int check_prior(kfx_ctx* c, const kfx_prior* p) {
 }
 
 // Build the hit index into the context workspace.
-int build_index(kfx_ctx* c, const kfx_hits* h, int32_t* bin_out, hipStream_t st) {
+int build_index(kfx_ctx* c, const kfx_hits* h, int32_t* bin_out, bool stable, hipStream_t st) {
   const Geometry& G = c->host_geo;
   const long nb = (long)G.n_eta * G.n_phi;
   const long n_keys = (long)h->n_events * G.n_layers * nb;
@@ -172,7 +172,7 @@ int build_index(kfx_ctx* c, const kfx_hits* h, int32_t* bin_out, hipStream_t st)
   w.perm = (int*)ws(c, "bin.perm", nh * 4, st, rc); if (rc) return rc;
   w.sorted = (float4*)ws(c, "bin.sorted", nh * 16, st, rc); if (rc) return rc;
   w.scan_scratch = (int*)ws(c, "bin.scan", ((n_keys + 1) / 4096 + 4) * 4, st, rc); if (rc) return rc;
-  launch_bin(c->dev_geo, view(h), G.n_layers, (int)nb, w, bin_out, st);
+  launch_bin(c->dev_geo, view(h), G.n_layers, (int)nb, w, bin_out, stable, st);
   if ((rc = hip_check(c, hipGetLastError(), "binning kernels"))) return rc;
   c->have_index = true;
   c->index_hits_key[0] = h->x;
@@ -322,7 +322,7 @@ int kfx_bin_hits(kfx_ctx* c, const kfx_hits* hits, int32_t* bin_out, int32_t* of
   if (rc) return rc;
   DeviceGuard dg(c->device);
   hipStream_t st = (hipStream_t)stream;
-  if ((rc = build_index(c, hits, bin_out, st))) return rc;
+  if ((rc = build_index(c, hits, bin_out, true, st))) return rc;
   const long n_keys = (long)hits->n_events * c->host_geo.n_layers * c->host_geo.n_eta * c->host_geo.n_phi;
   if (offsets_out &&
       (rc = hip_check(c, hipMemcpyAsync(offsets_out, c->bw.off, (n_keys + 1) * 4, hipMemcpyDeviceToDevice, st),
@@ -443,7 +443,8 @@ int build_impl(kfx_ctx* c, const kfx_hits* hits, const int32_t* seeds, const int
     return KFX_OK;
   };
   auto bin = [&]() -> int {
-    int r = build_index(c, hits, nullptr, st);
+    // the building does not depend on the order within a bin: no sort
+    int r = build_index(c, hits, nullptr, false, st);
     if (!r && tev) r = hip_check(c, hipEventRecord(tev[1], st), "timing event");
     return r;
   };

@@ -24,7 +24,7 @@ struct BinWork {
 void launch_fill(int* p, long n, int v, hipStream_t st);
 void exclusive_scan(const int* in, long n, int* out, int* scratch, hipStream_t st);
 void launch_bin(const Geometry* G, const HitsView& H, int n_layers, int n_bins, BinWork& w, int* bin_out,
-                hipStream_t st);
+                bool stable, hipStream_t st);
 void launch_fit(const Geometry* G, const HitsView& H, const int* trk_off, const int* trk_hits, int n,
                 const Prior& pr, const float* align, float fscale, const FitOut& o, hipStream_t st);
 int fit_backward_blocks(int n);

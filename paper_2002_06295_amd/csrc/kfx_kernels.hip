@@ -901,8 +901,11 @@ void launch_fill(int* p, long n, int v, hipStream_t st) {
   hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)blocks), dim3(256), 0, st, p, n, v);
 }
 
+// stable: hits of one bin in ascending hit index (else in the order the
+// atomics gave them, which the building does not depend on: its best-K
+// sets and counts ignore the scan order, ties go by hit index)
 void launch_bin(const Geometry* G, const HitsView& H, int n_layers, int n_bins, BinWork& w,
-                int* bin_out, hipStream_t st) {
+                int* bin_out, bool stable, hipStream_t st) {
   const long n_keys = (long)H.n_events * n_layers * n_bins;
   launch_fill(w.counts, n_keys + 1, 0, st);
   if (H.n_hits > 0)
@@ -911,7 +914,7 @@ void launch_bin(const Geometry* G, const HitsView& H, int n_layers, int n_bins, 
   exclusive_scan(w.counts, n_keys, w.off, w.scan_scratch, st);
   if (H.n_hits > 0)
     hipLaunchKernelGGL(k_bin_scatter, dim3(nblk(H.n_hits, 256)), dim3(256), 0, st, H, w.key, w.off, w.rank, w.perm);
-  hipLaunchKernelGGL(k_bin_sort, dim3(nblk(n_keys, 256)), dim3(256), 0, st, w.off, n_keys, w.perm);
+  if (stable) hipLaunchKernelGGL(k_bin_sort, dim3(nblk(n_keys, 256)), dim3(256), 0, st, w.off, n_keys, w.perm);
   if (H.n_hits > 0)
     hipLaunchKernelGGL(k_bin_gather, dim3(nblk(H.n_hits, 256)), dim3(256), 0, st, H, w.perm, w.off + n_keys,
                        w.sorted);
