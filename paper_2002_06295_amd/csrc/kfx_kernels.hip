@@ -14,12 +14,12 @@
 namespace kfx {
 
 // ---------------------------------------------------------------- utility
-__global__ void k_fill_i32(int* p, long n, int v) {
+__global__ void __launch_bounds__(256) k_fill_i32(int* p, long n, int v) {
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) p[i] = v;
 }
 // the same with 16-byte stores (p 16-byte aligned), the last n % 4 by the
 // first threads
-__global__ void k_fill_i32x4(int* p, long n, int v) {
+__global__ void __launch_bounds__(256) k_fill_i32x4(int* p, long n, int v) {
   const long n4 = n >> 2;
   int4* q = reinterpret_cast<int4*>(p);
   const int4 v4 = make_int4(v, v, v, v);
@@ -56,7 +56,7 @@ __device__ inline int block_exclusive_scan(int v, int* lds, int& total) {
   return base + x - v;
 }
 
-__global__ void k_scan_reduce(const int* in, long n, int* block_sums) {
+__global__ void __launch_bounds__(256) k_scan_reduce(const int* in, long n, int* block_sums) {
   __shared__ int lds[kScanThreads / 64];
   const long base = (long)blockIdx.x * kScanTile;
   int s = 0;
@@ -69,7 +69,7 @@ __global__ void k_scan_reduce(const int* in, long n, int* block_sums) {
   if (threadIdx.x == 0) block_sums[blockIdx.x] = tot;
 }
 
-__global__ void k_scan_sums(int* sums, int nb) {
+__global__ void __launch_bounds__(256) k_scan_sums(int* sums, int nb) {
   // single block: sequential over chunks of kScanThreads
   __shared__ int lds[kScanThreads / 64];
   int carry = 0;
@@ -84,7 +84,7 @@ __global__ void k_scan_sums(int* sums, int nb) {
   }
 }
 
-__global__ void k_scan_apply(const int* in, long n, const int* block_offsets, int* out) {
+__global__ void __launch_bounds__(256) k_scan_apply(const int* in, long n, const int* block_offsets, int* out) {
   __shared__ int lds[kScanThreads / 64];
   // thread t owns the contiguous run [t*items, (t+1)*items) of the tile
   const long base = (long)blockIdx.x * kScanTile + (long)threadIdx.x * kScanItems;
@@ -124,7 +124,7 @@ __device__ inline int event_of(const int* ev_off, int n_events, int hit) {
   return lo;
 }
 
-__global__ void k_bin_keys(const Geometry* __restrict__ G, HitsView H, int* key_out, int* bin_out,
+__global__ void __launch_bounds__(256) k_bin_keys(const Geometry* __restrict__ G, HitsView H, int* key_out, int* bin_out,
                            int* counts, int* rank) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= H.n_hits) return;
@@ -144,7 +144,7 @@ __global__ void k_bin_keys(const Geometry* __restrict__ G, HitsView H, int* key_
   if (bin_out) bin_out[i] = bin;
 }
 
-__global__ void k_bin_scatter(HitsView H, const int* key, const int* off, const int* rank, int* perm) {
+__global__ void __launch_bounds__(256) k_bin_scatter(HitsView H, const int* key, const int* off, const int* rank, int* perm) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= H.n_hits) return;
   const int k = key[i];
@@ -154,7 +154,7 @@ __global__ void k_bin_scatter(HitsView H, const int* key, const int* off, const 
 
 // bins hold a handful of hits: insertion sort by hit index gives the same
 // order as a stable sort, whatever order the atomics produced
-__global__ void k_bin_sort(const int* off, long n_keys, int* perm) {
+__global__ void __launch_bounds__(256) k_bin_sort(const int* off, long n_keys, int* perm) {
   const long k = blockIdx.x * (long)blockDim.x + threadIdx.x;
   if (k >= n_keys) return;
   const int a = off[k], b = off[k + 1];
@@ -171,7 +171,7 @@ __global__ void k_bin_sort(const int* off, long n_keys, int* perm) {
 
 // only the first off[n_keys] entries of perm are filled (hits with a layer
 // id outside the geometry are not indexed)
-__global__ void k_bin_gather(HitsView H, const int* perm, const int* n_valid, float4* sorted) {
+__global__ void __launch_bounds__(256) k_bin_gather(HitsView H, const int* perm, const int* n_valid, float4* sorted) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= *n_valid) return;
   const int h = perm[p];
@@ -240,7 +240,7 @@ __global__ void __launch_bounds__(64) k_fit_backward(const Geometry* __restrict_
 
 // dalign[3 l + c] = sum over blocks of the partial rows (0 for disks),
 // dfield = the last row; summed in block order.
-__global__ void k_grad_reduce(const Geometry* __restrict__ G, const double* partial, int nblocks, double* dalign,
+__global__ void __launch_bounds__(64) k_grad_reduce(const Geometry* __restrict__ G, const double* partial, int nblocks, double* dalign,
                               double* dfield) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int nl = G->n_layers, nrow = 3 * G->n_barrel + 1;
@@ -261,7 +261,7 @@ __global__ void k_grad_reduce(const Geometry* __restrict__ G, const double* part
 }
 
 // ------------------------------------------------------ seeds and step (a2-a6)
-__global__ void k_seed_states(const Geometry* __restrict__ G, HitsView H, const int* seeds, int n, Prior pr,
+__global__ void __launch_bounds__(128) k_seed_states(const Geometry* __restrict__ G, HitsView H, const int* seeds, int n, Prior pr,
                               StateSoA out, float* chi2, int* status) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n) return;
@@ -280,7 +280,7 @@ __global__ void k_seed_states(const Geometry* __restrict__ G, HitsView H, const 
 
 // One building step on given states: navigate, transport, then list every
 // compatible hit through the binned index (ascending hit index).
-__global__ void k_step_compat(const Geometry* __restrict__ G, HitsView H, BinIndex B, const int* cand_event,
+__global__ void __launch_bounds__(128) k_step_compat(const Geometry* __restrict__ G, HitsView H, BinIndex B, const int* cand_event,
                               const int* cand_layer, StateSoA in, int n, float cut, int* next_layer,
                               StateSoA pred, int* pair_count, int* pair_hit, float* pair_chi2,
                               int max_pairs) {
@@ -351,40 +351,40 @@ __device__ inline void add_stat(unsigned long long* p, unsigned long long v) {
   if ((threadIdx.x & 63) == 0 && s) atomicAdd(p, s);
 }
 
-__global__ void k_build_init(BuildArgs a) {
+__global__ void __launch_bounds__(128) k_build_init(BuildArgs a) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= a.n_seeds) return;
   init_seed_slots(a, s);
 }
 
-__global__ void k_build_predict(BuildArgs a, int cur) {
+__global__ void __launch_bounds__(128) k_build_predict(BuildArgs a, int cur) {
   const long slot = blockIdx.x * (long)blockDim.x + threadIdx.x;
   int took = 0;
   if (slot < (long)a.n_seeds * a.K) took = predict_slot(a, cur, slot);
   add_stat(a.stats + 0, (unsigned long long)took);
 }
 
-__global__ void k_build_pairs(BuildArgs a) {
+__global__ void __launch_bounds__(128) k_build_pairs(BuildArgs a) {
   const long slot = blockIdx.x * (long)blockDim.x + threadIdx.x;
   int found = 0;
   if (slot < (long)a.n_seeds * a.K) found = pairs_slot(a, slot, a.seed_event[slot / a.K]);
   add_stat(a.stats + 1, (unsigned long long)found);
 }
 
-__global__ void k_build_select(BuildArgs a, int cur) {
+__global__ void __launch_bounds__(128) k_build_select(BuildArgs a, int cur) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= a.n_seeds) return;
   select_seed(a, cur, s);
 }
 
-__global__ void k_build_update(BuildArgs a, int cur, int t) {
+__global__ void __launch_bounds__(128) k_build_update(BuildArgs a, int cur, int t) {
   const long slot = blockIdx.x * (long)blockDim.x + threadIdx.x;
   int upd = 0;
   if (slot < (long)a.n_seeds * a.K) upd = update_slot(a, cur, (int)(slot / a.K), (int)(slot % a.K), t);
   add_stat(a.stats + 2, (unsigned long long)upd);
 }
 
-__global__ void k_build_finalize(BuildArgs a, int fin, TracksOut o) {
+__global__ void __launch_bounds__(128) k_build_finalize(BuildArgs a, int fin, TracksOut o) {
   const long slot = blockIdx.x * (long)blockDim.x + threadIdx.x;
   if (slot >= (long)a.n_seeds * a.K) return;
   const int s = (int)(slot / a.K), j = (int)(slot % a.K);
