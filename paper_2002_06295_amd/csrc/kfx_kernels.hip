@@ -583,13 +583,21 @@ __device__ int wave_scan(const BinIndex& B, int n_phi, int lane, bool has, const
     for (int r = 0; r < nro; ++r) {
       int qa, qe;
       scan_range(W, B, n_phi, r, qa, qe);
-      // four loads of 64 consecutive hits in flight per pass
+      // four loads of 64 consecutive hits per pass; the next pass's loads
+      // are issued before this pass is processed
+      float4 nx[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int q = qa + 64 * u + lane;
+        nx[u] = q < qe ? B.sorted[q] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      }
       for (int base = qa; base < qe; base += 256) {
         float4 hv[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-          const int q = base + 64 * u + lane;
-          hv[u] = q < qe ? B.sorted[q] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+          hv[u] = nx[u];
+          const int q = base + 256 + 64 * u + lane;
+          nx[u] = q < qe ? B.sorted[q] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         }
         // keys of the pairs under the cut that would enter the owner's list
         uint64_t kk[4];
