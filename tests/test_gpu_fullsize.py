@@ -143,6 +143,15 @@ def test_build_smallest_and_largest_K(dev, kfx, K):
     compare_sampled(ev, g, np.arange(ev.n_tracks))
 
 
+def test_build_largest_lds_shape(dev, kfx):
+    # K = 16 on 16 lanes per seed, 256-thread blocks and 40 steps: the
+    # fused kernel's largest LDS need (state slots, child streams and the
+    # per-step history of 256 lanes)
+    ev = kfsynth.generate("build5k", tracks_per_event=400)
+    g = gpu_build(kfx, dev, ev, tune=False, max_cands=16, max_steps=40)
+    compare_sampled(ev, g, np.arange(ev.n_tracks))
+
+
 def test_build_longest_search(dev, kfx):
     # the largest step budget: the oracle runs to the end of every candidate
     ev = kfsynth.generate("batch256", n_events=2)
