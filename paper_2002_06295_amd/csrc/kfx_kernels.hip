@@ -144,12 +144,20 @@ __global__ void __launch_bounds__(256) k_bin_keys(const Geometry* __restrict__ G
   if (bin_out) bin_out[i] = bin;
 }
 
-__global__ void __launch_bounds__(256) k_bin_scatter(HitsView H, const int* key, const int* off, const int* rank, int* perm) {
+__global__ void __launch_bounds__(256) k_bin_scatter(HitsView H, const int* key, const int* off, const int* rank, int* perm,
+                                                     float4* sorted) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= H.n_hits) return;
   const int k = key[i];
   if (k < 0) return;
-  perm[off[k] + rank[i]] = i;
+  const int p = off[k] + rank[i];
+  if (perm) perm[p] = i;
+  if (sorted) {
+    // unsorted bins: the hit goes to its place at once
+    float w;
+    __builtin_memcpy(&w, &i, 4);
+    sorted[p] = make_float4(H.x[i], H.y[i], H.z[i], w);
+  }
 }
 
 // bins hold a handful of hits: insertion sort by hit index gives the same
@@ -921,11 +929,15 @@ void launch_bin(const Geometry* G, const HitsView& H, int n_layers, int n_bins, 
                        w.rank);
   exclusive_scan(w.counts, n_keys, w.off, w.scan_scratch, st);
   if (H.n_hits > 0)
-    hipLaunchKernelGGL(k_bin_scatter, dim3(nblk(H.n_hits, 256)), dim3(256), 0, st, H, w.key, w.off, w.rank, w.perm);
-  if (stable) hipLaunchKernelGGL(k_bin_sort, dim3(nblk(n_keys, 256)), dim3(256), 0, st, w.off, n_keys, w.perm);
-  if (H.n_hits > 0)
-    hipLaunchKernelGGL(k_bin_gather, dim3(nblk(H.n_hits, 256)), dim3(256), 0, st, H, w.perm, w.off + n_keys,
-                       w.sorted);
+    hipLaunchKernelGGL(k_bin_scatter, dim3(nblk(H.n_hits, 256)), dim3(256), 0, st, H, w.key, w.off, w.rank,
+                       stable ? w.perm : nullptr, stable ? nullptr : w.sorted);
+  if (stable) {
+    // hits of a bin in ascending index, then the hits re-laid in that order
+    hipLaunchKernelGGL(k_bin_sort, dim3(nblk(n_keys, 256)), dim3(256), 0, st, w.off, n_keys, w.perm);
+    if (H.n_hits > 0)
+      hipLaunchKernelGGL(k_bin_gather, dim3(nblk(H.n_hits, 256)), dim3(256), 0, st, H, w.perm, w.off + n_keys,
+                         w.sorted);
+  }
 }
 
 void launch_fit(const Geometry* G, const HitsView& H, const int* trk_off, const int* trk_hits, int n,
