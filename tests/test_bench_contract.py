@@ -1,0 +1,46 @@
+"""CPU checks of the benchmark's contract that need no GPU: more than one
+GPU is refused with a message and a non-zero exit, before anything touches
+a device; the algorithmic operation counts it prices the kernels with are
+the documented ones; the stored traffic summary is used only while the
+kernel sources are the ones it was taken on."""
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120, cwd=ROOT)
+    assert r.returncode != 0
+    line = json.loads(r.stdout.strip().splitlines()[-1])
+    assert "one GPU" in line["error"] and line["n_gpus"] == 2
+
+
+def test_operation_counts():
+    import bench
+    assert bench.FLOP_PER_STEP == 830.0 and bench.FLOP_PER_PAIR == 35.0 and bench.FLOP_PER_UPDATE == 500.0
+    assert bench.algorithmic_flops([10, 20, 30]) == 10 * 830.0 + 20 * 35.0 + 30 * 500.0
+    # 256 CUs x 2.4 GHz x 128 FLOP per clock
+    assert bench.ALU_PEAK_TFLOPS == pytest.approx(78.6432)
+
+
+def test_stored_traffic_follows_the_sources(tmp_path, monkeypatch):
+    import bench
+    rec = {"source_sha256": bench.source_sha256(), "hbm_bytes_per_launch": 123.0}
+    d = tmp_path / "profiles"
+    d.mkdir()
+    (d / "t.json").write_text(json.dumps(rec))
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    # the hash covers the sources under ROOT: a tree without them hashes
+    # differently from the repository's, so the record no longer applies
+    assert bench.stored_traffic("t.json") is None
+    rec["source_sha256"] = bench.source_sha256()
+    (d / "t.json").write_text(json.dumps(rec))
+    assert bench.stored_traffic("t.json") == 123.0
+    assert bench.stored_traffic("missing.json") is None
