@@ -96,12 +96,14 @@ KFX_HD int predict_slot(const BuildArgs& a, int cur, long slot) {
   sincos_d(st.phi, sphi, cphi);
   const double kappa = -kHcD * G.bz;
   double s = 0.0;
-  const int nl = navigate(G, a.layer[cur][slot], st, cphi, sphi, kappa * st.k, s);
+  double sth, cth;
+  sincos_d(st.th, sth, cth);
+  const int nl = navigate(G, a.layer[cur][slot], st, cphi, sphi, sth, cth, kappa * st.k, s);
   if (nl < 0) {
     a.next_layer[slot] = -1;
     return 0;
   }
-  transport(st, G.L[nl], cphi, sphi, s, kappa, pr);
+  transport(st, G.L[nl], cphi, sphi, sth, cth, s, kappa, pr);
   store_state(a.pred, slot, pr);
   a.next_layer[slot] = nl;
   return 1;

@@ -296,19 +296,20 @@ __global__ void __launch_bounds__(128) k_step_compat(const Geometry* __restrict_
   if (i >= n) return;
   State st, pr;
   load_state(in, i, st);
-  double cphi, sphi;
+  double cphi, sphi, sth, cth;
   sincos_d(st.phi, sphi, cphi);
+  sincos_d(st.th, sth, cth);
   const double kappa = -kHcD * G->bz;
   double s = 0.0;
   const int cl = cand_layer[i], ce = cand_event[i];
   const int nl = (cl >= 0 && cl < G->n_layers && ce >= 0 && ce < H.n_events)
-                     ? navigate(*G, cl, st, cphi, sphi, kappa * st.k, s) : -1;
+                     ? navigate(*G, cl, st, cphi, sphi, sth, cth, kappa * st.k, s) : -1;
   next_layer[i] = nl;
   if (nl < 0) {
     pair_count[i] = 0;
     return;
   }
-  transport(st, G->L[nl], cphi, sphi, s, kappa, pr);
+  transport(st, G->L[nl], cphi, sphi, sth, cth, s, kappa, pr);
   store_state(pred, i, pr);
   Frame F;
   make_frame(pr, G->L[nl], F);
@@ -768,9 +769,11 @@ k_build_fused(BuildArgs a, TracksOut o, int* seed_counter) {
         double cphi, sphi;
         sincos_d(st.phi, sphi, cphi);
         double s = 0.0;
-        nl = navigate(G, layer, st, cphi, sphi, kappa * st.k, s);
+        double sth, cth;
+        sincos_d(st.th, sth, cth);
+        nl = navigate(G, layer, st, cphi, sphi, sth, cth, kappa * st.k, s);
         if (nl >= 0) {
-          transport(st, G.L[nl], cphi, sphi, s, kappa, pr);
+          transport(st, G.L[nl], cphi, sphi, sth, cth, s, kappa, pr);
           ++n_steps;
         }
       }

@@ -314,8 +314,8 @@ KFX_HD double path_to_layer(const StateT<R>& st, const Layer& Ld, double r_surf,
 // outward (when its outgoing crossing lies within |z| <= zmax) and the
 // first disk ahead in z whose crossing lies within [rmin, rmax] while the
 // track still moves outward.  Returns the layer id (or -1) and its path.
-KFX_HD int navigate(const Geometry& G, int cur, const State& st, double cphi, double sphi,
-                    double omega_d, double& s_out) {
+KFX_HD int navigate(const Geometry& G, int cur, const State& st, double cphi, double sphi, double sth,
+                    double cth, double omega_d, double& s_out) {
   double best = 3.0e38;
   int bl = -1;
   int nb = -1;
@@ -324,8 +324,6 @@ KFX_HD int navigate(const Geometry& G, int cur, const State& st, double cphi, do
   if (!__builtin_isfinite(st.x) || !__builtin_isfinite(st.y) || !__builtin_isfinite(st.z) || !__builtin_isfinite(st.phi) || !__builtin_isfinite(st.th) ||
       !__builtin_isfinite(st.k) || !__builtin_isfinite(omega_d))
     return -1;
-  double sth, cth;
-  sincos_d(st.th, sth, cth);
   const Layer& Lc = G.L[cur];
   if (Lc.kind == kBarrel) {
     nb = G.next_barrel[cur];
@@ -405,6 +403,14 @@ KFX_HD int navigate(const Geometry& G, int cur, const State& st, double cphi, do
   return bl;
 }
 
+// The same with sin and cos of the polar angle computed here.
+KFX_HD int navigate(const Geometry& G, int cur, const State& st, double cphi, double sphi, double omega_d,
+                    double& s_out) {
+  double sth, cth;
+  sincos_d(st.th, sth, cth);
+  return navigate(G, cur, st, cphi, sphi, sth, cth, omega_d, s_out);
+}
+
 // Multiple scattering at a layer for a state on it (Highland, beta = 1,
 // no energy loss): var(theta) = th0^2, var(phi) = th0^2 / sin^2(theta),
 // and k = q/(|p| sin theta) follows theta at fixed |p|.
@@ -432,12 +438,10 @@ KFX_HD void add_noise(StateT<R>& st, const Layer& Ld, R sth, R cth, R cinc) {
 // which exploits the unit rows of A (k and theta) and needs no branch
 // between barrel and disk except in c.
 template <class R>
-KFX_HD void transport(const StateT<R>& in, const Layer& Ld, double cphi, double sphi, double s_d,
-                      double kappa_d, StateT<R>& out) {
+KFX_HD void transport(const StateT<R>& in, const Layer& Ld, double cphi, double sphi, double sth_d, double cth_d,
+                      double s_d, double kappa_d, StateT<R>& out) {
   const double omega_d = kappa_d * in.k;
   const ChordD cd = chord_d(s_d, omega_d, cphi, sphi);
-  double sth_d, cth_d;
-  sincos_d(in.th, sth_d, cth_d);
   const bool disk = Ld.kind == kDisk;
   out.x = in.x + cd.dx;
   out.y = in.y + cd.dy;
@@ -570,6 +574,15 @@ KFX_HD void transport(const StateT<R>& in, const Layer& Ld, double cphi, double 
     cinc = mabs(sth * (e0_n * c1 + e1_n * s1));
   }
   add_noise(out, Ld, sth, cth, cinc);
+}
+
+// The same with sin and cos of the polar angle computed here.
+template <class R>
+KFX_HD void transport(const StateT<R>& in, const Layer& Ld, double cphi, double sphi, double s_d, double kappa_d,
+                      StateT<R>& out) {
+  double sth_d, cth_d;
+  sincos_d(in.th, sth_d, cth_d);
+  transport(in, Ld, cphi, sphi, sth_d, cth_d, s_d, kappa_d, out);
 }
 
 // Measurement frame at a predicted state: rows u, v, n of H (acting on the
