@@ -30,6 +30,16 @@ Geometry make_geo(const double* table, int nl, double bz) {
     L.v_u = (float)(r[5] * r[5]);
     L.v_v = (float)(r[6] * r[6]);
     L.v_n = (float)(r[7] * r[7]);
+    // the pseudorapidity range of the layer's bins, as the library sets it
+    if (L.kind == kBarrel) {
+      L.eta_lo = asinh(L.lo / L.pos);
+      L.eta_hi = asinh(L.hi / L.pos);
+    } else {
+      const double a = asinh(L.pos / L.hi), b = asinh(L.pos / L.lo);
+      L.eta_lo = a < b ? a : b;
+      L.eta_hi = a < b ? b : a;
+    }
+    L.eta_scale = (float)(G.n_eta / (L.eta_hi - L.eta_lo));
   }
   return G;
 }
@@ -206,3 +216,39 @@ double hs_fit_grad(const double* table, int nl, double bz, const float* x, const
 }
 
 }  // extern "C"
+
+// search window of a prediction on `layer` (the device's window_bins) and
+// the bin of a point on that layer (the binning's hit_bin): eta rows
+// [eb0, eb1], phi bins pb0 .. pb0 + npb - 1 modulo n_phi
+extern "C" void hs_window(const double* table, int nl, int layer, const double* p, const float* cov, float cut,
+                          int* out4) {
+  Geometry G = make_geo(table, nl, 0.0);
+  State st;
+  to_state(p, cov, st);
+  Frame F;
+  make_frame(st, G.L[layer], F);
+  const Window w = window_bins(G, G.L[layer], st, F, cut);
+  out4[0] = w.eb0;
+  out4[1] = w.eb1;
+  out4[2] = w.pb0;
+  out4[3] = w.npb;
+}
+
+extern "C" int hs_hit_bin(const double* table, int nl, int layer, float x, float y, float z) {
+  Geometry G = make_geo(table, nl, 0.0);
+  return hit_bin(G, layer, x, y, z);
+}
+
+// the frame's rows (u, v, n) and S^-1 of a prediction, for placing points
+// on its chi2 ellipse
+extern "C" void hs_frame(const double* table, int nl, int layer, const double* p, const float* cov, double* h9,
+                         double* si6) {
+  Geometry G = make_geo(table, nl, 0.0);
+  State st;
+  to_state(p, cov, st);
+  Frame F;
+  make_frame(st, G.L[layer], F);
+  for (int a = 0; a < 3; ++a)
+    for (int j = 0; j < 3; ++j) h9[3 * a + j] = F.h[a][j];
+  for (int i = 0; i < 6; ++i) si6[i] = F.Si[i];
+}
