@@ -244,9 +244,11 @@ int kfx_enable_timing(kfx_ctx* ctx, int n_calls);
 
 /* Milliseconds of up to the last n_calls timed builds, oldest first, four
  * floats per call into ms (host): hit binning, the search (the fused
- * kernel, or the per-step kernels of the plain path), building (seed start,
- * search, output), total.  Waits for those events; returns the number of
- * calls written (>= 0) or an error code. */
+ * kernel, which also writes the outputs, or the per-step kernels of the
+ * plain path), building (seed start, search, output; the fused build runs
+ * its seed start on a second stream beside the binning), total.  Waits for
+ * those events; returns the number of calls written (>= 0) or an error
+ * code. */
 int kfx_build_times(kfx_ctx* ctx, float* ms, int n_calls);
 
 /* A HIP graph of one kfx_build_tracks call.  kfx_build_graph runs the call

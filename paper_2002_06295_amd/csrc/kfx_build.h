@@ -43,7 +43,8 @@ struct BuildArgs {
   int* sel_parent;
   int* sel_code;
   float* sel_chi2;
-  // history, per seed: [S][max_steps][K] parent slot and child code
+  // history of the plain path, per seed: [S][max_steps][K] parent slot and
+  // child code (the fused kernel keeps its own in LDS)
   signed char* hist_parent;
   int* hist_code;
   int* n_steps;           // [S] steps recorded

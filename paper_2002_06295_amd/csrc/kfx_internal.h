@@ -39,7 +39,8 @@ void launch_step_compat(const Geometry* G, const HitsView& H, const BinIndex& B,
                         const StateSoA& pred, int* pair_count, int* pair_hit, float* pair_chi2, int max_pairs,
                         hipStream_t st);
 // ev: NULL, or two events recorded after the seed start and after the
-// search (before the output kernel)
+// search (before the plain path's output kernel; the fused kernel writes
+// its outputs itself, so its second event follows it)
 void launch_build_plain(const BuildArgs& a, const TracksOut& o, hipStream_t st, const hipEvent_t* ev);
 size_t fused_lds_bytes(int lanes, int threads, int max_steps);
 size_t fused_static_lds_bytes();

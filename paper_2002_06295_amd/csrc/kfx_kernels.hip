@@ -1,7 +1,7 @@
 // HIP kernels for gfx950 (MI355X): hit binning, seed states, the plain
-// per-step building path, the fused persistent building kernel and the
-// Kalman fit.  Launch wrappers at the bottom are called by the C ABI
-// (kfx_api.cpp).
+// per-step building path, the fused persistent building kernel, the Kalman
+// fit and its adjoint.  Launch wrappers at the bottom are called by the C
+// ABI (kfx_api.hip).
 //
 // Paper: arXiv 2002.06295, Sec. 1-3 (Kalman-filter track building and
 // fitting over a lightweight barrel/disk geometry, best-ranking candidates
