@@ -1,4 +1,4 @@
-// Internal interface between the C ABI (kfx_api.cpp) and the kernels
+// Internal interface between the C ABI (kfx_api.hip) and the kernels
 // (kfx_kernels.hip): workspace layouts and launch wrappers.
 #pragma once
 
