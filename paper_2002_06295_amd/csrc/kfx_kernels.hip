@@ -104,9 +104,44 @@ __global__ void __launch_bounds__(256) k_scan_apply(const int* in, long n, const
   }
 }
 
+// The apply pass for few blocks: each block adds up the totals of the
+// blocks before it itself (no separate pass over the totals).
+constexpr int kScanFewBlocks = 64;
+__global__ void __launch_bounds__(256) k_scan_apply_few(const int* in, long n, const int* block_sums, int* out) {
+  __shared__ int lds[kScanThreads / 64];
+  __shared__ int base_sh;
+  if (threadIdx.x < 64) {
+    int v = threadIdx.x < blockIdx.x ? block_sums[threadIdx.x] : 0;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    if (threadIdx.x == 0) base_sh = v;
+  }
+  __syncthreads();
+  const long base = (long)blockIdx.x * kScanTile + (long)threadIdx.x * kScanItems;
+  int v[kScanItems];
+  int s = 0;
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    v[i] = (base + i < n) ? in[base + i] : 0;
+    s += v[i];
+  }
+  int tot;
+  int ex = block_exclusive_scan(s, lds, tot) + base_sh;
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    if (base + i < n) out[base + i] = ex;
+    ex += v[i];
+  }
+}
+
 // exclusive scan of n values; out has n + 1 entries (out[n] = total)
 void exclusive_scan(const int* in, long n, int* out, int* scratch, hipStream_t st) {
   const long nb = (n + 1 + kScanTile - 1) / kScanTile;
+  if (nb <= kScanFewBlocks) {
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kScanThreads), 0, st, in, n, scratch);
+    hipLaunchKernelGGL(k_scan_apply_few, dim3(nb), dim3(kScanThreads), 0, st, in, n + 1, scratch, out);
+    return;
+  }
   // treat in[n] as 0 by scanning n + 1 values where the last is read as 0:
   // simplest is to scan n values and compute the total from the sums.
   hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kScanThreads), 0, st, in, n, scratch);
