@@ -726,7 +726,9 @@ struct LdsHist {
   }
 };
 
-template <int G_LANES, int OCC>
+// KM: capacity of a candidate's best-K list (>= K; the lane count unless a
+// shorter list is instantiated for smaller K)
+template <int G_LANES, int OCC, int KM = G_LANES>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC, OCC)))
 k_build_fused(BuildArgs a, TracksOut o, int* seed_counter) {
   extern __shared__ unsigned char smem_raw[];
@@ -817,7 +819,7 @@ k_build_fused(BuildArgs a, TracksOut o, int* seed_counter) {
     me.chi2 = chi2;
     if (nl < 0) lds_put(me, st, layer);
     // ---- (b) window scan, best K hit children in registers
-    BestK<G_LANES> best;
+    BestK<KM> best;
     {
       ScanWin sw;
       PairFrame pf;
@@ -846,7 +848,7 @@ k_build_fused(BuildArgs a, TracksOut o, int* seed_counter) {
         m = 1;
       } else {
 #pragma unroll
-        for (int p = 0; p < G_LANES; ++p)
+        for (int p = 0; p < KM; ++p)
           if (p < best.n) {
             const float tot = ks.chi2 + pair_key_chi2(best.k[p]);
             me.ekey[p] = child_key(ks.nh + 1, ks.nho, tot, ks.parent, p);
@@ -1062,6 +1064,8 @@ void launch_build_fused(const BuildArgs& a, const TracksOut& o, int* seed_counte
   const size_t shmem = fused_lds_bytes(lanes, threads, a.max_steps);
 #define KFX_FUSED(GL, OC) \
   hipLaunchKernelGGL((k_build_fused<GL, OC>), dim3(blocks), dim3(threads), shmem, st, a, o, seed_counter)
+#define KFX_FUSED_KM(GL, OC, KM) \
+  hipLaunchKernelGGL((k_build_fused<GL, OC, KM>), dim3(blocks), dim3(threads), shmem, st, a, o, seed_counter)
   const bool two = waves_per_simd == 2;
   switch (lanes) {
     case 4:
@@ -1071,10 +1075,16 @@ void launch_build_fused(const BuildArgs& a, const TracksOut& o, int* seed_counte
       if (two) KFX_FUSED(8, 2); else KFX_FUSED(8, 1);
       break;
     default:
-      if (two) KFX_FUSED(16, 2); else KFX_FUSED(16, 1);
+      // K of 9 to 12 keeps a 12-entry best-K list (fewer registers)
+      if (a.K <= 12) {
+        if (two) KFX_FUSED_KM(16, 2, 12); else KFX_FUSED_KM(16, 1, 12);
+      } else {
+        if (two) KFX_FUSED(16, 2); else KFX_FUSED(16, 1);
+      }
       break;
   }
 #undef KFX_FUSED
+#undef KFX_FUSED_KM
   if (ev) (void)hipEventRecord(ev[1], st);
 }
 
