@@ -1072,7 +1072,12 @@ void launch_build_fused(const BuildArgs& a, const TracksOut& o, int* seed_counte
       if (two) KFX_FUSED(4, 2); else KFX_FUSED(4, 1);
       break;
     case 8:
-      if (two) KFX_FUSED(8, 2); else KFX_FUSED(8, 1);
+      // K of 5 or 6 keeps a 6-entry best-K list
+      if (a.K <= 6 && a.K >= 5) {
+        if (two) KFX_FUSED_KM(8, 2, 6); else KFX_FUSED_KM(8, 1, 6);
+      } else {
+        if (two) KFX_FUSED(8, 2); else KFX_FUSED(8, 1);
+      }
       break;
     default:
       // K of 9 to 12 keeps a 12-entry best-K list (fewer registers)
