@@ -588,3 +588,78 @@ def generate(w: Workload | str, n_events: int | None = None,
                   trk_event=trk_event, trk_offsets=trk_off.astype(np.int32),
                   trk_hits=trk_hits, trk_truth=trk_truth, trk_vertex=vx,
                   seeds=seeds.astype(np.int32), align_true=align)
+
+
+def duplicate_seeds(ev: Events, frac: float, seed: int = 0):
+    """The event's seeds (first three hits of every track) plus, for a
+    random fraction `frac` of the tracks with at least four hits, a second
+    seed from hits 1, 2 and 4 of the same track, as when several hit
+    triplets of one particle seed it.  Returns (seeds [S, 3], seed_event
+    [S], seed_track [S]); the extra seeds follow the originals."""
+    rng = np.random.default_rng([7, ev.workload.seed_id, seed])
+    nrec = np.diff(ev.trk_offsets)
+    cand = np.nonzero(nrec >= 4)[0]
+    pick = np.sort(cand[rng.random(cand.shape[0]) < frac])
+    o = ev.trk_offsets[pick]
+    extra = np.stack([ev.trk_hits[o], ev.trk_hits[o + 1], ev.trk_hits[o + 3]], axis=1)
+    seeds = np.concatenate([ev.seeds, extra]).astype(np.int32)
+    seed_event = np.concatenate([ev.trk_event, ev.trk_event[pick]]).astype(np.int32)
+    seed_track = np.concatenate([np.arange(ev.n_tracks), pick]).astype(np.int32)
+    return seeds, seed_event, seed_track
+
+
+def track_lists(n_seeds: int, K: int, max_hits: int, n_hits_total: int,
+                seed: int = 0, seeds_per_truth: float = 2.0, p_hole: float = 0.1,
+                p_swap: float = 0.15, chi2_levels: int = 6, p_empty: float = 0.03):
+    """Synthetic building output (hit lists, counts, chi2 per seed and slot)
+    with clusters of overlapping tracks, for the duplicate-removal step.
+
+    Truth tracks are lists of distinct hit indices; each seed copies one
+    truth track (popular truths are copied many times), turns entries into
+    holes (-1) or other hits at random and may drop its tail; lists are
+    padded with -3.  chi2 takes few distinct values so that ties in the
+    ranking occur.  A few seeds have no candidate, a few lists repeat an
+    entry or hold an index outside [0, n_hits_total).  Slots above 0 hold
+    random hits.  Returns a dict of numpy arrays shaped like the building
+    output: n_cands [S], hits [S*K, max_hits], n_hits, n_holes [S*K] int32,
+    chi2 [S*K] float32."""
+    rng = np.random.default_rng([11, seed])
+    S = n_seeds
+    n_truth = max(1, int(S / seeds_per_truth))
+    L = max(1, min(max_hits, 26))
+    truth_len = rng.integers(3, L + 1, n_truth)
+    truth = [rng.choice(n_hits_total, size=min(int(n), n_hits_total), replace=False)
+             if n_hits_total > 0 else np.zeros(0, np.int64) for n in truth_len]
+    # popularity: a Zipf-like choice of truth track per seed
+    w = 1.0 / np.arange(1, n_truth + 1) ** 0.8
+    owner = rng.choice(n_truth, size=S, p=w / w.sum())
+    hits = rng.integers(-1, max(n_hits_total, 1), (S * K, max_hits)).astype(np.int32)
+    n_cands = rng.integers(1, K + 1, S).astype(np.int32)
+    n_cands[rng.random(S) < p_empty] = 0
+    n_hits = rng.integers(0, 30, S * K).astype(np.int32)
+    n_holes = rng.integers(0, 4, S * K).astype(np.int32)
+    chi2 = (rng.integers(0, chi2_levels, S * K) * 2.5).astype(np.float32)
+    for s in range(S):
+        t = truth[owner[s]].copy()
+        if t.shape[0] > 3 and rng.random() < 0.3:
+            t = t[:rng.integers(3, t.shape[0] + 1)]
+        row = t.astype(np.int64)
+        u = rng.random(row.shape[0])
+        row[u < p_hole] = -1
+        swap = (u >= p_hole) & (u < p_hole + p_swap)
+        if n_hits_total > 0:
+            row[swap] = rng.integers(0, n_hits_total, int(swap.sum()))
+        r = rng.random()
+        if r < 0.02 and row.shape[0] > 1:
+            row[-1] = row[0]                      # a repeated entry
+        elif r < 0.04 and row.shape[0] > 0:
+            row[-1] = n_hits_total + 5            # not a hit index
+        elif r < 0.05:
+            row[:] = -1                           # no hit at all
+        row = row[:max_hits]
+        full = np.full(max_hits, -3, np.int64)
+        full[:row.shape[0]] = row
+        hits[s * K] = full.astype(np.int32)
+        n_hits[s * K] = int((row >= 0).sum())
+        n_holes[s * K] = int((row == -1).sum())
+    return dict(n_cands=n_cands, hits=hits, n_hits=n_hits, n_holes=n_holes, chi2=chi2)
