@@ -198,6 +198,27 @@ int kfx_build_tracks(kfx_ctx* ctx, const kfx_hits* hits, const int32_t* seeds,
                      const int32_t* seed_event, int32_t n_seeds, const kfx_build_params* params,
                      kfx_tracks* out, void* stream);
 
+/* Duplicate removal after building (abstract; Sec. 3: the duplicate
+ * tracks that building produces are removed in a step of their own; the
+ * paper gives no criterion, the reading below is this library's).
+ * tracks: a building output (kfx_tracks of kfx_build_tracks, or the same
+ * layout filled by the caller) of n_seeds seeds with K slots each; only
+ * n_cands, hits, n_hits, n_holes and chi2 are read.  Each seed with
+ * n_cands > 0 contributes one track, its slot 0.  The hits of a track are
+ * the distinct entries h of its hit list with 0 <= h < n_hits (the hit
+ * count of the batch); holes and padding are not hits.  Track b is a
+ * duplicate of track a when they share at least one hit, frac_den * shared
+ * >= frac_num * (hit count of the shorter of the two), and a ranks above b
+ * in the building order: larger n_hits, then smaller n_holes, then smaller
+ * chi2 (float32, must be finite), then smaller seed index.  The judgement
+ * is pairwise.  Output dup_of: device int32 [n_seeds]: -2 for a seed
+ * without a candidate, -1 for a kept track, else the seed of the
+ * highest-ranked track of which it is a duplicate.  Needs 0 < frac_num <=
+ * frac_den, max_hits <= 256, capacity >= n_seeds * K; the workspace grows
+ * with n_seeds * max_hits and n_hits.  Deterministic. */
+int kfx_find_duplicates(kfx_ctx* ctx, const kfx_tracks* tracks, int32_t n_seeds, int32_t K, int32_t n_hits,
+                        int32_t frac_num, int32_t frac_den, int32_t* dup_of, void* stream);
+
 /* Track fit (Sec. 1): the Kalman filter over fixed hit lists.  trk_off:
  * device int32 [n_tracks+1] into trk_hits (device int32 hit indices in
  * crossing order).  Starts at hit 1 from the three-hit estimate with the

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdint>
 #include <cstring>
 #include <map>
 #include <string>
@@ -774,6 +775,50 @@ int kfx_autotune_build(kfx_ctx* c, const kfx_hits* hits, const int32_t* seeds, c
   p->seeds_per_wave = cur.seeds_per_wave;
   if (best_ms) *best_ms = best;
   return KFX_OK;
+}
+
+int kfx_find_duplicates(kfx_ctx* c, const kfx_tracks* tracks, int32_t n_seeds, int32_t K, int32_t n_hits,
+                        int32_t frac_num, int32_t frac_den, int32_t* dup_of, void* stream) {
+  if (!c) return KFX_EINVAL;
+  c->err.clear();
+  if (!tracks) return fail(c, KFX_EINVAL, "tracks is NULL");
+  if (n_seeds < 0 || n_hits < 0) return fail(c, KFX_EINVAL, "n_seeds < 0 or n_hits < 0");
+  if (K < 1 || K > KFX_MAX_CANDS) return fail(c, KFX_EINVAL, "K outside 1..KFX_MAX_CANDS");
+  if (frac_num < 1 || frac_den < frac_num) return fail(c, KFX_EINVAL, "need 0 < frac_num <= frac_den");
+  if (n_seeds == 0) return KFX_OK;
+  const int H = tracks->max_hits;
+  if (H < 1 || H > 256 || (size_t)H * 64 * sizeof(int) > c->max_lds)
+    return fail(c, KFX_EINVAL, "max_hits outside 1..256");
+  if (tracks->capacity < (int64_t)n_seeds * K) return fail(c, KFX_EINVAL, "capacity < n_seeds * K");
+  if ((int64_t)n_seeds * H > INT32_MAX) return fail(c, KFX_EINVAL, "n_seeds * max_hits exceeds 2^31 - 1");
+  if (!tracks->n_cands || !tracks->hits || !tracks->n_hits || !tracks->n_holes || !tracks->chi2 || !dup_of)
+    return fail(c, KFX_EINVAL, "NULL track arrays or dup_of");
+  DeviceGuard dg(c->device);
+  hipStream_t st = (hipStream_t)stream;
+  const size_t SH = (size_t)n_seeds * H;
+  int rc = KFX_OK;
+  DupArgs a;
+  a.n_cands = tracks->n_cands;
+  a.hits = tracks->hits;
+  a.n_hits_c = tracks->n_hits;
+  a.n_holes_c = tracks->n_holes;
+  a.chi2_c = tracks->chi2;
+  a.S = n_seeds;
+  a.K = K;
+  a.H = H;
+  a.n_hits = n_hits;
+  a.num = frac_num;
+  a.den = frac_den;
+  a.dup_of = dup_of;
+  a.list = (int*)ws(c, "dup.list", SH * 4, st, rc); if (rc) return rc;
+  a.rank = (int*)ws(c, "dup.rank", SH * 4, st, rc); if (rc) return rc;
+  a.trk = (int*)ws(c, "dup.trk", SH * 4, st, rc); if (rc) return rc;
+  a.len = (int*)ws(c, "dup.len", (size_t)n_seeds * 4, st, rc); if (rc) return rc;
+  a.cnt = (int*)ws(c, "dup.cnt", ((size_t)n_hits + 1) * 4, st, rc); if (rc) return rc;
+  a.off = (int*)ws(c, "dup.off", ((size_t)n_hits + 2) * 4, st, rc); if (rc) return rc;
+  int* scratch = (int*)ws(c, "dup.scan", (((size_t)n_hits + 1) / 4096 + 4) * 4, st, rc); if (rc) return rc;
+  launch_find_duplicates(a, scratch, st);
+  return hip_check(c, hipGetLastError(), "duplicate removal kernels");
 }
 
 int kfx_fit_tracks(kfx_ctx* c, const kfx_hits* hits, const int32_t* trk_off, const int32_t* trk_hits,

@@ -21,6 +21,24 @@ struct BinWork {
   int* scan_scratch;  // [n_keys / tile + 2]
 };
 
+// Duplicate removal over the best candidate (slot 0) of every seed.
+struct DupArgs {
+  const int* n_cands;    // [S]
+  const int* hits;       // [S*K][H]
+  const int* n_hits_c;   // [S*K]
+  const int* n_holes_c;  // [S*K]
+  const float* chi2_c;   // [S*K]
+  int S, K, H, n_hits;   // seeds, slots per seed, list capacity, hit count
+  int num, den;          // shared-hit fraction
+  int* list;             // [S][H] ascending distinct hits of each track
+  int* len;              // [S]
+  int* rank;             // [S][H] place of the track in the hit's list
+  int* cnt;              // [n_hits + 1] tracks per hit
+  int* off;              // [n_hits + 1] exclusive scan of cnt
+  int* trk;              // [S*H] tracks of each hit
+  int* dup_of;           // [S] output
+};
+
 void launch_fill(int* p, long n, int v, hipStream_t st);
 void exclusive_scan(const int* in, long n, int* out, int* scratch, hipStream_t st);
 void launch_bin(const Geometry* G, const HitsView& H, int n_layers, int n_bins, BinWork& w, int* bin_out,
@@ -48,5 +66,6 @@ void launch_build_init(const BuildArgs& a, hipStream_t st);
 void launch_build_fused(const BuildArgs& a, const TracksOut& o, int* seed_counter, int blocks, int threads,
                         int lanes, int waves_per_simd, hipStream_t st, const hipEvent_t* ev);
 int fused_lanes_for(int K);
+void launch_find_duplicates(const DupArgs& a, int* scan_scratch, hipStream_t st);
 
 }  // namespace kfx

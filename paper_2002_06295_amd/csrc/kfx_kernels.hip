@@ -943,6 +943,125 @@ k_build_fused(BuildArgs a, TracksOut o, int* seed_counter) {
   add_stat(a.stats + 2, n_upd);
 }
 
+// ------------------------------------------------------ duplicate removal
+// After building, the best candidate of every seed is one track; a track is
+// a duplicate of a higher-ranked track when their hit sets overlap by at
+// least frac_num / frac_den of the shorter one (abstract and Sec. 3: the
+// duplicates the building produces are removed in a step of their own).
+// Three passes: sorted distinct hit list per track (plus the track's place
+// in each of its hits' track lists), the hit -> tracks lists, then one
+// thread per track merging its list with those of its higher-ranked
+// partners.
+
+// insertion into the ascending, repeat-free list held in LDS column t;
+// returns the new length
+__device__ inline int sorted_insert(int* col, int n, int h) {
+  int p = n;
+  while (p > 0 && col[(p - 1) * 64] > h) --p;
+  if (p > 0 && col[(p - 1) * 64] == h) return n;
+  for (int q = n; q > p; --q) col[q * 64] = col[(q - 1) * 64];
+  col[p * 64] = h;
+  return n + 1;
+}
+
+__global__ void __launch_bounds__(64) k_dup_lists(DupArgs a) {
+  extern __shared__ int dup_lds[];  // [H][64]: column t is thread t's list
+  const int t = threadIdx.x;
+  const int s = blockIdx.x * 64 + t;
+  if (s >= a.S) return;
+  int* col = dup_lds + t;
+  int n = 0;
+  const int nc = a.n_cands[s];
+  if (nc > 0) {
+    const int* row = a.hits + (long)s * a.K * a.H;
+    for (int k = 0; k < a.H; ++k) {
+      const int h = row[k];
+      if (h >= 0 && h < a.n_hits) n = sorted_insert(col, n, h);
+    }
+  }
+  a.dup_of[s] = nc > 0 ? -1 : -2;
+  a.len[s] = n;
+  int* out = a.list + (long)s * a.H;
+  int* rk = a.rank + (long)s * a.H;
+  for (int k = 0; k < n; ++k) {
+    const int h = col[k * 64];
+    out[k] = h;
+    rk[k] = atomicAdd(a.cnt + h, 1);
+  }
+}
+
+__global__ void __launch_bounds__(256) k_dup_fill(DupArgs a) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= a.S) return;
+  const int n = a.len[s];
+  const int* l = a.list + (long)s * a.H;
+  const int* rk = a.rank + (long)s * a.H;
+  for (int k = 0; k < n; ++k) a.trk[a.off[l[k]] + rk[k]] = s;
+}
+
+// rank of the building order: more hits, fewer holes, smaller chi2, lower
+// seed index
+struct DupKey {
+  int nh, ho;
+  float c2;
+  int s;
+};
+__device__ inline DupKey dup_key(const DupArgs& a, int s) {
+  const long e = (long)s * a.K;
+  return DupKey{a.n_hits_c[e], a.n_holes_c[e], a.chi2_c[e], s};
+}
+__device__ inline bool ranks_above(const DupKey& x, const DupKey& y) {
+  if (x.nh != y.nh) return x.nh > y.nh;
+  if (x.ho != y.ho) return x.ho < y.ho;
+  if (x.c2 != y.c2) return x.c2 < y.c2;
+  return x.s < y.s;
+}
+
+__global__ void __launch_bounds__(256) k_dup_find(DupArgs a) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= a.S) return;
+  const int nb = a.len[b];
+  if (nb == 0) return;  // dup_of already -1 (no hits) or -2 (no track)
+  const int* lb = a.list + (long)b * a.H;
+  const DupKey kb = dup_key(a, b);
+  DupKey best{0, 0, 0.0f, -1};
+  for (int k = 0; k < nb; ++k) {
+    const int h = lb[k];
+    const int e1 = a.off[h + 1];
+    for (int e = a.off[h]; e < e1; ++e) {
+      const int j = a.trk[e];
+      if (j == b) continue;
+      const DupKey kj = dup_key(a, j);
+      if (!ranks_above(kj, kb)) continue;
+      if (best.s >= 0 && !ranks_above(kj, best)) continue;
+      // merge the two ascending lists; the first common hit is their
+      // smallest, and when it lies below h the pair was judged at that hit
+      const int* lj = a.list + (long)j * a.H;
+      const int nj = a.len[j];
+      int x = 0, y = 0, shared = 0;
+      bool earlier = false;
+      while (x < nb && y < nj) {
+        const int u = lb[x], v = lj[y];
+        if (u == v) {
+          if (shared == 0 && u < h) {
+            earlier = true;
+            break;
+          }
+          ++shared, ++x, ++y;
+        } else if (u < v) {
+          ++x;
+        } else {
+          ++y;
+        }
+      }
+      if (earlier) continue;
+      const int shorter = nb < nj ? nb : nj;
+      if ((long)a.den * shared >= (long)a.num * shorter) best = kj;
+    }
+  }
+  a.dup_of[b] = best.s;
+}
+
 // ---------------------------------------------------------------- launchers
 static inline unsigned nblk(long n, int b) { return (unsigned)((n + b - 1) / b); }
 
@@ -1101,5 +1220,15 @@ size_t fused_lds_bytes(int lanes, int threads, int max_steps) {
   return (fs + 4 * (size_t)max_steps) * threads;
 }
 size_t fused_static_lds_bytes() { return sizeof(Geometry); }
+
+void launch_find_duplicates(const DupArgs& a, int* scan_scratch, hipStream_t st) {
+  if (a.S <= 0) return;
+  launch_fill(a.cnt, (long)a.n_hits + 1, 0, st);
+  hipLaunchKernelGGL(k_dup_lists, dim3((a.S + 63) / 64), dim3(64), (size_t)a.H * 64 * sizeof(int), st, a);
+  exclusive_scan(a.cnt, a.n_hits, a.off, scan_scratch, st);
+  const unsigned nb = (unsigned)((a.S + 255) / 256);
+  hipLaunchKernelGGL(k_dup_fill, dim3(nb), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(k_dup_find, dim3(nb), dim3(256), 0, st, a);
+}
 
 }  // namespace kfx

@@ -30,7 +30,7 @@ MAX_STEPS = 40
 EXPORTED = ["kfx_create", "kfx_destroy", "kfx_last_error", "kfx_load_layers", "kfx_bin_hits",
             "kfx_seed_states", "kfx_step_compat", "kfx_build_tracks", "kfx_fit_tracks",
             "kfx_fit_tracks_backward", "kfx_enable_timing", "kfx_build_times", "kfx_build_graph",
-            "kfx_graph_launch", "kfx_graph_destroy", "kfx_autotune_build"]
+            "kfx_graph_launch", "kfx_graph_destroy", "kfx_autotune_build", "kfx_find_duplicates"]
 
 
 class c_states(ctypes.Structure):
@@ -114,6 +114,9 @@ def load_library():
     lib.kfx_autotune_build.argtypes = [ctypes.c_void_p, ctypes.POINTER(c_hits), ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.c_int32, ctypes.POINTER(c_build_params), ctypes.POINTER(c_tracks),
                                        ctypes.c_int32, ctypes.POINTER(ctypes.c_float), ctypes.c_void_p]
+    lib.kfx_find_duplicates.argtypes = [ctypes.c_void_p, ctypes.POINTER(c_tracks), ctypes.c_int32,
+                                        ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                        ctypes.c_void_p, ctypes.c_void_p]
     lib.kfx_enable_timing.argtypes = [ctypes.c_void_p, ctypes.c_int]
     lib.kfx_build_times.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
     for name in EXPORTED:
@@ -406,6 +409,39 @@ class Context:
                                   out["stats"].data_ptr(), int(max_hits), n, 0)
         out["S"], out["K"] = S, K
         return out
+
+    def tracks_from_arrays(self, n_cands, hits, n_hits, n_holes, chi2, K):
+        """A building-output dict (as build_tracks returns) holding the given
+        host arrays on the device: n_cands [S], hits [S*K, max_hits],
+        n_hits, n_holes, chi2 [S*K].  The states are left unset."""
+        import torch
+        d = self.device
+        hits = np.ascontiguousarray(hits, dtype=np.int32)
+        S = int(np.asarray(n_cands).shape[0])
+        out = dict(n_cands=torch.as_tensor(np.ascontiguousarray(n_cands, dtype=np.int32), device=d),
+                   hits=torch.as_tensor(hits, device=d),
+                   n_hits=torch.as_tensor(np.ascontiguousarray(n_hits, dtype=np.int32), device=d),
+                   n_holes=torch.as_tensor(np.ascontiguousarray(n_holes, dtype=np.int32), device=d),
+                   chi2=torch.as_tensor(np.ascontiguousarray(chi2, dtype=np.float32), device=d))
+        out["_struct"] = c_tracks(out["n_cands"].data_ptr(), out["hits"].data_ptr(), out["n_hits"].data_ptr(),
+                                  out["n_holes"].data_ptr(), out["chi2"].data_ptr(), c_states(None, None, 0),
+                                  None, int(hits.shape[1]), int(hits.shape[0]), 0)
+        out["S"], out["K"] = S, int(K)
+        return out
+
+    def find_duplicates(self, out, n_hits, frac=(1, 2), n_seeds=None, dup_of=None):
+        """dup_of [S] (device int32) of a building output `out` (a dict from
+        build_tracks or tracks_from_arrays): -2 no candidate, -1 kept, else
+        the seed of the highest-ranked track it duplicates.  n_hits: hit
+        count of the batch; frac = (num, den) shared-hit fraction."""
+        import torch
+        S = out["S"] if n_seeds is None else int(n_seeds)
+        if dup_of is None:
+            dup_of = torch.empty(max(S, 1), dtype=torch.int32, device=self.device)
+        self._check(self.lib.kfx_find_duplicates(self.h, ctypes.byref(out["_struct"]), S, int(out["K"]),
+                                                 int(n_hits), int(frac[0]), int(frac[1]), _ptr(dup_of),
+                                                 self._stream()))
+        return dup_of[:S]
 
     def fit_tracks(self, hits: DeviceHits, trk_off, trk_hits, prior=(0.1, 0.5, 0.05, 0.05), align=None,
                    field_scale=1.0, ckpt=False, out=None):

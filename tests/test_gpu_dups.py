@@ -1,0 +1,162 @@
+"""GPU parity of duplicate removal (kfx_find_duplicates) against the oracle
+(oracle/duplicates.py; abstract and Sec. 3).  Every decision is integer or a
+float32 comparison of the inputs, so the result must be identical."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import kfsynth
+import oracle
+from oracle import duplicates as D
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda", 0)
+
+
+@pytest.fixture(scope="module")
+def kfx():
+    from paper_2002_06295_amd import kfx as k
+    return k
+
+
+@pytest.fixture(scope="module")
+def ctx(kfx, dev):
+    return kfx.Context(0)
+
+
+def _gpu(ctx, t, K, NH, num=1, den=2):
+    import torch
+    out = ctx.tracks_from_arrays(t["n_cands"], t["hits"], t["n_hits"], t["n_holes"], t["chi2"], K)
+    d = ctx.find_duplicates(out, NH, (num, den))
+    torch.cuda.synchronize()
+    return d.cpu().numpy()
+
+
+def _oracle(t, K, NH, num=1, den=2, only=None):
+    return D.find_duplicates(t["n_cands"], t["hits"], t["n_hits"], t["n_holes"], t["chi2"], K, NH, num, den,
+                             only=only)
+
+
+@pytest.mark.parametrize("frac", ["1/2", "1/1", "1/100"])
+def test_golden(ctx, frac):
+    with open(os.path.join(HERE, "golden", "duplicates_small.json")) as f:
+        d = json.load(f)
+    num, den = map(int, frac.split("/"))
+    t = {k: np.array(d[k]) for k in ("n_cands", "hits", "n_hits", "n_holes", "chi2")}
+    print(f"golden {frac}", flush=True)
+    assert _gpu(ctx, t, d["K"], d["n_hits_total"], num, den).tolist() == d["expected"][frac]
+
+
+# (seeds, K, max_hits, hits in the batch, fraction, generator seed): sizes
+# around the 64-thread list blocks and 256-thread blocks, K at 1 and 16,
+# list capacities 3 and 256, no hits at all, heavy sharing (few hits)
+CASES = [
+    (1, 1, 48, 10, 1, 2, 0), (63, 6, 48, 100, 1, 2, 1), (64, 6, 48, 100, 1, 3, 2), (65, 16, 48, 500, 2, 3, 3),
+    (257, 1, 3, 50, 1, 2, 4), (1000, 6, 256, 4000, 1, 2, 5), (3000, 10, 48, 40, 1, 100, 6),
+    (2000, 6, 48, 0, 1, 2, 7), (20000, 6, 48, 200000, 1, 2, 8), (5000, 6, 64, 20000, 1, 1, 9),
+]
+
+
+@pytest.mark.parametrize("S,K,H,NH,num,den,seed", CASES)
+def test_parity_synthetic(ctx, S, K, H, NH, num, den, seed):
+    print(f"dups S={S} K={K} H={H} NH={NH} frac={num}/{den} seed={seed}", flush=True)
+    t = kfsynth.track_lists(S, K, H, NH, seed=seed, chi2_levels=1 + seed % 5)
+    g = _gpu(ctx, t, K, NH, num, den)
+    o = _oracle(t, K, NH, num, den)
+    np.testing.assert_array_equal(g, o)
+
+
+def test_parity_full_size_sampled(ctx):
+    """100k seeds over 1.5M hits (the batched workload's scale): every seed's
+    result is checked for validity, 3000 sampled seeds against the oracle."""
+    S, K, NH = 100000, 6, 1500000
+    print(f"dups full size S={S}", flush=True)
+    t = kfsynth.track_lists(S, K, 48, NH, seed=21, seeds_per_truth=1.3)
+    g = _gpu(ctx, t, K, NH)
+    sample = np.random.default_rng(5).choice(S, 3000, replace=False)
+    o = _oracle(t, K, NH, only=sample)
+    np.testing.assert_array_equal(g[sample], o[sample])
+    # validity everywhere: a flagged seed points to a seed with a track
+    nc = t["n_cands"]
+    assert ((g == -2) == (nc <= 0)).all()
+    f = np.nonzero(g >= 0)[0]
+    assert (nc[g[f]] > 0).all() and (g[f] != f).all()
+
+
+def test_repeat_calls_and_shrinking_input(ctx):
+    """Workspaces are reused: a large call, then a small one, then the large
+    one again give the oracle's result each time."""
+    big = kfsynth.track_lists(3000, 6, 48, 5000, seed=31)
+    small = kfsynth.track_lists(100, 6, 48, 300, seed=32)
+    for t, NH in ((big, 5000), (small, 300), (big, 5000)):
+        np.testing.assert_array_equal(_gpu(ctx, t, 6, NH), _oracle(t, 6, NH))
+
+
+def test_empty_and_errors(ctx, kfx):
+    import torch
+    t = kfsynth.track_lists(10, 6, 48, 100, seed=1)
+    out = ctx.tracks_from_arrays(t["n_cands"], t["hits"], t["n_hits"], t["n_holes"], t["chi2"], 6)
+    assert ctx.find_duplicates(out, 100, n_seeds=0).numel() == 0
+    for frac in ((0, 2), (3, 2), (-1, 1)):
+        with pytest.raises(kfx.KfxError):
+            ctx.find_duplicates(out, 100, frac)
+    with pytest.raises(kfx.KfxError):
+        ctx.find_duplicates(out, -1)
+    bad = dict(out)
+    bad["K"] = 17
+    with pytest.raises(kfx.KfxError):
+        ctx.find_duplicates(bad, 100)
+    wide = kfsynth.track_lists(4, 1, 300, 100, seed=2)
+    out = ctx.tracks_from_arrays(wide["n_cands"], wide["hits"], wide["n_hits"], wide["n_holes"], wide["chi2"], 1)
+    with pytest.raises(kfx.KfxError):
+        ctx.find_duplicates(out, 100)
+    torch.cuda.synchronize()
+
+
+def test_after_building_with_duplicate_seeds(kfx, dev):
+    """End to end on the 5k-track event with a second seed for a quarter of
+    the particles: GPU building + GPU duplicate removal against oracle
+    building + oracle duplicate removal (the builds agree on nearly every
+    best candidate; the duplicate decisions must agree as often), and the
+    physics: extra seeds flagged as duplicates of their particle's track."""
+    import torch
+    ev = kfsynth.generate("build5k")
+    seeds, seed_event, seed_track = kfsynth.duplicate_seeds(ev, 0.25, seed=0)
+    S, T, K = seeds.shape[0], ev.n_tracks, 6
+    print(f"dups after building S={S}", flush=True)
+    ctx = kfx.Context(0)
+    w = ev.workload
+    ctx.load_layers(ev.geometry.as_records(), ev.bz, w.n_eta_bins, w.n_phi_bins)
+    hits = kfx.DeviceHits.from_events(ev, dev)
+    out = ctx.build_tracks(hits, seeds, seed_event, chi2_cut=30.0, max_cands=K, max_holes=3, max_steps=32,
+                           prior=oracle.DEFAULT_PRIOR, mode=kfx.MODE_FUSED)
+    g = ctx.find_duplicates(out, ev.n_hits)
+    torch.cuda.synchronize()
+    g = g.cpu().numpy()
+    o_b = oracle.build_tracks(ev, seeds=seeds, seed_event=seed_event, prior=oracle.DEFAULT_PRIOR,
+                              max_hits=out["hits"].shape[1])
+    o = D.find_duplicates(o_b["n"], o_b["hits"].reshape(S * K, -1), o_b["nhits"].ravel(),
+                          o_b["nholes"].ravel(), o_b["chi2"].ravel().astype(np.float32), K, ev.n_hits)
+    agree = np.mean(g == o)
+    assert agree >= 0.98, agree
+    extra = np.arange(T, S)
+    assert np.mean(g[extra] == seed_track[extra]) > 0.8
+    # validity of every GPU decision on the GPU's own building output
+    gh = out["hits"].cpu().numpy()
+    nh = out["n_hits"].cpu().numpy()[::K]
+    for b in np.nonzero(g >= 0)[0][:2000]:
+        a = g[b]
+        hb = set(gh[b * K][gh[b * K] >= 0].tolist())
+        ha = set(gh[a * K][gh[a * K] >= 0].tolist())
+        assert 2 * len(ha & hb) >= min(len(ha), len(hb)) and nh[a] >= nh[b]
