@@ -206,6 +206,21 @@ def cpu_baseline(ev, n_seeds, min_reps, min_seconds=3.0):
                        f"search, {len(chunks)} threads on {host_cpu_model()}, {dt:.1f} s wall"), res
 
 
+def time_dedup(ctx, out, n_hits, reps=20):
+    """Mean time (ms, torch events on the call's stream) of duplicate
+    removal over a building output, and its result."""
+    import torch
+    d = ctx.find_duplicates(out, n_hits)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        d = ctx.find_duplicates(out, n_hits, dup_of=d)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps, d.cpu().numpy()
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -328,6 +343,20 @@ def main():
                                         "kernels_ms": float(np.mean([t[1] for t in times_p]))}
         log(f"[bench] plain path: {wall_p:.3f} ms/step")
         del out
+        # duplicate removal after building: the 5k-track event with a second
+        # seed (hits 1, 2, 4) for a quarter of the particles
+        dseeds, dsev, dtrk = kfsynth.duplicate_seeds(ev, 0.25, seed=0)
+        dout = ctx.build_tracks(hits, dseeds, dsev, **build_kw(ev, kfx.MODE_FUSED), **shape)
+        dms, dres = time_dedup(ctx, dout, ev.n_hits)
+        extra = np.arange(ev.n_tracks, dseeds.shape[0])
+        sec["duplicate_removal"] = {
+            "workload": "build5k + a second seed for 25 % of the particles",
+            "seeds": int(dseeds.shape[0]), "extra_seeds": int(extra.size), "ms": dms,
+            "tracks_per_s": dseeds.shape[0] / (dms * 1e-3), "flagged": int((dres >= 0).sum()),
+            "extra_flagged_to_own_particle": float(np.mean(dres[extra] == dtrk[extra]))}
+        log(f"[bench] duplicate removal: {dms * 1e3:.1f} us, flagged {(dres >= 0).sum()} of "
+            f"{extra.size} extra seeds")
+        del dout
         for name in ("batch256", "occ10k"):
             if name == args.workload:
                 continue
@@ -342,6 +371,7 @@ def main():
             sh2 = ctx2.autotune_build(h2, s2, e2, reps=1, **build_kw(ev2, kfx.MODE_FUSED))
             sh2.pop("ms")
             wf, tf, sf, o2 = run_build(ctx2, kfx, h2, ev2, 4, 1, kfx.MODE_FUSED, shape=sh2)
+            dms2, dres2 = time_dedup(ctx2, o2, ev2.n_hits)
             wp, tp, sp, o2 = run_build(ctx2, kfx, h2, ev2, 2, 1, kfx.MODE_PLAIN, out=o2)
             km = float(np.mean([t[1] for t in tf]))
             fl = algorithmic_flops(sf)
@@ -349,7 +379,8 @@ def main():
                          "binning_ms": float(np.mean([t[0] for t in tf])),
                          "building_ms": float(np.mean([t[2] for t in tf])),
                          "alu_frac": fl / (km * 1e-3) / 1e12 / ALU_PEAK_TFLOPS, "launch_shape": sh2,
-                         "plain_steps_per_s": sp[0] / (wp * 1e-3), "steps_per_launch": sf[0]}
+                         "plain_steps_per_s": sp[0] / (wp * 1e-3), "steps_per_launch": sf[0],
+                         "duplicate_removal_ms": dms2, "duplicates_flagged": int((dres2 >= 0).sum())}
             log(f"[bench] {name}: fused {sec[name]['steps_per_s']:.3e} steps/s, plain "
                 f"{sec[name]['plain_steps_per_s']:.3e}")
             del o2, h2, ctx2, ev2

@@ -787,8 +787,8 @@ int kfx_find_duplicates(kfx_ctx* c, const kfx_tracks* tracks, int32_t n_seeds, i
   if (frac_num < 1 || frac_den < frac_num) return fail(c, KFX_EINVAL, "need 0 < frac_num <= frac_den");
   if (n_seeds == 0) return KFX_OK;
   const int H = tracks->max_hits;
-  if (H < 1 || H > 256 || (size_t)H * 64 * sizeof(int) > c->max_lds)
-    return fail(c, KFX_EINVAL, "max_hits outside 1..256");
+  if (H < 1 || H > 128 || (size_t)H * 64 * 2 * sizeof(int) > c->max_lds)
+    return fail(c, KFX_EINVAL, "max_hits outside 1..128");
   if (tracks->capacity < (int64_t)n_seeds * K) return fail(c, KFX_EINVAL, "capacity < n_seeds * K");
   if ((int64_t)n_seeds * H > INT32_MAX) return fail(c, KFX_EINVAL, "n_seeds * max_hits exceeds 2^31 - 1");
   if (!tracks->n_cands || !tracks->hits || !tracks->n_hits || !tracks->n_holes || !tracks->chi2 || !dup_of)
@@ -811,13 +811,10 @@ int kfx_find_duplicates(kfx_ctx* c, const kfx_tracks* tracks, int32_t n_seeds, i
   a.den = frac_den;
   a.dup_of = dup_of;
   a.list = (int*)ws(c, "dup.list", SH * 4, st, rc); if (rc) return rc;
-  a.rank = (int*)ws(c, "dup.rank", SH * 4, st, rc); if (rc) return rc;
-  a.trk = (int*)ws(c, "dup.trk", SH * 4, st, rc); if (rc) return rc;
-  a.len = (int*)ws(c, "dup.len", (size_t)n_seeds * 4, st, rc); if (rc) return rc;
-  a.cnt = (int*)ws(c, "dup.cnt", ((size_t)n_hits + 1) * 4, st, rc); if (rc) return rc;
-  a.off = (int*)ws(c, "dup.off", ((size_t)n_hits + 2) * 4, st, rc); if (rc) return rc;
-  int* scratch = (int*)ws(c, "dup.scan", (((size_t)n_hits + 1) / 4096 + 4) * 4, st, rc); if (rc) return rc;
-  launch_find_duplicates(a, scratch, st);
+  a.next = (int*)ws(c, "dup.next", SH * 4, st, rc); if (rc) return rc;
+  a.key = (int4*)ws(c, "dup.key", (size_t)n_seeds * 16, st, rc); if (rc) return rc;
+  a.head = (int*)ws(c, "dup.head", ((size_t)n_hits + 4) * 4, st, rc); if (rc) return rc;
+  launch_find_duplicates(a, st);
   return hip_check(c, hipGetLastError(), "duplicate removal kernels");
 }
 

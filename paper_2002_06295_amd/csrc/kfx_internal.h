@@ -30,12 +30,10 @@ struct DupArgs {
   const float* chi2_c;   // [S*K]
   int S, K, H, n_hits;   // seeds, slots per seed, list capacity, hit count
   int num, den;          // shared-hit fraction
-  int* list;             // [S][H] ascending distinct hits of each track
-  int* len;              // [S]
-  int* rank;             // [S][H] place of the track in the hit's list
-  int* cnt;              // [n_hits + 1] tracks per hit
-  int* off;              // [n_hits + 1] exclusive scan of cnt
-  int* trk;              // [S*H] tracks of each hit
+  int* list;             // [S][H] ascending distinct hits of each track, -1 after
+  int* next;             // [S][H] next entry holding the same hit, -1 at the end
+  int* head;             // [n_hits] last entry pushed for each hit, -1 none
+  int4* key;             // [S] n_hits, n_holes, chi2 bits, hit count of the list
   int* dup_of;           // [S] output
 };
 
@@ -66,6 +64,6 @@ void launch_build_init(const BuildArgs& a, hipStream_t st);
 void launch_build_fused(const BuildArgs& a, const TracksOut& o, int* seed_counter, int blocks, int threads,
                         int lanes, int waves_per_simd, hipStream_t st, const hipEvent_t* ev);
 int fused_lanes_for(int K);
-void launch_find_duplicates(const DupArgs& a, int* scan_scratch, hipStream_t st);
+void launch_find_duplicates(const DupArgs& a, hipStream_t st);
 
 }  // namespace kfx

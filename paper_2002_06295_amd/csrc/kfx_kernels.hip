@@ -948,118 +948,174 @@ k_build_fused(BuildArgs a, TracksOut o, int* seed_counter) {
 // a duplicate of a higher-ranked track when their hit sets overlap by at
 // least frac_num / frac_den of the shorter one (abstract and Sec. 3: the
 // duplicates the building produces are removed in a step of their own).
-// Three passes: sorted distinct hit list per track (plus the track's place
-// in each of its hits' track lists), the hit -> tracks lists, then one
-// thread per track merging its list with those of its higher-ranked
-// partners.
+//
+// Two passes over blocks of 64 tracks.  The first sorts each track's
+// distinct hits (in LDS, rows loaded and stored with coalesced accesses)
+// and pushes every (track, hit) entry onto a per-hit linked list with one
+// atomic exchange (head[hit] -> entry -> next[entry] -> ...; entry =
+// track * H + position).  The second walks, for each hit of a track, the
+// list of the hit's other holders and merges the track's list with those of
+// the holders that rank above it.  Random accesses per entry: the exchange
+// and one read of head[hit]; the per-hit arrays span the whole batch, so
+// blocks are ordered so that each XCD (and its L2) works through one
+// contiguous range of seeds, i.e. of events and their hits.
 
-// insertion into the ascending, repeat-free list held in LDS column t;
-// returns the new length
+constexpr int kDupBlock = 64;
+
+// logical block of this workgroup when workgroups are dealt to the 8 XCDs
+// in turn: XCD x takes logical blocks [x * per, (x + 1) * per); -1 = idle
+__device__ inline int xcd_block(int nblk) {
+  const int per = (nblk + 7) >> 3;
+  const int lb = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+  return lb < nblk ? lb : -1;
+}
+
+// insertion into the ascending, repeat-free list held in LDS column
+// (stride kDupBlock); returns the new length
 __device__ inline int sorted_insert(int* col, int n, int h) {
   int p = n;
-  while (p > 0 && col[(p - 1) * 64] > h) --p;
-  if (p > 0 && col[(p - 1) * 64] == h) return n;
-  for (int q = n; q > p; --q) col[q * 64] = col[(q - 1) * 64];
-  col[p * 64] = h;
+  while (p > 0 && col[(p - 1) * kDupBlock] > h) --p;
+  if (p > 0 && col[(p - 1) * kDupBlock] == h) return n;
+  for (int q = n; q > p; --q) col[q * kDupBlock] = col[(q - 1) * kDupBlock];
+  col[p * kDupBlock] = h;
   return n + 1;
 }
 
-__global__ void __launch_bounds__(64) k_dup_lists(DupArgs a) {
-  extern __shared__ int dup_lds[];  // [H][64]: column t is thread t's list
-  const int t = threadIdx.x;
-  const int s = blockIdx.x * 64 + t;
-  if (s >= a.S) return;
+__global__ void __launch_bounds__(kDupBlock) k_dup_lists(DupArgs a, int nblk) {
+  extern __shared__ int dup_lds[];  // [H][64]: column t holds track t's row
+  __shared__ int lens[kDupBlock];
+  const int lb = xcd_block(nblk);
+  if (lb < 0) return;
+  const int t = threadIdx.x, H = a.H;
+  const int s0 = lb * kDupBlock;
+  const int nrow = min(kDupBlock, a.S - s0);
+  for (int i = t; i < nrow * H; i += kDupBlock) {
+    const int r = i / H, c = i - r * H;
+    dup_lds[c * kDupBlock + r] = a.hits[(long)(s0 + r) * a.K * H + c];
+  }
+  __syncthreads();
   int* col = dup_lds + t;
   int n = 0;
-  const int nc = a.n_cands[s];
-  if (nc > 0) {
-    const int* row = a.hits + (long)s * a.K * a.H;
-    for (int k = 0; k < a.H; ++k) {
-      const int h = row[k];
-      if (h >= 0 && h < a.n_hits) n = sorted_insert(col, n, h);
+  if (t < nrow) {
+    const int s = s0 + t;
+    const int nc = a.n_cands[s];
+    if (nc > 0) {
+      // in place: element k is read before any write reaches index k
+      for (int k = 0; k < H; ++k) {
+        const int h = col[k * kDupBlock];
+        if (h >= 0 && h < a.n_hits) n = sorted_insert(col, n, h);
+      }
+      const long e = (long)s * a.K;
+      a.key[s] = make_int4(a.n_hits_c[e], a.n_holes_c[e], __float_as_int(a.chi2_c[e]), n);
+    } else {
+      a.key[s] = make_int4(0, 0, 0, 0);
     }
+    a.dup_of[s] = nc > 0 ? -1 : -2;
   }
-  a.dup_of[s] = nc > 0 ? -1 : -2;
-  a.len[s] = n;
-  int* out = a.list + (long)s * a.H;
-  int* rk = a.rank + (long)s * a.H;
-  for (int k = 0; k < n; ++k) {
-    const int h = col[k * 64];
-    out[k] = h;
-    rk[k] = atomicAdd(a.cnt + h, 1);
+  lens[t] = n;
+  __syncthreads();
+  int* lst = a.list + (long)s0 * H;
+  for (int i = t; i < nrow * H; i += kDupBlock) {
+    const int r = i / H, c = i - r * H;
+    lst[i] = c < lens[r] ? dup_lds[c * kDupBlock + r] : -1;
   }
-}
-
-__global__ void __launch_bounds__(256) k_dup_fill(DupArgs a) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= a.S) return;
-  const int n = a.len[s];
-  const int* l = a.list + (long)s * a.H;
-  const int* rk = a.rank + (long)s * a.H;
-  for (int k = 0; k < n; ++k) a.trk[a.off[l[k]] + rk[k]] = s;
+  __syncthreads();
+  // push the entries; four exchanges in flight per thread
+  const int base = (s0 + t) * H;
+  for (int k = 0; k < n; k += 4) {
+    int old[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (k + u < n) old[u] = atomicExch(a.head + col[(k + u) * kDupBlock], base + k + u);
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (k + u < n) col[(k + u) * kDupBlock] = old[u];
+  }
+  __syncthreads();
+  int* nxt = a.next + (long)s0 * H;
+  for (int i = t; i < nrow * H; i += kDupBlock) {
+    const int r = i / H, c = i - r * H;
+    if (c < lens[r]) nxt[i] = dup_lds[c * kDupBlock + r];
+  }
 }
 
 // rank of the building order: more hits, fewer holes, smaller chi2, lower
-// seed index
-struct DupKey {
-  int nh, ho;
-  float c2;
-  int s;
-};
-__device__ inline DupKey dup_key(const DupArgs& a, int s) {
-  const long e = (long)s * a.K;
-  return DupKey{a.n_hits_c[e], a.n_holes_c[e], a.chi2_c[e], s};
-}
-__device__ inline bool ranks_above(const DupKey& x, const DupKey& y) {
-  if (x.nh != y.nh) return x.nh > y.nh;
-  if (x.ho != y.ho) return x.ho < y.ho;
-  if (x.c2 != y.c2) return x.c2 < y.c2;
-  return x.s < y.s;
+// seed index (x = n_hits, y = n_holes, z = chi2 bits)
+__device__ inline bool ranks_above(const int4& x, int xs, const int4& y, int ys) {
+  if (x.x != y.x) return x.x > y.x;
+  if (x.y != y.y) return x.y < y.y;
+  const float cx = __int_as_float(x.z), cy = __int_as_float(y.z);
+  if (cx != cy) return cx < cy;
+  return xs < ys;
 }
 
-__global__ void __launch_bounds__(256) k_dup_find(DupArgs a) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= a.S) return;
-  const int nb = a.len[b];
+__global__ void __launch_bounds__(kDupBlock) k_dup_find(DupArgs a, int nblk) {
+  extern __shared__ int dup_lds[];  // [2][H][64]: own sorted hits, own next
+  const int lb = xcd_block(nblk);
+  if (lb < 0) return;
+  const int t = threadIdx.x, H = a.H;
+  const int s0 = lb * kDupBlock;
+  const int nrow = min(kDupBlock, a.S - s0);
+  int* lh = dup_lds;
+  int* ln = dup_lds + H * kDupBlock;
+  const int* lst = a.list + (long)s0 * H;
+  const int* nx = a.next + (long)s0 * H;
+  for (int i = t; i < nrow * H; i += kDupBlock) {
+    const int r = i / H, c = i - r * H;
+    const int h = lst[i];
+    lh[c * kDupBlock + r] = h;
+    ln[c * kDupBlock + r] = h >= 0 ? nx[i] : -1;
+  }
+  __syncthreads();
+  if (t >= nrow) return;
+  const int b = s0 + t;
+  const int4 kb = a.key[b];
+  const int nb = kb.w;
   if (nb == 0) return;  // dup_of already -1 (no hits) or -2 (no track)
-  const int* lb = a.list + (long)b * a.H;
-  const DupKey kb = dup_key(a, b);
-  DupKey best{0, 0, 0.0f, -1};
+  const int own = b * H;
+  int4 kbest = make_int4(0, 0, 0, 0);
+  int best = -1;
   for (int k = 0; k < nb; ++k) {
-    const int h = lb[k];
-    const int e1 = a.off[h + 1];
-    for (int e = a.off[h]; e < e1; ++e) {
-      const int j = a.trk[e];
-      if (j == b) continue;
-      const DupKey kj = dup_key(a, j);
-      if (!ranks_above(kj, kb)) continue;
-      if (best.s >= 0 && !ranks_above(kj, best)) continue;
-      // merge the two ascending lists; the first common hit is their
-      // smallest, and when it lies below h the pair was judged at that hit
-      const int* lj = a.list + (long)j * a.H;
-      const int nj = a.len[j];
-      int x = 0, y = 0, shared = 0;
-      bool earlier = false;
-      while (x < nb && y < nj) {
-        const int u = lb[x], v = lj[y];
-        if (u == v) {
-          if (shared == 0 && u < h) {
-            earlier = true;
-            break;
-          }
-          ++shared, ++x, ++y;
-        } else if (u < v) {
-          ++x;
-        } else {
-          ++y;
-        }
+    const int h = lh[k * kDupBlock + t];
+    int e = a.head[h];
+    while (e >= 0) {
+      const int j = e / H;
+      if (j == b) {
+        e = ln[(e - own) * kDupBlock + t];
+        continue;
       }
-      if (earlier) continue;
-      const int shorter = nb < nj ? nb : nj;
-      if ((long)a.den * shared >= (long)a.num * shorter) best = kj;
+      const int en = a.next[e];
+      const int4 kj = a.key[j];
+      if (ranks_above(kj, j, kb, b) && (best < 0 || ranks_above(kj, j, kbest, best))) {
+        // merge the two ascending lists; the first common hit is their
+        // smallest, and when it lies below h the pair was judged there
+        const int* lj = a.list + (long)j * H;
+        const int nj = kj.w;
+        int x = 0, y = 0, shared = 0;
+        bool earlier = false;
+        int u = lh[t], v = nj > 0 ? lj[0] : 0;
+        while (x < nb && y < nj) {
+          if (u == v) {
+            if (shared == 0 && u < h) {
+              earlier = true;
+              break;
+            }
+            ++shared;
+            if (++x < nb) u = lh[x * kDupBlock + t];
+            if (++y < nj) v = lj[y];
+          } else if (u < v) {
+            if (++x < nb) u = lh[x * kDupBlock + t];
+          } else {
+            if (++y < nj) v = lj[y];
+          }
+        }
+        const int shorter = nb < nj ? nb : nj;
+        if (!earlier && (long)a.den * shared >= (long)a.num * shorter) best = j, kbest = kj;
+      }
+      e = en;
     }
   }
-  a.dup_of[b] = best.s;
+  a.dup_of[b] = best;
 }
 
 // ---------------------------------------------------------------- launchers
@@ -1221,14 +1277,13 @@ size_t fused_lds_bytes(int lanes, int threads, int max_steps) {
 }
 size_t fused_static_lds_bytes() { return sizeof(Geometry); }
 
-void launch_find_duplicates(const DupArgs& a, int* scan_scratch, hipStream_t st) {
+void launch_find_duplicates(const DupArgs& a, hipStream_t st) {
   if (a.S <= 0) return;
-  launch_fill(a.cnt, (long)a.n_hits + 1, 0, st);
-  hipLaunchKernelGGL(k_dup_lists, dim3((a.S + 63) / 64), dim3(64), (size_t)a.H * 64 * sizeof(int), st, a);
-  exclusive_scan(a.cnt, a.n_hits, a.off, scan_scratch, st);
-  const unsigned nb = (unsigned)((a.S + 255) / 256);
-  hipLaunchKernelGGL(k_dup_fill, dim3(nb), dim3(256), 0, st, a);
-  hipLaunchKernelGGL(k_dup_find, dim3(nb), dim3(256), 0, st, a);
+  launch_fill(a.head, a.n_hits, -1, st);
+  const int nblk = (a.S + kDupBlock - 1) / kDupBlock;
+  const dim3 grid((unsigned)(8 * ((nblk + 7) / 8)));
+  hipLaunchKernelGGL(k_dup_lists, grid, dim3(kDupBlock), (size_t)a.H * kDupBlock * sizeof(int), st, a, nblk);
+  hipLaunchKernelGGL(k_dup_find, grid, dim3(kDupBlock), (size_t)a.H * kDupBlock * 2 * sizeof(int), st, a, nblk);
 }
 
 }  // namespace kfx
