@@ -214,7 +214,7 @@ int kfx_build_tracks(kfx_ctx* ctx, const kfx_hits* hits, const int32_t* seeds,
  * is pairwise.  Output dup_of: device int32 [n_seeds]: -2 for a seed
  * without a candidate, -1 for a kept track, else the seed of the
  * highest-ranked track of which it is a duplicate.  Needs 0 < frac_num <=
- * frac_den, max_hits <= 128, capacity >= n_seeds * K; the workspace grows
+ * frac_den, max_hits <= 64, capacity >= n_seeds * K; the workspace grows
  * with n_seeds * max_hits and n_hits.  Deterministic. */
 int kfx_find_duplicates(kfx_ctx* ctx, const kfx_tracks* tracks, int32_t n_seeds, int32_t K, int32_t n_hits,
                         int32_t frac_num, int32_t frac_den, int32_t* dup_of, void* stream);

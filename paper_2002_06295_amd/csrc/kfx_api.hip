@@ -787,8 +787,7 @@ int kfx_find_duplicates(kfx_ctx* c, const kfx_tracks* tracks, int32_t n_seeds, i
   if (frac_num < 1 || frac_den < frac_num) return fail(c, KFX_EINVAL, "need 0 < frac_num <= frac_den");
   if (n_seeds == 0) return KFX_OK;
   const int H = tracks->max_hits;
-  if (H < 1 || H > 128 || (size_t)H * 64 * 2 * sizeof(int) > c->max_lds)
-    return fail(c, KFX_EINVAL, "max_hits outside 1..128");
+  if (H < 1 || H > 64) return fail(c, KFX_EINVAL, "max_hits outside 1..64");
   if (tracks->capacity < (int64_t)n_seeds * K) return fail(c, KFX_EINVAL, "capacity < n_seeds * K");
   if ((int64_t)n_seeds * H > INT32_MAX) return fail(c, KFX_EINVAL, "n_seeds * max_hits exceeds 2^31 - 1");
   if (!tracks->n_cands || !tracks->hits || !tracks->n_hits || !tracks->n_holes || !tracks->chi2 || !dup_of)

@@ -8,6 +8,8 @@
 // cloned with a per-seed cap).
 #include <hip/hip_runtime.h>
 
+#include <climits>
+
 #include "kfx_build.h"
 #include "kfx_internal.h"
 
@@ -949,18 +951,19 @@ k_build_fused(BuildArgs a, TracksOut o, int* seed_counter) {
 // least frac_num / frac_den of the shorter one (abstract and Sec. 3: the
 // duplicates the building produces are removed in a step of their own).
 //
-// Two passes over blocks of 64 tracks.  The first sorts each track's
-// distinct hits (in LDS, rows loaded and stored with coalesced accesses)
+// One wavefront per track, lane k on entry k of its list (at most 64).  The
+// first pass sorts the list across the lanes (bitonic network on shuffles),
+// drops repeats and non-hits (ballot compaction), stores the ascending list
 // and pushes every (track, hit) entry onto a per-hit linked list with one
 // atomic exchange (head[hit] -> entry -> next[entry] -> ...; entry =
-// track * H + position).  The second walks, for each hit of a track, the
-// list of the hit's other holders and merges the track's list with those of
-// the holders that rank above it.  Random accesses per entry: the exchange
-// and one read of head[hit]; the per-hit arrays span the whole batch, so
-// blocks are ordered so that each XCD (and its L2) works through one
-// contiguous range of seeds, i.e. of events and their hits.
+// track * H + position).  The second pass walks, lane per hit, the list of
+// the hit's other holders, merges the track's list with those of the
+// holders that rank above it, and reduces the lanes' best partners.  The
+// per-hit arrays span the whole batch, so blocks are ordered so that each
+// XCD (and its L2) works through one contiguous range of seeds, i.e. of
+// events and their hits.
 
-constexpr int kDupBlock = 64;
+constexpr int kDupRows = 4;  // tracks (wavefronts) per block
 
 // logical block of this workgroup when workgroups are dealt to the 8 XCDs
 // in turn: XCD x takes logical blocks [x * per, (x + 1) * per); -1 = idle
@@ -970,72 +973,52 @@ __device__ inline int xcd_block(int nblk) {
   return lb < nblk ? lb : -1;
 }
 
-// insertion into the ascending, repeat-free list held in LDS column
-// (stride kDupBlock); returns the new length
-__device__ inline int sorted_insert(int* col, int n, int h) {
-  int p = n;
-  while (p > 0 && col[(p - 1) * kDupBlock] > h) --p;
-  if (p > 0 && col[(p - 1) * kDupBlock] == h) return n;
-  for (int q = n; q > p; --q) col[q * kDupBlock] = col[(q - 1) * kDupBlock];
-  col[p * kDupBlock] = h;
-  return n + 1;
+// ascending sort of one value per lane over the 64 lanes
+__device__ inline int wave_sort_asc(int v, int lane) {
+#pragma unroll
+  for (int k = 2; k <= 64; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      const int o = __shfl_xor(v, j, 64);
+      const bool keep_min = ((lane & j) == 0) == ((lane & k) == 0);
+      v = keep_min ? min(v, o) : max(v, o);
+    }
+  }
+  return v;
 }
 
-__global__ void __launch_bounds__(kDupBlock) k_dup_lists(DupArgs a, int nblk) {
-  extern __shared__ int dup_lds[];  // [H][64]: column t holds track t's row
-  __shared__ int lens[kDupBlock];
+__global__ void __launch_bounds__(256) k_dup_lists(DupArgs a, int nblk) {
   const int lb = xcd_block(nblk);
   if (lb < 0) return;
-  const int t = threadIdx.x, H = a.H;
-  const int s0 = lb * kDupBlock;
-  const int nrow = min(kDupBlock, a.S - s0);
-  for (int i = t; i < nrow * H; i += kDupBlock) {
-    const int r = i / H, c = i - r * H;
-    dup_lds[c * kDupBlock + r] = a.hits[(long)(s0 + r) * a.K * H + c];
+  const int lane = threadIdx.x & 63;
+  const int b = lb * kDupRows + (int)(threadIdx.x >> 6);
+  if (b >= a.S) return;  // whole wavefront
+  const int H = a.H;
+  const int nc = a.n_cands[b];
+  int v = INT_MAX;
+  if (nc > 0 && lane < H) {
+    const int h = a.hits[(long)b * a.K * H + lane];
+    if (h >= 0 && h < a.n_hits) v = h;
   }
-  __syncthreads();
-  int* col = dup_lds + t;
-  int n = 0;
-  if (t < nrow) {
-    const int s = s0 + t;
-    const int nc = a.n_cands[s];
-    if (nc > 0) {
-      // in place: element k is read before any write reaches index k
-      for (int k = 0; k < H; ++k) {
-        const int h = col[k * kDupBlock];
-        if (h >= 0 && h < a.n_hits) n = sorted_insert(col, n, h);
-      }
-      const long e = (long)s * a.K;
-      a.key[s] = make_int4(a.n_hits_c[e], a.n_holes_c[e], __float_as_int(a.chi2_c[e]), n);
-    } else {
-      a.key[s] = make_int4(0, 0, 0, 0);
-    }
-    a.dup_of[s] = nc > 0 ? -1 : -2;
+  v = wave_sort_asc(v, lane);
+  const int prev = __shfl_up(v, 1, 64);
+  const bool keep = v != INT_MAX && (lane == 0 || v != prev);
+  const unsigned long long m = __ballot(keep);
+  const int n = __popcll(m);
+  const int pos = __popcll(m & ((1ull << lane) - 1ull));
+  int* row = a.list + (long)b * H;
+  // positions n..H-1 are cleared by their own lanes; kept lanes write below n
+  if (lane >= n && lane < H) row[lane] = -1;
+  if (keep) {
+    row[pos] = v;
+    const int e = b * H + pos;
+    a.next[e] = atomicExch(a.head + v, e);
   }
-  lens[t] = n;
-  __syncthreads();
-  int* lst = a.list + (long)s0 * H;
-  for (int i = t; i < nrow * H; i += kDupBlock) {
-    const int r = i / H, c = i - r * H;
-    lst[i] = c < lens[r] ? dup_lds[c * kDupBlock + r] : -1;
-  }
-  __syncthreads();
-  // push the entries; four exchanges in flight per thread
-  const int base = (s0 + t) * H;
-  for (int k = 0; k < n; k += 4) {
-    int old[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-      if (k + u < n) old[u] = atomicExch(a.head + col[(k + u) * kDupBlock], base + k + u);
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-      if (k + u < n) col[(k + u) * kDupBlock] = old[u];
-  }
-  __syncthreads();
-  int* nxt = a.next + (long)s0 * H;
-  for (int i = t; i < nrow * H; i += kDupBlock) {
-    const int r = i / H, c = i - r * H;
-    if (c < lens[r]) nxt[i] = dup_lds[c * kDupBlock + r];
+  if (lane == 0) {
+    const long e = (long)b * a.K;
+    a.key[b] = nc > 0 ? make_int4(a.n_hits_c[e], a.n_holes_c[e], __float_as_int(a.chi2_c[e]), n)
+                      : make_int4(0, 0, 0, 0);
+    a.dup_of[b] = nc > 0 ? -1 : -2;
   }
 }
 
@@ -1049,73 +1032,71 @@ __device__ inline bool ranks_above(const int4& x, int xs, const int4& y, int ys)
   return xs < ys;
 }
 
-__global__ void __launch_bounds__(kDupBlock) k_dup_find(DupArgs a, int nblk) {
-  extern __shared__ int dup_lds[];  // [2][H][64]: own sorted hits, own next
+__global__ void __launch_bounds__(256) k_dup_find(DupArgs a, int nblk) {
   const int lb = xcd_block(nblk);
   if (lb < 0) return;
-  const int t = threadIdx.x, H = a.H;
-  const int s0 = lb * kDupBlock;
-  const int nrow = min(kDupBlock, a.S - s0);
-  int* lh = dup_lds;
-  int* ln = dup_lds + H * kDupBlock;
-  const int* lst = a.list + (long)s0 * H;
-  const int* nx = a.next + (long)s0 * H;
-  for (int i = t; i < nrow * H; i += kDupBlock) {
-    const int r = i / H, c = i - r * H;
-    const int h = lst[i];
-    lh[c * kDupBlock + r] = h;
-    ln[c * kDupBlock + r] = h >= 0 ? nx[i] : -1;
-  }
-  __syncthreads();
-  if (t >= nrow) return;
-  const int b = s0 + t;
+  const int lane = threadIdx.x & 63;
+  const int b = lb * kDupRows + (int)(threadIdx.x >> 6);
+  if (b >= a.S) return;  // whole wavefront
   const int4 kb = a.key[b];
   const int nb = kb.w;
   if (nb == 0) return;  // dup_of already -1 (no hits) or -2 (no track)
-  const int own = b * H;
-  int4 kbest = make_int4(0, 0, 0, 0);
+  const int H = a.H;
+  const int* lbp = a.list + (long)b * H;
   int best = -1;
-  for (int k = 0; k < nb; ++k) {
-    const int h = lh[k * kDupBlock + t];
+  int4 kbest = make_int4(0, 0, 0, 0);
+  if (lane < nb) {
+    const int h = lbp[lane];
     int e = a.head[h];
     while (e >= 0) {
       const int j = e / H;
-      if (j == b) {
-        e = ln[(e - own) * kDupBlock + t];
-        continue;
-      }
       const int en = a.next[e];
-      const int4 kj = a.key[j];
-      if (ranks_above(kj, j, kb, b) && (best < 0 || ranks_above(kj, j, kbest, best))) {
-        // merge the two ascending lists; the first common hit is their
-        // smallest, and when it lies below h the pair was judged there
-        const int* lj = a.list + (long)j * H;
-        const int nj = kj.w;
-        int x = 0, y = 0, shared = 0;
-        bool earlier = false;
-        int u = lh[t], v = nj > 0 ? lj[0] : 0;
-        while (x < nb && y < nj) {
-          if (u == v) {
-            if (shared == 0 && u < h) {
-              earlier = true;
-              break;
+      if (j != b) {
+        const int4 kj = a.key[j];
+        if (ranks_above(kj, j, kb, b) && (best < 0 || ranks_above(kj, j, kbest, best))) {
+          // merge the two ascending lists; the first common hit is their
+          // smallest, and when it lies below h the pair was judged there
+          const int* lj = a.list + (long)j * H;
+          const int nj = kj.w;
+          int x = 0, y = 0, shared = 0;
+          bool earlier = false;
+          int u = lbp[0], w = lj[0];
+          while (x < nb && y < nj) {
+            if (u == w) {
+              if (shared == 0 && u < h) {
+                earlier = true;
+                break;
+              }
+              ++shared;
+              if (++x < nb) u = lbp[x];
+              if (++y < nj) w = lj[y];
+            } else if (u < w) {
+              if (++x < nb) u = lbp[x];
+            } else {
+              if (++y < nj) w = lj[y];
             }
-            ++shared;
-            if (++x < nb) u = lh[x * kDupBlock + t];
-            if (++y < nj) v = lj[y];
-          } else if (u < v) {
-            if (++x < nb) u = lh[x * kDupBlock + t];
-          } else {
-            if (++y < nj) v = lj[y];
           }
+          const int shorter = nb < nj ? nb : nj;
+          if (!earlier && (long)a.den * shared >= (long)a.num * shorter) best = j, kbest = kj;
         }
-        const int shorter = nb < nj ? nb : nj;
-        if (!earlier && (long)a.den * shared >= (long)a.num * shorter) best = j, kbest = kj;
       }
       e = en;
     }
   }
-  a.dup_of[b] = best;
+  // the highest-ranked of the lanes' partners
+  unsigned long long m = __ballot(best >= 0);
+  if (m == 0) return;  // dup_of stays -1
+  int g = -1;
+  int4 kg = make_int4(0, 0, 0, 0);
+  while (m) {
+    const int l = __ffsll((long long)m) - 1;
+    m &= m - 1ull;
+    const int j = __shfl(best, l, 64);
+    const int4 kj = make_int4(__shfl(kbest.x, l, 64), __shfl(kbest.y, l, 64), __shfl(kbest.z, l, 64),
+                              __shfl(kbest.w, l, 64));
+    if (g < 0 || ranks_above(kj, j, kg, g)) g = j, kg = kj;
+  }
+  if (lane == 0) a.dup_of[b] = g;
 }
 
 // ---------------------------------------------------------------- launchers
@@ -1280,10 +1261,10 @@ size_t fused_static_lds_bytes() { return sizeof(Geometry); }
 void launch_find_duplicates(const DupArgs& a, hipStream_t st) {
   if (a.S <= 0) return;
   launch_fill(a.head, a.n_hits, -1, st);
-  const int nblk = (a.S + kDupBlock - 1) / kDupBlock;
+  const int nblk = (a.S + kDupRows - 1) / kDupRows;
   const dim3 grid((unsigned)(8 * ((nblk + 7) / 8)));
-  hipLaunchKernelGGL(k_dup_lists, grid, dim3(kDupBlock), (size_t)a.H * kDupBlock * sizeof(int), st, a, nblk);
-  hipLaunchKernelGGL(k_dup_find, grid, dim3(kDupBlock), (size_t)a.H * kDupBlock * 2 * sizeof(int), st, a, nblk);
+  hipLaunchKernelGGL(k_dup_lists, grid, dim3(64 * kDupRows), 0, st, a, nblk);
+  hipLaunchKernelGGL(k_dup_find, grid, dim3(64 * kDupRows), 0, st, a, nblk);
 }
 
 }  // namespace kfx

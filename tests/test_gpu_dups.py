@@ -60,10 +60,10 @@ def test_golden(ctx, frac):
 
 # (seeds, K, max_hits, hits in the batch, fraction, generator seed): sizes
 # around the 64-track blocks, K at 1 and 16,
-# list capacities 3 and 128, no hits at all, heavy sharing (few hits)
+# list capacities 3 and 64, no hits at all, heavy sharing (few hits)
 CASES = [
     (1, 1, 48, 10, 1, 2, 0), (63, 6, 48, 100, 1, 2, 1), (64, 6, 48, 100, 1, 3, 2), (65, 16, 48, 500, 2, 3, 3),
-    (257, 1, 3, 50, 1, 2, 4), (1000, 6, 128, 4000, 1, 2, 5), (3000, 10, 48, 40, 1, 100, 6),
+    (257, 1, 3, 50, 1, 2, 4), (1000, 6, 64, 4000, 1, 2, 5), (3000, 10, 48, 40, 1, 100, 6),
     (2000, 6, 48, 0, 1, 2, 7), (20000, 6, 48, 200000, 1, 2, 8), (5000, 6, 64, 20000, 1, 1, 9),
 ]
 
@@ -117,7 +117,7 @@ def test_empty_and_errors(ctx, kfx):
     bad["K"] = 17
     with pytest.raises(kfx.KfxError):
         ctx.find_duplicates(bad, 100)
-    wide = kfsynth.track_lists(4, 1, 300, 100, seed=2)
+    wide = kfsynth.track_lists(4, 1, 65, 100, seed=2)
     out = ctx.tracks_from_arrays(wide["n_cands"], wide["hits"], wide["n_hits"], wide["n_holes"], wide["chi2"], 1)
     with pytest.raises(kfx.KfxError):
         ctx.find_duplicates(out, 100)
