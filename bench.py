@@ -357,6 +357,56 @@ def main():
         log(f"[bench] duplicate removal: {dms * 1e3:.1f} us, flagged {(dres >= 0).sum()} of "
             f"{extra.size} extra seeds")
         del dout
+        # two iterations: the first from half of the particles (even ids);
+        # the hits of its good tracks (kept, >= 8 hits, chi2/ndof <= 3)
+        # masked; the second from a second seed (hits 1, 2, 4) of the
+        # particles whose seed hits are all free, with and without the mask
+        half = np.arange(0, ev.n_tracks, 2)
+        out1 = ctx.build_tracks(hits, torch.as_tensor(ev.seeds[half], device=dev),
+                                torch.as_tensor(ev.trk_event[half].astype(np.int32), device=dev),
+                                **build_kw(ev, kfx.MODE_FUSED), **shape)
+        dup1 = ctx.find_duplicates(out1, ev.n_hits)
+        lay2 = ctx.mask_hits(out1, hits.layer, dup1, 8, 3.0)
+        torch.cuda.synchronize()
+        m0, m1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        m0.record()
+        for _ in range(20):
+            ctx.mask_hits(out1, hits.layer, dup1, 8, 3.0, layer_out=lay2)
+        m1.record()
+        torch.cuda.synchronize()
+        mask_ms = m0.elapsed_time(m1) / 20
+        lay2_h = lay2.cpu().numpy()
+        s2, e2_, _ = kfsynth.duplicate_seeds(ev, 1.0, seed=0)
+        s2, e2_ = s2[ev.n_tracks:], e2_[ev.n_tracks:]
+        free = (lay2_h[s2] >= 0).all(axis=1)
+        s2, e2_ = s2[free], e2_[free]
+        n_s2 = int(s2.shape[0])
+        s2 = torch.as_tensor(s2, device=dev)
+        e2_ = torch.as_tensor(e2_, device=dev)
+        hits_m = kfx.DeviceHits(hits.x, hits.y, hits.z, lay2, hits.event_offsets)
+        it2 = {}
+        for tag, hh in (("masked", hits_m), ("unmasked", hits)):
+            o2i = ctx.build_tracks(hh, s2, e2_, **build_kw(ev, kfx.MODE_FUSED), **shape)
+            st2 = o2i["stats"]
+            st2.zero_()
+            t2a, t2b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            t2a.record()
+            for _ in range(10):
+                ctx.build_tracks(hh, s2, e2_, **build_kw(ev, kfx.MODE_FUSED), **shape, out=o2i)
+            t2b.record()
+            torch.cuda.synchronize()
+            st = st2.cpu().numpy() / 10
+            it2[tag] = {"ms": t2a.elapsed_time(t2b) / 10, "steps": float(st[0]), "pairs": float(st[1])}
+            del o2i
+        sec["second_iteration"] = {
+            "workload": "build5k: iteration 1 from the first three hits of half of the particles; "
+                        "iteration 2 from hits 1, 2, 4 of the particles whose seed hits the mask left free",
+            "mask_ms": mask_ms, "hits_masked": int((lay2_h == -1).sum()) - int((ev.layer < 0).sum()),
+            "hits": ev.n_hits, "seeds_iteration2": n_s2, "iteration2": it2}
+        log(f"[bench] second iteration: mask {mask_ms * 1e3:.1f} us, {sec['second_iteration']['hits_masked']} "
+            f"hits masked, {n_s2} seeds: {it2['masked']['ms']:.3f} ms masked vs "
+            f"{it2['unmasked']['ms']:.3f} ms unmasked")
+        del out1
         for name in ("batch256", "occ10k"):
             if name == args.workload:
                 continue

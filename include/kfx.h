@@ -219,6 +219,19 @@ int kfx_build_tracks(kfx_ctx* ctx, const kfx_hits* hits, const int32_t* seeds,
 int kfx_find_duplicates(kfx_ctx* ctx, const kfx_tracks* tracks, int32_t n_seeds, int32_t K, int32_t n_hits,
                         int32_t frac_num, int32_t frac_den, int32_t* dup_of, void* stream);
 
+/* Hit masking between iterations (Sec. 3: the hits used by tracks of good
+ * quality are masked before the next iteration, which then searches fewer
+ * hits).  Writes layer_out (device int32 [n_hits]) = layer_in, with -1 (a
+ * hit every call ignores) at each valid hit index (0 <= h < n_hits) of the
+ * hit list of every good track; layer_out may equal layer_in (in place).
+ * A track is slot 0 of a seed with n_cands > 0 (layout as for
+ * kfx_find_duplicates); it is good when dup_of is NULL or dup_of[s] == -1,
+ * n_hits >= min_hits and chi2 <= max_chi2_ndof * (2 n_hits - 5), that
+ * product formed in float32.  Deterministic (every write stores -1). */
+int kfx_mask_hits(kfx_ctx* ctx, const kfx_tracks* tracks, int32_t n_seeds, int32_t K, const int32_t* dup_of,
+                  int32_t min_hits, float max_chi2_ndof, const int32_t* layer_in, int32_t* layer_out,
+                  int32_t n_hits, void* stream);
+
 /* Track fit (Sec. 1): the Kalman filter over fixed hit lists.  trk_off:
  * device int32 [n_tracks+1] into trk_hits (device int32 hit indices in
  * crossing order).  Starts at hit 1 from the three-hit estimate with the

@@ -1,5 +1,6 @@
-"""Duplicate removal after building, written out plainly (test
-infrastructure only, like the rest of this package).
+"""Duplicate removal after building, and the hit masking between
+iterations, written out plainly (test infrastructure only, like the rest of
+this package).
 
 The paper (abstract; Sec. 3) states that the building used to produce too
 many duplicate tracks and that these are now removed in a separate step
@@ -110,3 +111,35 @@ def find_duplicates(n_cands, hits, n_hits, n_holes, chi2, K, n_hits_total,
                     best = a
         dup_of[b] = best
     return dup_of
+
+
+def mask_hits(n_cands, hits, n_hits, chi2, K, layer, dup_of=None, min_hits=8,
+              max_chi2_ndof=3.0):
+    """Hits of high-quality tracks masked for the next iteration (Sec. 3:
+    later iterations run on the hits that the tracks of good quality found
+    by earlier ones did not use).  Reading: a track (slot 0 of a seed with
+    candidates) is good when it is kept by duplicate removal (dup_of == -1;
+    every track when dup_of is None), has n_hits >= min_hits and chi2 <=
+    max_chi2_ndof * (2 n_hits - 5), the product formed in float32.  Returns
+    a copy of `layer` (int32 [n_hits_total]) with -1 at every valid hit of
+    a good track."""
+    n_cands = np.asarray(n_cands)
+    hits = np.asarray(hits)
+    out = np.array(layer, dtype=np.int32, copy=True)
+    NH = out.shape[0]
+    S = n_cands.shape[0]
+    for s in range(S):
+        if n_cands[s] <= 0:
+            continue
+        if dup_of is not None and int(dup_of[s]) != KEPT:
+            continue
+        nh = int(n_hits[s * K])
+        if nh < min_hits:
+            continue
+        cut = np.float32(max_chi2_ndof) * np.float32(2 * nh - 5)
+        if not (np.float32(chi2[s * K]) <= cut):
+            continue
+        for h in hits[s * K]:
+            if 0 <= int(h) < NH:
+                out[int(h)] = -1
+    return out

@@ -817,6 +817,40 @@ int kfx_find_duplicates(kfx_ctx* c, const kfx_tracks* tracks, int32_t n_seeds, i
   return hip_check(c, hipGetLastError(), "duplicate removal kernels");
 }
 
+int kfx_mask_hits(kfx_ctx* c, const kfx_tracks* tracks, int32_t n_seeds, int32_t K, const int32_t* dup_of,
+                  int32_t min_hits, float max_chi2_ndof, const int32_t* layer_in, int32_t* layer_out,
+                  int32_t n_hits, void* stream) {
+  if (!c) return KFX_EINVAL;
+  c->err.clear();
+  if (!tracks) return fail(c, KFX_EINVAL, "tracks is NULL");
+  if (n_seeds < 0 || n_hits < 0) return fail(c, KFX_EINVAL, "n_seeds < 0 or n_hits < 0");
+  if (K < 1 || K > KFX_MAX_CANDS) return fail(c, KFX_EINVAL, "K outside 1..KFX_MAX_CANDS");
+  if (std::isnan(max_chi2_ndof)) return fail(c, KFX_EINVAL, "max_chi2_ndof is NaN");
+  if (n_hits > 0 && (!layer_in || !layer_out)) return fail(c, KFX_EINVAL, "NULL layer arrays");
+  if (n_seeds > 0) {
+    if (tracks->max_hits < 1) return fail(c, KFX_EINVAL, "max_hits < 1");
+    if (tracks->capacity < (int64_t)n_seeds * K) return fail(c, KFX_EINVAL, "capacity < n_seeds * K");
+    if (!tracks->n_cands || !tracks->hits || !tracks->n_hits || !tracks->chi2)
+      return fail(c, KFX_EINVAL, "NULL track arrays");
+  }
+  DeviceGuard dg(c->device);
+  MaskArgs a;
+  a.n_cands = tracks->n_cands;
+  a.hits = tracks->hits;
+  a.n_hits_c = tracks->n_hits;
+  a.chi2_c = tracks->chi2;
+  a.dup_of = dup_of;
+  a.S = n_seeds;
+  a.K = K;
+  a.H = tracks->max_hits;
+  a.n_hits = n_hits;
+  a.min_hits = min_hits;
+  a.max_chi2_ndof = max_chi2_ndof;
+  a.layer_out = layer_out;
+  launch_mask_hits(a, layer_in, (hipStream_t)stream);
+  return hip_check(c, hipGetLastError(), "hit masking kernels");
+}
+
 int kfx_fit_tracks(kfx_ctx* c, const kfx_hits* hits, const int32_t* trk_off, const int32_t* trk_hits,
                    int32_t n_tracks, const kfx_prior* prior, const float* align, float field_scale,
                    kfx_states* out, float* chi2, int32_t* ndof, int32_t* status, kfx_states* ckpt, void* stream) {

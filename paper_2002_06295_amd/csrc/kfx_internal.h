@@ -37,6 +37,19 @@ struct DupArgs {
   int* dup_of;           // [S] output
 };
 
+// Hit masking between iterations over slot 0 of every seed.
+struct MaskArgs {
+  const int* n_cands;    // [S]
+  const int* hits;       // [S*K][H]
+  const int* n_hits_c;   // [S*K]
+  const float* chi2_c;   // [S*K]
+  const int* dup_of;     // [S] or NULL (every track counts as kept)
+  int S, K, H, n_hits;
+  int min_hits;
+  float max_chi2_ndof;
+  int* layer_out;        // [n_hits]
+};
+
 void launch_fill(int* p, long n, int v, hipStream_t st);
 void exclusive_scan(const int* in, long n, int* out, int* scratch, hipStream_t st);
 void launch_bin(const Geometry* G, const HitsView& H, int n_layers, int n_bins, BinWork& w, int* bin_out,
@@ -65,5 +78,6 @@ void launch_build_fused(const BuildArgs& a, const TracksOut& o, int* seed_counte
                         int lanes, int waves_per_simd, hipStream_t st, const hipEvent_t* ev);
 int fused_lanes_for(int K);
 void launch_find_duplicates(const DupArgs& a, hipStream_t st);
+void launch_mask_hits(const MaskArgs& a, const int* layer_in, hipStream_t st);
 
 }  // namespace kfx

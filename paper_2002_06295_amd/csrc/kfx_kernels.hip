@@ -8,6 +8,7 @@
 // cloned with a per-seed cap).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <climits>
 
 #include "kfx_build.h"
@@ -1099,6 +1100,34 @@ __global__ void __launch_bounds__(256) k_dup_find(DupArgs a, int nblk) {
   if (lane == 0) a.dup_of[b] = g;
 }
 
+// ------------------------------------------------ hit masking (iterations)
+// Between iterations the hits of good tracks are taken out of the next
+// iteration's input (Sec. 3): a copy of the layer array with -1 (no layer:
+// ignored by every call) at the valid hits of every good track.  Good: a
+// kept track (dup_of -1, or any track without dup_of) with n_hits >=
+// min_hits and chi2 <= max_chi2_ndof * (2 n_hits - 5) in float32.
+
+__global__ void __launch_bounds__(256) k_copy_i32(const int* __restrict__ in, int* __restrict__ out, long n) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) out[i] = in[i];
+}
+
+// one thread per list entry of slot 0
+__global__ void __launch_bounds__(256) k_mask_hits(MaskArgs a) {
+  const long n = (long)a.S * a.H;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const int s = (int)(i / a.H), k = (int)(i - (long)s * a.H);
+    if (a.n_cands[s] <= 0) continue;
+    if (a.dup_of && a.dup_of[s] != -1) continue;
+    const long e = (long)s * a.K;
+    const int nh = a.n_hits_c[e];
+    if (nh < a.min_hits) continue;
+    const float cut = a.max_chi2_ndof * (float)(2 * nh - 5);
+    if (!(a.chi2_c[e] <= cut)) continue;
+    const int h = a.hits[e * a.H + k];
+    if (h >= 0 && h < a.n_hits) a.layer_out[h] = -1;
+  }
+}
+
 // ---------------------------------------------------------------- launchers
 static inline unsigned nblk(long n, int b) { return (unsigned)((n + b - 1) / b); }
 
@@ -1265,6 +1294,17 @@ void launch_find_duplicates(const DupArgs& a, hipStream_t st) {
   const dim3 grid((unsigned)(8 * ((nblk + 7) / 8)));
   hipLaunchKernelGGL(k_dup_lists, grid, dim3(64 * kDupRows), 0, st, a, nblk);
   hipLaunchKernelGGL(k_dup_find, grid, dim3(64 * kDupRows), 0, st, a, nblk);
+}
+
+void launch_mask_hits(const MaskArgs& a, const int* layer_in, hipStream_t st) {
+  if (a.n_hits > 0 && layer_in != a.layer_out) {
+    const long nb = std::min<long>(((long)a.n_hits + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_copy_i32, dim3((unsigned)nb), dim3(256), 0, st, layer_in, a.layer_out, (long)a.n_hits);
+  }
+  const long n = (long)a.S * a.H;
+  if (n <= 0 || a.n_hits <= 0) return;
+  const long nb = std::min<long>((n + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_mask_hits, dim3((unsigned)nb), dim3(256), 0, st, a);
 }
 
 }  // namespace kfx

@@ -30,7 +30,7 @@ MAX_STEPS = 40
 EXPORTED = ["kfx_create", "kfx_destroy", "kfx_last_error", "kfx_load_layers", "kfx_bin_hits",
             "kfx_seed_states", "kfx_step_compat", "kfx_build_tracks", "kfx_fit_tracks",
             "kfx_fit_tracks_backward", "kfx_enable_timing", "kfx_build_times", "kfx_build_graph",
-            "kfx_graph_launch", "kfx_graph_destroy", "kfx_autotune_build", "kfx_find_duplicates"]
+            "kfx_graph_launch", "kfx_graph_destroy", "kfx_autotune_build", "kfx_find_duplicates", "kfx_mask_hits"]
 
 
 class c_states(ctypes.Structure):
@@ -117,6 +117,9 @@ def load_library():
     lib.kfx_find_duplicates.argtypes = [ctypes.c_void_p, ctypes.POINTER(c_tracks), ctypes.c_int32,
                                         ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                         ctypes.c_void_p, ctypes.c_void_p]
+    lib.kfx_mask_hits.argtypes = [ctypes.c_void_p, ctypes.POINTER(c_tracks), ctypes.c_int32, ctypes.c_int32,
+                                  ctypes.c_void_p, ctypes.c_int32, ctypes.c_float, ctypes.c_void_p,
+                                  ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]
     lib.kfx_enable_timing.argtypes = [ctypes.c_void_p, ctypes.c_int]
     lib.kfx_build_times.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
     for name in EXPORTED:
@@ -442,6 +445,21 @@ class Context:
                                                  int(n_hits), int(frac[0]), int(frac[1]), _ptr(dup_of),
                                                  self._stream()))
         return dup_of[:S]
+
+    def mask_hits(self, out, layer, dup_of=None, min_hits=8, max_chi2_ndof=3.0, layer_out=None, n_seeds=None):
+        """Layer array for the next iteration (device int32 [n_hits]): a copy
+        of `layer` with -1 at the hits of the good tracks of the building
+        output `out` (see kfx_mask_hits in kfx.h).  layer_out may be `layer`
+        itself."""
+        import torch
+        S = out["S"] if n_seeds is None else int(n_seeds)
+        if layer_out is None:
+            layer_out = torch.empty_like(layer)
+        self._check(self.lib.kfx_mask_hits(self.h, ctypes.byref(out["_struct"]), S, int(out["K"]),
+                                           None if dup_of is None else _ptr(dup_of), int(min_hits),
+                                           float(max_chi2_ndof), _ptr(layer), _ptr(layer_out),
+                                           int(layer.numel()), self._stream()))
+        return layer_out
 
     def fit_tracks(self, hits: DeviceHits, trk_off, trk_hits, prior=(0.1, 0.5, 0.05, 0.05), align=None,
                    field_scale=1.0, ckpt=False, out=None):

@@ -1,12 +1,15 @@
-"""Pins of the duplicate-removal oracle (abstract and Sec. 3: duplicates
-left by building are removed in a step of their own; the criterion is the
-reading in oracle/duplicates.py).
+"""Pins of the duplicate-removal and hit-masking oracle (abstract and
+Sec. 3: duplicates left by building are removed in a step of their own, and
+the hits of good tracks are masked before the next iteration; the criteria
+are the readings in oracle/duplicates.py).
 
 Pinned by: a small case worked out by hand (tests/golden), an independent
 brute force (incidence-matrix product for the shared counts, lexsort for the
 rank), properties that any correct result has (monotone in the fraction,
 containment at fraction 1, relabelling), and the physics of the synthetic
 events (a second seed of the same particle is flagged, the original kept).
+The masking is pinned by a hand-worked case on the same fixture and by
+monotonicity, idempotence and the set of masked hits.
 """
 import json
 import os
@@ -166,3 +169,53 @@ def test_second_seed_of_a_particle_is_flagged():
     # tracks of particles seeded once are rarely flagged
     once = ~np.isin(np.arange(T), seed_track[extra])
     assert np.mean(got[:T][once] >= 0) < 0.1
+
+
+# ------------------------------------------------------------ hit masking
+# Sec. 3: the hits of good tracks are masked before the next iteration.
+
+def _golden_mask_inputs():
+    d = _golden()
+    t = {k: np.array(d[k]) for k in ("n_cands", "hits", "n_hits", "n_holes", "chi2")}
+    dup = np.array(d["expected"]["1/2"], np.int32)
+    layer = (np.arange(d["n_hits_total"]) % 7).astype(np.int32)
+    return d, t, dup, layer
+
+
+@pytest.mark.parametrize("cut", ["3.0", "1.0"])
+def test_mask_golden_hand_worked(cut):
+    d, t, dup, layer = _golden_mask_inputs()
+    out = D.mask_hits(t["n_cands"], t["hits"], t["n_hits"], t["chi2"], d["K"], layer, dup,
+                      d["mask"]["min_hits"], float(cut))
+    masked = np.nonzero(out == -1)[0].tolist()
+    assert masked == d["mask"]["expected_masked"][cut]
+    keep = out != -1
+    np.testing.assert_array_equal(out[keep], layer[keep])
+
+
+def test_mask_properties():
+    NH, K = 2000, 6
+    t = kfsynth.track_lists(500, K, 48, NH, seed=3, chi2_levels=8)
+    layer = np.random.default_rng(0).integers(0, 35, NH).astype(np.int32)
+    dup = D.find_duplicates(t["n_cands"], t["hits"], t["n_hits"], t["n_holes"], t["chi2"], K, NH)
+    m = lambda **kw: D.mask_hits(t["n_cands"], t["hits"], t["n_hits"], t["chi2"], K, layer, **kw)
+    a = m(dup_of=dup, min_hits=4, max_chi2_ndof=1.0)
+    b = m(dup_of=dup, min_hits=4, max_chi2_ndof=2.0)
+    # a looser chi2 cut masks a superset; never unmasks; masking is idempotent
+    assert ((a == -1) <= (b == -1)).all() and (a == -1).sum() < (b == -1).sum()
+    again = D.mask_hits(t["n_cands"], t["hits"], t["n_hits"], t["chi2"], K, a, dup, 4, 1.0)
+    np.testing.assert_array_equal(again, a)
+    # no duplicate list: every track counts as kept
+    allk = np.where(t["n_cands"] > 0, -1, -2).astype(np.int32)
+    np.testing.assert_array_equal(m(dup_of=None, min_hits=4, max_chi2_ndof=2.0),
+                                  m(dup_of=allk, min_hits=4, max_chi2_ndof=2.0))
+    # an unreachable hit count masks nothing
+    np.testing.assert_array_equal(m(dup_of=dup, min_hits=10**6, max_chi2_ndof=1e9), layer)
+    # masked hits all lie on tracks that pass the cut
+    sets = D.track_hit_sets(t["n_cands"], t["hits"], K, NH)
+    on_good = set()
+    for s, hs in enumerate(sets):
+        if hs is not None and dup[s] == -1 and t["n_hits"][s * K] >= 4 and \
+                t["chi2"][s * K] <= np.float32(2.0) * np.float32(2 * t["n_hits"][s * K] - 5):
+            on_good |= hs
+    assert set(np.nonzero(b == -1)[0].tolist()) == on_good
