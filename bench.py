@@ -407,6 +407,32 @@ def main():
             f"hits masked, {n_s2} seeds: {it2['masked']['ms']:.3f} ms masked vs "
             f"{it2['unmasked']['ms']:.3f} ms unmasked")
         del out1
+        # strip clustering: 16 events of the full strip detector in one call,
+        # and one event alone
+        sdet = kfsynth.strip_detector()
+        sev = kfsynth.strip_events(sdet, 16, seed=7)
+        sd16, scal = ctx.strip_inputs(sev, sdet)
+        one = {k: v[:int(sev["event_offsets"][1])] for k, v in sev.items() if k != "event_offsets"}
+        one["event_offsets"] = sev["event_offsets"][:2]
+        sd1, _ = ctx.strip_inputs(one, sdet)
+        strip = {"workload": "16 events of 15,000 modules x 768 strips, 20,000 particles and 1 % noise "
+                             "digis per event", "digis": int(sev["module"].shape[0])}
+        for tag, dg in (("batch16", sd16), ("one_event", sd1)):
+            so = ctx.cluster_strips(dg, scal)
+            torch.cuda.synchronize()
+            c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            c0.record()
+            for _ in range(20):
+                ctx.cluster_strips(dg, scal, out=so)
+            c1.record()
+            torch.cuda.synchronize()
+            ms_c = c0.elapsed_time(c1) / 20
+            nd = int(dg["module"].numel())
+            strip[tag] = {"ms": ms_c, "digis": nd, "digis_per_s": nd / (ms_c * 1e-3),
+                          "clusters": int(so["n"].cpu()[0])}
+        sec["strip_clustering"] = strip
+        log(f"[bench] strip clustering: 16 events {strip['batch16']['ms'] * 1e3:.0f} us "
+            f"({strip['batch16']['digis_per_s']:.3e} digis/s), one event {strip['one_event']['ms'] * 1e3:.0f} us")
         for name in ("batch256", "occ10k"):
             if name == args.workload:
                 continue

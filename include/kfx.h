@@ -232,6 +232,63 @@ int kfx_mask_hits(kfx_ctx* ctx, const kfx_tracks* tracks, int32_t n_seeds, int32
                   int32_t min_hits, float max_chi2_ndof, const int32_t* layer_in, int32_t* layer_out,
                   int32_t n_hits, void* stream);
 
+/* Silicon-strip digis of a batch of events (device).  Digis of event e are
+ * [event_offsets[e], event_offsets[e+1]), sorted by (module, strip) with at
+ * most one digi per strip; a digi whose (module, strip) lies outside the
+ * calibration table is ignored. */
+typedef struct {
+  const int32_t* module;
+  const int32_t* strip;
+  const uint16_t* adc;
+  const int32_t* event_offsets; /* [n_events + 1] */
+  int32_t n;
+  int32_t n_events;
+} kfx_digis;
+
+/* Calibration of the strip modules (device): noise in ADC counts and a bad
+ * flag (nonzero = bad) per strip, index module * strips_per_module + strip. */
+typedef struct {
+  const float* noise;
+  const uint8_t* bad;
+  int32_t n_modules;
+  int32_t strips_per_module;
+} kfx_strip_calib;
+
+typedef struct {
+  float seed_thr;    /* seed strip: adc > seed_thr * noise (3)               */
+  float chan_thr;    /* cluster strip: adc > chan_thr * noise (2), not bad   */
+  float clus_thr;    /* kept: sum adc^2 > clus_thr^2 * sum noise^2 (5)       */
+  int32_t max_gap;   /* strips between two cluster strips, all bad (1)      */
+  int32_t min_charge;/* kept: sum adc >= min_charge                         */
+} kfx_cluster_params;
+
+/* Kept clusters (device, caller-owned), in (event, module, first strip)
+ * order. */
+typedef struct {
+  int32_t* event;
+  int32_t* module;
+  int32_t* first;      /* first strip                                      */
+  int32_t* size;       /* last - first + 1 (bridged bad strips included)   */
+  int32_t* charge;     /* sum of the ADCs                                  */
+  float* barycenter;   /* sum(strip * adc) / sum(adc), float64 divide      */
+  int32_t capacity;
+  int32_t* n_out;      /* device int32 [1]: number of kept clusters; those
+                          beyond capacity are counted but not written      */
+} kfx_clusters;
+
+/* Strip clustering (Sec. 4: the clustering of silicon-strip data ported to
+ * GPUs for the HLT; thresholds and the gap rule as read in
+ * kfx_cluster_params).  Two consecutive cluster strips of a module (in
+ * digi order) join when at most max_gap strips lie between them and all
+ * of those are bad; a cluster is a maximal chain and is kept when it holds
+ * a seed strip, sum adc^2 > clus_thr^2 * sum noise^2 (noise^2 summed in
+ * float64 in strip order) and sum adc >= min_charge.  All events of the
+ * batch in one pass; deterministic.  KFX_EINVAL for bad sizes, NULL arrays,
+ * non-finite or negative thresholds, max_gap outside 0..64, or
+ * n_modules * strips_per_module >= 2^31. */
+int kfx_cluster_strips(kfx_ctx* ctx, const kfx_digis* digis, const kfx_strip_calib* calib,
+                       const kfx_cluster_params* params, kfx_clusters* out, void* stream);
+
 /* Track fit (Sec. 1): the Kalman filter over fixed hit lists.  trk_off:
  * device int32 [n_tracks+1] into trk_hits (device int32 hit indices in
  * crossing order).  Starts at hit 1 from the three-hit estimate with the

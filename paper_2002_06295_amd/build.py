@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libkfx.so")
-SOURCES = ["kfx_kernels.hip", "kfx_api.hip"]
+SOURCES = ["kfx_kernels.hip", "kfx_strips.hip", "kfx_api.hip"]
 HEADERS = ["kfx_math.h", "kfx_work.h", "kfx_build.h", "kfx_internal.h"]
 ARCH = os.environ.get("KFX_OFFLOAD_ARCH", "gfx950")
 FLAGS = [

@@ -851,6 +851,59 @@ int kfx_mask_hits(kfx_ctx* c, const kfx_tracks* tracks, int32_t n_seeds, int32_t
   return hip_check(c, hipGetLastError(), "hit masking kernels");
 }
 
+int kfx_cluster_strips(kfx_ctx* c, const kfx_digis* d, const kfx_strip_calib* cal, const kfx_cluster_params* p,
+                       kfx_clusters* out, void* stream) {
+  if (!c) return KFX_EINVAL;
+  c->err.clear();
+  if (!d || !cal || !p || !out) return fail(c, KFX_EINVAL, "NULL argument");
+  if (d->n < 0 || d->n_events < 1 || !d->event_offsets) return fail(c, KFX_EINVAL, "bad digi sizes");
+  if (d->n > 0 && (!d->module || !d->strip || !d->adc)) return fail(c, KFX_EINVAL, "NULL digi arrays");
+  if (cal->n_modules < 1 || cal->strips_per_module < 1 ||
+      (int64_t)cal->n_modules * cal->strips_per_module >= INT32_MAX)
+    return fail(c, KFX_EINVAL, "bad calibration table size");
+  if (!cal->noise || !cal->bad) return fail(c, KFX_EINVAL, "NULL calibration arrays");
+  const float thr[3] = {p->seed_thr, p->chan_thr, p->clus_thr};
+  for (float t : thr)
+    if (!std::isfinite(t) || t < 0.0f) return fail(c, KFX_EINVAL, "thresholds must be finite and >= 0");
+  if (p->max_gap < 0 || p->max_gap > 64) return fail(c, KFX_EINVAL, "max_gap outside 0..64");
+  if (out->capacity < 0 || !out->n_out) return fail(c, KFX_EINVAL, "bad output capacity or NULL n_out");
+  if (out->capacity > 0 && (!out->event || !out->module || !out->first || !out->size || !out->charge ||
+                            !out->barycenter))
+    return fail(c, KFX_EINVAL, "NULL output arrays");
+  DeviceGuard dg(c->device);
+  hipStream_t st = (hipStream_t)stream;
+  int rc = KFX_OK;
+  StripArgs a;
+  a.module = d->module;
+  a.strip = d->strip;
+  a.adc = d->adc;
+  a.ev_off = d->event_offsets;
+  a.n = d->n;
+  a.n_events = d->n_events;
+  a.noise = cal->noise;
+  a.bad = cal->bad;
+  a.n_modules = cal->n_modules;
+  a.spm = cal->strips_per_module;
+  a.seed_thr = p->seed_thr;
+  a.chan_thr = p->chan_thr;
+  a.clus_thr2 = (double)p->clus_thr * (double)p->clus_thr;
+  a.max_gap = p->max_gap;
+  a.min_charge = p->min_charge;
+  a.flag = (int*)ws(c, "strip.flag", ((size_t)d->n + 1) * 4, st, rc); if (rc) return rc;
+  a.pos = (int*)ws(c, "strip.pos", ((size_t)d->n + 2) * 4, st, rc); if (rc) return rc;
+  int* scratch = (int*)ws(c, "strip.scan", (((size_t)d->n + 1) / 4096 + 4) * 4, st, rc); if (rc) return rc;
+  a.out_event = out->event;
+  a.out_module = out->module;
+  a.out_first = out->first;
+  a.out_size = out->size;
+  a.out_charge = out->charge;
+  a.out_bary = out->barycenter;
+  a.capacity = out->capacity;
+  a.n_out = out->n_out;
+  launch_cluster_strips(a, scratch, st);
+  return hip_check(c, hipGetLastError(), "strip clustering kernels");
+}
+
 int kfx_fit_tracks(kfx_ctx* c, const kfx_hits* hits, const int32_t* trk_off, const int32_t* trk_hits,
                    int32_t n_tracks, const kfx_prior* prior, const float* align, float field_scale,
                    kfx_states* out, float* chi2, int32_t* ndof, int32_t* status, kfx_states* ckpt, void* stream) {

@@ -50,6 +50,31 @@ struct MaskArgs {
   int* layer_out;        // [n_hits]
 };
 
+// Strip clustering over the digis of a batch of events.
+struct StripArgs {
+  const int* module;        // [n] digis, sorted by (event, module, strip)
+  const int* strip;         // [n]
+  const unsigned short* adc;  // [n]
+  const int* ev_off;        // [n_events + 1]
+  int n, n_events;
+  const float* noise;       // [n_modules * spm]
+  const unsigned char* bad; // [n_modules * spm]
+  int n_modules, spm;
+  float seed_thr, chan_thr;
+  double clus_thr2;         // clus_thr squared
+  int max_gap, min_charge;
+  int* flag;                // [n + 1] kept-cluster head flags
+  int* pos;                 // [n + 1] their exclusive scan
+  int* out_event;           // [capacity] kept clusters
+  int* out_module;
+  int* out_first;
+  int* out_size;
+  int* out_charge;
+  float* out_bary;
+  int capacity;
+  int* n_out;               // [1] kept clusters (all, also beyond capacity)
+};
+
 void launch_fill(int* p, long n, int v, hipStream_t st);
 void exclusive_scan(const int* in, long n, int* out, int* scratch, hipStream_t st);
 void launch_bin(const Geometry* G, const HitsView& H, int n_layers, int n_bins, BinWork& w, int* bin_out,
@@ -79,5 +104,6 @@ void launch_build_fused(const BuildArgs& a, const TracksOut& o, int* seed_counte
 int fused_lanes_for(int K);
 void launch_find_duplicates(const DupArgs& a, hipStream_t st);
 void launch_mask_hits(const MaskArgs& a, const int* layer_in, hipStream_t st);
+void launch_cluster_strips(const StripArgs& a, int* scan_scratch, hipStream_t st);
 
 }  // namespace kfx

@@ -30,7 +30,8 @@ MAX_STEPS = 40
 EXPORTED = ["kfx_create", "kfx_destroy", "kfx_last_error", "kfx_load_layers", "kfx_bin_hits",
             "kfx_seed_states", "kfx_step_compat", "kfx_build_tracks", "kfx_fit_tracks",
             "kfx_fit_tracks_backward", "kfx_enable_timing", "kfx_build_times", "kfx_build_graph",
-            "kfx_graph_launch", "kfx_graph_destroy", "kfx_autotune_build", "kfx_find_duplicates", "kfx_mask_hits"]
+            "kfx_graph_launch", "kfx_graph_destroy", "kfx_autotune_build", "kfx_find_duplicates", "kfx_mask_hits",
+            "kfx_cluster_strips"]
 
 
 class c_states(ctypes.Structure):
@@ -61,6 +62,27 @@ class c_tracks(ctypes.Structure):
                 ("n_holes", ctypes.c_void_p), ("chi2", ctypes.c_void_p), ("state", c_states),
                 ("stats", ctypes.c_void_p), ("max_hits", ctypes.c_int32), ("capacity", ctypes.c_int64),
                 ("needed", ctypes.c_int64)]
+
+
+class c_digis(ctypes.Structure):
+    _fields_ = [("module", ctypes.c_void_p), ("strip", ctypes.c_void_p), ("adc", ctypes.c_void_p),
+                ("event_offsets", ctypes.c_void_p), ("n", ctypes.c_int32), ("n_events", ctypes.c_int32)]
+
+
+class c_strip_calib(ctypes.Structure):
+    _fields_ = [("noise", ctypes.c_void_p), ("bad", ctypes.c_void_p), ("n_modules", ctypes.c_int32),
+                ("strips_per_module", ctypes.c_int32)]
+
+
+class c_cluster_params(ctypes.Structure):
+    _fields_ = [("seed_thr", ctypes.c_float), ("chan_thr", ctypes.c_float), ("clus_thr", ctypes.c_float),
+                ("max_gap", ctypes.c_int32), ("min_charge", ctypes.c_int32)]
+
+
+class c_clusters(ctypes.Structure):
+    _fields_ = [("event", ctypes.c_void_p), ("module", ctypes.c_void_p), ("first", ctypes.c_void_p),
+                ("size", ctypes.c_void_p), ("charge", ctypes.c_void_p), ("barycenter", ctypes.c_void_p),
+                ("capacity", ctypes.c_int32), ("n_out", ctypes.c_void_p)]
 
 
 _lib = None
@@ -120,6 +142,9 @@ def load_library():
     lib.kfx_mask_hits.argtypes = [ctypes.c_void_p, ctypes.POINTER(c_tracks), ctypes.c_int32, ctypes.c_int32,
                                   ctypes.c_void_p, ctypes.c_int32, ctypes.c_float, ctypes.c_void_p,
                                   ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]
+    lib.kfx_cluster_strips.argtypes = [ctypes.c_void_p, ctypes.POINTER(c_digis), ctypes.POINTER(c_strip_calib),
+                                       ctypes.POINTER(c_cluster_params), ctypes.POINTER(c_clusters),
+                                       ctypes.c_void_p]
     lib.kfx_enable_timing.argtypes = [ctypes.c_void_p, ctypes.c_int]
     lib.kfx_build_times.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
     for name in EXPORTED:
@@ -460,6 +485,57 @@ class Context:
                                            float(max_chi2_ndof), _ptr(layer), _ptr(layer_out),
                                            int(layer.numel()), self._stream()))
         return layer_out
+
+    def strip_inputs(self, digis, calib):
+        """Device copies of digis (dict: module, strip, adc, event_offsets) and
+        of a calibration table (dict: noise, bad, n_modules,
+        strips_per_module); tensors already on the device are kept."""
+        import torch
+        d = self.device
+
+        def t(a, dt):
+            if isinstance(a, torch.Tensor):
+                return a
+            return torch.as_tensor(np.ascontiguousarray(a, dtype=dt), device=d)
+        dg = dict(module=t(digis["module"], np.int32), strip=t(digis["strip"], np.int32),
+                  adc=t(np.asarray(digis["adc"]).astype(np.int16) if not isinstance(digis["adc"], torch.Tensor)
+                        else digis["adc"], np.int16),
+                  event_offsets=t(digis["event_offsets"], np.int32))
+        cb = dict(noise=t(calib["noise"], np.float32), bad=t(calib["bad"], np.uint8),
+                  n_modules=int(calib["n_modules"]), strips_per_module=int(calib["strips_per_module"]))
+        return dg, cb
+
+    def cluster_strips(self, digis, calib, seed_thr=3.0, chan_thr=2.0, clus_thr=5.0, max_gap=1, min_charge=0,
+                       capacity=None, out=None):
+        """Kept clusters of a batch of strip events (see kfx_cluster_strips):
+        dict of device tensors event, module, first, size, charge,
+        barycenter (the first n of each) and n (a device int32 [1]).  digis
+        and calib as returned by strip_inputs; the adc tensor holds the
+        16-bit ADCs."""
+        import torch
+        d = self.device
+        n = int(digis["module"].numel())
+        E = int(digis["event_offsets"].numel()) - 1
+        if out is None:
+            cap = max(n, 1) if capacity is None else int(capacity)
+            out = dict(event=torch.empty(max(cap, 1), dtype=torch.int32, device=d),
+                       module=torch.empty(max(cap, 1), dtype=torch.int32, device=d),
+                       first=torch.empty(max(cap, 1), dtype=torch.int32, device=d),
+                       size=torch.empty(max(cap, 1), dtype=torch.int32, device=d),
+                       charge=torch.empty(max(cap, 1), dtype=torch.int32, device=d),
+                       barycenter=torch.empty(max(cap, 1), dtype=torch.float32, device=d),
+                       n=torch.zeros(1, dtype=torch.int32, device=d), capacity=cap)
+        dg = c_digis(digis["module"].data_ptr(), digis["strip"].data_ptr(), digis["adc"].data_ptr(),
+                     digis["event_offsets"].data_ptr(), n, E)
+        cb = c_strip_calib(calib["noise"].data_ptr(), calib["bad"].data_ptr(), int(calib["n_modules"]),
+                           int(calib["strips_per_module"]))
+        pr = c_cluster_params(float(seed_thr), float(chan_thr), float(clus_thr), int(max_gap), int(min_charge))
+        oc = c_clusters(out["event"].data_ptr(), out["module"].data_ptr(), out["first"].data_ptr(),
+                        out["size"].data_ptr(), out["charge"].data_ptr(), out["barycenter"].data_ptr(),
+                        int(out["capacity"]), out["n"].data_ptr())
+        self._check(self.lib.kfx_cluster_strips(self.h, ctypes.byref(dg), ctypes.byref(cb), ctypes.byref(pr),
+                                                ctypes.byref(oc), self._stream()))
+        return out
 
     def fit_tracks(self, hits: DeviceHits, trk_off, trk_hits, prior=(0.1, 0.5, 0.05, 0.05), align=None,
                    field_scale=1.0, ckpt=False, out=None):
