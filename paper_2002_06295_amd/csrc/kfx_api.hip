@@ -889,6 +889,12 @@ int kfx_cluster_strips(kfx_ctx* c, const kfx_digis* d, const kfx_strip_calib* ca
   a.clus_thr2 = (double)p->clus_thr * (double)p->clus_thr;
   a.max_gap = p->max_gap;
   a.min_charge = p->min_charge;
+  a.code = (unsigned char*)ws(c, "strip.code", (size_t)d->n + 16, st, rc); if (rc) return rc;
+  a.nz = (float*)ws(c, "strip.nz", (size_t)d->n * 4, st, rc); if (rc) return rc;
+  a.st_last = (int*)ws(c, "strip.last", (size_t)d->n * 4, st, rc); if (rc) return rc;
+  a.st_charge = (int*)ws(c, "strip.charge", (size_t)d->n * 4, st, rc); if (rc) return rc;
+  a.st_sa = (long*)ws(c, "strip.sa", (size_t)d->n * 8, st, rc); if (rc) return rc;
+  a.st_event = (int*)ws(c, "strip.event", (size_t)d->n * 4, st, rc); if (rc) return rc;
   a.flag = (int*)ws(c, "strip.flag", ((size_t)d->n + 1) * 4, st, rc); if (rc) return rc;
   a.pos = (int*)ws(c, "strip.pos", ((size_t)d->n + 2) * 4, st, rc); if (rc) return rc;
   int* scratch = (int*)ws(c, "strip.scan", (((size_t)d->n + 1) / 4096 + 4) * 4, st, rc); if (rc) return rc;

@@ -63,8 +63,14 @@ struct StripArgs {
   float seed_thr, chan_thr;
   double clus_thr2;         // clus_thr squared
   int max_gap, min_charge;
+  unsigned char* code;      // [n] bit 0 cluster strip, bit 1 seed
+  float* nz;                // [n] noise of each digi
   int* flag;                // [n + 1] kept-cluster head flags
   int* pos;                 // [n + 1] their exclusive scan
+  int* st_last;             // [n] per kept head: last strip, charge,
+  int* st_charge;           //     sum strip * adc, event
+  long* st_sa;
+  int* st_event;
   int* out_event;           // [capacity] kept clusters
   int* out_module;
   int* out_first;
