@@ -2,7 +2,9 @@
 
 Only tests/, the smoke check and the CPU-baseline leg of the benchmark may
 import this package.  It wraps the plain C++ reference in kfo.cpp through
-ctypes; it shares no code with the GPU library.
+ctypes (building, fit, adjoint); duplicates.py (duplicate removal, hit
+masking) and strips.py (strip clustering) are plain Python.  It shares no
+code with the GPU library.
 
 Covariances are exchanged as full row-major 6x6 float64 blocks.  Geometry is
 the float64 layer table [L, 8] = (kind, pos, lo, hi, x0, su, sv, sn).
