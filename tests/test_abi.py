@@ -19,7 +19,8 @@ def declared_functions():
 def test_header_declares_the_boundary():
     names = declared_functions()
     for n in ["kfx_create", "kfx_destroy", "kfx_last_error", "kfx_load_layers", "kfx_bin_hits",
-              "kfx_seed_states", "kfx_step_compat", "kfx_build_tracks", "kfx_fit_tracks"]:
+              "kfx_seed_states", "kfx_step_compat", "kfx_build_tracks", "kfx_fit_tracks",
+              "kfx_fit_tracks_backward", "kfx_find_duplicates", "kfx_mask_hits", "kfx_cluster_strips"]:
         assert n in names
 
 
@@ -51,3 +52,13 @@ def test_null_context_calls_fail_cleanly():
     lib.kfx_destroy(None)
     lib.kfx_create.argtypes = [ctypes.c_int, ctypes.c_void_p]
     assert lib.kfx_create(0, None) == -1
+    # the entry points after building reject a NULL context before any
+    # device call
+    lib.kfx_find_duplicates.argtypes = [ctypes.c_void_p] * 2 + [ctypes.c_int32] * 5 + [ctypes.c_void_p] * 2
+    assert lib.kfx_find_duplicates(None, None, 0, 1, 0, 1, 2, None, None) == -1
+    lib.kfx_mask_hits.argtypes = ([ctypes.c_void_p] * 2 + [ctypes.c_int32] * 2 + [ctypes.c_void_p, ctypes.c_int32,
+                                  ctypes.c_float, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                  ctypes.c_void_p])
+    assert lib.kfx_mask_hits(None, None, 0, 1, None, 8, 3.0, None, None, 0, None) == -1
+    lib.kfx_cluster_strips.argtypes = [ctypes.c_void_p] * 6
+    assert lib.kfx_cluster_strips(None, None, None, None, None, None) == -1
