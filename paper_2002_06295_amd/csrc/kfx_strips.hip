@@ -79,7 +79,9 @@ __global__ void __launch_bounds__(256) k_strip_flags(StripArgs a) {
     const unsigned char ci = a.code[i];
     if (ci & 1) {
       const int e = strip_event_of(a.ev_off, a.n_events, i);
-      const int ev_start = a.ev_off[e], ev_end = a.ev_off[e + 1];
+      // clamped to the digis, so that malformed offsets cannot lead a walk
+      // out of the arrays
+      const int ev_start = max(a.ev_off[e], 0), ev_end = min(a.ev_off[e + 1], a.n);
       bool head = true;
       for (int j = i - 1, lo = max(ev_start, i - 1 - a.max_gap); j >= lo; --j)
         if (a.code[j] & 1) {
