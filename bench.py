@@ -206,6 +206,32 @@ def cpu_baseline(ev, n_seeds, min_reps, min_seconds=3.0):
                        f"search, {len(chunks)} threads on {host_cpu_model()}, {dt:.1f} s wall"), res
 
 
+HBM_PEAK_GBPS = 8000.0
+
+
+def hbm_roofline(bytes_per_call, ms, what):
+    """Roofline object of an HBM-bound step: algorithmic bytes per call
+    over the measured time per call, against the 8 TB/s HBM peak."""
+    gbps = bytes_per_call / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+            "frac": gbps / HBM_PEAK_GBPS, "bytes_per_call": int(bytes_per_call), "bytes": what}
+
+
+def dedup_bytes(out, n_hits):
+    """Algorithmic bytes of one duplicate-removal call: per track its hit
+    list row read twice (sort, then merge) and its sorted list written once
+    (3 x 4 max_hits B), its counts and chi2 read (16 B), its key written
+    and read (32 B) and its result written (4 B); per (track, hit) entry the
+    exchange on the hit's head (8 B), the next link written and read (8 B)
+    and the head read again (4 B); the heads cleared (4 B per hit)."""
+    S, K = int(out["S"]), int(out["K"])
+    h = out["hits"].reshape(-1, out["hits"].shape[-1])[::K][:S]
+    has = (out["n_cands"][:S] > 0).reshape(-1, 1)
+    entries = int((((h >= 0) & (h < n_hits)) & has).sum().item())
+    H = int(h.shape[1])
+    return S * (12 * H + 16 + 32 + 4) + entries * 20 + 4 * n_hits
+
+
 def time_dedup(ctx, out, n_hits, reps=20):
     """Mean time (ms, torch events on the call's stream) of duplicate
     removal over a building output, and its result."""
@@ -369,7 +395,9 @@ def main():
             "workload": "build5k + a second seed for 25 % of the particles",
             "seeds": int(dseeds.shape[0]), "extra_seeds": int(extra.size), "ms": dms,
             "tracks_per_s": dseeds.shape[0] / (dms * 1e-3), "flagged": int((dres >= 0).sum()),
-            "extra_flagged_to_own_particle": float(np.mean(dres[extra] == dtrk[extra]))}
+            "extra_flagged_to_own_particle": float(np.mean(dres[extra] == dtrk[extra])),
+            "roofline": hbm_roofline(dedup_bytes(dout, ev.n_hits), dms,
+                                     "per track 12 max_hits + 52 B, per (track, hit) entry 20 B, 4 B per hit")}
         log(f"[bench] duplicate removal: {dms * 1e3:.1f} us, flagged {(dres >= 0).sum()} of "
             f"{extra.size} extra seeds")
         del dout
@@ -418,6 +446,10 @@ def main():
             "workload": "build5k: iteration 1 from the first three hits of half of the particles; "
                         "iteration 2 from hits 1, 2, 4 of the particles whose seed hits the mask left free",
             "mask_ms": mask_ms, "hits_masked": int((lay2_h == -1).sum()) - int((ev.layer < 0).sum()),
+            "mask_roofline": hbm_roofline(
+                8 * ev.n_hits + int(out1["S"]) * (4 * int(out1["hits"].shape[1]) + 16)
+                + 4 * (int((lay2_h == -1).sum()) - int((ev.layer < 0).sum())), mask_ms,
+                "layer array read and written (8 B per hit), per track its list row and 16 B, 4 B per masked hit"),
             "hits": ev.n_hits, "seeds_iteration2": n_s2, "iteration2": it2}
         log(f"[bench] second iteration: mask {mask_ms * 1e3:.1f} us, {sec['second_iteration']['hits_masked']} "
             f"hits masked, {n_s2} seeds: {it2['masked']['ms']:.3f} ms masked vs "
@@ -444,8 +476,11 @@ def main():
             torch.cuda.synchronize()
             ms_c = c0.elapsed_time(c1) / 20
             nd = int(dg["module"].numel())
-            strip[tag] = {"ms": ms_c, "digis": nd, "digis_per_s": nd / (ms_c * 1e-3),
-                          "clusters": int(so["n"].cpu()[0])}
+            ncl = int(so["n"].cpu()[0])
+            strip[tag] = {"ms": ms_c, "digis": nd, "digis_per_s": nd / (ms_c * 1e-3), "clusters": ncl,
+                          "roofline": hbm_roofline(15 * nd + 24 * ncl, ms_c,
+                                                   "per digi 10 B read and 5 B of calibration, 24 B per kept "
+                                                   "cluster written")}
         sec["strip_clustering"] = strip
         log(f"[bench] strip clustering: 16 events {strip['batch16']['ms'] * 1e3:.0f} us "
             f"({strip['batch16']['digis_per_s']:.3e} digis/s), one event {strip['one_event']['ms'] * 1e3:.0f} us")
@@ -464,6 +499,7 @@ def main():
             sh2.pop("ms")
             wf, tf, sf, o2 = run_build(ctx2, kfx, h2, ev2, 4, 1, kfx.MODE_FUSED, shape=sh2)
             dms2, dres2 = time_dedup(ctx2, o2, ev2.n_hits)
+            dbytes2 = dedup_bytes(o2, ev2.n_hits)
             wp, tp, sp, o2 = run_build(ctx2, kfx, h2, ev2, 2, 1, kfx.MODE_PLAIN, out=o2)
             km = float(np.mean([t[1] for t in tf]))
             fl = algorithmic_flops(sf)
@@ -472,7 +508,10 @@ def main():
                          "building_ms": float(np.mean([t[2] for t in tf])),
                          "alu_frac": fl / (km * 1e-3) / 1e12 / ALU_PEAK_TFLOPS, "launch_shape": sh2,
                          "plain_steps_per_s": sp[0] / (wp * 1e-3), "steps_per_launch": sf[0],
-                         "duplicate_removal_ms": dms2, "duplicates_flagged": int((dres2 >= 0).sum())}
+                         "duplicate_removal_ms": dms2, "duplicates_flagged": int((dres2 >= 0).sum()),
+                         "duplicate_removal_roofline": hbm_roofline(
+                             dbytes2, dms2, "per track 12 max_hits + 52 B, per (track, hit) entry 20 B, "
+                                            "4 B per hit")}
             log(f"[bench] {name}: fused {sec[name]['steps_per_s']:.3e} steps/s, plain "
                 f"{sec[name]['plain_steps_per_s']:.3e}")
             del o2, h2, ctx2, ev2
