@@ -234,8 +234,9 @@ int kfx_mask_hits(kfx_ctx* ctx, const kfx_tracks* tracks, int32_t n_seeds, int32
 
 /* Silicon-strip digis of a batch of events (device).  Digis of event e are
  * [event_offsets[e], event_offsets[e+1]), sorted by (module, strip) with at
- * most one digi per strip; a digi whose (module, strip) lies outside the
- * calibration table is ignored. */
+ * most one digi per strip (the results for unsorted digis are unspecified;
+ * no access leaves the arrays); a digi whose (module, strip) lies outside
+ * the calibration table is ignored. */
 typedef struct {
   const int32_t* module;
   const int32_t* strip;

@@ -889,6 +889,8 @@ int kfx_cluster_strips(kfx_ctx* c, const kfx_digis* d, const kfx_strip_calib* ca
   a.clus_thr2 = (double)p->clus_thr * (double)p->clus_thr;
   a.max_gap = p->max_gap;
   a.min_charge = p->min_charge;
+  a.bnd = (int*)ws(c, "strip.bnd", (size_t)d->n_events * (strip_chunks(cal->n_modules) + 1) * 4, st, rc);
+  if (rc) return rc;
   a.code = (unsigned char*)ws(c, "strip.code", (size_t)d->n + 16, st, rc); if (rc) return rc;
   a.nz = (float*)ws(c, "strip.nz", (size_t)d->n * 4, st, rc); if (rc) return rc;
   a.st_last = (int*)ws(c, "strip.last", (size_t)d->n * 4, st, rc); if (rc) return rc;

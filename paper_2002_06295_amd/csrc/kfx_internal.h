@@ -63,6 +63,8 @@ struct StripArgs {
   float seed_thr, chan_thr;
   double clus_thr2;         // clus_thr squared
   int max_gap, min_charge;
+  int* bnd;                 // [n_events * (chunks + 1)] first digi of each
+                            // (event, module chunk)
   unsigned char* code;      // [n] bit 0 cluster strip, bit 1 seed
   float* nz;                // [n] noise of each digi
   int* flag;                // [n + 1] kept-cluster head flags
@@ -110,6 +112,7 @@ void launch_build_fused(const BuildArgs& a, const TracksOut& o, int* seed_counte
 int fused_lanes_for(int K);
 void launch_find_duplicates(const DupArgs& a, hipStream_t st);
 void launch_mask_hits(const MaskArgs& a, const int* layer_in, hipStream_t st);
+int strip_chunks(int n_modules);
 void launch_cluster_strips(const StripArgs& a, int* scan_scratch, hipStream_t st);
 
 }  // namespace kfx

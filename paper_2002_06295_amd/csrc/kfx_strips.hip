@@ -7,8 +7,8 @@
 //
 // Data-parallel over the digis of a whole batch of events (the paper's
 // remedy for single-event GPU runs dominated by overheads).  The first pass
-// classifies every digi once (the calibration gathers) into a code byte and
-// its noise; in the second one thread per digi decides, from the codes of
+// classifies every digi once (the calibration gathers, module-major across
+// the events) into a code byte and its noise; in the second one thread per digi decides, from the codes of
 // its neighbours, whether it starts a cluster, and if so walks the cluster
 // and keeps its sums when the cluster passes; an exclusive scan of the
 // kept flags gives every kept cluster its output slot, in (event, module,
@@ -31,21 +31,6 @@ __device__ inline int strip_event_of(const int* ev_off, int n_events, int i) {
   return lo;
 }
 
-// code of a digi: bit 0 cluster strip (not bad, adc > chan_thr * noise),
-// bit 1 seed (adc > seed_thr * noise); 0 for a digi outside the table
-__device__ inline unsigned char strip_code(const StripArgs& a, int i, float* nz_out) {
-  const int m = a.module[i], s = a.strip[i];
-  *nz_out = 0.0f;
-  if (m < 0 || m >= a.n_modules || s < 0 || s >= a.spm) return 0;
-  const int c = m * a.spm + s;
-  if (a.bad[c]) return 0;
-  const float adc = (float)a.adc[i];
-  const float nz = a.noise[c];
-  *nz_out = nz;
-  if (!(adc > a.chan_thr * nz)) return 0;
-  return (unsigned char)(1 | ((adc > a.seed_thr * nz) ? 2 : 0));
-}
-
 // consecutive cluster strips j < i (digi order) of one cluster: same module,
 // at most max_gap strips between them, all of them bad
 __device__ inline bool strips_linked(const StripArgs& a, int j, int i) {
@@ -60,12 +45,93 @@ __device__ inline bool strips_linked(const StripArgs& a, int j, int i) {
 
 }  // namespace
 
-// pass 1: the code and noise of every digi (coalesced writes)
-__global__ void __launch_bounds__(256) k_strip_codes(StripArgs a) {
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += gridDim.x * blockDim.x) {
-    float nz;
-    a.code[i] = strip_code(a, i, &nz);
-    a.nz[i] = nz;
+// pass 1 runs module-major: block c owns modules [c * kStripChunk,
+// (c + 1) * kStripChunk) and classifies their digis in every event, so that
+// the chunk's calibration (noise and bad flags of its strips, ~60 KB) is
+// fetched once and reused from the cache by all events, instead of every
+// event gathering its own sectors of the table.  bnd[e * (C + 1) + c] is
+// the first digi of event e in chunk c (chunk 0 starts at the event's
+// first digi and chunk C is its end, so digis outside the table are
+// classified too).
+constexpr int kStripChunk = 16;
+
+__global__ void __launch_bounds__(256) k_strip_bounds(StripArgs a, int C) {
+  const long n_b = (long)a.n_events * (C + 1);
+  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n_b; t += (long)gridDim.x * blockDim.x) {
+    const int e = (int)(t / (C + 1)), c = (int)(t - (long)e * (C + 1));
+    const int lo = min(max(a.ev_off[e], 0), a.n), hi = min(max(a.ev_off[e + 1], lo), a.n);
+    int b;
+    if (c == 0) {
+      b = lo;
+    } else if (c == C) {
+      b = hi;
+    } else {
+      // first digi of the event whose module is >= c * kStripChunk
+      const int m = c * kStripChunk;
+      int l = lo, h = hi;
+      while (l < h) {
+        const int mid = (l + h) >> 1;
+        if (a.module[mid] < m) l = mid + 1; else h = mid;
+      }
+      b = l;
+    }
+    a.bnd[t] = b;
+  }
+}
+
+// Code of a digi: bit 0 cluster strip (in the table, not bad, adc >
+// chan_thr * noise), bit 1 seed (adc > seed_thr * noise); its noise (0 for
+// a bad strip or one outside the table).  Four events per round, their
+// digis' loads and gathers in flight together.
+__global__ void __launch_bounds__(256) k_strip_codes(StripArgs a, int C) {
+  const int c = blockIdx.x;
+  for (int e0 = 0; e0 < a.n_events; e0 += 4) {
+    int lo[4], cnt[4];
+    int span = 0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = e0 + u;
+      lo[u] = 0;
+      cnt[u] = 0;
+      if (e < a.n_events) {
+        lo[u] = a.bnd[(long)e * (C + 1) + c];
+        cnt[u] = max(a.bnd[(long)e * (C + 1) + c + 1] - lo[u], 0);
+      }
+      span = max(span, cnt[u]);
+    }
+    for (int k = threadIdx.x; k < span; k += blockDim.x) {
+      int mm[4], ss[4], qq[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const bool in = k < cnt[u];
+        const int i = lo[u] + k;
+        mm[u] = in ? a.module[i] : -1;
+        ss[u] = in ? a.strip[i] : 0;
+        qq[u] = in ? (int)a.adc[i] : 0;
+      }
+      float nzv[4];
+      bool bd[4], valid[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        valid[u] = mm[u] >= 0 && mm[u] < a.n_modules && ss[u] >= 0 && ss[u] < a.spm;
+        const int cal = valid[u] ? mm[u] * a.spm + ss[u] : 0;
+        nzv[u] = valid[u] ? a.noise[cal] : 0.0f;
+        bd[u] = valid[u] ? a.bad[cal] != 0 : true;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (k >= cnt[u]) continue;
+        unsigned char cd = 0;
+        float nzo = 0.0f;
+        if (valid[u] && !bd[u]) {
+          nzo = nzv[u];
+          const float adc = (float)qq[u];
+          if (adc > a.chan_thr * nzv[u]) cd = (unsigned char)(1 | ((adc > a.seed_thr * nzv[u]) ? 2 : 0));
+        }
+        a.code[lo[u] + k] = cd;
+        a.nz[lo[u] + k] = nzo;
+      }
+    }
   }
 }
 
@@ -144,9 +210,14 @@ __global__ void __launch_bounds__(256) k_strip_write(StripArgs a) {
   if (blockIdx.x == 0 && threadIdx.x == 0) *a.n_out = a.pos[a.n];
 }
 
+int strip_chunks(int n_modules) { return (n_modules + kStripChunk - 1) / kStripChunk; }
+
 void launch_cluster_strips(const StripArgs& a, int* scan_scratch, hipStream_t st) {
   const int nb = std::max(1, (int)std::min<long>(((long)a.n + 255) / 256, 16384));
-  hipLaunchKernelGGL(k_strip_codes, dim3(nb), dim3(256), 0, st, a);
+  const int C = strip_chunks(a.n_modules);
+  const long n_b = (long)a.n_events * (C + 1);
+  hipLaunchKernelGGL(k_strip_bounds, dim3((unsigned)std::min<long>((n_b + 255) / 256, 16384)), dim3(256), 0, st, a, C);
+  hipLaunchKernelGGL(k_strip_codes, dim3((unsigned)C), dim3(256), 0, st, a, C);
   hipLaunchKernelGGL(k_strip_flags, dim3(nb), dim3(256), 0, st, a);
   exclusive_scan(a.flag, a.n, a.pos, scan_scratch, st);
   hipLaunchKernelGGL(k_strip_write, dim3(nb), dim3(256), 0, st, a);
