@@ -813,6 +813,7 @@ int kfx_find_duplicates(kfx_ctx* c, const kfx_tracks* tracks, int32_t n_seeds, i
   a.next = (int*)ws(c, "dup.next", SH * 4, st, rc); if (rc) return rc;
   a.key = (int4*)ws(c, "dup.key", (size_t)n_seeds * 16, st, rc); if (rc) return rc;
   a.head = (int*)ws(c, "dup.head", ((size_t)n_hits + 4) * 4, st, rc); if (rc) return rc;
+  a.head2 = (int*)ws(c, "dup.head2", ((size_t)n_hits + 4) * 4, st, rc); if (rc) return rc;
   launch_find_duplicates(a, st);
   return hip_check(c, hipGetLastError(), "duplicate removal kernels");
 }

@@ -32,7 +32,9 @@ struct DupArgs {
   int num, den;          // shared-hit fraction
   int* list;             // [S][H] ascending distinct hits of each track, -1 after
   int* next;             // [S][H] next entry holding the same hit, -1 at the end
-  int* head;             // [n_hits] last entry pushed for each hit, -1 none
+  int* head;             // [n_hits] one holder's entry, -2 once the hit is
+                         // known to be shared
+  int* head2;            // [n_hits] of a shared hit: last entry pushed, -1 none
   int4* key;             // [S] n_hits, n_holes, chi2 bits, hit count of the list
   int* dup_of;           // [S] output
 };

@@ -955,10 +955,11 @@ k_build_fused(BuildArgs a, TracksOut o, int* seed_counter) {
 // One wavefront per track, lane k on entry k of its list (at most 64).  The
 // first pass sorts the list across the lanes (bitonic network on shuffles),
 // drops repeats and non-hits (ballot compaction), stores the ascending list
-// and pushes every (track, hit) entry onto a per-hit linked list with one
-// atomic exchange (head[hit] -> entry -> next[entry] -> ...; entry =
-// track * H + position).  The second pass walks, lane per hit, the list of
-// the hit's other holders, merges the track's list with those of the
+// and writes each entry (entry = track * H + position) to head[hit]; the
+// next two passes find the shared hits and push only their entries onto a
+// per-hit linked list with an atomic exchange (head2[hit] -> entry ->
+// next[entry] -> ...).  The last pass walks, lane per shared hit, the list
+// of the hit's other holders, merges the track's list with those of the
 // holders that rank above it, and reduces the lanes' best partners.  The
 // per-hit arrays span the whole batch, so blocks are ordered so that each
 // XCD (and its L2) works through one contiguous range of seeds, i.e. of
@@ -1012,14 +1013,53 @@ __global__ void __launch_bounds__(256) k_dup_lists(DupArgs a, int nblk) {
   if (lane >= n && lane < H) row[lane] = -1;
   if (keep) {
     row[pos] = v;
-    const int e = b * H + pos;
-    a.next[e] = atomicExch(a.head + v, e);
+    a.head[v] = b * H + pos;  // one of the hit's holders wins
   }
   if (lane == 0) {
     const long e = (long)b * a.K;
     a.key[b] = nc > 0 ? make_int4(a.n_hits_c[e], a.n_holes_c[e], __float_as_int(a.chi2_c[e]), n)
                       : make_int4(0, 0, 0, 0);
     a.dup_of[b] = nc > 0 ? -1 : -2;
+  }
+}
+
+// An entry that does not find itself in head[hit] shares its hit with
+// another track: it marks the hit (head = -2; every holder but one sees a
+// foreign entry, so a shared hit always ends marked) and clears the hit's
+// list head.  Only the entries of marked hits are pushed (with an atomic
+// exchange) onto a linked list per hit; a hit held by one track, the
+// common case, costs a plain store and two reads.
+__global__ void __launch_bounds__(256) k_dup_mark(DupArgs a, int nblk) {
+  const int lb = xcd_block(nblk);
+  if (lb < 0) return;
+  const int lane = threadIdx.x & 63;
+  const int b = lb * kDupRows + (int)(threadIdx.x >> 6);
+  if (b >= a.S) return;
+  const int H = a.H;
+  const int nb = a.key[b].w;
+  if (lane < nb) {
+    const int h = a.list[(long)b * H + lane];
+    if (a.head[h] != b * H + lane) {
+      a.head[h] = -2;
+      a.head2[h] = -1;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256) k_dup_push(DupArgs a, int nblk) {
+  const int lb = xcd_block(nblk);
+  if (lb < 0) return;
+  const int lane = threadIdx.x & 63;
+  const int b = lb * kDupRows + (int)(threadIdx.x >> 6);
+  if (b >= a.S) return;
+  const int H = a.H;
+  const int nb = a.key[b].w;
+  if (lane < nb) {
+    const int h = a.list[(long)b * H + lane];
+    if (a.head[h] == -2) {
+      const int e = b * H + lane;
+      a.next[e] = atomicExch(a.head2 + h, e);
+    }
   }
 }
 
@@ -1048,7 +1088,7 @@ __global__ void __launch_bounds__(256) k_dup_find(DupArgs a, int nblk) {
   int4 kbest = make_int4(0, 0, 0, 0);
   if (lane < nb) {
     const int h = lbp[lane];
-    int e = a.head[h];
+    int e = a.head[h] == -2 ? a.head2[h] : -1;  // -1: no other holder
     while (e >= 0) {
       const int j = e / H;
       const int en = a.next[e];
@@ -1289,10 +1329,11 @@ size_t fused_static_lds_bytes() { return sizeof(Geometry); }
 
 void launch_find_duplicates(const DupArgs& a, hipStream_t st) {
   if (a.S <= 0) return;
-  launch_fill(a.head, a.n_hits, -1, st);
   const int nblk = (a.S + kDupRows - 1) / kDupRows;
   const dim3 grid((unsigned)(8 * ((nblk + 7) / 8)));
   hipLaunchKernelGGL(k_dup_lists, grid, dim3(64 * kDupRows), 0, st, a, nblk);
+  hipLaunchKernelGGL(k_dup_mark, grid, dim3(64 * kDupRows), 0, st, a, nblk);
+  hipLaunchKernelGGL(k_dup_push, grid, dim3(64 * kDupRows), 0, st, a, nblk);
   hipLaunchKernelGGL(k_dup_find, grid, dim3(64 * kDupRows), 0, st, a, nblk);
 }
 
