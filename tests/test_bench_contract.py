@@ -44,3 +44,22 @@ def test_stored_traffic_follows_the_sources(tmp_path, monkeypatch):
     (d / "t.json").write_text(json.dumps(rec))
     assert bench.stored_traffic("t.json") == 123.0
     assert bench.stored_traffic("missing.json") is None
+
+
+def test_hbm_roofline_and_dedup_bytes():
+    """The secondary rooflines: bytes over time against 8 TB/s, and the
+    duplicate-removal byte count from its stated per-track, per-entry and
+    per-hit terms."""
+    import torch
+
+    import bench
+    r = bench.hbm_roofline(8e9, 1000.0, "x")
+    assert r["bound"] == "hbm" and abs(r["achieved"] - 8.0) < 1e-9 and abs(r["frac"] - 1e-3) < 1e-12
+    S, K, H = 4, 2, 5
+    hits = torch.full((S * K, H), -3, dtype=torch.int32)
+    hits[0, :3] = torch.tensor([0, 1, 9])      # 9 is not a hit of a 5-hit batch
+    hits[2 * K, :2] = torch.tensor([2, 3])
+    hits[1, :] = 4                              # slot 1 is not read
+    out = dict(S=S, K=K, hits=hits, n_cands=torch.tensor([1, 0, 1, 1], dtype=torch.int32))
+    entries = 2 + 2
+    assert bench.dedup_bytes(out, 5) == S * (12 * H + 52) + 20 * entries + 4 * 5
