@@ -366,3 +366,20 @@ def test_load_layers_rejects_bad_tables(dev, kfx):
     with pytest.raises(kfx.KfxError):
         kfx.Context(0).bin_hits(kfx.DeviceHits.from_events(kfsynth.generate("fit1k", tracks_per_event=5),
                                                            "cuda:0"))
+
+
+def test_short_candidates_preserved(dev, kfx):
+    """Particles cut after six hits (their later hits' layers set to -1):
+    the GPU's best candidates equal the oracle's (which keep the six hits
+    and max_holes holes; tests/test_oracle_pins.py), on both paths."""
+    from test_oracle_pins import _truncated_event
+    ev, ev2, cut = _truncated_event()
+    print("short candidates", flush=True)
+    o = oracle.build_tracks(ev2, prior=PRIOR, max_hits=48)
+    K = ev.workload.max_cands
+    for mode in (kfx.MODE_FUSED, kfx.MODE_PLAIN):
+        g = run_build(kfx, dev, ev2, mode)
+        assert g["hits"].shape[1] == 48
+        same = [np.array_equal(g["hits"][t * K], o["hits"][t, 0]) for t in cut]
+        assert all(same), (mode, same)
+        assert all(g["n_hits"][t * K] == o["nhits"][t, 0] for t in cut)

@@ -521,3 +521,36 @@ def test_building_efficiency_on_build5k(build_event):
     assert eff / n > 0.97
     st = out["stats"]
     assert st[0] > 10 * n and st[1] > 0 and st[2] > 0
+
+
+def _truncated_event():
+    """A noise-free build5k-like event in which 20 particles lose every hit
+    after their sixth (those hits' layers set to -1: ignored)."""
+    import dataclasses
+    w = kfsynth.workload("build5k", noise_per_event=0, tracks_per_event=200, ineff=0.0)
+    ev = kfsynth.generate(w)
+    nrec = np.diff(ev.trk_offsets)
+    cut = np.nonzero(nrec >= 12)[0][::3][:20]
+    lay = ev.layer.copy()
+    for t in cut:
+        lay[ev.trk_hits[ev.trk_offsets[t] + 6: ev.trk_offsets[t + 1]]] = -1
+    return ev, dataclasses.replace(ev, layer=lay), cut
+
+
+def test_short_candidates_are_preserved():
+    """Abstract and Sec. 3: short candidates are kept rather than extended
+    over many layers.  Reading 11's stop child: a candidate that reaches
+    the hole limit keeps its state and stays in the seed's top-K.  A track
+    cut after six hits must come out as its six hits and max_holes holes,
+    not be dropped or replaced by a longer fake."""
+    ev, ev2, cut = _truncated_event()
+    o = oracle.build_tracks(ev2, max_hits=48)
+    exact = 0
+    for t in cut:
+        truth = ev.trk_hits[ev.trk_offsets[t]: ev.trk_offsets[t] + 6]
+        row = o["hits"][t, 0]
+        assert o["n"][t] >= 1
+        np.testing.assert_array_equal(row[:6], truth)
+        exact += (o["nhits"][t, 0] == 6 and row[6:9].tolist() == [-1, -1, -1] and (row[9:] == -3).all())
+    # the rest picked up a hit of another particle after a hole or two
+    assert exact >= 0.9 * len(cut), exact
