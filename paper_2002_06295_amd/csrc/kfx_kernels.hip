@@ -1073,6 +1073,14 @@ __device__ inline bool ranks_above(const int4& x, int xs, const int4& y, int ys)
   return xs < ys;
 }
 
+// The wave judges one candidate partner J at a time: J's list is loaded
+// one entry per lane and every lane tests its own hit against it, so the
+// shared count is a ballot.  Lane k walks the holders of its track's hit k
+// and offers the next holder that ranks above the track and above the best
+// partner so far; a lane whose offer was judged, or can no longer win,
+// moves on.  Every holder that could become the best is judged with its
+// exact shared count, so the result is the highest-ranked qualifying
+// partner whatever the order of the chains.
 __global__ void __launch_bounds__(256) k_dup_find(DupArgs a, int nblk) {
   const int lb = xcd_block(nblk);
   if (lb < 0) return;
@@ -1083,61 +1091,47 @@ __global__ void __launch_bounds__(256) k_dup_find(DupArgs a, int nblk) {
   const int nb = kb.w;
   if (nb == 0) return;  // dup_of already -1 (no hits) or -2 (no track)
   const int H = a.H;
-  const int* lbp = a.list + (long)b * H;
-  int best = -1;
+  const int h = lane < nb ? a.list[(long)b * H + lane] : -1;
+  int e = (lane < nb && a.head[h] == -2) ? a.head2[h] : -1;  // -1: no other holder
+  int best = -1;  // uniform across the wave
   int4 kbest = make_int4(0, 0, 0, 0);
-  if (lane < nb) {
-    const int h = lbp[lane];
-    int e = a.head[h] == -2 ? a.head2[h] : -1;  // -1: no other holder
+  int j = -1;  // this lane's offer
+  int4 kj = make_int4(0, 0, 0, 0);
+  // next holder on this lane's chain that could still become the best
+  auto advance = [&]() {
+    j = -1;
     while (e >= 0) {
-      const int j = e / H;
-      const int en = a.next[e];
-      if (j != b) {
-        const int4 kj = a.key[j];
-        if (ranks_above(kj, j, kb, b) && (best < 0 || ranks_above(kj, j, kbest, best))) {
-          // merge the two ascending lists; the first common hit is their
-          // smallest, and when it lies below h the pair was judged there
-          const int* lj = a.list + (long)j * H;
-          const int nj = kj.w;
-          int x = 0, y = 0, shared = 0;
-          bool earlier = false;
-          int u = lbp[0], w = lj[0];
-          while (x < nb && y < nj) {
-            if (u == w) {
-              if (shared == 0 && u < h) {
-                earlier = true;
-                break;
-              }
-              ++shared;
-              if (++x < nb) u = lbp[x];
-              if (++y < nj) w = lj[y];
-            } else if (u < w) {
-              if (++x < nb) u = lbp[x];
-            } else {
-              if (++y < nj) w = lj[y];
-            }
-          }
-          const int shorter = nb < nj ? nb : nj;
-          if (!earlier && (long)a.den * shared >= (long)a.num * shorter) best = j, kbest = kj;
-        }
-      }
-      e = en;
+      const int jj = e / H;
+      e = a.next[e];
+      if (jj == b) continue;
+      const int4 kjj = a.key[jj];
+      if (!ranks_above(kjj, jj, kb, b)) continue;
+      if (best >= 0 && !ranks_above(kjj, jj, kbest, best)) continue;
+      j = jj;
+      kj = kjj;
+      break;
     }
-  }
-  // the highest-ranked of the lanes' partners
-  unsigned long long m = __ballot(best >= 0);
-  if (m == 0) return;  // dup_of stays -1
-  int g = -1;
-  int4 kg = make_int4(0, 0, 0, 0);
-  while (m) {
+  };
+  advance();
+  for (;;) {
+    const unsigned long long m = __ballot(j >= 0);
+    if (m == 0) break;
     const int l = __ffsll((long long)m) - 1;
-    m &= m - 1ull;
-    const int j = __shfl(best, l, 64);
-    const int4 kj = make_int4(__shfl(kbest.x, l, 64), __shfl(kbest.y, l, 64), __shfl(kbest.z, l, 64),
-                              __shfl(kbest.w, l, 64));
-    if (g < 0 || ranks_above(kj, j, kg, g)) g = j, kg = kj;
+    const int J = rl_i(j, l);
+    const int4 kJ = make_int4(rl_i(kj.x, l), rl_i(kj.y, l), rl_i(kj.z, l), rl_i(kj.w, l));
+    const int nJ = kJ.w;
+    const int v = lane < nJ ? a.list[(long)J * H + lane] : -2;
+    bool hit = false;
+    for (int y = 0; y < nJ; ++y) hit |= (lane < nb) && (h == rl_i(v, y));
+    const int shared = __popcll(__ballot(hit));
+    const int shorter = nb < nJ ? nb : nJ;
+    if ((long)a.den * shared >= (long)a.num * shorter && (best < 0 || ranks_above(kJ, J, kbest, best))) {
+      best = J;
+      kbest = kJ;
+    }
+    if (j == J || (j >= 0 && best >= 0 && !ranks_above(kj, j, kbest, best))) advance();
   }
-  if (lane == 0) a.dup_of[b] = g;
+  if (lane == 0 && best >= 0) a.dup_of[b] = best;
 }
 
 // ------------------------------------------------ hit masking (iterations)
