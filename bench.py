@@ -219,7 +219,7 @@ def hbm_roofline(bytes_per_call, ms, what):
 
 def dedup_bytes(out, n_hits):
     """Algorithmic bytes of one duplicate-removal call: per track its hit
-    list row read twice (sort, then merge) and its sorted list written once
+    list row read twice (sort, then judging) and its sorted list written once
     (3 x 4 max_hits B), its counts and chi2 read (16 B), its key written
     and read (32 B) and its result written (4 B); per (track, hit) entry the
     exchange on the hit's head (8 B), the next link written and read (8 B)
