@@ -41,14 +41,17 @@ def test_golden(ctx, key):
 
 
 # (modules, strips per module, events, particles, noise fraction, bad
-# fraction, params, seed): tiny to a few 10^5 digis, gap limits 0-4,
-# a charge cut, raised thresholds, dense noise
+# fraction, params, seed): tiny to a few 10^5 digis, gap limits 0-4 and 64,
+# a charge cut, raised thresholds, dense noise, dense bad strips
 CASES = [
     (4, 16, 1, 3, 0.1, 0.1, {}, 0),
     (50, 64, 3, 40, 0.05, 0.08, dict(max_gap=0), 1),
     (200, 128, 5, 300, 0.03, 0.05, dict(max_gap=2, min_charge=60), 2),
     (300, 256, 4, 800, 0.2, 0.05, dict(max_gap=4, seed_thr=6.0, chan_thr=2.5, clus_thr=7.0), 3),
     (3000, 768, 2, 4000, 0.01, 0.01, {}, 4),
+    # the gap limit at its maximum over 40 % bad strips (clusters bridge
+    # runs of several bad strips)
+    (100, 256, 2, 400, 0.05, 0.45, dict(max_gap=64), 5),
 ]
 
 
