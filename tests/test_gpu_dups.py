@@ -187,7 +187,9 @@ def test_mask_golden(ctx, cut):
 @pytest.mark.parametrize("S,K,H,NH,min_hits,cut,use_dup,in_place,seed", [
     (1, 1, 48, 10, 3, 3.0, True, False, 0), (300, 6, 48, 2000, 4, 1.0, True, False, 1),
     (5000, 16, 64, 30000, 6, 2.5, False, True, 2), (20000, 6, 48, 0, 3, 3.0, True, False, 3),
-    (20000, 6, 3, 100000, 1, float("inf"), True, True, 4)])
+    (20000, 6, 3, 100000, 1, float("inf"), True, True, 4),
+    # masking has no list-width limit (duplicate removal stops at 64)
+    (500, 4, 100, 3000, 5, 2.0, False, False, 5)])
 def test_mask_parity(ctx, S, K, H, NH, min_hits, cut, use_dup, in_place, seed):
     print(f"mask S={S} K={K} H={H} NH={NH} min_hits={min_hits} cut={cut} dup={use_dup} "
           f"in_place={in_place}", flush=True)
