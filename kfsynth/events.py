@@ -12,8 +12,9 @@ Particles move on helices in a uniform field along +z.  Crossings are found
 by brute force over every surface with the closed-form intersection of the
 particle's transverse circle with each cylinder (and a linear solve in z for
 each disk).  The particle is followed to its earliest crossing; a crossing
-reached while the particle moves radially inward ends it (loopers are not
-followed past their turning point).
+beyond the turning point of its transverse circle (the point farthest from
+the beam line) ends it: loopers are not followed back inward, and a particle
+that leaves the tracker does not re-enter it after a whole loop.
 
 Units: cm, GeV, T, rad.  All arithmetic is float64; the stored hit
 coordinates are float32.
@@ -133,6 +134,10 @@ class Workload:
     seed_id: int = 1
     smear: bool = True
     scatter: bool = True
+    # prior of the fit's start estimate: sigma_pos [cm], sigma_k / |k|,
+    # sigma_phi, sigma_theta (a reconstruction setting carried with the
+    # workload, like the chi2 cut)
+    fit_prior: tuple = (0.1, 0.5, 0.05, 0.05)
 
 
 def _geom_barrel10():
@@ -183,7 +188,12 @@ def workload(name: str, **overrides) -> Workload:
                        tracks_per_event=200000, pt_range=(0.5, 20.0),
                        eta_range=(-1.0, 1.0), noise_per_event=0, ineff=0.0,
                        min_hits=3, max_hits=40, field_scale_true=1.002,
-                       align_sigma=50e-4, seed_id=4),
+                       align_sigma=50e-4, seed_id=4,
+                       # the start estimate comes from the recorded
+                       # (uncorrected) hits; 50 um offsets at the innermost
+                       # radii can exceed a high-pT seed's sagitta, so the
+                       # curvature prior is widened to 5 |k|
+                       fit_prior=(0.1, 5.0, 0.05, 0.05)),
         occ10k=dict(geometry=_geom_full(), bz=3.8, n_events=4,
                     tracks_per_event=10000, pt_range=(0.3, 50.0),
                     eta_range=(-2.5, 2.5), noise_per_event=300000,
@@ -284,6 +294,16 @@ def _simulate(rng, w: Workload, n: int, align: np.ndarray):
         m = idx.size
         best_s = np.full(m, np.inf)
         best_l = np.full(m, -1, dtype=np.int64)
+        # path to the turning point (the point of the transverse circle
+        # farthest from the beam line): a crossing beyond it is either
+        # inward or, after a whole loop outside the tracker, outward again
+        # far from where the particle left; both end the particle
+        with np.errstate(divide="ignore", invalid="ignore"):
+            om_t = np.where(np.abs(om) < 1e-12, 1e-12, om)
+            ccx = xi - np.sin(ph) / om_t
+            ccy = yi + np.cos(ph) / om_t
+            dlt_t = np.mod(np.sign(om_t) * (np.arctan2(ccy, ccx) - np.arctan2(yi - ccy, xi - ccx)), 2.0 * np.pi)
+            s_turn = np.where(np.abs(om) < 1e-12, np.inf, dlt_t / np.abs(om_t))
 
         # --- barrel: transverse circle vs cylinder, closed form
         if bar.size:
@@ -317,6 +337,7 @@ def _simulate(rng, w: Workload, n: int, align: np.ndarray):
                 for root in (-D - sq, -D + sq):
                     s_lin = np.where((disc >= 0) & (root > 1e-9) & (root < s_lin), root, s_lin)
                 s_b = np.where(straight[:, None], s_lin, s_b)
+            s_b = np.where(s_b < s_turn[:, None], s_b, np.inf)
             zc = zi[:, None] + s_b * cot[:, None]
             valid = np.isfinite(s_b) & (np.abs(zc) <= g.hi[bar][None, :])
             # a particle sitting on a cylinder does not re-cross it at s ~ 0
@@ -331,7 +352,7 @@ def _simulate(rng, w: Workload, n: int, align: np.ndarray):
         if dsk.size:
             with np.errstate(divide="ignore", invalid="ignore"):
                 s_d = (z_disk[None, :] - zi[:, None]) / cot[:, None]
-            s_d = np.where(np.isfinite(s_d) & (s_d > 1e-9), s_d, np.inf)
+            s_d = np.where(np.isfinite(s_d) & (s_d > 1e-9) & (s_d < s_turn[:, None]), s_d, np.inf)
             a = 0.5 * om[:, None] * np.where(np.isfinite(s_d), s_d, 0.0)
             chord = np.where(np.abs(a) > 1e-12,
                              np.sin(a) / np.where(a == 0, 1.0, a), 1.0)
