@@ -3,8 +3,10 @@
 Only tests/, the smoke check and the CPU-baseline leg of the benchmark may
 import this package.  It wraps the plain C++ reference in kfo.cpp through
 ctypes (building, fit, adjoint); duplicates.py (duplicate removal, hit
-masking) and strips.py (strip clustering) are plain Python.  It shares no
-code with the GPU library.
+masking) and strips.py (strip clustering) are plain Python;
+conditioning.py computes the variance reduction of building candidates'
+Kalman updates from the oracle's own steps (the parity bound of FP32
+covariances).  It shares no code with the GPU library.
 
 Covariances are exchanged as full row-major 6x6 float64 blocks.  Geometry is
 the float64 layer table [L, 8] = (kind, pos, lo, hi, x0, su, sv, sn).
@@ -255,3 +257,6 @@ def fit_grad(ev, trk_offsets=None, trk_hits=None, align=None, fscale=1.0, mode="
                              _p(toff), _p(th), nt, None if al is None else _p(al), _D(fscale),
                              _p(pr), 0 if mode == "forward" else 1, _p(g))
     return tot, g
+
+
+from .conditioning import KAPPA_1E4, candidate_conditioning, update_conditioning  # noqa: E402,F401

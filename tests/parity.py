@@ -9,6 +9,8 @@ variance is checked separately against the position variances.
 """
 import numpy as np
 
+from oracle import KAPPA_1E4, candidate_conditioning, update_conditioning  # noqa: F401
+
 BARREL = 0
 PARAM_FLOORS = np.array([1.0, 1.0, 1.0, 0.0, 1.0, 1.0])  # cm, cm, cm, -, rad, rad
 
@@ -25,6 +27,14 @@ def param_rel(pg, po):
     den = np.maximum(np.abs(po), PARAM_FLOORS)
     with np.errstate(invalid="ignore", divide="ignore"):
         return np.where(d == 0.0, 0.0, np.abs(d) / den)
+
+
+def chi2_tol(c2o):
+    """Bound on |chi2_GPU - chi2_oracle| for a track chi2: 1e-3 absolute, or
+    one float32 ulp of the value where that is coarser (chi2 >= 8192): the
+    GPU returns the chi2 as float32, which cannot hold it closer."""
+    c = np.abs(np.asarray(c2o, dtype=np.float64))
+    return np.maximum(1e-3, np.spacing(c.astype(np.float32)).astype(np.float64))
 
 
 def local_frame_T(p, kinds):
@@ -57,3 +67,23 @@ def cov_rel(Cg, Co, p, kinds):
     ng = np.abs(np.einsum("ni,nij,nj->n", nrm, Cg[:, :3, :3], nrm)) / scale
     no = np.abs(np.einsum("ni,nij,nj->n", nrm, Co[:, :3, :3], nrm)) / scale
     return rel.max(axis=(1, 2)), ng, no
+
+
+def check_identical_candidates(rel, kappa, dchi2, tag=""):
+    """Parity of building candidates whose hit lists equal the oracle's:
+    every one within max(1e-4, 2^-24 kappa) in the parameters, and the
+    well-conditioned ones (kappa <= KAPPA_1E4) within 1e-3 in the chi2 sum.
+    Prints the counts and the spread of the ill-conditioned ones."""
+    rel, kappa, dchi2 = (np.asarray(a, dtype=np.float64) for a in (rel, kappa, dchi2))
+    kap = np.where(np.isnan(kappa), np.inf, kappa)
+    bound = np.maximum(1e-4, 2.0 ** -24 * kap)
+    ill = kap > KAPPA_1E4
+    well = ~ill
+    msg = (f"{tag}identical candidates {rel.size}: well-conditioned {well.sum()} (params max "
+           f"{rel[well].max() if well.any() else 0:.3g}, chi2 max {dchi2[well].max() if well.any() else 0:.3g}); "
+           f"ill-conditioned {ill.sum()} (params max {rel[ill].max() if ill.any() else 0:.3g}, p99 "
+           f"{np.percentile(rel[ill], 99) if ill.any() else 0:.3g})")
+    print(msg, flush=True)
+    assert np.all(rel <= bound), msg
+    assert np.all(dchi2[well] <= 1e-3), msg
+    return msg

@@ -7,17 +7,20 @@ largest K, the longest search.
 
 Bars: best candidates' hit lists identical for >= 98 % of the sampled seeds
 (candidates whose chi2 sums differ by less than the FP32 rounding of ~20
-pair chi2 may swap ranks), the number of candidates equal, and the best
-candidate's parameters within 1e-4 (floors 1 cm, 1 rad; none for k) for
->= 99 % of the identical ones; fits within 1e-3 absolute in chi2 and 1e-4
-in the parameters, excluding near-tangent tracks (oracle chi2/ndof > 5).
+pair chi2 may swap ranks), the number of candidates equal, and for every
+identical best candidate the parameters within max(1e-4, 2^-24 kappa)
+(floors 1 cm, 1 rad; none for k), kappa being the candidate's largest
+variance reduction in one update (the FP32 covariance of building loses
+about 2^-24 kappa there; see tests/parity.py), and its chi2 sum within
+1e-3 where kappa <= 2^24 * 1e-4; every fitted track within 1e-3 absolute
+in chi2 (one float32 ulp above 8192) and 1e-4 in the parameters.
 """
 import numpy as np
 import pytest
 
 import kfsynth
 import oracle
-from parity import param_rel
+from parity import candidate_conditioning, check_identical_candidates, chi2_tol, param_rel
 
 pytestmark = pytest.mark.gpu
 
@@ -65,19 +68,21 @@ def compare_sampled(ev, g, idx, **okw):
     o = oracle.build_tracks(ev, seeds=ev.seeds[idx], seed_event=ev.trk_event[idx].astype(np.int32),
                             prior=PRIOR, max_hits=48, max_cands=K, **okw)
     same = 0
-    rel = []
     ncand = 0
+    rel, kap, dchi = [], [], []
     for j, s in enumerate(idx):
         gb = g["hits"][s * K]
         ncand += g["n_cands"][s] == o["n"][j]
         if np.array_equal(gb[:48], o["hits"][j, 0, :48]):
             same += 1
             rel.append(param_rel(g["p"][s * K][None], o["p"][j, 0][None]).max())
-    rel = np.asarray(rel)
+            nh = int(o["nhits"][j, 0] + o["nholes"][j, 0])
+            kap.append(candidate_conditioning(ev, ev.seeds[s], o["hits"][j, 0, 3:nh], PRIOR))
+            dchi.append(abs(float(g["chi2"][s * K]) - o["chi2"][j, 0]))
     n = len(idx)
     assert same >= 0.98 * n, f"best identical {same}/{n}"
     assert ncand >= 0.99 * n, f"candidate counts equal {ncand}/{n}"
-    assert np.mean(rel <= 1e-4) >= 0.99, f"params within 1e-4: {np.mean(rel <= 1e-4)}"
+    check_identical_candidates(np.asarray(rel), np.asarray(kap), np.asarray(dchi))
     return same, rel
 
 
@@ -122,10 +127,11 @@ def test_align200k_fit_full_size(dev, kfx):
     soff = np.concatenate([[0], np.cumsum(lens)]).astype(np.int32)
     shits = np.concatenate([ev.trk_hits[toff[i]:toff[i + 1]] for i in idx]).astype(np.int32)
     po, _, c2o, ndo, oko = oracle.fit(ev, trk_offsets=soff, trk_hits=shits, prior=PRIOR)
-    ok = (oko == 1) & (stg[idx] == 1) & (c2o / np.maximum(ndo, 1) <= 5)
+    # every sampled track the oracle fits, badly fitting ones included
+    ok = (oko == 1) & (stg[idx] == 1)
     assert ok.sum() >= 0.95 * len(idx)
     assert np.array_equal(stg[idx] == 1, oko == 1)
-    assert np.abs(c2g[idx][ok] - c2o[ok]).max() <= 1e-3
+    assert np.all(np.abs(c2g[idx][ok] - c2o[ok]) <= chi2_tol(c2o[ok]))
     assert param_rel(pg[idx][ok], po[ok]).max() <= 1e-4
 
 

@@ -19,7 +19,7 @@ import pytest
 
 import kfsynth
 import oracle
-from parity import cov_rel, param_rel
+from parity import candidate_conditioning, check_identical_candidates, chi2_tol, cov_rel, param_rel
 
 pytestmark = pytest.mark.gpu
 
@@ -201,31 +201,32 @@ def fit_compare(kfx, dev, ev, align=None, fscale=1.0):
     okg = out["status"].cpu().numpy() == 1
     c2g = out["chi2"].cpu().numpy()
     assert np.array_equal(okg, oko)
-    good = oko & (c2o / np.maximum(ndo, 1) < 5.0)
+    # every track the oracle fits is compared, badly fitting ones included
+    good = oko
     kinds = ev.geometry.kind[ev.layer[ev.trk_hits[ev.trk_offsets[1:] - 1]]]
     check_states(pg[good], Cg[good], po[good], Co[good], kinds[good], "fit")
     d = np.abs(c2g[good] - c2o[good])
-    assert d.max() <= 1e-3, d.max()
+    assert np.all(d <= chi2_tol(c2o[good])), d.max()
     assert np.array_equal(out["ndof"].cpu().numpy()[:ev.n_tracks], ndo)
     return good, oko
 
 
 def test_fit_barrel10(dev, kfx):
     good, ok = fit_compare(kfx, dev, kfsynth.generate("fit1k"))
-    assert good.sum() >= 0.98 * ok.sum()
+    assert ok.sum() >= 0.98 * len(ok)
 
 
 def test_fit_full_geometry_with_disks(dev, kfx):
     ev = kfsynth.generate(kfsynth.workload("build5k", noise_per_event=0), tracks_per_event=800)
     good, ok = fit_compare(kfx, dev, ev)
-    assert good.sum() >= 0.97 * ok.sum()
+    assert ok.sum() >= 0.97 * len(ok)
 
 
 def test_fit_with_alignment_and_field_scale(dev, kfx):
     ev = kfsynth.generate("align200k", tracks_per_event=600)
     al = ev.align_true.copy()
     good, ok = fit_compare(kfx, dev, ev, align=al, fscale=1.002)
-    assert good.sum() >= 0.98 * ok.sum()
+    assert ok.sum() >= 0.98 * len(ok)
 
 
 def test_fit_short_and_invalid_tracks(dev, kfx):
@@ -292,10 +293,21 @@ def test_build_matches_oracle(dev, kfx, ev_build):
     K = ev.workload.max_cands
     same_best = 0
     same_all = 0
+    rel, kap, dchi = [], [], []
     for s in range(n):
         gb = g["hits"][s * K]
-        same_best += np.array_equal(gb[:48], o["hits"][s, 0, :48])
+        if np.array_equal(gb[:48], o["hits"][s, 0, :48]):
+            same_best += 1
+            rel.append(param_rel(g["p"][s * K][None], o["p"][s, 0][None]).max())
+            nh = int(o["nhits"][s, 0] + o["nholes"][s, 0])
+            kap.append(candidate_conditioning(ev, seeds[s], o["hits"][s, 0, 3:nh], PRIOR))
+            dchi.append(abs(float(g["chi2"][s * K]) - o["chi2"][s, 0]))
         same_all += all(np.array_equal(g["hits"][s * K + j][:48], o["hits"][s, j, :48]) for j in range(K))
+        for j in range(int(o["n"][s])):
+            # equal lists mean equal hit and hole counts
+            if np.array_equal(g["hits"][s * K + j][:48], o["hits"][s, j, :48]):
+                assert g["n_hits"][s * K + j] == o["nhits"][s, j] and g["n_holes"][s * K + j] == o["nholes"][s, j]
+    check_identical_candidates(np.asarray(rel), np.asarray(kap), np.asarray(dchi))
     # candidates whose total chi2 differ by less than the FP32 rounding of a
     # sum of ~20 pair chi2 may swap ranks; the best hit list must agree
     assert same_best >= 0.99 * n, same_best
@@ -383,3 +395,46 @@ def test_short_candidates_preserved(dev, kfx):
         same = [np.array_equal(g["hits"][t * K], o["hits"][t, 0]) for t in cut]
         assert all(same), (mode, same)
         assert all(g["n_hits"][t * K] == o["nhits"][t, 0] for t in cut)
+
+
+def test_non_finite_hits(dev, kfx):
+    """NaN and infinite hit coordinates: the binning gives those hits no bin
+    (as the oracle), building never uses them and a seed that contains one
+    gives no candidate (both paths), a fit that contains one fails; the
+    calls return OK and the other results agree with the oracle."""
+    ev = kfsynth.generate("build5k", tracks_per_event=300)
+    bad = ev.trk_hits[ev.trk_offsets[5] + 4]
+    seedhit = ev.seeds[7, 1]
+    noise = np.nonzero(ev.sim < 0)[0][:50]
+    ev.x = ev.x.copy()
+    ev.y = ev.y.copy()
+    ev.z = ev.z.copy()
+    ev.x[[bad, seedhit]] = np.nan
+    ev.y[noise[:25]] = np.inf
+    ev.z[noise[25:]] = -np.inf
+    ctx = make_ctx(kfx, ev)
+    hits = kfx.DeviceHits.from_events(ev, dev)
+    bins, off, perm = ctx.bin_hits(hits)
+    bo = oracle.bin_hits(ev.geometry, 20, 128, ev.x, ev.y, ev.z, ev.layer)
+    assert np.array_equal(bins.cpu().numpy()[:ev.n_hits], bo)
+    assert np.all(bo[[bad, seedhit, *noise]] == -1)
+    o = oracle.build_tracks(ev, prior=PRIOR, max_hits=48)
+    K = ev.workload.max_cands
+    for mode in (kfx.MODE_FUSED, kfx.MODE_PLAIN):
+        g = run_build(kfx, dev, ev, mode)
+        assert g["n_cands"][7] == 0 and o["n"][7] == 0
+        used = g["hits"][g["hits"] >= 0]
+        assert not np.isin(used, [bad, seedhit, *noise]).any()
+        same = sum(np.array_equal(g["hits"][s * K][:48], o["hits"][s, 0, :48]) for s in range(ev.n_tracks))
+        assert same >= 0.98 * ev.n_tracks
+    out = ctx.fit_tracks(hits, ev.trk_offsets, ev.trk_hits, prior=PRIOR)
+    st = out["status"].cpu().numpy()[:ev.n_tracks]
+    _, _, _, _, oko = oracle.fit(ev, prior=PRIOR)
+    assert np.array_equal(st == 1, oko) and st[5] == 0 and st[7] == 0
+
+
+def test_invalid_device(dev, kfx):
+    for d in (-1, 64):
+        with pytest.raises(kfx.KfxError) as e:
+            kfx.Context(d)
+        assert e.value.code == kfx.KFX_EINVAL
