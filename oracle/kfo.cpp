@@ -507,7 +507,14 @@ static double hit_eta(const Layer& Lr, double x, double y, double z) {
   return std::asinh(Lr.pos / std::sqrt(x * x + y * y));  // r of a float32 hit
 }
 
+static bool finite3(double x, double y, double z) {
+  return std::isfinite(x) && std::isfinite(y) && std::isfinite(z);
+}
+
+// A hit with a coordinate that is not finite has no place on its layer: it
+// gets no bin (-1) and is not indexed, like a hit without a layer.
 static int hit_bin(const Geom& g, int layer, double x, double y, double z) {
+  if (!finite3(x, y, z)) return -1;
   const Layer& Lr = g.L[layer];
   int eb = eta_bin_of(g, Lr, hit_eta(Lr, x, y, z));
   int pb = phi_bin_of(g, std::atan2(y, x));
@@ -532,8 +539,10 @@ static void index_event(const Geom& g, EventHits& ev) {
   for (int h = ev.begin; h < ev.end; ++h) {
     int l = ev.layer[h];
     if (l < 0 || l >= nl) continue;
+    const int b = hit_bin(g, l, ev.x[h], ev.y[h], ev.z[h]);
+    if (b < 0) continue;
     ev.by_layer[l].push_back(h);
-    ev.bins[l][hit_bin(g, l, ev.x[h], ev.y[h], ev.z[h])].push_back(h);
+    ev.bins[l][b].push_back(h);
   }
 }
 
@@ -722,6 +731,7 @@ static bool seed_state(const Geom& g, const EventHits& ev, const int sh[3], cons
   double m[3][3];
   for (int i = 0; i < 3; ++i) {
     m[i][0] = ev.x[sh[i]]; m[i][1] = ev.y[sh[i]]; m[i][2] = ev.z[sh[i]];
+    if (!finite3(m[i][0], m[i][1], m[i][2])) return false;  // a seed needs three real points
   }
   seed_estimate(g, m[0], m[1], m[2], p);
   prior_cov(pr, p, C);
@@ -829,6 +839,9 @@ bool fit_track(const Geom& g, const float* hx, const float* hy, const float* hz,
                const Prior& pr, T pout[6], T Cout[6][6], T& chi2_tot) {
   using std::cos; using std::sin;
   if (n < 3) return false;
+  // every hit must be a real point
+  for (int i = 0; i < n; ++i)
+    if (!finite3(hx[hits[i]], hy[hits[i]], hz[hits[i]])) return false;
   double m0[3][3];
   for (int i = 0; i < 3; ++i) {
     m0[i][0] = hx[hits[i]]; m0[i][1] = hy[hits[i]]; m0[i][2] = hz[hits[i]];
@@ -986,8 +999,13 @@ void kfo_seed_states(const double* layers, int nl, double bz, const float* x, co
   EventHits ev{x, y, z, layer, 0, nhits, {}, {}};
   Prior pr{prior[0], prior[1], prior[2], prior[3]};
   for (int i = 0; i < ns; ++i) {
-    double p[6], C[6][6], c2 = 0;
+    double p[6] = {0, 0, 0, 0, 0, 0}, C[6][6] = {}, c2 = 0;
     ok[i] = seed_state(g, ev, seeds + 3 * i, pr, p, C, c2) ? 1 : 0;
+    if (!ok[i]) {
+      std::memset(p, 0, sizeof(p));
+      std::memset(C, 0, sizeof(C));
+      c2 = 0;
+    }
     std::memcpy(p_out + 6 * i, p, sizeof(p));
     std::memcpy(C_out + 36 * i, C, sizeof(C));
     chi2[i] = c2;

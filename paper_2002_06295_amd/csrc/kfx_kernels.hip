@@ -170,8 +170,8 @@ __global__ void __launch_bounds__(256) k_bin_keys(const Geometry* __restrict__ G
   const int nb = G->n_eta * G->n_phi;
   int bin = -1;
   long key = -1;
-  if (l >= 0 && l < G->n_layers) {
-    bin = hit_bin(*G, l, H.x[i], H.y[i], H.z[i]);
+  if (l >= 0 && l < G->n_layers) bin = hit_bin(*G, l, H.x[i], H.y[i], H.z[i]);
+  if (bin >= 0) {
     const int e = event_of(H.ev_off, H.n_events, i);
     key = ((long)e * G->n_layers + l) * nb + bin;
     // the hit's place among its bin's hits (arrival order; the per-bin sort

@@ -9,10 +9,10 @@
 // Paper: arXiv 2002.06295.  Sec. 1: building is a combinatorial search that
 // starts from a seed in the innermost layers and proceeds outward with the
 // propagate/update Kalman step; fitting applies the Kalman filter to the
-// hits that building found.  Sec. 2: only the best ranking candidates are
-// cloned at each layer, with a per-seed cap, and explored candidates are
-// kept with compact bookkeeping.  Sec. 3: missing hits are counted
-// consistently and enter the ranking score.
+// hits that building found.  Sec. 2: per layer, a seed keeps a bounded number
+// of its children (the highest-ranked ones) and the bookkeeping of the
+// explored candidates is compact.  Sec. 3: holes are counted the same way
+// everywhere and take part in the ranking.
 #pragma once
 
 #include "kfx_math.h"
@@ -28,7 +28,8 @@ constexpr int kSeedHits = 3;
 // (barrel: asinh(z/R) over +-zmax; disk: asinh(Z/r) over [rmin, rmax]) and
 // n_phi equal bins of phi over [-pi, pi).  Computed in FP64 from the FP32
 // hit coordinates; an edge belongs to the upper bin, phi = pi wraps to 0,
-// eta outside the range is clamped.
+// eta outside the range is clamped.  A hit with a coordinate that is not
+// finite gets no bin (-1) and is not indexed.
 KFX_HD int eta_bin(const Geometry& G, const Layer& Lr, double eta) {
   double f = floor((eta - Lr.eta_lo) / (Lr.eta_hi - Lr.eta_lo) * (double)G.n_eta);
   if (f < 0.0) f = 0.0;
@@ -43,7 +44,12 @@ KFX_HD int phi_bin(const Geometry& G, double phi) {
   return b;
 }
 
+KFX_HD bool finite_hit(float x, float y, float z) {
+  return __builtin_isfinite(x) && __builtin_isfinite(y) && __builtin_isfinite(z);
+}
+
 KFX_HD int hit_bin(const Geometry& G, int layer, float x, float y, float z) {
+  if (!finite_hit(x, y, z)) return -1;
   const Layer& Lr = G.L[layer];
   const double xd = x, yd = y, zd = z;
   const double eta = Lr.kind == kBarrel ? asinh(zd / Lr.pos) : asinh(Lr.pos / sqrt(xd * xd + yd * yd));
@@ -456,6 +462,7 @@ KFX_HD bool seed_state(const Geometry& G, const HitsView& H, const int sh[3], co
   for (int i = 0; i < 3; ++i)
     if (sh[i] < 0 || sh[i] >= H.n_hits) return false;
   for (int i = 0; i < 3; ++i) {
+    if (!finite_hit(H.x[sh[i]], H.y[sh[i]], H.z[sh[i]])) return false;  // three real points
     m[i][0] = H.x[sh[i]];
     m[i][1] = H.y[sh[i]];
     m[i][2] = H.z[sh[i]];
@@ -523,6 +530,7 @@ KFX_HD void fit_track(const Geometry& G, const HitsView& H, const int* trk_off, 
   for (int i = 0; ok && i < n; ++i) {
     const int h = trk_hits[b + i];
     if (h < 0 || h >= H.n_hits || H.layer[h] < 0 || H.layer[h] >= G.n_layers) ok = false;
+    else if (!finite_hit(H.x[h], H.y[h], H.z[h])) ok = false;
   }
   if (ok) {
     double m0[3][3];

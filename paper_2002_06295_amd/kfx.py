@@ -75,7 +75,7 @@ class c_strip_calib(ctypes.Structure):
 
 
 class c_cluster_params(ctypes.Structure):
-    _fields_ = [("seed_thr", ctypes.c_float), ("chan_thr", ctypes.c_float), ("clus_thr", ctypes.c_float),
+    _fields_ = [("seed_thr", ctypes.c_float), ("chan_thr", ctypes.c_float), ("clus_thr", ctypes.c_double),
                 ("max_gap", ctypes.c_int32), ("min_charge", ctypes.c_int32)]
 
 
@@ -281,12 +281,12 @@ class Context:
         if not torch.cuda.is_available():
             raise RuntimeError("kfx needs a HIP GPU (torch.cuda.is_available() is False)")
         self.lib = load_library()
-        self.device = torch.device("cuda", device)
         h = ctypes.c_void_p()
         rc = self.lib.kfx_create(int(device), ctypes.byref(h))
         if rc != KFX_OK:
-            raise KfxError(rc, "kfx_create failed")
+            raise KfxError(rc, f"kfx_create failed for device {device}")
         self.h = h
+        self.device = torch.device("cuda", device)
 
     def close(self):
         if getattr(self, "h", None):

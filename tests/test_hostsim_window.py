@@ -100,3 +100,22 @@ def test_window_holds_the_chi2_ellipsoid(hs):
         checked += 1
     assert checked == 240
     assert bad == 0, f"{bad} points of the chi2 ellipsoids fall outside their windows"
+
+
+def test_device_binning_of_non_finite_hits(hs):
+    """The device binning (host build) gives a hit with a NaN or infinite
+    coordinate no bin, as the oracle does, on barrel and disk layers; finite
+    hits agree with the oracle."""
+    import oracle
+    ev = kfsynth.generate("build5k", tracks_per_event=20)
+    tab = np.ascontiguousarray(ev.geometry.as_records(), dtype=np.float64)
+    nan, inf = float("nan"), float("inf")
+    pts = [(nan, 1.0, 1.0), (1.0, nan, 1.0), (1.0, 1.0, nan), (inf, 1.0, 1.0), (1.0, -inf, 1.0),
+           (1.0, 1.0, inf), (30.0, 4.0, 50.0), (-20.0, 50.0, 270.0)]
+    for layer in (5, 20):
+        for x, y, z in pts:
+            b = hs.hs_hit_bin(P(tab), tab.shape[0], layer, x, y, z)
+            bo = oracle.bin_hits(ev.geometry, N_ETA, N_PHI, np.array([x], np.float32), np.array([y], np.float32),
+                                 np.array([z], np.float32), np.array([layer], np.int32))[0]
+            assert b == bo, (layer, x, y, z, b, bo)
+            assert (b == -1) == (not np.isfinite([x, y, z]).all())

@@ -554,3 +554,36 @@ def test_short_candidates_are_preserved():
         exact += (o["nhits"][t, 0] == 6 and row[6:9].tolist() == [-1, -1, -1] and (row[9:] == -3).all())
     # the rest picked up a hit of another particle after a hole or two
     assert exact >= 0.9 * len(cut), exact
+
+
+def test_non_finite_hits_are_not_indexed():
+    """A hit with a NaN or infinite coordinate has no place on its layer:
+    no bin, never compatible, a seed that uses it gives no candidate, a fit
+    that uses it fails; every other result is unchanged."""
+    g = kfsynth.make_geometry(1, 10.0, 10.0, 100.0)
+    nan, inf = np.float32("nan"), np.float32("inf")
+    x = np.array([nan, 1.0, 10.0, -inf, 10.0], np.float32)
+    y = np.array([0.0, inf, 0.0, 0.0, 0.0], np.float32)
+    z = np.array([0.0, 0.0, nan, 0.0, 0.0], np.float32)
+    b = oracle.bin_hits(g, 20, 128, x, y, z, np.zeros(5, np.int32))
+    assert list(b[:4]) == [-1, -1, -1, -1] and b[4] >= 0
+    ev = kfsynth.generate("build5k", tracks_per_event=300)
+    ref = oracle.build_tracks(ev, max_hits=48)
+    bad = ev.trk_hits[ev.trk_offsets[5] + 4]          # a hit of track 5 after its seed
+    seedhit = ev.seeds[7, 1]                          # a seed hit of track 7
+    noise = np.nonzero(ev.sim < 0)[0][:50]            # some noise hits
+    ev.x = ev.x.copy()
+    ev.y = ev.y.copy()
+    ev.x[[bad, seedhit]] = np.nan
+    ev.y[noise] = np.inf
+    out = oracle.build_tracks(ev, max_hits=48)
+    assert out["n"][7] == 0
+    used = out["hits"][out["hits"] >= 0]
+    assert not np.isin(used, [bad, seedhit, *noise]).any()
+    # seeds whose candidates never met a changed hit are untouched
+    touched = np.isin(ref["hits"], [bad, seedhit, *noise]).any(axis=(1, 2))
+    same = ~touched
+    same[7] = False
+    assert np.array_equal(out["hits"][same], ref["hits"][same])
+    p, C, c2, nd, ok = oracle.fit(ev)
+    assert not ok[5] and not ok[7] and ok.sum() >= ev.n_tracks - 2 - 10
