@@ -256,9 +256,11 @@ typedef struct {
 } kfx_strip_calib;
 
 typedef struct {
-  float seed_thr;    /* seed strip: adc > seed_thr * noise (3)               */
-  float chan_thr;    /* cluster strip: adc > chan_thr * noise (2), not bad   */
-  float clus_thr;    /* kept: sum adc^2 > clus_thr^2 * sum noise^2 (5)       */
+  float seed_thr;    /* seed strip: adc > seed_thr * noise (3), float32      */
+  float chan_thr;    /* cluster strip: adc > chan_thr * noise (2), not bad,
+                        float32 product                                      */
+  double clus_thr;   /* kept: sum adc^2 > clus_thr^2 * sum noise^2 (5),
+                        clus_thr^2 formed in float64                         */
   int32_t max_gap;   /* strips between two cluster strips, all bad (1)      */
   int32_t min_charge;/* kept: sum adc >= min_charge                         */
 } kfx_cluster_params;

@@ -863,9 +863,9 @@ int kfx_cluster_strips(kfx_ctx* c, const kfx_digis* d, const kfx_strip_calib* ca
       (int64_t)cal->n_modules * cal->strips_per_module >= INT32_MAX)
     return fail(c, KFX_EINVAL, "bad calibration table size");
   if (!cal->noise || !cal->bad) return fail(c, KFX_EINVAL, "NULL calibration arrays");
-  const float thr[3] = {p->seed_thr, p->chan_thr, p->clus_thr};
-  for (float t : thr)
-    if (!std::isfinite(t) || t < 0.0f) return fail(c, KFX_EINVAL, "thresholds must be finite and >= 0");
+  const double thr[3] = {p->seed_thr, p->chan_thr, p->clus_thr};
+  for (double t : thr)
+    if (!std::isfinite(t) || t < 0.0) return fail(c, KFX_EINVAL, "thresholds must be finite and >= 0");
   if (p->max_gap < 0 || p->max_gap > 64) return fail(c, KFX_EINVAL, "max_gap outside 0..64");
   if (out->capacity < 0 || !out->n_out) return fail(c, KFX_EINVAL, "bad output capacity or NULL n_out");
   if (out->capacity > 0 && (!out->event || !out->module || !out->first || !out->size || !out->charge ||
@@ -887,7 +887,7 @@ int kfx_cluster_strips(kfx_ctx* c, const kfx_digis* d, const kfx_strip_calib* ca
   a.spm = cal->strips_per_module;
   a.seed_thr = p->seed_thr;
   a.chan_thr = p->chan_thr;
-  a.clus_thr2 = (double)p->clus_thr * (double)p->clus_thr;
+  a.clus_thr2 = p->clus_thr * p->clus_thr;
   a.max_gap = p->max_gap;
   a.min_charge = p->min_charge;
   a.bnd = (int*)ws(c, "strip.bnd", (size_t)d->n_events * (strip_chunks(cal->n_modules) + 1) * 4, st, rc);

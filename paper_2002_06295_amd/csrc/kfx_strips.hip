@@ -142,12 +142,16 @@ __global__ void __launch_bounds__(256) k_strip_codes(StripArgs a, int C) {
 __global__ void __launch_bounds__(256) k_strip_flags(StripArgs a) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += gridDim.x * blockDim.x) {
     int kept = 0;
-    const unsigned char ci = a.code[i];
+    // a digi outside every event's range (before the first event, after
+    // the last, or skipped by offsets that go backwards) was not
+    // classified: its code byte is not read
+    const int e = strip_event_of(a.ev_off, a.n_events, i);
+    // clamped to the digis, so that malformed offsets cannot lead a walk
+    // out of the arrays
+    const int ev_start = max(a.ev_off[e], 0), ev_end = min(a.ev_off[e + 1], a.n);
+    const bool in_event = i >= ev_start && i < ev_end;
+    const unsigned char ci = in_event ? a.code[i] : 0;
     if (ci & 1) {
-      const int e = strip_event_of(a.ev_off, a.n_events, i);
-      // clamped to the digis, so that malformed offsets cannot lead a walk
-      // out of the arrays
-      const int ev_start = max(a.ev_off[e], 0), ev_end = min(a.ev_off[e + 1], a.n);
       bool head = true;
       for (int j = i - 1, lo = max(ev_start, i - 1 - a.max_gap); j >= lo; --j)
         if (a.code[j] & 1) {

@@ -117,3 +117,42 @@ def test_repeat_calls_shrinking(ctx):
         o = O.cluster_strips(ev, det)
         for k in o:
             np.testing.assert_array_equal(r[k], o[k], err_msg=k)
+
+
+def test_digis_outside_the_events_are_ignored(ctx):
+    """Digis before the first event's offset or after the last one's end
+    are not clustered, even when the context's workspace still holds the
+    codes of an earlier call over the same digis (they were cluster strips
+    there); a moved boundary between two events moves digis between them."""
+    det = kfsynth.strip_detector(400, 256, seed=8)
+    ev = kfsynth.strip_events(det, 4, particles_per_event=800, noise_frac=0.03, seed=8)
+    off = np.asarray(ev["event_offsets"]).copy()
+    n, r = _gpu(ctx, ev, det)                      # fills the workspace
+    cut = dict(ev)
+    # event 0 starts late, event 3 ends early, and the boundary between
+    # events 1 and 2 moves
+    o2 = off.copy()
+    o2[0] = off[0] + 50
+    o2[2] = off[2] - 300
+    o2[4] = off[4] - 120
+    cut["event_offsets"] = o2
+    print("strips outside events", o2.tolist(), flush=True)
+    n2, r2 = _gpu(ctx, cut, det)
+    o = O.cluster_strips(cut, det)
+    assert n2 == o["charge"].shape[0]
+    for k in o:
+        np.testing.assert_array_equal(r2[k], o[k], err_msg=k)
+
+
+@pytest.mark.parametrize("thr", [5.1, 4.3, 6.7])
+def test_non_dyadic_quadrature_threshold(ctx, thr):
+    """clus_thr crosses the boundary as a float64 and is squared in float64
+    on both sides, so thresholds that float32 cannot hold give the same
+    clusters as the oracle."""
+    det = kfsynth.strip_detector(300, 256, seed=9)
+    ev = kfsynth.strip_events(det, 3, particles_per_event=600, noise_frac=0.03, seed=9)
+    n, r = _gpu(ctx, ev, det, clus_thr=thr)
+    o = O.cluster_strips(ev, det, params=dict(clus_thr=thr))
+    assert n == o["charge"].shape[0]
+    for k in o:
+        np.testing.assert_array_equal(r[k], o[k], err_msg=k)
