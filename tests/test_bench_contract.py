@@ -8,6 +8,7 @@ import os
 import subprocess
 import sys
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -63,3 +64,28 @@ def test_hbm_roofline_and_dedup_bytes():
     out = dict(S=S, K=K, hits=hits, n_cands=torch.tensor([1, 0, 1, 1], dtype=torch.int32))
     entries = 2 + 2
     assert bench.dedup_bytes(out, 5) == S * (12 * H + 52) + 20 * entries + 4 * 5
+
+
+def test_roofline_against_the_fp32_peak():
+    import bench
+    # 256 CUs x 2.4 GHz x 256 FLOP per clock (packed FP32, the published peak)
+    assert bench.FP32_PEAK_TFLOPS == pytest.approx(157.2864)
+    st = [1e6, 2e6, 5e5]
+    r = bench.alu_roofline(st, 1.0, "k", None)
+    flops = 1e6 * 830 + 2e6 * 35 + 5e5 * 500
+    assert r["bound"] == "alu" and r["peak"] == bench.FP32_PEAK_TFLOPS
+    assert r["achieved"] == pytest.approx(flops / 1e-3 / 1e12)
+    assert r["frac"] == pytest.approx(r["achieved"] / 157.2864)
+    assert r["frac_of_issue_peak"] == pytest.approx(2 * r["frac"])
+    assert r["fp64_flop_share"] == pytest.approx((1e6 * 55 + 2e6 * 10 + 5e5 * 500) / flops)
+
+
+def test_parity_sample_spans_the_batch():
+    import bench
+    import kfsynth
+    ev = kfsynth.generate("batch256", n_events=40)
+    idx = bench.parity_sample(ev)
+    assert idx.size >= 2000 and np.unique(idx).size == idx.size
+    assert np.unique(ev.trk_event[idx]).size >= 16
+    one = kfsynth.generate("build5k", tracks_per_event=3000)
+    assert bench.parity_sample(one).size >= 2000
