@@ -13,9 +13,9 @@
  *            proceeds outward; fitting applies the filter to the hits that
  *            building found.
  *   Sec. 2   lightweight geometry: barrel layers at their radius, forward
- *            layers at their z, hits known by their 3D position; only the
- *            best ranking candidates are cloned at each layer, with a
- *            per-seed cap.
+ *            layers at their z, hits known by their 3D position; per
+ *            layer a seed keeps at most K candidates, its highest-ranked
+ *            children.
  *   Sec. 3   missing hits are counted consistently and enter the score.
  *
  * Conventions.  Units cm, GeV, T, rad.  Field along +z.  Track state

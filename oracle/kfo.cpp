@@ -15,8 +15,8 @@
 //     fitting applies the same KF to the hits that building found.
 //   * Sec. 2: lightweight geometry -- barrel layers collapsed to a radius,
 //     forward layers to a z position, hits known by their 3D position -- and
-//     a per-seed cap on the candidates cloned at each layer, keeping only the
-//     best ranking ones.
+//     at most K candidates kept per seed at each layer, the highest-ranked
+//     of its children.
 //   * Sec. 3: missing hits are counted consistently and enter the score that
 //     ranks candidates.
 // The paper gives no formulas for propagation, material, update, score or

@@ -4,8 +4,8 @@
 // ABI (kfx_api.hip).
 //
 // Paper: arXiv 2002.06295, Sec. 1-3 (Kalman-filter track building and
-// fitting over a lightweight barrel/disk geometry, best-ranking candidates
-// cloned with a per-seed cap).
+// fitting over a lightweight barrel/disk geometry, at most K candidates
+// per seed kept at each layer).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

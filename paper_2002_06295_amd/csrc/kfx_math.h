@@ -780,7 +780,9 @@ KFX_HD void add_material(StateT<R>& st, const Layer& Ld) {
 // Start estimate from three hits (FP64): signed curvature of the circle
 // through the transverse points (omega = 2 cross / product of the sides),
 // phi = tangent at hit 1 = chord direction minus half the turning angle,
-// cot(theta) = dz / arc(1 -> 3).  Position = hit 1.
+// cot(theta) = dz / arc(1 -> 3).  Position = hit 1.  Without a field, or
+// for three points on one line, the start is the straight line along the
+// chord 1 -> 3 with k = 0.
 template <class R>
 KFX_HD void seed_estimate(double bz, const double m1[3], const double m2[3], const double m3[3],
                           StateT<R>& st) {
@@ -789,11 +791,16 @@ KFX_HD void seed_estimate(double bz, const double m1[3], const double m2[3], con
   const double cx = m3[0] - m2[0], cy = m3[1] - m2[1];
   const double la = sqrt(ax * ax + ay * ay), lb = sqrt(bx * bx + by * by), lc = sqrt(cx * cx + cy * cy);
   const double cr = ax * by - ay * bx;
-  double omega = 2.0 * cr / (la * lb * lc);
-  if (bz == 0.0) omega = 0.0;
   st.x = m1[0];
   st.y = m1[1];
   st.z = m1[2];
+  if (bz == 0.0 || fabs(2.0 * cr) < 1e-300) {
+    st.k = 0.0;
+    st.phi = atan2(by, bx);
+    st.th = atan2(lb, m3[2] - m1[2]);
+    return;
+  }
+  const double omega = 2.0 * cr / (la * lb * lc);
   st.k = bz == 0.0 ? 0.0 : -omega / (kHcD * bz);
   // turning angle over the chord 1->2 is 2 asin(omega |P2-P1| / 2)
   const double half12 = asin(fmin(1.0, fmax(-1.0, 0.5 * omega * la)));

@@ -252,3 +252,79 @@ extern "C" void hs_frame(const double* table, int nl, int layer, const double* p
     for (int j = 0; j < 3; ++j) h9[3 * a + j] = F.h[a][j];
   for (int i = 0; i < 6; ++i) si6[i] = F.Si[i];
 }
+
+// the building's chi2 of a candidate-hit pair on `layer` (FP32 frame and
+// S^-1 of the prediction, FP64 difference of the positions)
+extern "C" float hs_pair_chi2(const double* table, int nl, int layer, const double* p, const float* cov,
+                              const float* hit3) {
+  Geometry G = make_geo(table, nl, 0.0);
+  State st;
+  to_state(p, cov, st);
+  Frame F;
+  make_frame(st, G.L[layer], F);
+  PairFrame P;
+  pair_frame(st, F, G.L[layer].kind == kDisk, P);
+  return pair_chi2(P, make_float4(hit3[0], hit3[1], hit3[2], 0.0f));
+}
+
+// FP64-covariance forms of the transport and the update (the fit's
+// arithmetic), for comparing the building's FP32 covariance step by step
+extern "C" double hs_predict64(const double* table, int nl, double bz, int layer, const double* p, const double* cov,
+                               double* p_out, double* cov_out) {
+  Geometry G = make_geo(table, nl, bz);
+  StateT<double> st, out;
+  st.x = p[0]; st.y = p[1]; st.z = p[2]; st.k = p[3]; st.phi = p[4]; st.th = p[5];
+  for (int i = 0; i < 21; ++i) st.C[i] = cov[i];
+  double cphi, sphi;
+  sincos_d(st.phi, sphi, cphi);
+  const double kappa = -kHcD * bz;
+  const Layer& L = G.L[layer];
+  const double s = path_to_layer(st, L, L.pos, cphi, sphi, kappa * st.k);
+  if (!(s > 0.0)) return -1.0;
+  transport(st, L, cphi, sphi, s, kappa, out);
+  p_out[0] = out.x; p_out[1] = out.y; p_out[2] = out.z; p_out[3] = out.k; p_out[4] = out.phi; p_out[5] = out.th;
+  for (int i = 0; i < 21; ++i) cov_out[i] = out.C[i];
+  return s;
+}
+
+extern "C" double hs_update64(const double* table, int nl, int layer, const double* p, const double* cov,
+                              const double* m, double* p_out, double* cov_out) {
+  Geometry G = make_geo(table, nl, 0.0);
+  StateT<double> st;
+  st.x = p[0]; st.y = p[1]; st.z = p[2]; st.k = p[3]; st.phi = p[4]; st.th = p[5];
+  for (int i = 0; i < 21; ++i) st.C[i] = cov[i];
+  FrameT<double> F;
+  make_frame(st, G.L[layer], F);
+  const double c2 = kf_update(st, F, m[0], m[1], m[2]);
+  p_out[0] = st.x; p_out[1] = st.y; p_out[2] = st.z; p_out[3] = st.k; p_out[4] = st.phi; p_out[5] = st.th;
+  for (int i = 0; i < 21; ++i) cov_out[i] = st.C[i];
+  return c2;
+}
+
+extern "C" int hs_seed_state64(const double* table, int nl, double bz, const float* x, const float* y,
+                               const float* z, const int* layer, const int* sh, const float* prior, double* p_out,
+                               double* cov_out, double* chi2) {
+  Geometry G = make_geo(table, nl, bz);
+  Prior pr{prior[0], prior[1], prior[2], prior[3]};
+  double m[3][3];
+  for (int i = 0; i < 3; ++i) {
+    m[i][0] = x[sh[i]];
+    m[i][1] = y[sh[i]];
+    m[i][2] = z[sh[i]];
+  }
+  StateT<double> st;
+  seed_estimate(G.bz, m[0], m[1], m[2], st);
+  prior_cov(pr, st);
+  const double kappa = -kHcD * G.bz;
+  double c2sum = 0.0;
+  for (int i = 0; i < 3; ++i) {
+    const Layer& Ld = G.L[layer[sh[i]]];
+    double c2 = 0.0;
+    if (!filter_step(st, Ld, Ld.pos, kappa, i == 0, m[i], c2)) return 0;
+    c2sum += c2;
+  }
+  p_out[0] = st.x; p_out[1] = st.y; p_out[2] = st.z; p_out[3] = st.k; p_out[4] = st.phi; p_out[5] = st.th;
+  for (int i = 0; i < 21; ++i) cov_out[i] = st.C[i];
+  *chi2 = c2sum;
+  return 1;
+}
