@@ -40,10 +40,15 @@ def compile_lib(force: bool = False) -> str:
 
 
 def lib():
+    """The oracle library.  KFO_LIB names a prebuilt one to load instead
+    (the tests' sanitizer build); otherwise libkfo.so is (re)built."""
     global _lib
     if _lib is None:
-        compile_lib()
-        _lib = ctypes.CDLL(_LIB)
+        path = os.environ.get("KFO_LIB")
+        if not path:
+            compile_lib()
+            path = _LIB
+        _lib = ctypes.CDLL(path)
         _lib.kfo_step_compat.restype = ctypes.c_long
         _lib.kfo_fit_grad.restype = ctypes.c_double
     return _lib
