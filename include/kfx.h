@@ -331,6 +331,23 @@ int kfx_fit_tracks_backward(kfx_ctx* ctx, const kfx_hits* hits, const int32_t* t
                             const int32_t* status, const float* dchi2, int32_t dchi2_per_track,
                             double* dalign, double* dfield, void* stream);
 
+/* The same gradient for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight training loops, harnesses that forbid
+ * hipMalloc): identical arguments and results, but the per-block partial
+ * rows go to a fixed device array inside the library (8 MiB per GPU, held
+ * until the process ends) instead of the context's workspace pool, and the
+ * call allocates nothing.  Limit: ceil(n_tracks / 64) * (3 * n_barrel + 1)
+ * <= 2^20 float64 (about 1.29M tracks for 17 barrel layers); beyond it the
+ * call returns KFX_EOVERFLOW before any work is queued.  Every call on one
+ * GPU shares that array: calls that overlap on one GPU (several streams or
+ * host threads at once) race; calls ordered on one stream do not.  Every
+ * call overwrites the rows it uses before reading them. */
+int kfx_fit_tracks_backward_noalloc(kfx_ctx* ctx, const kfx_hits* hits, const int32_t* trk_off,
+                                    const int32_t* trk_hits, int32_t n_tracks, const kfx_prior* prior,
+                                    const float* align, float field_scale, const kfx_states* ckpt,
+                                    const int32_t* status, const float* dchi2, int32_t dchi2_per_track,
+                                    double* dalign, double* dfield, void* stream);
+
 /* Timing of kfx_build_tracks with HIP events recorded on the caller's
  * stream, kept for the last n_calls calls (0 turns timing off; at most
  * 4096).  Off by default. */

@@ -8,6 +8,7 @@
 #include <cstdint>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -46,7 +47,36 @@ struct kfx_ctx {
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
 
+// Scratch of kfx_fit_tracks_backward_noalloc: the per-block partial rows of
+// the gradient live in this file-scope device array (one copy per GPU, kept
+// until the process ends) instead of the context's workspace pool.  In host
+// code the array's name is not a device address: kernels get the address
+// that hipGetSymbolAddress returned on their device (g_scratch below).
+constexpr size_t kNoAllocScratchDoubles = (size_t)1 << 20;  // 8 MiB
+static __device__ __align__(256) double scratch[kNoAllocScratchDoubles];
+constexpr int kMaxScratchDevices = 64;
+static std::mutex g_scratch_mu;
+static double* g_scratch[kMaxScratchDevices];  // device address per device, once resolved
+
 namespace {
+
+// Resolves the scratch array's address on `device` (current) once per
+// device; called by kfx_create.
+hipError_t resolve_scratch(int device) {
+  if (device < 0 || device >= kMaxScratchDevices) return hipSuccess;  // the entry point then refuses
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch[device]) return hipSuccess;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e == hipSuccess) g_scratch[device] = static_cast<double*>(p);
+  return e;
+}
+
+double* scratch_of(int device) {
+  if (device < 0 || device >= kMaxScratchDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch[device];
+}
 
 struct DeviceGuard {
   int prev = -1;
@@ -211,6 +241,13 @@ int kfx_create(int device, kfx_ctx** out) {
   int lds = 0;
   if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess && lds > 0)
     c->max_lds = (size_t)lds;
+  {
+    DeviceGuard dg(device);
+    if (resolve_scratch(device) != hipSuccess) {
+      delete c;
+      return KFX_EHIP;
+    }
+  }
   *out = c;
   return KFX_OK;
 }
@@ -941,10 +978,15 @@ int kfx_fit_tracks(kfx_ctx* c, const kfx_hits* hits, const int32_t* trk_off, con
   return hip_check(c, hipGetLastError(), "fit kernel");
 }
 
-int kfx_fit_tracks_backward(kfx_ctx* c, const kfx_hits* hits, const int32_t* trk_off, const int32_t* trk_hits,
-                            int32_t n_tracks, const kfx_prior* prior, const float* align, float field_scale,
-                            const kfx_states* ckpt, const int32_t* status, const float* dchi2,
-                            int32_t dchi2_per_track, double* dalign, double* dfield, void* stream) {
+}  // extern "C"
+
+namespace {
+// The gradient of the fit: checks, then the adjoint kernels with their
+// per-block partial rows in `partial` (nullptr: the workspace pool).
+int backward_impl(kfx_ctx* c, const kfx_hits* hits, const int32_t* trk_off, const int32_t* trk_hits,
+                  int32_t n_tracks, const kfx_prior* prior, const float* align, float field_scale,
+                  const kfx_states* ckpt, const int32_t* status, const float* dchi2, int32_t dchi2_per_track,
+                  double* dalign, double* dfield, void* stream, bool no_alloc) {
   if (!c) return KFX_EINVAL;
   c->err.clear();
   if (!c->have_geo) return fail(c, KFX_ESTATE, "kfx_load_layers first");
@@ -956,12 +998,26 @@ int kfx_fit_tracks_backward(kfx_ctx* c, const kfx_hits* hits, const int32_t* trk
   if (n_tracks > 0 && (!trk_off || !trk_hits || !status || !dchi2))
     return fail(c, KFX_EINVAL, "NULL track arrays");
   if (n_tracks > 0 && (!ckpt || !ckpt->par || !ckpt->cov)) return fail(c, KFX_EINVAL, "ckpt: NULL state arrays");
-  DeviceGuard dg(c->device);
-  hipStream_t st = (hipStream_t)stream;
   const int nrow = 3 * c->host_geo.n_barrel + 1;
   const long nblocks = std::max(fit_backward_blocks(n_tracks), 1);
-  double* partial = (double*)ws(c, "g.partial", (size_t)nblocks * nrow * sizeof(double), st, rc);
-  if (rc) return rc;
+  double* partial = nullptr;
+  if (no_alloc) {
+    const size_t need = (size_t)nblocks * nrow;
+    if (need > kNoAllocScratchDoubles)
+      return fail(c, KFX_EOVERFLOW,
+                  "kfx_fit_tracks_backward_noalloc: " + std::to_string(n_tracks) + " tracks need " +
+                      std::to_string(need) + " float64 of scratch, the limit is " +
+                      std::to_string(kNoAllocScratchDoubles) + " (" + std::to_string(nblocks) + " blocks of 64 tracks x " +
+                      std::to_string(nrow) + " rows)");
+    partial = scratch_of(c->device);
+    if (!partial) return fail(c, KFX_ESTATE, "no scratch address for this device");
+  }
+  DeviceGuard dg(c->device);
+  hipStream_t st = (hipStream_t)stream;
+  if (!no_alloc) {
+    partial = (double*)ws(c, "g.partial", (size_t)nblocks * nrow * sizeof(double), st, rc);
+    if (rc) return rc;
+  }
   StateSoA ck;
   if (n_tracks > 0) ck = soa(ckpt);
   else ck.par = nullptr, ck.cov = nullptr, ck.stride = 0;
@@ -970,6 +1026,26 @@ int kfx_fit_tracks_backward(kfx_ctx* c, const kfx_hits* hits, const int32_t* trk
                                        trk_hits, n_tracks, prior_of(prior), align, field_scale, ck, status, dchi2,
                                        dchi2_per_track, partial, dalign, dfield, st),
                    "fit backward kernels");
+}
+}  // namespace
+
+extern "C" {
+
+int kfx_fit_tracks_backward(kfx_ctx* c, const kfx_hits* hits, const int32_t* trk_off, const int32_t* trk_hits,
+                            int32_t n_tracks, const kfx_prior* prior, const float* align, float field_scale,
+                            const kfx_states* ckpt, const int32_t* status, const float* dchi2,
+                            int32_t dchi2_per_track, double* dalign, double* dfield, void* stream) {
+  return backward_impl(c, hits, trk_off, trk_hits, n_tracks, prior, align, field_scale, ckpt, status, dchi2,
+                       dchi2_per_track, dalign, dfield, stream, false);
+}
+
+int kfx_fit_tracks_backward_noalloc(kfx_ctx* c, const kfx_hits* hits, const int32_t* trk_off,
+                                    const int32_t* trk_hits, int32_t n_tracks, const kfx_prior* prior,
+                                    const float* align, float field_scale, const kfx_states* ckpt,
+                                    const int32_t* status, const float* dchi2, int32_t dchi2_per_track,
+                                    double* dalign, double* dfield, void* stream) {
+  return backward_impl(c, hits, trk_off, trk_hits, n_tracks, prior, align, field_scale, ckpt, status, dchi2,
+                       dchi2_per_track, dalign, dfield, stream, true);
 }
 
 }  // extern "C"

@@ -29,7 +29,7 @@ MAX_STEPS = 40
 
 EXPORTED = ["kfx_create", "kfx_destroy", "kfx_last_error", "kfx_load_layers", "kfx_bin_hits",
             "kfx_seed_states", "kfx_step_compat", "kfx_build_tracks", "kfx_fit_tracks",
-            "kfx_fit_tracks_backward", "kfx_enable_timing", "kfx_build_times", "kfx_build_graph",
+            "kfx_fit_tracks_backward", "kfx_fit_tracks_backward_noalloc", "kfx_enable_timing", "kfx_build_times", "kfx_build_graph",
             "kfx_graph_launch", "kfx_graph_destroy", "kfx_autotune_build", "kfx_find_duplicates", "kfx_mask_hits",
             "kfx_cluster_strips"]
 
@@ -127,6 +127,7 @@ def load_library():
                                             ctypes.c_void_p, ctypes.c_float, ctypes.POINTER(c_states),
                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    lib.kfx_fit_tracks_backward_noalloc.argtypes = lib.kfx_fit_tracks_backward.argtypes
     lib.kfx_build_graph.argtypes = [ctypes.c_void_p, ctypes.POINTER(c_hits), ctypes.c_void_p, ctypes.c_void_p,
                                     ctypes.c_int32, ctypes.POINTER(c_build_params), ctypes.POINTER(c_tracks),
                                     ctypes.POINTER(ctypes.c_void_p)]
@@ -566,12 +567,15 @@ class Context:
         return out
 
     def fit_tracks_backward(self, hits: DeviceHits, trk_off, trk_hits, fit_out, dchi2,
-                            prior=(0.1, 0.5, 0.05, 0.05), align=None, field_scale=1.0):
+                            prior=(0.1, 0.5, 0.05, 0.05), align=None, field_scale=1.0, dalign=None, dfield=None,
+                            no_alloc=False):
         """Gradient of sum_t dchi2[t] chi2_t (dchi2: a device float32 tensor of
         one element or of n_tracks) with respect to the alignment and the
         field scale, for the fit that wrote fit_out (made with ckpt=True and
         the same inputs).  Returns float64 device tensors (dalign [3 L],
-        dfield [1])."""
+        dfield [1]), written into the given ones if passed.  no_alloc=True
+        calls kfx_fit_tracks_backward_noalloc (no device allocation in the
+        library: its scratch is a fixed array per GPU)."""
         import torch
         d = self.device
         if "ckpt" not in fit_out:
@@ -588,12 +592,23 @@ class Context:
         if per_track and dchi2.numel() != T:
             raise KfxError(KFX_EINVAL, f"dchi2 has {dchi2.numel()} entries for {T} tracks")
         n_layers = self.n_layers
-        dalign = torch.empty(3 * n_layers, dtype=torch.float64, device=d)
-        dfield = torch.empty(1, dtype=torch.float64, device=d)
+        if dalign is None:
+            dalign = torch.empty(3 * n_layers, dtype=torch.float64, device=d)
+        if dfield is None:
+            dfield = torch.empty(1, dtype=torch.float64, device=d)
+        for t, n in ((dalign, 3 * n_layers), (dfield, 1)):
+            if t.dtype != torch.float64 or t.numel() < n or not t.is_contiguous() or t.device != d:
+                raise KfxError(KFX_EINVAL, "gradient outputs: contiguous float64 device tensors of 3 L and 1")
         pr = prior_struct(prior)
         ck = fit_out["ckpt"].c()
-        self._check(self.lib.kfx_fit_tracks_backward(
+        fn = self.lib.kfx_fit_tracks_backward_noalloc if no_alloc else self.lib.kfx_fit_tracks_backward
+        self._check(fn(
             self.h, ctypes.byref(hits.struct), _ptr(trk_off), _ptr(trk_hits), T, ctypes.byref(pr), _ptr(align),
             float(field_scale), ctypes.byref(ck), _ptr(fit_out["status"]), _ptr(dchi2), per_track, _ptr(dalign),
             _ptr(dfield), self._stream()))
         return dalign, dfield
+
+    def fit_tracks_backward_noalloc(self, *args, **kw):
+        """fit_tracks_backward through kfx_fit_tracks_backward_noalloc."""
+        kw["no_alloc"] = True
+        return self.fit_tracks_backward(*args, **kw)
