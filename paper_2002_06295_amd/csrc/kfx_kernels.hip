@@ -452,7 +452,6 @@ __global__ void __launch_bounds__(128) k_build_finalize(BuildArgs a, int fin, Tr
 // path: navigate + transport, window scan, selection (here K rounds of a
 // segmented wavefront minimum over the lanes' child streams) and update;
 // states move between lanes through LDS.
-template <int G_LANES>
 struct FusedShared {
   // per lane: the state its children start from -- the prediction on the
   // next surface, or the current state when its child is a stop child --
@@ -462,10 +461,6 @@ struct FusedShared {
   int layer;
   int meta;
   float chi2;
-  // the lane's children in stream order (keys, codes, chi2 totals)
-  uint64_t ekey[G_LANES + 1];
-  int ecode[G_LANES + 1];
-  float echi2[G_LANES + 1];
   // the child picked for this slot by the selection (written by the winner)
   int sel_code;
   float sel_chi2;
@@ -735,7 +730,7 @@ template <int G_LANES, int OCC, int KM = G_LANES>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC, OCC)))
 k_build_fused(BuildArgs a, TracksOut o, int* seed_counter) {
   extern __shared__ unsigned char smem_raw[];
-  using FS = FusedShared<G_LANES>;
+  using FS = FusedShared;
   FS* sh = reinterpret_cast<FS*>(smem_raw);
   unsigned int* hl = reinterpret_cast<unsigned int*>(smem_raw + sizeof(FS) * blockDim.x);
   // the layer table is read at every step with lane-dependent indices: keep
@@ -796,87 +791,89 @@ k_build_fused(BuildArgs a, TracksOut o, int* seed_counter) {
     const bool active = seed >= 0;
     if (__ballot(active) == 0) break;
 
-    // ---- (a) navigate + transport; the prediction goes to LDS at once (the
-    // lane's children start from it, unless its child is a stop child, which
-    // keeps the current state and overwrites it after the scan)
+    // ---- (a) navigate + transport.  The children's start state goes to
+    // LDS at once: the prediction, or the current state when there is no
+    // next surface (a stop child).  A lane at the hole limit may still end
+    // as a stop child after the scan (no compatible hit): it parks its
+    // current state in its own slot of the candidate buffer (unused by this
+    // kernel after the seed start), so that no current state stays live in
+    // registers through the scan.
     int nl = -2;
-    State pr;
     const bool live = active && (meta_flags(meta) & kFlagLive) && gl < K;
-    if (live) {
-      if (meta_flags(meta) & kFlagDone) {
-        nl = -1;
-      } else {
-        double cphi, sphi;
-        sincos_d(st.phi, sphi, cphi);
-        double s = 0.0;
-        double sth, cth;
-        sincos_d(st.th, sth, cth);
-        nl = navigate(G, layer, st, cphi, sphi, sth, cth, kappa * st.k, s);
-        if (nl >= 0) {
-          transport(st, G.L[nl], cphi, sphi, sth, cth, s, kappa, pr);
-          ++n_steps;
-        }
-      }
-    }
-    me.meta = meta;
-    me.chi2 = chi2;
-    if (nl < 0) lds_put(me, st, layer);
-    // ---- (b) window scan, best K hit children in registers
     BestK<KM> best;
     {
       ScanWin sw;
       PairFrame pf;
-      if (nl >= 0) {
-        lds_put(me, pr, nl);
-        Frame F;
-        const Layer& Ln = G.L[nl];
-        make_frame(pr, Ln, F);
-        sw = scan_win(G, a.B, a.seed_event[seed], nl, window_bins(G, Ln, pr, F, a.cut));
-        pair_frame(pr, F, Ln.kind == kDisk, pf);
+      {
+        State pr;
+        if (live) {
+          if (meta_flags(meta) & kFlagDone) {
+            nl = -1;
+          } else {
+            double cphi, sphi;
+            sincos_d(st.phi, sphi, cphi);
+            double s = 0.0;
+            double sth, cth;
+            sincos_d(st.th, sth, cth);
+            nl = navigate(G, layer, st, cphi, sphi, sth, cth, kappa * st.k, s);
+            if (nl >= 0) {
+              transport(st, G.L[nl], cphi, sphi, sth, cth, s, kappa, pr);
+              ++n_steps;
+            }
+          }
+        }
+        me.meta = meta;
+        me.chi2 = chi2;
+        if (nl < 0) {
+          lds_put(me, st, layer);
+        } else {
+          lds_put(me, pr, nl);
+          if (meta_consec(meta) >= a.max_holes) store_state(a.cand[0], (long)seed * K + gl, st);
+          // ---- (b) the window of the prediction
+          Frame F;
+          const Layer& Ln = G.L[nl];
+          make_frame(pr, Ln, F);
+          sw = scan_win(G, a.B, a.seed_event[seed], nl, window_bins(G, Ln, pr, F, a.cut));
+          pair_frame(pr, F, Ln.kind == kDisk, pf);
+        }
       }
+      // ---- window scan, best K hit children in registers
       n_pairs += (unsigned long long)wave_scan(a.B, G.n_phi, lane, nl >= 0, sw, pf, a.cut, K, a.coop_min, best);
     }
     const KidStream ks = kid_stream(a, live ? meta : 0, chi2, nl, best.n, gl);
-    if (nl >= 0 && ks.stop) lds_put(me, st, layer);
-    // ---- (c) selection: each lane lists its children in stream order in
-    // LDS (hit children by (chi2, hit), then the hole; or its stop child),
-    // then K rounds of a segmented minimum over the lanes' stream heads;
-    // round i fills new slot i (lane gbase + i)
-    int m = 0;
-    if (ks.live) {
-      if (ks.stop) {
-        me.ekey[0] = child_key(ks.nh, ks.nho, ks.chi2, ks.parent, 0);
-        me.ecode[0] = kStop;
-        me.echi2[0] = ks.chi2;
-        m = 1;
-      } else {
-#pragma unroll
-        for (int p = 0; p < KM; ++p)
-          if (p < best.n) {
-            const float tot = ks.chi2 + pair_key_chi2(best.k[p]);
-            me.ekey[p] = child_key(ks.nh + 1, ks.nho, tot, ks.parent, p);
-            me.ecode[p] = pair_key_hit(best.k[p]);
-            me.echi2[p] = tot;
-          }
-        m = best.n;
-        if (ks.hole) {
-          me.ekey[m] = child_key(ks.nh, ks.nho + 1, ks.chi2, ks.parent, K);
-          me.ecode[m] = kHole;
-          me.echi2[m] = ks.chi2;
-          ++m;
-        }
-      }
+    if (nl >= 0 && ks.stop) {
+      State cur;
+      load_state(a.cand[0], (long)seed * K + gl, cur);
+      lds_put(me, cur, layer);
     }
-    // the stream's head and the entry after it are held in registers, so
-    // that a winning lane's next key is at hand in the next round
+    // ---- (c) selection: K rounds of a segmented minimum over the lanes'
+    // stream heads; round i fills new slot i (lane gbase + i).  A lane's
+    // stream is its stop child, or its hit children by (chi2, hit) followed
+    // by the hole; the head is formed from the front of the best-K list,
+    // which shifts by one when the lane wins.
     int idx = 0;
-    uint64_t head = m > 0 ? me.ekey[0] : ~0ull;
-    uint64_t next = m > 1 ? me.ekey[1] : ~0ull;
-    int hcode = m > 0 ? me.ecode[0] : kStop;
-    float hchi2 = m > 0 ? me.echi2[0] : 0.0f;
     int my_parent = -1, my_code = kStop;
     float my_chi2 = 0.0f;
     for (int i = 0; i < K; ++i) {
+      uint64_t head = ~0ull;
+      int hcode = kStop;
+      float hchi2 = 0.0f;
+      if (ks.live) {
+        if (ks.stop) {
+          if (idx == 0) {
+            head = child_key(ks.nh, ks.nho, ks.chi2, ks.parent, 0);
+            hchi2 = ks.chi2;
+          }
+        } else if (idx < best.n) {
+          hchi2 = ks.chi2 + pair_key_chi2(best.k[0]);
+          head = child_key(ks.nh + 1, ks.nho, hchi2, ks.parent, idx);
+          hcode = pair_key_hit(best.k[0]);
+        } else if (idx == best.n && ks.hole) {
+          head = child_key(ks.nh, ks.nho + 1, ks.chi2, ks.parent, K);
+          hcode = kHole;
+          hchi2 = ks.chi2;
+        }
+      }
       const uint64_t mn = group_min<G_LANES>(head);
       const unsigned long long win = __ballot(head == mn && mn != ~0ull) & gmask;
       // winner lane in the wave (unique: keys differ by parent slot); it
@@ -887,11 +884,9 @@ k_build_fused(BuildArgs a, TracksOut o, int* seed_counter) {
         sh[gbase + i].sel_code = hcode;
         sh[gbase + i].sel_chi2 = hchi2;
         ++idx;
-        head = next;
-        const bool more = idx < m;
-        hcode = more ? me.ecode[idx] : kStop;
-        hchi2 = more ? me.echi2[idx] : 0.0f;
-        next = idx + 1 < m ? me.ekey[idx + 1] : ~0ull;
+#pragma unroll
+        for (int q = 0; q + 1 < KM; ++q) best.k[q] = best.k[q + 1];
+        best.k[KM - 1] = kNoKey;
       }
     }
     wave_sync();
@@ -900,12 +895,14 @@ k_build_fused(BuildArgs a, TracksOut o, int* seed_counter) {
       my_chi2 = me.sel_chi2;
     }
     // ---- (d) children: copy the parent's state from LDS, update hit children
+    // (the lane's state is reassigned on every path, so that the old one is
+    // dead from the prediction on and holds no registers through the scan)
     int new_meta = 0, new_layer = -1;
+    const FS& par = sh[gbase + (my_parent >= 0 ? my_parent : 0)];
+    lds_get(par, st);
     if (active && gl < K) {
       if (my_parent >= 0) {
-        const FS& par = sh[gbase + my_parent];
-        State ns;
-        lds_get(par, ns);
+        State& ns = st;
         const int pm = par.meta;
         new_layer = par.layer;
         if (my_code == kStop) {
@@ -918,7 +915,6 @@ k_build_fused(BuildArgs a, TracksOut o, int* seed_counter) {
         } else {
           new_meta = meta_pack(meta_nhits(pm), meta_nholes(pm) + 1, meta_consec(pm) + 1, kFlagLive);
         }
-        st = ns;
       }
       hl[t * blockDim.x + threadIdx.x] = hist_pack(my_parent >= 0 ? my_code : kStop, my_parent);
     }
@@ -1315,9 +1311,8 @@ void launch_build_fused(const BuildArgs& a, const TracksOut& o, int* seed_counte
 // Dynamic LDS of a fused launch: the lanes' state slots and their history
 // words (one per step); the layer table comes on top of it.
 size_t fused_lds_bytes(int lanes, int threads, int max_steps) {
-  const size_t fs = lanes == 4 ? sizeof(FusedShared<4>) : lanes == 8 ? sizeof(FusedShared<8>)
-                                                                     : sizeof(FusedShared<16>);
-  return (fs + 4 * (size_t)max_steps) * threads;
+  (void)lanes;
+  return (sizeof(FusedShared) + 4 * (size_t)max_steps) * threads;
 }
 size_t fused_static_lds_bytes() { return sizeof(Geometry); }
 
