@@ -587,3 +587,104 @@ def test_non_finite_hits_are_not_indexed():
     assert np.array_equal(out["hits"][same], ref["hits"][same])
     p, C, c2, nd, ok = oracle.fit(ev)
     assert not ok[5] and not ok[7] and ok.sum() >= ev.n_tracks - 2 - 10
+
+
+def _python_beam(ev, seed, K, max_holes, cut, prior):
+    """Reading 11 written out in Python over the oracle's per-step
+    primitives (step_compat: navigation, prediction and the compatible hits;
+    update: the Kalman update): every child of every candidate is listed,
+    and the K best are taken by a heap selection on the ranking key (hits
+    desc, holes asc, chi2 asc, parent asc, hit index asc with holes and
+    stops last), independent of the oracle's own sort-and-truncate."""
+    import heapq
+    p, C, c2, ok = oracle.seed_states(ev, seeds=np.asarray([seed], np.int32), prior=prior)
+    if not ok[0]:
+        return []
+    beam = [dict(p=p[0], C=C[0], chi2=c2[0], layer=int(ev.layer[seed[2]]), nh=3, nho=0, consec=0,
+                 done=False, hits=[int(h) for h in seed])]
+    for _ in range(64):
+        if all(c["done"] for c in beam):
+            break
+        kids, pred = [], {}
+        for slot, c in enumerate(beam):
+            stop = (slot, -2, c["nh"], c["nho"], c["chi2"])
+            if c["done"]:
+                kids.append(stop)
+                continue
+            nl, p1, C1, off, ph, pc = oracle.step_compat(ev, 0, [c["layer"]], c["p"][None], c["C"][None],
+                                                         chi2_cut=cut)
+            if nl[0] < 0:
+                kids.append(stop)
+                continue
+            pred[slot] = (int(nl[0]), p1[0], C1[0])
+            n0 = len(kids)
+            for h, x2 in zip(ph[off[0]:off[1]], pc[off[0]:off[1]]):
+                kids.append((slot, int(h), c["nh"] + 1, c["nho"], c["chi2"] + x2))
+            if c["consec"] < max_holes:
+                kids.append((slot, -1, c["nh"], c["nho"] + 1, c["chi2"]))
+            if len(kids) == n0:
+                kids.append(stop)
+        best = heapq.nsmallest(K, kids, key=lambda k: (-k[2], k[3], k[4], k[0], k[1] % (1 << 32)))
+        nb = []
+        for parent, hit, nh, nho, x2 in best:
+            c = dict(beam[parent])
+            c["hits"] = list(c["hits"])
+            if hit == -2:
+                c["done"] = True
+            else:
+                nl, p1, C1 = pred[parent]
+                c["layer"] = nl
+                if hit >= 0:
+                    m = np.array([ev.x[hit], ev.y[hit], ev.z[hit]], np.float64)
+                    c["p"], c["C"], _ = oracle.update(ev.geometry, nl, p1, C1, m)
+                    c.update(nh=nh, consec=0, chi2=x2)
+                    c["hits"].append(hit)
+                else:
+                    c.update(p=p1, C=C1, nho=nho, consec=c["consec"] + 1)
+                    c["hits"].append(-1)
+            nb.append(c)
+        beam = nb
+    return beam
+
+
+def _beam_event(ineff, dup):
+    """A small build5k-like event (60 tracks, 3000 noise hits); with dup,
+    exact copies of 40 hits of the first tracks (not their seed hits)
+    appended, so that children of one parent tie in chi2 (broken by hit
+    index) and twin candidates make children of different parents tie
+    (broken by parent slot)."""
+    import dataclasses
+    w = kfsynth.workload("build5k", tracks_per_event=60, noise_per_event=3000, ineff=ineff)
+    ev = kfsynth.generate(w)
+    if dup:
+        src = np.concatenate([ev.trk_hits[ev.trk_offsets[t] + 3:ev.trk_offsets[t + 1]] for t in range(12)])[:40]
+        cat = lambda a: np.concatenate([a, a[src]])  # noqa: E731
+        ev = dataclasses.replace(ev, x=cat(ev.x), y=cat(ev.y), z=cat(ev.z), layer=cat(ev.layer), sim=cat(ev.sim),
+                                 event_offsets=np.array([0, ev.n_hits + len(src)], np.int32))
+    return ev
+
+
+@pytest.mark.parametrize("K,ineff,max_holes,dup", [(1, 0.01, 3, False), (3, 0.01, 3, False), (6, 0.01, 3, False),
+                                                   (40, 0.01, 3, False), (6, 0.3, 1, False), (4, 0.3, 2, True),
+                                                   (6, 0.01, 3, True)])
+def test_beam_search_matches_heap_selection(K, ineff, max_holes, dup):
+    """The oracle's building (sort of all children, truncate to K) against
+    the Python beam of _python_beam: the same candidates, in the same order,
+    with the same hit lists, counts, chi2 and states, for K from 1 (greedy)
+    to 40 (no child dropped on these seeds), with many holes against a low
+    hole limit, and with exact ties (duplicated hits)."""
+    ev = _beam_event(ineff, dup)
+    w = ev.workload
+    prior = oracle.DEFAULT_PRIOR
+    seeds = ev.seeds[:12]
+    o = oracle.build_tracks(ev, seeds=seeds, seed_event=np.zeros(len(seeds), np.int32), max_cands=K,
+                            max_holes=max_holes, max_hits=64, prior=prior)
+    for i, s in enumerate(seeds):
+        ref = _python_beam(ev, s, K, max_holes, w.chi2_cut, prior)
+        assert o["n"][i] == len(ref)
+        for j, c in enumerate(ref):
+            row = o["hits"][i, j]
+            assert row[:len(c["hits"])].tolist() == c["hits"] and (row[len(c["hits"]):] == -3).all()
+            assert o["nhits"][i, j] == c["nh"] and o["nholes"][i, j] == c["nho"]
+            assert abs(o["chi2"][i, j] - c["chi2"]) <= 1e-9 * max(1.0, abs(c["chi2"]))
+            np.testing.assert_allclose(o["p"][i, j], c["p"], rtol=1e-12, atol=1e-12)
