@@ -535,12 +535,15 @@ int build_impl(kfx_ctx* c, const kfx_hits* hits, const int32_t* seeds, const int
   a.sel_parent = (int*)ws(c, "b.selp", N * 4, st, rc); if (rc) return rc;
   a.sel_code = (int*)ws(c, "b.selc", N * 4, st, rc); if (rc) return rc;
   a.sel_chi2 = (float*)ws(c, "b.selx", N * 4, st, rc); if (rc) return rc;
+  // the per-step history in HBM: parent and code arrays of the plain path,
+  // one packed word per entry for the fused kernel
   if (p->mode == KFX_MODE_PLAIN) {
-    // the per-step history in HBM (the fused kernel keeps it in LDS)
     a.hist_parent = (signed char*)ws(c, "b.histp", (size_t)N * p->max_steps, st, rc); if (rc) return rc;
     a.hist_code = (int*)ws(c, "b.histc", (size_t)N * p->max_steps * 4, st, rc); if (rc) return rc;
-    a.n_steps = (int*)ws(c, "b.nsteps", (size_t)std::max(n_seeds, 1) * 4, st, rc); if (rc) return rc;
+  } else {
+    a.hist_word = (unsigned int*)ws(c, "b.histw", (size_t)N * p->max_steps * 4, st, rc); if (rc) return rc;
   }
+  a.n_steps = (int*)ws(c, "b.nsteps", (size_t)std::max(n_seeds, 1) * 4, st, rc); if (rc) return rc;
   a.stats = (unsigned long long*)out->stats;
 
   TracksOut o;

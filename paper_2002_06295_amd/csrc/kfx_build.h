@@ -47,6 +47,9 @@ struct BuildArgs {
   // child code (the fused kernel keeps its own in LDS)
   signed char* hist_parent;
   int* hist_code;
+  // history of the fused kernel, per seed: [S][max_steps][K] words, the
+  // child's code + 2 in bits 0-26 and its parent slot + 1 in bits 27-31
+  unsigned int* hist_word;
   int* n_steps;           // [S] steps recorded
   unsigned long long* stats;  // steps, pairs, updates
 };
@@ -287,19 +290,18 @@ struct TracksOut {
   int max_hits;
 };
 
-// Output of one final slot (m its meta word, T the seed's step count): the
-// hit list rebuilt from the per-step history by one backward walk over the
-// parent pointers (the seed hits, then one entry per step with a hit or a
-// hole, n_hits + n_holes entries in all; stop entries add none), the
-// counts, the chi2 sum and the state.  hist(t, slot, code, parent) reads
-// the history entry of step t and slot.
+// Hit list of one final slot: the seed hits, then one entry per step with
+// a hit or a hole (-1), `total` entries in all (stop entries add none),
+// rebuilt from the per-step history by one backward walk over the parent
+// pointers; the rest of the row -3 (all of it for a slot without a
+// candidate).  T is the seed's step count; hist(t, slot, code, parent)
+// reads the history entry of step t and slot.
 template <class Hist>
-KFX_HD void write_slot_output(const BuildArgs& a, const TracksOut& o, int s, int j, int T, int m, float chi2,
-                              const State& st, const Hist& hist) {
+KFX_HD void write_slot_hits(const BuildArgs& a, const TracksOut& o, int s, int j, int T, bool live, int total,
+                            const Hist& hist) {
   const long slot = (long)s * a.K + j;
   int* out = o.hits + slot * o.max_hits;
-  const bool live = (meta_flags(m) & kFlagLive) != 0;
-  const int total = live ? meta_nhits(m) + meta_nholes(m) : 0;
+  if (!live) total = 0;
   {
     // unused entries: one by one up to a 16-byte boundary, then four at a
     // time (when the row is 16-byte aligned), then the rest
@@ -310,16 +312,7 @@ KFX_HD void write_slot_output(const BuildArgs& a, const TracksOut& o, int s, int
     }
     for (; q < o.max_hits; ++q) out[q] = -3;
   }
-  if (!live) {
-    o.n_hits[slot] = 0;
-    o.n_holes[slot] = 0;
-    o.chi2[slot] = 0.0f;
-    State z;
-    z.x = z.y = z.z = z.k = z.phi = z.th = 0.0;
-    for (int q = 0; q < 21; ++q) z.C[q] = 0.0f;
-    store_state(o.state, slot, z);
-    return;
-  }
+  if (!live) return;
   for (int q = 0; q < kSeedHits && q < o.max_hits; ++q) out[q] = a.seeds[3 * s + q];
   int w = total - 1, cj = j;
   for (int t = T - 1; t >= 0; --t) {
@@ -330,11 +323,36 @@ KFX_HD void write_slot_output(const BuildArgs& a, const TracksOut& o, int s, int
       --w;
     }
     cj = parent;
+    if (cj < 0) break;  // (a slot without a candidate has no parent)
+  }
+}
+
+// Counts, chi2 sum and state of one final slot (m its meta word); zeros for
+// a slot without a candidate.
+KFX_HD void write_slot_summary(const TracksOut& o, long slot, int m, float chi2, const State& st) {
+  if (!(meta_flags(m) & kFlagLive)) {
+    o.n_hits[slot] = 0;
+    o.n_holes[slot] = 0;
+    o.chi2[slot] = 0.0f;
+    State z;
+    z.x = z.y = z.z = z.k = z.phi = z.th = 0.0;
+    for (int q = 0; q < 21; ++q) z.C[q] = 0.0f;
+    store_state(o.state, slot, z);
+    return;
   }
   o.n_hits[slot] = meta_nhits(m);
   o.n_holes[slot] = meta_nholes(m);
   o.chi2[slot] = chi2;
   store_state(o.state, slot, st);
+}
+
+// The whole output of one final slot.
+template <class Hist>
+KFX_HD void write_slot_output(const BuildArgs& a, const TracksOut& o, int s, int j, int T, int m, float chi2,
+                              const State& st, const Hist& hist) {
+  const bool live = (meta_flags(m) & kFlagLive) != 0;
+  write_slot_hits(a, o, s, j, T, live, meta_nhits(m) + meta_nholes(m), hist);
+  write_slot_summary(o, (long)s * a.K + j, m, chi2, st);
 }
 
 // History entries of the plain path (HBM, per seed, step and slot).
@@ -347,6 +365,21 @@ struct HbmHist {
     parent = a->hist_parent[h];
   }
 };
+
+// History entries of the fused kernel (HBM, one packed word per seed, step
+// and slot).
+struct HbmWordHist {
+  const BuildArgs* a;
+  int s;
+  KFX_HD void operator()(int t, int j, int& code, int& parent) const {
+    const unsigned int e = a->hist_word[hist_index(*a, s, t, j)];
+    code = (int)(e & 0x7ffffffu) - 2;
+    parent = (int)(e >> 27) - 1;
+  }
+};
+KFX_HD unsigned int hist_word_pack(int code, int parent) {
+  return (unsigned int)(code + 2) | ((unsigned int)(parent + 1) << 27);
+}
 
 // The same for a slot of the plain path's final candidate buffer.
 KFX_HD void finalize_slot(const BuildArgs& a, int fin, const TracksOut& o, int s, int j) {

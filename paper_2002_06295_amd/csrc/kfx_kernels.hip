@@ -443,6 +443,50 @@ __global__ void __launch_bounds__(128) k_build_finalize(BuildArgs a, int fin, Tr
   }
 }
 
+// Hit lists of the fused build (the fused kernel wrote the counts, chi2
+// sums and states itself).  A block takes `rs` consecutive seeds (256 / the
+// power of two >= K, so that the walks fill the block): it
+// first copies their histories (n_steps x K words each, contiguous in HBM)
+// into LDS with coalesced loads, then one thread per (seed, slot) walks its
+// slot's parent pointers in LDS and writes the row.  A walk is a chain of
+// dependent reads; in LDS each costs tens of cycles instead of an HBM
+// round trip.
+constexpr int kRowThreads = 256;
+
+struct LdsWordHist {
+  const unsigned int* h;  // the seed's history, [t][K]
+  int K;
+  __device__ void operator()(int t, int j, int& code, int& parent) const {
+    const unsigned int e = h[t * K + j];
+    code = (int)(e & 0x7ffffffu) - 2;
+    parent = (int)(e >> 27) - 1;
+  }
+};
+
+__global__ void __launch_bounds__(kRowThreads) k_build_fused_rows(BuildArgs a, TracksOut o, int rs) {
+  extern __shared__ unsigned int hist_lds[];  // [rs][max_steps][K]
+  __shared__ int nst[kRowThreads / 4];
+  const int K = a.K;
+  const long s0 = (long)blockIdx.x * rs;
+  const int ns = (int)min((long)rs, (long)a.n_seeds - s0);
+  if (threadIdx.x < ns) nst[threadIdx.x] = min(a.n_steps[s0 + threadIdx.x], a.max_steps);
+  __syncthreads();
+  const int per = a.max_steps * K;  // words per seed
+  const unsigned int* src = a.hist_word + s0 * per;
+  for (int i = threadIdx.x; i < ns * per; i += kRowThreads) {
+    const int sl = i / per, t = (i % per) / K;
+    if (t < nst[sl]) hist_lds[i] = src[i];
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < ns * K; q += kRowThreads) {
+    const int sl = q / K, j = q % K;
+    const long s = s0 + sl, slot = s * K + j;
+    const bool live = j < o.n_cands[s];
+    write_slot_hits(a, o, (int)s, j, nst[sl], live, live ? o.n_hits[slot] + o.n_holes[slot] : 0,
+                    LdsWordHist{hist_lds + sl * per, K});
+  }
+}
+
 // ---------------------------------------------- fused persistent kernel (a12)
 // One wavefront runs 64 / G seed groups of G lanes (G = lanes per seed,
 // a power of two >= K); each lane holds one candidate slot in registers
@@ -510,6 +554,30 @@ __device__ inline uint64_t group_min(uint64_t v) {
   v = dpp_min_step<0x4E>(v);                // quad_perm [2, 3, 0, 1]
   v = dpp_min_step<0xB1>(v);                // quad_perm [1, 0, 3, 2]
   return v;
+}
+
+// Navigation of the fused kernel, kept out of line: inlined into the
+// persistent loop, its FP64 crossing code raised the loop's register peak by
+// about a hundred VGPRs (the scheduler interleaves it with the live state of
+// the other phases); as a call it needs no more than its own working set.
+// Scalars in, scalars out: nothing goes through scratch memory.
+struct NavResult {
+  double s;
+  int layer;
+};
+__device__ __attribute__((noinline)) NavResult navigate_call(const Geometry& G, int cur, double x, double y, double z,
+                                                             double k, double phi, double th, double cphi, double sphi,
+                                                             double sth, double cth, double omega) {
+  State st;
+  st.x = x;
+  st.y = y;
+  st.z = z;
+  st.k = k;
+  st.phi = phi;
+  st.th = th;
+  NavResult r;
+  r.layer = navigate(G, cur, st, cphi, sphi, sth, cth, omega, r.s);
+  return r;
 }
 
 // ---- window scan of a wavefront -----------------------------------------
@@ -708,22 +776,6 @@ __device__ int wave_scan(const BinIndex& B, int n_phi, int lane, bool has, const
   return found;
 }
 
-// History of the fused kernel in LDS: one word per lane and step, the
-// child's code + 2 in bits 0-26 (hit indices below 2^27 - 2) and its parent
-// slot + 1 in bits 27-31; column = the lane in the block.
-__device__ inline unsigned int hist_pack(int code, int parent) {
-  return (unsigned int)(code + 2) | ((unsigned int)(parent + 1) << 27);
-}
-struct LdsHist {
-  const unsigned int* h;
-  int stride, base;
-  __device__ void operator()(int t, int j, int& code, int& parent) const {
-    const unsigned int e = h[t * stride + base + j];
-    code = (int)(e & 0x7ffffffu) - 2;
-    parent = (int)(e >> 27) - 1;
-  }
-};
-
 // KM: capacity of a candidate's best-K list (>= K; the lane count unless a
 // shorter list is instantiated for smaller K)
 template <int G_LANES, int OCC, int KM = G_LANES>
@@ -732,7 +784,6 @@ k_build_fused(BuildArgs a, TracksOut o, int* seed_counter) {
   extern __shared__ unsigned char smem_raw[];
   using FS = FusedShared;
   FS* sh = reinterpret_cast<FS*>(smem_raw);
-  unsigned int* hl = reinterpret_cast<unsigned int*>(smem_raw + sizeof(FS) * blockDim.x);
   // the layer table is read at every step with lane-dependent indices: keep
   // a copy in LDS
   __shared__ Geometry g_lds;
@@ -750,9 +801,13 @@ k_build_fused(BuildArgs a, TracksOut o, int* seed_counter) {
   const double kappa = -kHcD * G.bz;
   const unsigned long long gmask = ((G_LANES == 64) ? ~0ull : ((1ull << G_LANES) - 1ull)) << (lane & ~(G_LANES - 1));
 
-  unsigned long long n_steps = 0, n_pairs = 0, n_upd = 0;
+  // per-lane counters (a lane sees at most a few thousand steps per launch)
+  unsigned int n_steps = 0, n_pairs = 0, n_upd = 0;
   // groups beyond the wave's quota never take a seed
   int seed = (lane / G_LANES) < a.groups_per_wave ? -1 : -2;
+  // a group's next seed is fetched when it takes its current one, so that
+  // the counter's latency overlaps the search (first lane of the group)
+  int pend = (seed == -1 && gl == 0) ? atomicAdd(seed_counter, 1) : -1;
   int t = 0;
   // register state of this lane's slot
   State st;
@@ -764,11 +819,10 @@ k_build_fused(BuildArgs a, TracksOut o, int* seed_counter) {
     // a group without a seed takes the next one (all lanes take part in
     // the broadcast; only groups that need a seed use it)
     const bool need = seed == -1;
-    int ns = -1;
-    if (need && gl == 0) ns = atomicAdd(seed_counter, 1);
-    ns = __shfl(ns, gbase & 63, 64);
+    const int ns = __shfl(pend, gbase & 63, 64);
     if (need) {
       if (ns < a.n_seeds) {
+        if (gl == 0) pend = atomicAdd(seed_counter, 1);
         seed = ns;
         t = 0;
         meta = 0;
@@ -815,7 +869,10 @@ k_build_fused(BuildArgs a, TracksOut o, int* seed_counter) {
             double s = 0.0;
             double sth, cth;
             sincos_d(st.th, sth, cth);
-            nl = navigate(G, layer, st, cphi, sphi, sth, cth, kappa * st.k, s);
+            const NavResult r = navigate_call(G, layer, st.x, st.y, st.z, st.k, st.phi, st.th, cphi, sphi, sth, cth,
+                                              kappa * st.k);
+            nl = r.layer;
+            s = r.s;
             if (nl >= 0) {
               transport(st, G.L[nl], cphi, sphi, sth, cth, s, kappa, pr);
               ++n_steps;
@@ -838,7 +895,7 @@ k_build_fused(BuildArgs a, TracksOut o, int* seed_counter) {
         }
       }
       // ---- window scan, best K hit children in registers
-      n_pairs += (unsigned long long)wave_scan(a.B, G.n_phi, lane, nl >= 0, sw, pf, a.cut, K, a.coop_min, best);
+      n_pairs += (unsigned int)wave_scan(a.B, G.n_phi, lane, nl >= 0, sw, pf, a.cut, K, a.coop_min, best);
     }
     const KidStream ks = kid_stream(a, live ? meta : 0, chi2, nl, best.n, gl);
     if (nl >= 0 && ks.stop) {
@@ -874,6 +931,8 @@ k_build_fused(BuildArgs a, TracksOut o, int* seed_counter) {
           hchi2 = ks.chi2;
         }
       }
+      // no group of the wave has a child left: the remaining slots stay empty
+      if (__ballot(head != ~0ull) == 0) break;
       const uint64_t mn = group_min<G_LANES>(head);
       const unsigned long long win = __ballot(head == mn && mn != ~0ull) & gmask;
       // winner lane in the wave (unique: keys differ by parent slot); it
@@ -916,7 +975,7 @@ k_build_fused(BuildArgs a, TracksOut o, int* seed_counter) {
           new_meta = meta_pack(meta_nhits(pm), meta_nholes(pm) + 1, meta_consec(pm) + 1, kFlagLive);
         }
       }
-      hl[t * blockDim.x + threadIdx.x] = hist_pack(my_parent >= 0 ? my_code : kStop, my_parent);
+      a.hist_word[hist_index(a, seed, t, gl)] = hist_word_pack(my_parent >= 0 ? my_code : kStop, my_parent);
     }
     wave_sync();
     if (active) {
@@ -929,11 +988,14 @@ k_build_fused(BuildArgs a, TracksOut o, int* seed_counter) {
     const bool running = active && (meta_flags(meta) & kFlagLive) && !(meta_flags(meta) & kFlagDone);
     const unsigned long long run_mask = __ballot(running) & gmask;
     if (active && (run_mask == 0 || t >= a.max_steps)) {
-      // the seed's output: each lane rebuilds its slot's hit list from the
-      // group's history in LDS (written before the wave sync above)
+      // the seed's counts, chi2 sums and states; its hit lists are rebuilt
+      // from the history by k_build_fused_rows after this kernel
       const unsigned long long live_mask = __ballot(gl < K && (meta_flags(meta) & kFlagLive)) & gmask;
-      if (gl == 0) o.n_cands[seed] = __popcll(live_mask);
-      if (gl < K) write_slot_output(a, o, seed, gl, t, meta, chi2, st, LdsHist{hl, (int)blockDim.x, gbase});
+      if (gl == 0) {
+        o.n_cands[seed] = __popcll(live_mask);
+        a.n_steps[seed] = t;
+      }
+      if (gl < K) write_slot_summary(o, (long)seed * K + gl, meta, chi2, st);
       seed = -1;
     }
   }
@@ -1306,13 +1368,18 @@ void launch_build_fused(const BuildArgs& a, const TracksOut& o, int* seed_counte
 #undef KFX_FUSED
 #undef KFX_FUSED_KM
   if (ev) (void)hipEventRecord(ev[1], st);
+  const int rs = kRowThreads / fused_lanes_for(a.K);
+  const size_t rows_lds = (size_t)rs * a.max_steps * a.K * 4;
+  hipLaunchKernelGGL(k_build_fused_rows, dim3((unsigned)((a.n_seeds + rs - 1) / rs)), dim3(kRowThreads), rows_lds, st,
+                     a, o, rs);
 }
 
-// Dynamic LDS of a fused launch: the lanes' state slots and their history
-// words (one per step); the layer table comes on top of it.
+// Dynamic LDS of a fused launch: the lanes' state slots (the history goes
+// to HBM); the layer table comes on top of it.
 size_t fused_lds_bytes(int lanes, int threads, int max_steps) {
   (void)lanes;
-  return (sizeof(FusedShared) + 4 * (size_t)max_steps) * threads;
+  (void)max_steps;
+  return sizeof(FusedShared) * threads;
 }
 size_t fused_static_lds_bytes() { return sizeof(Geometry); }
 
