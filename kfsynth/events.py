@@ -133,6 +133,9 @@ class Workload:
     max_holes: int = 3
     seed_id: int = 1
     smear: bool = True
+    # fraction of recorded crossings that leave a second hit on the same
+    # layer (a module overlap): the same crossing point smeared again
+    overlap_frac: float = 0.0
     scatter: bool = True
     # prior of the fit's start estimate: sigma_pos [cm], sigma_k / |k|,
     # sigma_phi, sigma_theta (a reconstruction setting carried with the
@@ -169,6 +172,8 @@ def workload(name: str, **overrides) -> Workload:
     occ10k      10k tracks (pT log-U[0.3,50], eta U[-2.5,2.5], 10% from
                 vertices with r_xy < 5 cm) + 300k noise hits per event,
                 geometry as build5k, K = 10, 4 events.
+    overlap5k   build5k with module overlaps: 20% of the recorded crossings
+                leave a second hit on the same layer.
     """
     base = dict(
         fit1k=dict(geometry=_geom_barrel10(), bz=3.8, n_events=1,
@@ -194,6 +199,11 @@ def workload(name: str, **overrides) -> Workload:
                        # radii can exceed a high-pT seed's sagitta, so the
                        # curvature prior is widened to 5 |k|
                        fit_prior=(0.1, 5.0, 0.05, 0.05)),
+        overlap5k=dict(geometry=_geom_full(), bz=3.8, n_events=1,
+                       tracks_per_event=5000, pt_range=(0.5, 20.0),
+                       eta_range=(-2.4, 2.4), noise_per_event=20000, ineff=0.01,
+                       min_hits=3, max_hits=40, max_cands=6, seed_id=6,
+                       overlap_frac=0.2),
         occ10k=dict(geometry=_geom_full(), bz=3.8, n_events=4,
                     tracks_per_event=10000, pt_range=(0.3, 50.0),
                     eta_range=(-2.5, 2.5), noise_per_event=300000,
@@ -417,6 +427,17 @@ def _simulate(rng, w: Workload, n: int, align: np.ndarray):
         hb_x = np.where(is_disk, (rxy + sv * e2) * np.cos(hb_phi), Rn * np.cos(hb_phi))
         hb_y = np.where(is_disk, (rxy + sv * e2) * np.sin(hb_phi), Rn * np.sin(hb_phi))
         hb_z = np.where(is_disk, g.pos[lay], z_loc + sv * e2)
+        if w.overlap_frac > 0.0:
+            # a second module over the same crossing: the point smeared again
+            ov = rng.random(k) < w.overlap_frac
+            e3 = rng.standard_normal(k) if w.smear else np.zeros(k)
+            e4 = rng.standard_normal(k) if w.smear else np.zeros(k)
+            ob_phi = ph_loc + su * e3 / np.where(is_disk, rxy, Rn)
+            ob_x = np.where(is_disk, (rxy + sv * e4) * np.cos(ob_phi), Rn * np.cos(ob_phi))
+            ob_y = np.where(is_disk, (rxy + sv * e4) * np.sin(ob_phi), Rn * np.sin(ob_phi))
+            ob_z = np.where(is_disk, g.pos[lay], z_loc + sv * e4)
+        else:
+            ov = np.zeros(k, dtype=bool)
 
         # --- multiple scattering (Highland), momentum magnitude kept
         ct, st = np.cos(th_g), np.sin(th_g)
@@ -459,6 +480,17 @@ def _simulate(rng, w: Workload, n: int, align: np.ndarray):
         truth[gi_r, sl, 4] = nph[can]
         truth[gi_r, sl, 5] = nth[can]
         nrec[gi_r] += 1
+        # the overlap hit follows its primary
+        can2 = can & ov & (slot + 1 < MAX_CROSSINGS)
+        if can2.any():
+            gi2 = gi[can2]
+            sl2 = slot[can2] + 1
+            hits_xyz[gi2, sl2, 0] = ob_x[can2]
+            hits_xyz[gi2, sl2, 1] = ob_y[can2]
+            hits_xyz[gi2, sl2, 2] = ob_z[can2]
+            hits_lay[gi2, sl2] = lay[can2]
+            truth[gi2, sl2] = truth[gi2, sl2 - 1]
+            nrec[gi2] += 1
     return hits_xyz, hits_lay, truth, nrec, vertex
 
 
@@ -496,7 +528,10 @@ def _draw_tracks(rng, w: Workload, n: int, align: np.ndarray):
     while need > 0:
         m = max(int(need * 1.3) + 16, 64)
         hx, hl, tr, nr, vx = _simulate(rng, w, m, align)
-        good = np.nonzero((nr >= w.min_hits) & (nr <= w.max_hits))[0][:need]
+        # layers crossed with a hit (an overlap hit repeats its primary's
+        # layer right after it)
+        nlay = nr - np.sum((hl[:, 1:] == hl[:, :-1]) & (hl[:, 1:] >= 0), axis=1)
+        good = np.nonzero((nlay >= w.min_hits) & (nr <= w.max_hits))[0][:need]
         out.append((hx[good], hl[good], tr[good], nr[good], vx[good]))
         need -= good.size
     cat = lambda i: np.concatenate([o[i] for o in out])
@@ -602,13 +637,35 @@ def generate(w: Workload | str, n_events: int | None = None,
     x = np.concatenate(xs).astype(np.float32)
     y = np.concatenate(ys).astype(np.float32)
     z = np.concatenate(zs).astype(np.float32)
-    seeds = np.stack([trk_hits[trk_off[:-1] + i] for i in range(3)], axis=1)
+    if w.overlap_frac > 0.0:
+        seeds = _first_three_layers(trk_hits, trk_off, np.concatenate(ls))
+    else:
+        seeds = np.stack([trk_hits[trk_off[:-1] + i] for i in range(3)], axis=1)
     return Events(workload=w, geometry=g, bz=w.bz, x=x, y=y, z=z,
                   layer=np.concatenate(ls), sim=np.concatenate(sims),
                   event_offsets=np.asarray(ev_off, dtype=np.int32),
                   trk_event=trk_event, trk_offsets=trk_off.astype(np.int32),
                   trk_hits=trk_hits, trk_truth=trk_truth, trk_vertex=vx,
                   seeds=seeds.astype(np.int32), align_true=align)
+
+
+def _first_three_layers(trk_hits, trk_off, layer):
+    """Seeds when tracks carry overlap hits: the first three hits of each
+    track on three different layers (an overlap hit repeats the layer of
+    the hit before it)."""
+    T = trk_off.shape[0] - 1
+    seeds = np.zeros((T, 3), np.int64)
+    for t in range(T):
+        got, prev = 0, -1
+        for j in range(trk_off[t], trk_off[t + 1]):
+            h = trk_hits[j]
+            if layer[h] != prev:
+                seeds[t, got] = h
+                got += 1
+                prev = layer[h]
+                if got == 3:
+                    break
+    return seeds
 
 
 def duplicate_seeds(ev: Events, frac: float, seed: int = 0):

@@ -717,6 +717,7 @@ struct BuildParams {
   int max_holes = 3;
   int max_steps = 64;
   int brute = 0;
+  int overlap = 0;  // recover a second hit on the layer of a kept hit child
 };
 
 struct SeedResult {
@@ -813,6 +814,30 @@ static SeedResult build_seed(const Geom& g, const EventHits& ev, const int sh[3]
           R.updates++;
           c.nhits++; c.consec = 0; c.chi2 = k.chi2;
           c.hits.push_back(k.hit);
+          if (bp.overlap) {
+            // overlap recovery (Sec. 3 names it as planned work; the reading
+            // is ours): on the state just updated with k.hit, the hits of the
+            // same layer with a larger index and chi2 < cut are compatible;
+            // the best of them by (chi2, index) becomes a second hit of this
+            // layer.  The index condition keeps two children of one parent
+            // that took the two hits of one overlap from recovering each
+            // other's hit and becoming one candidate twice.
+            std::vector<Pair> comp = bp.brute ? compat_brute(g, ev, c.layer, c.p, c.C, bp.chi2_cut)
+                                              : compat_binned(g, ev, c.layer, c.p, c.C, bp.chi2_cut);
+            int h2 = -1;
+            double x2 = 0.0;
+            for (const Pair& q : comp) {
+              if (q.hit <= k.hit) continue;
+              if (h2 < 0 || q.chi2 < x2 || (q.chi2 == x2 && q.hit < h2)) { h2 = q.hit; x2 = q.chi2; }
+            }
+            if (h2 >= 0) {
+              double m2[3] = {ev.x[h2], ev.y[h2], ev.z[h2]}, c2b;
+              kf_update<double>(g.L[c.layer], c.p, c.C, m2, c2b);
+              R.updates++;
+              c.nhits++; c.chi2 += x2;
+              c.hits.push_back(h2);
+            }
+          }
         } else {
           c.nholes++; c.consec++;
           c.hits.push_back(-1);
@@ -1067,12 +1092,13 @@ long kfo_step_compat(const double* layers, int nl, double bz, int neta, int nphi
 void kfo_build(const double* layers, int nl, double bz, int neta, int nphi, const float* x,
                const float* y, const float* z, const int* layer, const int* ev_off, int nev,
                const int* seeds, const int* seed_event, int ns, double chi2_cut, int K,
-               int max_holes, int brute, const double* prior, int maxh, int* out_n,
+               int max_holes, int brute, int overlap, const double* prior, int maxh, int* out_n,
                int* out_hits, int* out_nhits, int* out_nholes, double* out_chi2,
                double* out_p, double* out_C, long* stats) {
   Geom g = make_geom(layers, nl, bz, neta, nphi);
   BuildParams bp;
   bp.chi2_cut = chi2_cut; bp.max_cands = K; bp.max_holes = max_holes; bp.brute = brute;
+  bp.overlap = overlap;
   Prior pr{prior[0], prior[1], prior[2], prior[3]};
   std::vector<EventHits> evs(nev);
   for (int e = 0; e < nev; ++e) {

@@ -589,7 +589,23 @@ def test_non_finite_hits_are_not_indexed():
     assert not ok[5] and not ok[7] and ok.sum() >= ev.n_tracks - 2 - 10
 
 
-def _python_beam(ev, seed, K, max_holes, cut, prior):
+def _python_recover(ev, layer, p, C, h1, cut):
+    """Reading 18 written out: the hits of the layer with an index above h1
+    whose chi2 against the updated state (p, C) is below the cut, by brute
+    force over the layer's hits (the update's chi2 is that of its pair);
+    the best by (chi2, index), or None."""
+    best = None
+    for h in np.nonzero(ev.layer == layer)[0]:
+        if h <= h1:
+            continue
+        m = np.array([ev.x[h], ev.y[h], ev.z[h]], np.float64)
+        _, _, x2 = oracle.update(ev.geometry, layer, p, C, m)
+        if x2 is not None and x2 < cut and (best is None or (x2, h) < best):
+            best = (x2, int(h))
+    return best
+
+
+def _python_beam(ev, seed, K, max_holes, cut, prior, overlap=False):
     """Reading 11 written out in Python over the oracle's per-step
     primitives (step_compat: navigation, prediction and the compatible hits;
     update: the Kalman update): every child of every candidate is listed,
@@ -639,6 +655,12 @@ def _python_beam(ev, seed, K, max_holes, cut, prior):
                     c["p"], c["C"], _ = oracle.update(ev.geometry, nl, p1, C1, m)
                     c.update(nh=nh, consec=0, chi2=x2)
                     c["hits"].append(hit)
+                    rec = _python_recover(ev, nl, c["p"], c["C"], hit, cut) if overlap else None
+                    if rec is not None:
+                        m2 = np.array([ev.x[rec[1]], ev.y[rec[1]], ev.z[rec[1]]], np.float64)
+                        c["p"], c["C"], _ = oracle.update(ev.geometry, nl, c["p"], c["C"], m2)
+                        c.update(nh=c["nh"] + 1, chi2=c["chi2"] + rec[0])
+                        c["hits"].append(rec[1])
                 else:
                     c.update(p=p1, C=C1, nho=nho, consec=c["consec"] + 1)
                     c["hits"].append(-1)
@@ -688,3 +710,61 @@ def test_beam_search_matches_heap_selection(K, ineff, max_holes, dup):
             assert o["nhits"][i, j] == c["nh"] and o["nholes"][i, j] == c["nho"]
             assert abs(o["chi2"][i, j] - c["chi2"]) <= 1e-9 * max(1.0, abs(c["chi2"]))
             np.testing.assert_allclose(o["p"][i, j], c["p"], rtol=1e-12, atol=1e-12)
+
+
+def _overlap_event(frac, noise, tracks=60):
+    w = kfsynth.workload("overlap5k", tracks_per_event=tracks, noise_per_event=noise, overlap_frac=frac)
+    return kfsynth.generate(w)
+
+
+@pytest.mark.parametrize("K", [2, 6])
+def test_overlap_recovery_matches_python_beam(K):
+    """Reading 18 (overlap recovery) in the oracle against the Python beam
+    with the recovery written out by brute force over the layer's hits:
+    the same candidates, hit lists (the recovered hit right after the one it
+    joins), counts, chi2 and states."""
+    ev = _overlap_event(0.5, 2000)
+    w = ev.workload
+    prior = oracle.DEFAULT_PRIOR
+    seeds = ev.seeds[:10]
+    o = oracle.build_tracks(ev, seeds=seeds, seed_event=np.zeros(len(seeds), np.int32), max_cands=K,
+                            max_hits=64, prior=prior, overlap=True)
+    recovered = 0
+    for i, s in enumerate(seeds):
+        ref = _python_beam(ev, s, K, w.max_holes, w.chi2_cut, prior, overlap=True)
+        assert o["n"][i] == len(ref)
+        for j, c in enumerate(ref):
+            row = o["hits"][i, j]
+            assert row[:len(c["hits"])].tolist() == c["hits"] and (row[len(c["hits"]):] == -3).all()
+            assert o["nhits"][i, j] == c["nh"] and o["nholes"][i, j] == c["nho"]
+            assert abs(o["chi2"][i, j] - c["chi2"]) <= 1e-9 * max(1.0, abs(c["chi2"]))
+            np.testing.assert_allclose(o["p"][i, j], c["p"], rtol=1e-12, atol=1e-12)
+        hl = o["hits"][i, 0]
+        hl = hl[hl >= 0]
+        recovered += int(np.sum(ev.layer[hl][1:] == ev.layer[hl][:-1]))
+    assert recovered > 10  # the recovery did take hits
+
+
+def test_overlap_recovery_finds_the_second_hits():
+    """On a noise-free event where every crossing leaves two hits, the best
+    candidate of a seed holds both hits of almost every layer of its
+    particle after the seed layers (a seed is three hits on three layers;
+    recovery follows the search); without the recovery it holds one per
+    layer."""
+    ev = _overlap_event(1.0, 0, tracks=200)
+    n = ev.n_tracks
+    on = oracle.build_tracks(ev, max_hits=64, overlap=True)
+    off = oracle.build_tracks(ev, max_hits=64, overlap=False)
+    full = 0
+    for t in range(n):
+        seed_layers = set(ev.layer[ev.seeds[t]].tolist())
+        truth = set(h for h in ev.trk_hits[ev.trk_offsets[t]:ev.trk_offsets[t + 1]].tolist()
+                    if ev.layer[h] not in seed_layers or h in ev.seeds[t])
+        got = on["hits"][t, 0]
+        got = set(got[got >= 0].tolist())
+        full += got == truth
+        one = off["hits"][t, 0]
+        one = one[one >= 0]
+        assert len(set(ev.layer[one].tolist())) == len(one)  # one hit per layer
+    assert full >= 0.9 * n, full
+    assert on["nhits"][:, 0].sum() > 1.8 * off["nhits"][:, 0].sum()
