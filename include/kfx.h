@@ -109,20 +109,36 @@ typedef struct {
                             scanned by the whole wavefront together; smaller
                             ones by their own lane; 0 = 64                    */
   int32_t waves_per_simd;/* fused: register budget of the kernel, 1 (all 512
-                            registers of a lane) or 2 (half, the rest spilled
-                            to scratch, two waves resident per SIMD); 0 = 1  */
+                            registers of a lane) or 2 (256, two waves resident
+                            per SIMD; K <= 6 fits it with at most a few
+                            registers spilled, larger K spill more); 0 = 1  */
   int32_t seeds_per_wave;/* fused: seeds a wavefront works on at once, 1 ..
                             64 / lanes_per_seed (the rest of its lanes idle):
                             fewer seeds per wavefront spread a small event
                             over more SIMDs; 0 = 64 / lanes_per_seed         */
+  float window_inflate;  /* factor widening every search window (>= 1; 0 =
+                            1): the window is already a superset of the
+                            compatible hits, so results do not change; a
+                            wider one only reads more bins                   */
+  int32_t overlap;       /* nonzero: overlap recovery -- after a kept hit
+                            child is updated with hit h1, the best (chi2,
+                            index) hit of the same layer with an index above
+                            h1 and chi2 < chi2_cut against the updated state
+                            is added as a second hit of that layer (one more
+                            update, hit and chi2 term; right after h1 in the
+                            hit list).  Sec. 3 of the paper names recovering
+                            hits of overlapping modules as planned work. */
 } kfx_build_params;
 
 /* Output of building, per seed s and slot j < K, best first (device). */
 typedef struct {
   int32_t* n_cands;  /* [S] candidates kept                                   */
   int32_t* hits;     /* [S][K][max_hits]: the 3 seed hits, then one entry per
-                        surface reached (hit index, or -1 for a hole);
-                        unused entries -3                                     */
+                        surface reached (hit index, or -1 for a hole; with
+                        overlap recovery a recovered hit follows its
+                        layer's hit); unused entries -3; a list longer than
+                        max_hits is cut (n_hits and n_holes still count
+                        all)                                                   */
   int32_t* n_hits;   /* [S][K]                                               */
   int32_t* n_holes;  /* [S][K]                                               */
   float* chi2;       /* [S][K] total chi2 (seed hits included)               */

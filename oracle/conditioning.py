@@ -52,7 +52,9 @@ def candidate_conditioning(ev, seed_hits, entries, prior):
     """Largest update_conditioning along a building candidate, replayed
     with the oracle from its seed through its list of entries after the
     three seed hits (hit index, or -1 for a hole): navigate, predict,
-    update where there is a hit."""
+    update where there is a hit.  A hit on the layer of the hit just before
+    it (a recovered overlap hit) is a second update on that surface, with
+    no navigation."""
     g = ev.geometry
     p, C, _, ok = seed_states(ev, seeds=np.asarray(seed_hits, np.int32)[None], prior=prior)
     if not ok[0]:
@@ -60,7 +62,15 @@ def candidate_conditioning(ev, seed_hits, entries, prior):
     p, C = p[0], C[0]
     cur = int(ev.layer[seed_hits[2]])
     kappa = 1.0
+    last_hit_layer = -1
     for e in entries:
+        if e >= 0 and int(ev.layer[e]) == last_hit_layer:
+            m = np.array([ev.x[e], ev.y[e], ev.z[e]], np.float64)
+            p2, C2, _ = update(g, cur, p, C, m)
+            kappa = max(kappa, update_conditioning(g, ev.bz, p, C, cur, p2, C2))
+            p, C = p2, C2
+            last_hit_layer = -1
+            continue
         nxt = navigate(g, ev.bz, cur, p)
         if nxt < 0:
             break
@@ -72,6 +82,7 @@ def candidate_conditioning(ev, seed_hits, entries, prior):
             p2, C2, _ = update(g, nxt, p, C, m)
             kappa = max(kappa, update_conditioning(g, ev.bz, p, C, nxt, p2, C2))
             p, C = p2, C2
+        last_hit_layer = nxt if e >= 0 else -1
         cur = nxt
     return kappa
 

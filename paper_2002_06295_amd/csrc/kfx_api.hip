@@ -439,6 +439,8 @@ int build_impl(kfx_ctx* c, const kfx_hits* hits, const int32_t* seeds, const int
   if (p->max_holes < 0 || p->max_holes > 200) return fail(c, KFX_EINVAL, "max_holes out of range");
   if (!(p->chi2_cut > 0.0f) || !std::isfinite(p->chi2_cut)) return fail(c, KFX_EINVAL, "chi2_cut must be finite and > 0");
   if (p->mode != KFX_MODE_PLAIN && p->mode != KFX_MODE_FUSED) return fail(c, KFX_EINVAL, "unknown mode");
+  if (!(p->window_inflate == 0.0f || (p->window_inflate >= 1.0f && p->window_inflate <= 1e4f)))
+    return fail(c, KFX_EINVAL, "window_inflate must be 0 or in [1, 1e4]");
   if (p->block_threads != 0 && (p->block_threads < 64 || p->block_threads > 256 || p->block_threads % 64))
     return fail(c, KFX_EINVAL, "block_threads must be 0 or a multiple of 64 in [64, 256]");
   if (p->blocks < 0) return fail(c, KFX_EINVAL, "blocks < 0");
@@ -505,6 +507,8 @@ int build_impl(kfx_ctx* c, const kfx_hits* hits, const int32_t* seeds, const int
   a.K = K;
   a.max_holes = p->max_holes;
   a.max_steps = p->max_steps;
+  a.overlap = p->overlap ? 1 : 0;
+  a.inflate = p->window_inflate > 0.0f ? p->window_inflate : 1.0f;
   a.coop_min = p->scan_tile ? p->scan_tile : 64;
   {
     const int lanes = p->lanes_per_seed ? p->lanes_per_seed : fused_lanes_for(K);
@@ -542,6 +546,9 @@ int build_impl(kfx_ctx* c, const kfx_hits* hits, const int32_t* seeds, const int
     a.hist_code = (int*)ws(c, "b.histc", (size_t)N * p->max_steps * 4, st, rc); if (rc) return rc;
   } else {
     a.hist_word = (unsigned int*)ws(c, "b.histw", (size_t)N * p->max_steps * 4, st, rc); if (rc) return rc;
+  }
+  if (a.overlap) {
+    a.hist_ov = (int*)ws(c, "b.histo", (size_t)N * p->max_steps * 4, st, rc); if (rc) return rc;
   }
   a.n_steps = (int*)ws(c, "b.nsteps", (size_t)std::max(n_seeds, 1) * 4, st, rc); if (rc) return rc;
   a.stats = (unsigned long long*)out->stats;

@@ -25,6 +25,8 @@ struct BuildArgs {
   int K;
   int max_holes;
   int max_steps;
+  int overlap;            // recover a second hit on the layer of a kept hit child
+  float inflate;          // window widening (>= 1; the window is a superset at 1)
   int coop_min;           // fused: window size scanned by the whole wave
   int groups_per_wave;    // fused: seed groups of a wavefront that take seeds
   // candidate slots (S K), two buffers used in turn
@@ -50,6 +52,9 @@ struct BuildArgs {
   // history of the fused kernel, per seed: [S][max_steps][K] words, the
   // child's code + 2 in bits 0-26 and its parent slot + 1 in bits 27-31
   unsigned int* hist_word;
+  // with overlap recovery, both paths: the recovered hit of each history
+  // entry, or -1 ([S][max_steps][K])
+  int* hist_ov;
   int* n_steps;           // [S] steps recorded
   unsigned long long* stats;  // steps, pairs, updates
 };
@@ -126,7 +131,7 @@ KFX_HD int pairs_slot(const BuildArgs& a, long slot, int ev) {
   Frame F;
   make_frame(pr, a.G->L[nl], F);
   BestK<kMaxK> b;
-  const int found = scan_window(*a.G, a.B, ev, nl, pr, F, a.cut, a.K, b);
+  const int found = scan_window(*a.G, a.B, ev, nl, pr, F, a.cut, a.K, b, a.inflate);
 #pragma unroll
   for (int r = 0; r < kMaxK; ++r)
     if (r < b.n) {
@@ -241,6 +246,7 @@ KFX_HD int update_slot(const BuildArgs& a, int cur, int s, int j, int t) {
   const long slot = (long)s * a.K + j;
   const int par = a.sel_parent[slot];
   const long hidx = hist_index(a, s, t, j);
+  if (a.overlap) a.hist_ov[hidx] = -1;
   if (par < 0) {
     a.meta[nxt][slot] = 0;
     a.layer[nxt][slot] = -1;
@@ -254,6 +260,7 @@ KFX_HD int update_slot(const BuildArgs& a, int cur, int s, int j, int t) {
   const int pm = a.meta[cur][ps];
   State st;
   int upd = 0;
+  float chi2 = a.sel_chi2[slot];
   if (code == kStop) {
     load_state(a.cand[cur], ps, st);
     a.layer[nxt][slot] = a.layer[cur][ps];
@@ -264,14 +271,26 @@ KFX_HD int update_slot(const BuildArgs& a, int cur, int s, int j, int t) {
     a.layer[nxt][slot] = nl;
     if (code >= 0) {
       kf_update_fp64(st, a.G->L[nl], (double)a.H.x[code], (double)a.H.y[code], (double)a.H.z[code]);
-      a.meta[nxt][slot] = meta_pack(meta_nhits(pm) + 1, meta_nholes(pm), 0, kFlagLive);
+      int nh = meta_nhits(pm) + 1;
       upd = 1;
+      if (a.overlap) {
+        float c2 = 0.0f;
+        const int h2 = recover_overlap(*a.G, a.B, a.seed_event[s], nl, st, a.cut, code, a.inflate, c2);
+        if (h2 >= 0) {
+          kf_update_fp64(st, a.G->L[nl], (double)a.H.x[h2], (double)a.H.y[h2], (double)a.H.z[h2]);
+          ++nh;
+          ++upd;
+          chi2 += c2;
+          a.hist_ov[hidx] = h2;
+        }
+      }
+      a.meta[nxt][slot] = meta_pack(nh, meta_nholes(pm), 0, kFlagLive);
     } else {
       a.meta[nxt][slot] = meta_pack(meta_nhits(pm), meta_nholes(pm) + 1, meta_consec(pm) + 1, kFlagLive);
     }
   }
   store_state(a.cand[nxt], slot, st);
-  a.chi2[nxt][slot] = a.sel_chi2[slot];
+  a.chi2[nxt][slot] = chi2;
   a.hist_parent[hidx] = (signed char)par;
   a.hist_code[hidx] = code;
   if (j == 0) a.n_steps[s] = t + 1;
@@ -290,41 +309,52 @@ struct TracksOut {
   int max_hits;
 };
 
-// Hit list of one final slot: the seed hits, then one entry per step with
+// Hit list of one final slot, written to `out` (max_hits entries): the seed
+// hits, then one entry per step with
 // a hit or a hole (-1), `total` entries in all (stop entries add none),
 // rebuilt from the per-step history by one backward walk over the parent
 // pointers; the rest of the row -3 (all of it for a slot without a
 // candidate).  T is the seed's step count; hist(t, slot, code, parent)
 // reads the history entry of step t and slot.
 template <class Hist>
-KFX_HD void write_slot_hits(const BuildArgs& a, const TracksOut& o, int s, int j, int T, bool live, int total,
-                            const Hist& hist) {
-  const long slot = (long)s * a.K + j;
-  int* out = o.hits + slot * o.max_hits;
+KFX_HD void write_hit_row(const BuildArgs& a, int* out, int max_hits, int s, int j, int T, bool live, int total,
+                          const Hist& hist) {
+  // (hist(t, slot, code, parent, ov): ov is the hit recovered after `code`
+  // on the same layer, or -1)
   if (!live) total = 0;
   {
     // unused entries: one by one up to a 16-byte boundary, then four at a
     // time (when the row is 16-byte aligned), then the rest
-    int q = total < o.max_hits ? total : o.max_hits;
+    int q = total < max_hits ? total : max_hits;
     if ((reinterpret_cast<uintptr_t>(out) & 15) == 0) {
-      for (; q < o.max_hits && (q & 3); ++q) out[q] = -3;
-      for (; q + 4 <= o.max_hits; q += 4) *reinterpret_cast<int4*>(out + q) = make_int4(-3, -3, -3, -3);
+      for (; q < max_hits && (q & 3); ++q) out[q] = -3;
+      for (; q + 4 <= max_hits; q += 4) *reinterpret_cast<int4*>(out + q) = make_int4(-3, -3, -3, -3);
     }
-    for (; q < o.max_hits; ++q) out[q] = -3;
+    for (; q < max_hits; ++q) out[q] = -3;
   }
   if (!live) return;
-  for (int q = 0; q < kSeedHits && q < o.max_hits; ++q) out[q] = a.seeds[3 * s + q];
+  for (int q = 0; q < kSeedHits && q < max_hits; ++q) out[q] = a.seeds[3 * s + q];
   int w = total - 1, cj = j;
   for (int t = T - 1; t >= 0; --t) {
-    int code, parent;
-    hist(t, cj, code, parent);
+    int code, parent, ov;
+    hist(t, cj, code, parent, ov);
+    if (ov >= 0) {
+      if (w < max_hits) out[w] = ov;
+      --w;
+    }
     if (code != kStop) {
-      if (w < o.max_hits) out[w] = code >= 0 ? code : -1;
+      if (w < max_hits) out[w] = code >= 0 ? code : -1;
       --w;
     }
     cj = parent;
     if (cj < 0) break;  // (a slot without a candidate has no parent)
   }
+}
+
+template <class Hist>
+KFX_HD void write_slot_hits(const BuildArgs& a, const TracksOut& o, int s, int j, int T, bool live, int total,
+                            const Hist& hist) {
+  write_hit_row(a, o.hits + ((long)s * a.K + j) * o.max_hits, o.max_hits, s, j, T, live, total, hist);
 }
 
 // Counts, chi2 sum and state of one final slot (m its meta word); zeros for
@@ -359,10 +389,11 @@ KFX_HD void write_slot_output(const BuildArgs& a, const TracksOut& o, int s, int
 struct HbmHist {
   const BuildArgs* a;
   int s;
-  KFX_HD void operator()(int t, int j, int& code, int& parent) const {
+  KFX_HD void operator()(int t, int j, int& code, int& parent, int& ov) const {
     const long h = hist_index(*a, s, t, j);
     code = a->hist_code[h];
     parent = a->hist_parent[h];
+    ov = a->overlap ? a->hist_ov[h] : -1;
   }
 };
 
@@ -371,10 +402,12 @@ struct HbmHist {
 struct HbmWordHist {
   const BuildArgs* a;
   int s;
-  KFX_HD void operator()(int t, int j, int& code, int& parent) const {
-    const unsigned int e = a->hist_word[hist_index(*a, s, t, j)];
+  KFX_HD void operator()(int t, int j, int& code, int& parent, int& ov) const {
+    const long h = hist_index(*a, s, t, j);
+    const unsigned int e = a->hist_word[h];
     code = (int)(e & 0x7ffffffu) - 2;
     parent = (int)(e >> 27) - 1;
+    ov = a->overlap ? a->hist_ov[h] : -1;
   }
 };
 KFX_HD unsigned int hist_word_pack(int code, int parent) {

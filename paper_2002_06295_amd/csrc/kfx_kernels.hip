@@ -170,7 +170,7 @@ __global__ void __launch_bounds__(256) k_bin_keys(const Geometry* __restrict__ G
   const int nb = G->n_eta * G->n_phi;
   int bin = -1;
   long key = -1;
-  if (l >= 0 && l < G->n_layers) bin = hit_bin(*G, l, H.x[i], H.y[i], H.z[i]);
+  if (l >= 0 && l < G->n_layers) bin = hit_bin_fast(*G, l, H.x[i], H.y[i], H.z[i]);
   if (bin >= 0) {
     const int e = event_of(H.ev_off, H.n_events, i);
     key = ((long)e * G->n_layers + l) * nb + bin;
@@ -445,26 +445,46 @@ __global__ void __launch_bounds__(128) k_build_finalize(BuildArgs a, int fin, Tr
 
 // Hit lists of the fused build (the fused kernel wrote the counts, chi2
 // sums and states itself).  A block takes `rs` consecutive seeds (256 / the
-// power of two >= K, so that the walks fill the block): it
-// first copies their histories (n_steps x K words each, contiguous in HBM)
-// into LDS with coalesced loads, then one thread per (seed, slot) walks its
-// slot's parent pointers in LDS and writes the row.  A walk is a chain of
-// dependent reads; in LDS each costs tens of cycles instead of an HBM
-// round trip.
+// power of two >= K, so that the walks fill the block): it first copies
+// their histories (n_steps x K words each, contiguous in HBM) into LDS with
+// coalesced loads, then one thread per (seed, slot) walks its slot's parent
+// pointers in LDS.  A walk is a chain of dependent reads; in LDS each costs
+// tens of cycles instead of an HBM round trip.  When the block's rows fit
+// in LDS too (stage_rows), they are built there and then written to HBM as
+// one contiguous range (the rows of consecutive seeds are adjacent), in
+// 16-byte stores across the block; otherwise each thread writes its row.
 constexpr int kRowThreads = 256;
+constexpr size_t kRowLds = 65536;
 
 struct LdsWordHist {
   const unsigned int* h;  // the seed's history, [t][K]
+  const int* ov;          // its recovered hits, [t][K] (nullptr: no recovery)
   int K;
-  __device__ void operator()(int t, int j, int& code, int& parent) const {
+  __device__ void operator()(int t, int j, int& code, int& parent, int& o) const {
     const unsigned int e = h[t * K + j];
     code = (int)(e & 0x7ffffffu) - 2;
     parent = (int)(e >> 27) - 1;
+    o = ov ? ov[t * K + j] : -1;
   }
 };
 
-__global__ void __launch_bounds__(kRowThreads) k_build_fused_rows(BuildArgs a, TracksOut o, int rs) {
-  extern __shared__ unsigned int hist_lds[];  // [rs][max_steps][K]
+// n words from HBM to LDS by the block, 16 bytes at a time where both ends
+// allow it
+__device__ inline void copy_words(unsigned int* dst, const unsigned int* src, long n) {
+  if (((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) & 15) == 0) {
+    const long n4 = n >> 2;
+    for (long i = threadIdx.x; i < n4; i += blockDim.x)
+      reinterpret_cast<uint4*>(dst)[i] = reinterpret_cast<const uint4*>(src)[i];
+    for (long i = (n4 << 2) + threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
+  } else {
+    for (long i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
+  }
+}
+
+__global__ void __launch_bounds__(kRowThreads) k_build_fused_rows(BuildArgs a, TracksOut o, int rs, int stage_rows) {
+  // [rs][max_steps][K] history words, with recovery as many recovered hits,
+  // then (stage_rows) the [rs K][max_hits] rows
+  extern __shared__ __align__(16) unsigned int hist_lds[];
   __shared__ int nst[kRowThreads / 4];
   const int K = a.K;
   const long s0 = (long)blockIdx.x * rs;
@@ -472,18 +492,37 @@ __global__ void __launch_bounds__(kRowThreads) k_build_fused_rows(BuildArgs a, T
   if (threadIdx.x < ns) nst[threadIdx.x] = min(a.n_steps[s0 + threadIdx.x], a.max_steps);
   __syncthreads();
   const int per = a.max_steps * K;  // words per seed
-  const unsigned int* src = a.hist_word + s0 * per;
-  for (int i = threadIdx.x; i < ns * per; i += kRowThreads) {
-    const int sl = i / per, t = (i % per) / K;
-    if (t < nst[sl]) hist_lds[i] = src[i];
-  }
+  int* ov_lds = a.overlap ? reinterpret_cast<int*>(hist_lds + (size_t)rs * per) : nullptr;
+  // the block's whole history range, steps past a seed's end included (they
+  // are never read): a straight copy, no index arithmetic per word
+  copy_words(hist_lds, a.hist_word + s0 * per, (long)ns * per);
+  if (ov_lds) copy_words(reinterpret_cast<unsigned int*>(ov_lds),
+                         reinterpret_cast<const unsigned int*>(a.hist_ov) + s0 * per, (long)ns * per);
   __syncthreads();
+  const int H = o.max_hits;
+  // rows after the histories, at a 16-byte boundary (as the launch sized it)
+  const size_t hwords = (size_t)rs * per * (a.overlap ? 2 : 1);
+  int* rows = reinterpret_cast<int*>(reinterpret_cast<char*>(hist_lds) + ((hwords * 4 + 15) & ~(size_t)15));
   for (int q = threadIdx.x; q < ns * K; q += kRowThreads) {
     const int sl = q / K, j = q % K;
     const long s = s0 + sl, slot = s * K + j;
     const bool live = j < o.n_cands[s];
-    write_slot_hits(a, o, (int)s, j, nst[sl], live, live ? o.n_hits[slot] + o.n_holes[slot] : 0,
-                    LdsWordHist{hist_lds + sl * per, K});
+    int* out = stage_rows ? rows + (size_t)q * H : o.hits + slot * H;
+    write_hit_row(a, out, H, (int)s, j, nst[sl], live, live ? o.n_hits[slot] + o.n_holes[slot] : 0,
+                  LdsWordHist{hist_lds + sl * per, ov_lds ? ov_lds + sl * per : nullptr, K});
+  }
+  if (!stage_rows) return;
+  __syncthreads();
+  // the block's rows are one contiguous range of o.hits
+  int* dst = o.hits + s0 * K * H;
+  const long n = (long)ns * K * H;
+  if ((reinterpret_cast<uintptr_t>(dst) & 15) == 0) {
+    const long n4 = n >> 2;
+    for (long i = threadIdx.x; i < n4; i += kRowThreads)
+      reinterpret_cast<int4*>(dst)[i] = reinterpret_cast<const int4*>(rows)[i];
+    for (long i = (n4 << 2) + threadIdx.x; i < n; i += kRowThreads) dst[i] = rows[i];
+  } else {
+    for (long i = threadIdx.x; i < n; i += kRowThreads) dst[i] = rows[i];
   }
 }
 
@@ -890,7 +929,7 @@ k_build_fused(BuildArgs a, TracksOut o, int* seed_counter) {
           Frame F;
           const Layer& Ln = G.L[nl];
           make_frame(pr, Ln, F);
-          sw = scan_win(G, a.B, a.seed_event[seed], nl, window_bins(G, Ln, pr, F, a.cut));
+          sw = scan_win(G, a.B, a.seed_event[seed], nl, window_bins(G, Ln, pr, F, a.cut, a.inflate));
           pair_frame(pr, F, Ln.kind == kDisk, pf);
         }
       }
@@ -956,7 +995,7 @@ k_build_fused(BuildArgs a, TracksOut o, int* seed_counter) {
     // ---- (d) children: copy the parent's state from LDS, update hit children
     // (the lane's state is reassigned on every path, so that the old one is
     // dead from the prediction on and holds no registers through the scan)
-    int new_meta = 0, new_layer = -1;
+    int new_meta = 0, new_layer = -1, h2 = -1;
     const FS& par = sh[gbase + (my_parent >= 0 ? my_parent : 0)];
     lds_get(par, st);
     if (active && gl < K) {
@@ -969,13 +1008,25 @@ k_build_fused(BuildArgs a, TracksOut o, int* seed_counter) {
         } else if (my_code >= 0) {
           kf_update_fp64(ns, G.L[new_layer], (double)a.H.x[my_code], (double)a.H.y[my_code],
                          (double)a.H.z[my_code]);
-          new_meta = meta_pack(meta_nhits(pm) + 1, meta_nholes(pm), 0, kFlagLive);
+          int nh = meta_nhits(pm) + 1;
           ++n_upd;
+          if (a.overlap) {
+            float c2 = 0.0f;
+            h2 = recover_overlap(G, a.B, a.seed_event[seed], new_layer, ns, a.cut, my_code, a.inflate, c2);
+            if (h2 >= 0) {
+              kf_update_fp64(ns, G.L[new_layer], (double)a.H.x[h2], (double)a.H.y[h2], (double)a.H.z[h2]);
+              ++nh;
+              ++n_upd;
+              my_chi2 += c2;
+            }
+          }
+          new_meta = meta_pack(nh, meta_nholes(pm), 0, kFlagLive);
         } else {
           new_meta = meta_pack(meta_nhits(pm), meta_nholes(pm) + 1, meta_consec(pm) + 1, kFlagLive);
         }
       }
       a.hist_word[hist_index(a, seed, t, gl)] = hist_word_pack(my_parent >= 0 ? my_code : kStop, my_parent);
+      if (a.overlap) a.hist_ov[hist_index(a, seed, t, gl)] = h2;
     }
     wave_sync();
     if (active) {
@@ -1369,9 +1420,14 @@ void launch_build_fused(const BuildArgs& a, const TracksOut& o, int* seed_counte
 #undef KFX_FUSED_KM
   if (ev) (void)hipEventRecord(ev[1], st);
   const int rs = kRowThreads / fused_lanes_for(a.K);
-  const size_t rows_lds = (size_t)rs * a.max_steps * a.K * 4;
-  hipLaunchKernelGGL(k_build_fused_rows, dim3((unsigned)((a.n_seeds + rs - 1) / rs)), dim3(kRowThreads), rows_lds, st,
-                     a, o, rs);
+  const size_t hist_lds = (size_t)rs * a.max_steps * a.K * 4 * (a.overlap ? 2 : 1);
+  // the hit rows are staged too when they fit; the history part is
+  // rounded to 16 bytes so that the rows start aligned
+  const size_t hist_al = (hist_lds + 15) & ~(size_t)15;
+  const size_t rows_lds = (size_t)rs * a.K * o.max_hits * 4;
+  const int stage = hist_al + rows_lds <= kRowLds ? 1 : 0;
+  hipLaunchKernelGGL(k_build_fused_rows, dim3((unsigned)((a.n_seeds + rs - 1) / rs)), dim3(kRowThreads),
+                     stage ? hist_al + rows_lds : hist_lds, st, a, o, rs, stage);
 }
 
 // Dynamic LDS of a fused launch: the lanes' state slots (the history goes

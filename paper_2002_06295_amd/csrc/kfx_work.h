@@ -56,6 +56,35 @@ KFX_HD int hit_bin(const Geometry& G, int layer, float x, float y, float z) {
   return eta_bin(G, Lr, eta) * G.n_phi + phi_bin(G, atan2(yd, xd));
 }
 
+// The same bin from FP32 estimates where they decide it: eta and phi from
+// the short FP32 asinh and atan2 below (errors under 2e-6 and 1e-6), scaled
+// to bin units; when the scaled value lies more than 2e-4 bin from every bin
+// edge (the estimate's error in bin units is below 1e-5), its floor is the
+// FP64 result's; otherwise the FP64 computation decides.  About one hit in
+// a few thousand takes the FP64 path.
+KFX_HD float asinh_win(float x);
+KFX_HD float atan2_win(float y, float x);
+KFX_HD bool near_edge(float f) {
+  const float d = f - floorf(f);
+  return d < 2e-4f || d > 1.0f - 2e-4f;
+}
+KFX_HD int hit_bin_fast(const Geometry& G, int layer, float x, float y, float z) {
+  if (!finite_hit(x, y, z)) return -1;
+  const Layer& Lr = G.L[layer];
+  const float r = sqrtf(x * x + y * y);
+  const float eta = Lr.kind == kBarrel ? asinh_win(z / (float)Lr.pos) : asinh_win((float)Lr.pos / r);
+  const float fe = (eta - (float)Lr.eta_lo) * Lr.eta_scale;
+  const float fp = (atan2_win(y, x) + 3.14159265358979f) * ((float)G.n_phi * 0.15915494309189535f);
+  const bool clamped = fe < -2e-4f || fe > (float)G.n_eta + 2e-4f;
+  // (a value within the margin of 0 or of the top edge counts as near an
+  // edge too, which covers the clamping of eta and the wrap of phi)
+  if (!__builtin_isfinite(fe) || !__builtin_isfinite(fp) || (!clamped && near_edge(fe)) || near_edge(fp) || r < 0.1f)
+    return hit_bin(G, layer, x, y, z);
+  int eb = (int)floorf(fe);
+  eb = eb < 0 ? 0 : (eb > G.n_eta - 1 ? G.n_eta - 1 : eb);
+  return eb * G.n_phi + (int)floorf(fp);
+}
+
 // ---- window: bins that can hold a hit with chi2 < cut ------------------
 // The chi2 ellipsoid's bounding box |r_u| <= sqrt(cut S_uu) etc. mapped to
 // phi and eta ranges, widened to cover FP32 rounding, so the window is a
@@ -107,8 +136,8 @@ KFX_HD float atan2_win(float y, float x) {
 KFX_HD float asin_upper(float w, float r) { return w / sqrtf((r - w) * (r + w)); }
 
 KFX_HD Window window_bins(const Geometry& G, const Layer& Lr, const State& pr, const Frame& F,
-                          float cut) {
-  const float infl = 1.0f + 1e-4f;
+                          float cut, float inflate = 1.0f) {
+  const float infl = (1.0f + 1e-4f) * inflate;
   const float wu = sqrtf(cut * F.S[0]) * infl + 1e-5f;
   const float wv = sqrtf(cut * F.S[2]) * infl + 1e-5f;
   const float wn = sqrtf(cut * F.S[5]) * infl + 1e-5f;
@@ -394,9 +423,9 @@ KFX_HD float pair_chi2(const PairFrame& P, const float4& hv) {
 // not only K).
 template <int KM>
 KFX_HD int scan_window(const Geometry& G, const BinIndex& B, int ev, int layer, const State& pr,
-                       const Frame& F, float cut, int K, BestK<KM>& best) {
+                       const Frame& F, float cut, int K, BestK<KM>& best, float inflate = 1.0f) {
   const Layer& Lr = G.L[layer];
-  const Window w = window_bins(G, Lr, pr, F, cut);
+  const Window w = window_bins(G, Lr, pr, F, cut, inflate);
   const ScanWin sw = scan_win(G, B, ev, layer, w);
   PairFrame P;
   pair_frame(pr, F, Lr.kind == kDisk, P);
@@ -418,6 +447,41 @@ KFX_HD int scan_window(const Geometry& G, const BinIndex& B, int ev, int layer, 
     }
   }
   return found;
+}
+
+// Overlap recovery (a hit of an overlapping module on the same layer): on a
+// state just updated with hit h1 on `layer`, the hits of the layer with an
+// index above h1 and chi2 < cut (the search's window and pair chi2 on the
+// updated state); returns the best by (chi2, index), or -1.
+KFX_HD int recover_overlap(const Geometry& G, const BinIndex& B, int ev, int layer, const State& st, float cut,
+                           int h1, float inflate, float& chi2_out) {
+  const Layer& Lr = G.L[layer];
+  Frame F;
+  make_frame(st, Lr, F);
+  const Window w = window_bins(G, Lr, st, F, cut, inflate);
+  const ScanWin sw = scan_win(G, B, ev, layer, w);
+  PairFrame P;
+  pair_frame(st, F, Lr.kind == kDisk, P);
+  uint64_t best = kNoKey;
+  const int nr = scan_nranges(sw);
+  for (int r = 0; r < nr; ++r) {
+    int a, e;
+    scan_range(sw, B, G.n_phi, r, a, e);
+    for (int q = a; q < e; ++q) {
+      const float4 hv = B.sorted[q];
+      int hid;
+      __builtin_memcpy(&hid, &hv.w, 4);
+      if (hid <= h1) continue;
+      const float c2 = pair_chi2(P, hv);
+      if (c2 < cut) {
+        const uint64_t k = pair_key(c2, hid);
+        best = k < best ? k : best;
+      }
+    }
+  }
+  if (best == kNoKey) return -1;
+  chi2_out = pair_key_chi2(best);
+  return pair_key_hit(best);
 }
 
 // Kalman update in FP64 for either state type.

@@ -328,3 +328,13 @@ extern "C" int hs_seed_state64(const double* table, int nl, double bz, const flo
   *chi2 = c2sum;
   return 1;
 }
+
+// the binning kernel's FP32-first bin of a batch of points on `layer`
+extern "C" void hs_hit_bin_fast_many(const double* table, int nl, int layer, const float* x, const float* y,
+                                     const float* z, int n, int* out_fast, int* out_exact) {
+  Geometry G = make_geo(table, nl, 0.0);
+  for (int i = 0; i < n; ++i) {
+    out_fast[i] = hit_bin_fast(G, layer, x[i], y[i], z[i]);
+    out_exact[i] = hit_bin(G, layer, x[i], y[i], z[i]);
+  }
+}

@@ -119,3 +119,61 @@ def test_device_binning_of_non_finite_hits(hs):
                                  np.array([z], np.float32), np.array([layer], np.int32))[0]
             assert b == bo, (layer, x, y, z, b, bo)
             assert (b == -1) == (not np.isfinite([x, y, z]).all())
+
+
+def test_fast_binning_equals_fp64_binning(hs):
+    """The binning kernel takes the bin from FP32 estimates of eta and phi
+    when they lie clearly inside a bin and falls back to the FP64 formula
+    otherwise: on every layer, for random points on and beyond the layer
+    and for points a few float32 ulps around every eta and phi bin edge, the
+    result equals the FP64 binning (itself equal to the oracle's)."""
+    ev = kfsynth.generate("build5k", tracks_per_event=20)
+    g = ev.geometry
+    tab = np.ascontiguousarray(g.as_records(), dtype=np.float64)
+    rng = np.random.default_rng(3)
+    vp, ci = ctypes.c_void_p, ctypes.c_int
+    hs.hs_hit_bin_fast_many.argtypes = [vp, ci, ci, vp, vp, vp, ci, vp, vp]
+    hs.hs_hit_bin_fast_many.restype = None
+    total = 0
+    for layer in range(g.n_layers):
+        kind, pos, lo, hi = tab[layer, :4]
+        n = 4000
+        phi = rng.uniform(-np.pi, np.pi, n)
+        if kind == 0:
+            r = np.full(n, pos)
+            z = rng.uniform(1.3 * lo, 1.3 * hi, n)
+            elo, ehi = np.arcsinh(lo / pos), np.arcsinh(hi / pos)
+        else:
+            r = rng.uniform(0.7 * lo, 1.3 * hi, n)
+            z = np.full(n, pos)
+            a, b = np.arcsinh(pos / hi), np.arcsinh(pos / lo)
+            elo, ehi = min(a, b), max(a, b)
+        pts = [np.stack([r * np.cos(phi), r * np.sin(phi), z], axis=1)]
+        # edges: every eta edge at random phi, every phi edge at random eta
+        ee = elo + (ehi - elo) * np.arange(N_ETA + 1) / N_ETA
+        pe = -np.pi + 2 * np.pi * np.arange(N_PHI + 1) / N_PHI
+        for m in (-3, -1, 0, 1, 3):
+            f = 1.0 + m * 2.0 ** -23
+            ph = rng.uniform(-np.pi, np.pi, ee.size)
+            if kind == 0:
+                zz = pos * np.sinh(ee) * f
+                pts.append(np.stack([pos * np.cos(ph), pos * np.sin(ph), zz], axis=1))
+            else:
+                rr = pos / np.sinh(ee) * f
+                pts.append(np.stack([rr * np.cos(ph), rr * np.sin(ph), np.full(ee.size, pos)], axis=1))
+            et = rng.uniform(elo, ehi, pe.size)
+            pp = pe * f
+            if kind == 0:
+                pts.append(np.stack([pos * np.cos(pp), pos * np.sin(pp), pos * np.sinh(et)], axis=1))
+            else:
+                rr = pos / np.sinh(et)
+                pts.append(np.stack([rr * np.cos(pp), rr * np.sin(pp), np.full(pe.size, pos)], axis=1))
+        p = np.concatenate(pts).astype(np.float32)
+        x, y, z = (np.ascontiguousarray(p[:, i]) for i in range(3))
+        fast = np.zeros(len(p), np.int32)
+        exact = np.zeros(len(p), np.int32)
+        hs.hs_hit_bin_fast_many(P(tab), tab.shape[0], layer, P(x), P(y), P(z), len(p), P(fast), P(exact))
+        bad = np.nonzero(fast != exact)[0]
+        assert bad.size == 0, (layer, p[bad[:5]], fast[bad[:5]], exact[bad[:5]])
+        total += len(p)
+    assert total > 100000
