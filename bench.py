@@ -575,9 +575,51 @@ def secondary(args, kfx, kfsynth, dev, ctx, hits, ev, shape):
     del dout
     sec["second_iteration"] = second_iteration(kfx, kfsynth, dev, ctx5, hits5, ev5, shape5)
     del hits5, ctx5
+    sec["overlap5k"] = overlap_build(kfx, dev)
     sec["strip_clustering"] = strip_clustering(kfx, kfsynth, ctx)
     sec["align200k_fit"] = align_fit(kfx, kfsynth, dev)
     return sec
+
+
+def overlap_build(kfx, dev):
+    """The overlap workload (20 % of the crossings leave a second hit on
+    the same layer) built with and without overlap recovery: graph-replayed
+    time, steps/s, and the hits recovered in the best candidates."""
+    import torch
+    ev, ctx, hits, s, e, _, _ = setup_workload(kfx, "overlap5k", dev)
+    res = {"workload": "build5k with 20 % of the crossings leaving a second hit on their layer (overlap5k)"}
+    K = ev.workload.max_cands
+    for on in (False, True):
+        kw = dict(build_kw(ev, kfx.MODE_FUSED), overlap=on)
+        shape = ctx.autotune_build(hits, s, e, reps=1, **kw)
+        shape.pop("ms")
+        out = ctx.build_tracks(hits, s, e, **kw, **shape)
+        graph, gout = ctx.build_graph(hits, s, e, **kw, **shape)
+        graph.launch()
+        torch.cuda.synchronize()
+        gout["stats"].zero_()
+        n = 5
+        t0 = time.perf_counter()
+        for _ in range(n):
+            graph.launch()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / n
+        st = gout["stats"].cpu().numpy().astype(np.float64) / n
+        best = gout["hits"].reshape(-1, gout["hits"].shape[-1])[::K][:ev.n_tracks].cpu().numpy()
+        lay = ev.layer
+        rec = 0
+        for row in best:
+            h = row[row >= 0]
+            rec += int(np.sum(lay[h][1:] == lay[h][:-1]))
+        tag = "recovery" if on else "no_recovery"
+        res[tag] = {"ms_per_step": ms, "steps_per_s": st[0] / (ms * 1e-3), "updates_per_launch": st[2],
+                    "recovered_hits_in_best_candidates": rec, "launch_shape": shape}
+        graph.close()
+        del gout, out
+        log(f"[bench] overlap5k {tag}: {ms:.3f} ms/step, {rec} recovered hits")
+    del hits, ctx
+    torch.cuda.empty_cache()
+    return res
 
 
 def second_iteration(kfx, kfsynth, dev, ctx, hits, ev, shape):

@@ -403,10 +403,22 @@ void kfx_graph_destroy(kfx_graph* graph);
  * seeds_per_wave from 2 up to 64 / lanes_per_seed.  Writes the fastest shape into
  * params (mode becomes KFX_MODE_FUSED) and its time into *best_ms
  * (nullable).  Every shape gives identical results; out holds the last
- * call's, out->stats is restored.  Synchronises the stream. */
+ * call's, out->stats is restored.  Synchronises the stream.
+ *
+ * Results are cached per device (its architecture name and compute-unit
+ * count) and workload signature (seed, hit and event counts, K, holes,
+ * steps, chi2 cut, window inflation, overlap recovery): a call with a
+ * cached key returns the cached shape and time without building (out is
+ * then untouched).  When the environment variable KFX_AUTOTUNE_CACHE names
+ * a file, the cache is read from it on first use and every new entry is
+ * appended to it (one text line per entry), so later processes reuse it. */
 int kfx_autotune_build(kfx_ctx* ctx, const kfx_hits* hits, const int32_t* seeds, const int32_t* seed_event,
                        int32_t n_seeds, kfx_build_params* params, kfx_tracks* out, int32_t reps,
                        float* best_ms, void* stream);
+
+/* Empties the autotuner's in-process cache; the cache file, if one is
+ * named, is read again on the next autotuner call. */
+void kfx_autotune_cache_clear(void);
 
 #ifdef __cplusplus
 }

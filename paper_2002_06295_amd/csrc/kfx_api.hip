@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdint>
 #include <cstring>
+#include <fstream>
 #include <map>
 #include <mutex>
 #include <string>
@@ -724,6 +725,67 @@ void kfx_graph_destroy(kfx_graph* g) {
 }
 
 // ---- autotuner of the fused kernel's launch shape -------------------------
+}  // extern "C"
+
+namespace {
+// Autotuner cache: key = device (architecture name, compute units) and
+// workload signature; value = the launch shape and its time.  Optionally
+// mirrored in the file named by KFX_AUTOTUNE_CACHE (lines "key<TAB>bt
+// blocks lanes tile waves spw ms").
+struct TuneEntry {
+  int block_threads, blocks, lanes, tile, waves, spw;
+  float ms;
+};
+std::mutex g_tune_mu;
+std::map<std::string, TuneEntry> g_tune;
+bool g_tune_loaded = false;
+
+std::string tune_key(const kfx_ctx* c, const kfx_hits* h, int n_seeds, const kfx_build_params* p) {
+  hipDeviceProp_t prop{};
+  (void)hipGetDeviceProperties(&prop, c->device);
+  char buf[512];
+  snprintf(buf, sizeof(buf), "%s/%d|S%d|H%d|E%d|K%d|holes%d|steps%d|cut%.9g|infl%.9g|ov%d", prop.gcnArchName,
+           prop.multiProcessorCount, n_seeds, h ? h->n_hits : -1, h ? h->n_events : -1, p->max_cands,
+           p->max_holes, p->max_steps, (double)p->chi2_cut, (double)p->window_inflate, p->overlap ? 1 : 0);
+  return buf;
+}
+
+void tune_load_locked() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  const char* path = std::getenv("KFX_AUTOTUNE_CACHE");
+  if (!path || !*path) return;
+  std::ifstream f(path);
+  std::string line;
+  while (std::getline(f, line)) {
+    const size_t tab = line.find('\t');
+    if (tab == std::string::npos) continue;
+    TuneEntry e{};
+    if (sscanf(line.c_str() + tab + 1, "%d %d %d %d %d %d %f", &e.block_threads, &e.blocks, &e.lanes, &e.tile,
+               &e.waves, &e.spw, &e.ms) == 7)
+      g_tune[line.substr(0, tab)] = e;
+  }
+}
+
+void tune_store(const std::string& key, const TuneEntry& e) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune[key] = e;
+  const char* path = std::getenv("KFX_AUTOTUNE_CACHE");
+  if (!path || !*path) return;
+  std::ofstream f(path, std::ios::app);
+  f << key << '\t' << e.block_threads << ' ' << e.blocks << ' ' << e.lanes << ' ' << e.tile << ' ' << e.waves << ' '
+    << e.spw << ' ' << e.ms << '\n';
+}
+}  // namespace
+
+extern "C" {
+
+void kfx_autotune_cache_clear(void) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune.clear();
+  g_tune_loaded = false;  // the file, if any, is read again on next use
+}
+
 int kfx_autotune_build(kfx_ctx* c, const kfx_hits* hits, const int32_t* seeds, const int32_t* seed_event,
                        int32_t n_seeds, kfx_build_params* p, kfx_tracks* out, int32_t reps, float* best_ms,
                        void* stream) {
@@ -731,6 +793,24 @@ int kfx_autotune_build(kfx_ctx* c, const kfx_hits* hits, const int32_t* seeds, c
   c->err.clear();
   if (!p || !out) return fail(c, KFX_EINVAL, "params or out is NULL");
   if (reps < 1 || reps > 100) return fail(c, KFX_EINVAL, "reps out of [1, 100]");
+  const std::string key = tune_key(c, hits, n_seeds, p);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_load_locked();
+    const auto it = g_tune.find(key);
+    if (it != g_tune.end()) {
+      const TuneEntry& e = it->second;
+      p->mode = KFX_MODE_FUSED;
+      p->block_threads = e.block_threads;
+      p->blocks = e.blocks;
+      p->lanes_per_seed = e.lanes;
+      p->scan_tile = e.tile;
+      p->waves_per_simd = e.waves;
+      p->seeds_per_wave = e.spw;
+      if (best_ms) *best_ms = e.ms;
+      return KFX_OK;
+    }
+  }
   DeviceGuard dg(c->device);
   hipStream_t st = (hipStream_t)stream;
   const bool saved_timing = c->timing;
@@ -821,6 +901,8 @@ int kfx_autotune_build(kfx_ctx* c, const kfx_hits* hits, const int32_t* seeds, c
   p->waves_per_simd = cur.waves_per_simd;
   p->seeds_per_wave = cur.seeds_per_wave;
   if (best_ms) *best_ms = best;
+  tune_store(key, TuneEntry{cur.block_threads, cur.blocks, cur.lanes_per_seed, cur.scan_tile, cur.waves_per_simd,
+                            cur.seeds_per_wave, best});
   return KFX_OK;
 }
 
@@ -941,10 +1023,7 @@ int kfx_cluster_strips(kfx_ctx* c, const kfx_digis* d, const kfx_strip_calib* ca
   if (rc) return rc;
   a.code = (unsigned char*)ws(c, "strip.code", (size_t)d->n + 16, st, rc); if (rc) return rc;
   a.nz = (float*)ws(c, "strip.nz", (size_t)d->n * 4, st, rc); if (rc) return rc;
-  a.st_last = (int*)ws(c, "strip.last", (size_t)d->n * 4, st, rc); if (rc) return rc;
-  a.st_charge = (int*)ws(c, "strip.charge", (size_t)d->n * 4, st, rc); if (rc) return rc;
-  a.st_sa = (long*)ws(c, "strip.sa", (size_t)d->n * 8, st, rc); if (rc) return rc;
-  a.st_event = (int*)ws(c, "strip.event", (size_t)d->n * 4, st, rc); if (rc) return rc;
+  a.rec = (StripRec*)ws(c, "strip.rec", (size_t)d->n * sizeof(StripRec), st, rc); if (rc) return rc;
   a.flag = (int*)ws(c, "strip.flag", ((size_t)d->n + 1) * 4, st, rc); if (rc) return rc;
   a.pos = (int*)ws(c, "strip.pos", ((size_t)d->n + 2) * 4, st, rc); if (rc) return rc;
   int* scratch = (int*)ws(c, "strip.scan", (((size_t)d->n + 1) / 4096 + 4) * 4, st, rc); if (rc) return rc;

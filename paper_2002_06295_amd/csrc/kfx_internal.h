@@ -53,6 +53,19 @@ struct MaskArgs {
 };
 
 // Strip clustering over the digis of a batch of events.
+// What the heads-and-walks pass keeps of a kept cluster, at its head
+// digi: one 32-byte record, so that the write pass reads one line per
+// cluster instead of a scattered word from each of several arrays.
+struct __align__(32) StripRec {
+  long sa;      // sum of strip * adc
+  int last;     // last strip
+  int charge;   // sum of adc
+  int event;
+  int module;
+  int first;    // first strip
+  int pad;
+};
+
 struct StripArgs {
   const int* module;        // [n] digis, sorted by (event, module, strip)
   const int* strip;         // [n]
@@ -71,10 +84,7 @@ struct StripArgs {
   float* nz;                // [n] noise of each digi
   int* flag;                // [n + 1] kept-cluster head flags
   int* pos;                 // [n + 1] their exclusive scan
-  int* st_last;             // [n] per kept head: last strip, charge,
-  int* st_charge;           //     sum strip * adc, event
-  long* st_sa;
-  int* st_event;
+  StripRec* rec;            // [n] per kept head: its cluster's sums
   int* out_event;           // [capacity] kept clusters
   int* out_module;
   int* out_first;

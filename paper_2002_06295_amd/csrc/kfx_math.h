@@ -152,27 +152,20 @@ KFX_HD void sincos_d(double x, double& s, double& c) {
   constexpr double k2Opi = 0.6366197723675814;        // 2/pi
   const double q = rint(x * k2Opi);
   const double r = fma(-q, kPio2Lo, fma(-q, kPio2Hi, x));
-  const double r2 = r * r;
-  // sin r = r (1 - r^2/3! + r^4/5! - ... + r^16/17!)
-  double ps = 1.0 / 355687428096000.0;                // 1/17!
-  ps = fma(ps, r2, -1.0 / 1307674368000.0);           // 1/15!
-  ps = fma(ps, r2, 1.0 / 6227020800.0);               // 1/13!
-  ps = fma(ps, r2, -1.0 / 39916800.0);                // 1/11!
-  ps = fma(ps, r2, 1.0 / 362880.0);                   // 1/9!
-  ps = fma(ps, r2, -1.0 / 5040.0);                    // 1/7!
-  ps = fma(ps, r2, 1.0 / 120.0);                      // 1/5!
-  ps = fma(ps, r2, -1.0 / 6.0);                       // 1/3!
-  const double sr = fma(ps * r2, r, r);
-  // cos r = 1 - r^2/2! + r^4/4! - ... + r^16/16!
-  double pc = 1.0 / 20922789888000.0;                 // 1/16!
-  pc = fma(pc, r2, -1.0 / 87178291200.0);             // 1/14!
-  pc = fma(pc, r2, 1.0 / 479001600.0);                // 1/12!
-  pc = fma(pc, r2, -1.0 / 3628800.0);                 // 1/10!
-  pc = fma(pc, r2, 1.0 / 40320.0);                    // 1/8!
-  pc = fma(pc, r2, -1.0 / 720.0);                     // 1/6!
-  pc = fma(pc, r2, 1.0 / 24.0);                       // 1/4!
-  pc = fma(pc, r2, -0.5);                             // 1/2!
-  const double cr = fma(pc, r2, 1.0);
+  const double y = r * r, y2 = y * y, y4 = y2 * y2;
+  // sin r = r + r y P(y), P(y) = -1/3! + y/5! - ... + y^7/17!; cos r = 1 +
+  // y Q(y), Q(y) = -1/2! + y/4! - ... + y^7/16!.  Both evaluated by
+  // Estrin's scheme (pairs, then pairs of pairs) rather than Horner's: a
+  // dependent chain of about four multiply-adds instead of eight, which is
+  // what the step's latency sees.
+  const double ps = fma(y4, fma(y2, fma(y, 1.0 / 355687428096000.0, -1.0 / 1307674368000.0),
+                                fma(y, 1.0 / 6227020800.0, -1.0 / 39916800.0)),
+                        fma(y2, fma(y, 1.0 / 362880.0, -1.0 / 5040.0), fma(y, 1.0 / 120.0, -1.0 / 6.0)));
+  const double sr = fma(ps * y, r, r);
+  const double pc = fma(y4, fma(y2, fma(y, 1.0 / 20922789888000.0, -1.0 / 87178291200.0),
+                                fma(y, 1.0 / 479001600.0, -1.0 / 3628800.0)),
+                        fma(y2, fma(y, 1.0 / 40320.0, -1.0 / 720.0), fma(y, 1.0 / 24.0, -0.5)));
+  const double cr = fma(pc, y, 1.0);
   const int qi = (int)(q - 4.0 * floor(0.25 * q));  // q mod 4, exact
   s = qi == 0 ? sr : (qi == 1 ? cr : (qi == 2 ? -sr : -cr));
   c = qi == 0 ? cr : (qi == 1 ? -sr : (qi == 2 ? -cr : sr));
@@ -268,20 +261,13 @@ KFX_HD double path_to_cylinder(const StateT<R>& st, double cphi, double sphi, do
   if (fabs(x) < 0.25) {
     // atan(x)/x = sum (-1)^n x^2n / (2n + 1), to the x^24 term: the
     // truncation (< 1e-17 for |x| < 0.25) is below FP64 rounding
-    const double x2 = x * x;
-    double p = 1.0 / 25.0;
-    p = fma(p, x2, -1.0 / 23.0);
-    p = fma(p, x2, 1.0 / 21.0);
-    p = fma(p, x2, -1.0 / 19.0);
-    p = fma(p, x2, 1.0 / 17.0);
-    p = fma(p, x2, -1.0 / 15.0);
-    p = fma(p, x2, 1.0 / 13.0);
-    p = fma(p, x2, -1.0 / 11.0);
-    p = fma(p, x2, 1.0 / 9.0);
-    p = fma(p, x2, -1.0 / 7.0);
-    p = fma(p, x2, 1.0 / 5.0);
-    p = fma(p, x2, -1.0 / 3.0);
-    s = tau * fma(p, x2, 1.0);
+    // (Estrin's scheme over u = x^2: pairs of terms, then pairs of pairs)
+    const double u = x * x, u2 = u * u, u4 = u2 * u2, u8 = u4 * u4;
+    const double b0 = fma(u2, fma(u, -1.0 / 7.0, 1.0 / 5.0), fma(u, -1.0 / 3.0, 1.0));       // u^0..3
+    const double b1 = fma(u2, fma(u, -1.0 / 15.0, 1.0 / 13.0), fma(u, -1.0 / 11.0, 1.0 / 9.0));  // u^4..7
+    const double b2 = fma(u2, fma(u, -1.0 / 23.0, 1.0 / 21.0), fma(u, -1.0 / 19.0, 1.0 / 17.0));  // u^8..11
+    const double p = fma(u8, fma(u4, 1.0 / 25.0, b2), fma(u4, b1, b0));
+    s = tau * p;
   } else {
     s = atan(x) / k;
   }
@@ -430,6 +416,22 @@ KFX_HD void add_noise(StateT<R>& st, const Layer& Ld, R sth, R cth, R cinc) {
   st.C[sidx(5, 3)] += -k * cot * var;
 }
 
+// Unit vector along (x, y) in the precision of R: for FP32 from the
+// coordinates rounded to FP32 (a result that is rounded to FP32 anyway
+// needs no FP64 square root and division, which are long dependent chains
+// on the GPU), for FP64 in FP64.
+KFX_HD void unit_xy(double x, double y, float& c, float& s) {
+  const float xf = (float)x, yf = (float)y;
+  const float ir = 1.0f / sqrtf(xf * xf + yf * yf);
+  c = xf * ir;
+  s = yf * ir;
+}
+KFX_HD void unit_xy(double x, double y, double& c, double& s) {
+  const double ir = 1.0 / sqrt(x * x + y * y);
+  c = x * ir;
+  s = y * ir;
+}
+
 // Transport (p, C) over transverse path s to the surface of layer Ld
 // (barrel radius possibly aligned): new parameters, C- = J C J^T + Q with
 // the surface-constrained Jacobian J = A + b c^T, where A = dF/dp at fixed
@@ -549,8 +551,8 @@ KFX_HD void transport(const StateT<R>& in, const Layer& Ld, double cphi, double 
     // e = (x, y, 0)/r.  Rounding leaves some; at a steep crossing it rivals
     // sigma_n^2 in S.  Apply P C P^T with P = I - e e^T (an identity in exact
     // arithmetic): C' = C - e w^T - w e^T + (e^T C e) e e^T, w = C e.
-    const double ir1 = 1.0 / sqrt(out.x * out.x + out.y * out.y);
-    const R e0 = (R)(out.x * ir1), e1 = (R)(out.y * ir1);
+    R e0, e1;
+    unit_xy(out.x, out.y, e0, e1);
     e0_n = e0;
     e1_n = e1;
     R w[6];
@@ -598,8 +600,8 @@ using Frame = FrameT<float>;
 
 template <class R>
 KFX_HD void make_frame(const StateT<R>& st, const Layer& Ld, FrameT<R>& F) {
-  const double ir = 1.0 / sqrt(st.x * st.x + st.y * st.y);
-  const R c = (R)(st.x * ir), s = (R)(st.y * ir);
+  R c, s;
+  unit_xy(st.x, st.y, c, s);
   const bool disk = Ld.kind == kDisk;
   const R z0 = (R)0, o1 = (R)1;
   F.h[0][0] = -s; F.h[0][1] = c; F.h[0][2] = z0;

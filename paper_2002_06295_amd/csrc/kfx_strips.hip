@@ -184,10 +184,15 @@ __global__ void __launch_bounds__(256) k_strip_flags(StripArgs a) {
         }
         if (seed && (double)sq > a.clus_thr2 * nsq && charge >= a.min_charge) {
           kept = 1;
-          a.st_last[i] = last;
-          a.st_charge[i] = charge;
-          a.st_sa[i] = sa;
-          a.st_event[i] = e;
+          StripRec r;
+          r.sa = sa;
+          r.last = last;
+          r.charge = charge;
+          r.event = e;
+          r.module = a.module[i];
+          r.first = a.strip[i];
+          r.pad = 0;
+          a.rec[i] = r;
         }
       }
     }
@@ -202,14 +207,13 @@ __global__ void __launch_bounds__(256) k_strip_write(StripArgs a) {
     if (!a.flag[i]) continue;
     const int p = a.pos[i];
     if (p >= a.capacity) continue;
-    const int first = a.strip[i];
-    const int charge = a.st_charge[i];
-    a.out_event[p] = a.st_event[i];
-    a.out_module[p] = a.module[i];
-    a.out_first[p] = first;
-    a.out_size[p] = a.st_last[i] - first + 1;
-    a.out_charge[p] = charge;
-    a.out_bary[p] = (float)((double)a.st_sa[i] / (double)charge);
+    const StripRec r = a.rec[i];
+    a.out_event[p] = r.event;
+    a.out_module[p] = r.module;
+    a.out_first[p] = r.first;
+    a.out_size[p] = r.last - r.first + 1;
+    a.out_charge[p] = r.charge;
+    a.out_bary[p] = (float)((double)r.sa / (double)r.charge);
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) *a.n_out = a.pos[a.n];
 }

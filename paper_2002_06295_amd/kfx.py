@@ -30,7 +30,7 @@ MAX_STEPS = 40
 EXPORTED = ["kfx_create", "kfx_destroy", "kfx_last_error", "kfx_load_layers", "kfx_bin_hits",
             "kfx_seed_states", "kfx_step_compat", "kfx_build_tracks", "kfx_fit_tracks",
             "kfx_fit_tracks_backward", "kfx_fit_tracks_backward_noalloc", "kfx_enable_timing", "kfx_build_times", "kfx_build_graph",
-            "kfx_graph_launch", "kfx_graph_destroy", "kfx_autotune_build", "kfx_find_duplicates", "kfx_mask_hits",
+            "kfx_graph_launch", "kfx_graph_destroy", "kfx_autotune_build", "kfx_autotune_cache_clear", "kfx_find_duplicates", "kfx_mask_hits",
             "kfx_cluster_strips"]
 
 
@@ -135,6 +135,8 @@ def load_library():
     lib.kfx_graph_launch.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
     lib.kfx_graph_destroy.argtypes = [ctypes.c_void_p]
     lib.kfx_graph_destroy.restype = None
+    lib.kfx_autotune_cache_clear.argtypes = []
+    lib.kfx_autotune_cache_clear.restype = None
     lib.kfx_autotune_build.argtypes = [ctypes.c_void_p, ctypes.POINTER(c_hits), ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.c_int32, ctypes.POINTER(c_build_params), ctypes.POINTER(c_tracks),
                                        ctypes.c_int32, ctypes.POINTER(ctypes.c_float), ctypes.c_void_p]
@@ -400,7 +402,8 @@ class Context:
         """Fastest launch shape of the fused kernel for this workload: a dict
         of block_threads, blocks, lanes_per_seed, scan_tile, waves_per_simd,
         seeds_per_wave (pass it back to build_tracks) and the time of one
-        build in ms."""
+        build in ms.  Cached per device and workload signature (see
+        kfx_autotune_build); autotune_cache_clear() empties the cache."""
         kw = dict(kw)
         kw["mode"] = MODE_FUSED
         seeds, seed_event, S, p, out = self._build_args(seeds, seed_event, **kw)
@@ -411,6 +414,9 @@ class Context:
         return dict(block_threads=p.block_threads, blocks=p.blocks, lanes_per_seed=p.lanes_per_seed,
                     scan_tile=p.scan_tile, waves_per_simd=p.waves_per_simd, seeds_per_wave=p.seeds_per_wave,
                     ms=float(ms.value))
+
+    def autotune_cache_clear(self):
+        self.lib.kfx_autotune_cache_clear()
 
     def enable_timing(self, n_calls=64):
         self._check(self.lib.kfx_enable_timing(self.h, int(n_calls)))

@@ -117,6 +117,39 @@ def test_autotune_shapes_are_bit_identical(dev, kfx, setup):
         assert same(snapshot(ctx.build_tracks(hits, seeds, sev, **kw, **shape)), ref), shape
 
 
+def test_autotune_cache(dev, kfx, setup, tmp_path, monkeypatch):
+    """A second autotuner call with the same device and workload signature
+    returns the cached shape and time without building; another signature
+    (another K) is tuned anew; with KFX_AUTOTUNE_CACHE set every new entry
+    is appended to the file, and after the in-process cache is cleared the
+    entries come back from the file."""
+    import time
+    ev, ctx, hits, seeds, sev, kw = setup
+    path = tmp_path / "tune.txt"
+    monkeypatch.setenv("KFX_AUTOTUNE_CACHE", str(path))
+    ctx.autotune_cache_clear()
+    t0 = time.perf_counter()
+    a = ctx.autotune_build(hits, seeds, sev, reps=1, **kw)
+    t1 = time.perf_counter()
+    b = ctx.autotune_build(hits, seeds, sev, reps=1, **kw)
+    t2 = time.perf_counter()
+    assert a == b
+    assert (t2 - t1) < 0.2 * (t1 - t0), (t1 - t0, t2 - t1)
+    c = ctx.autotune_build(hits, seeds, sev, reps=1, **dict(kw, max_cands=4))
+    assert c["lanes_per_seed"] in (4, 8, 16)
+    assert len(path.read_text().strip().splitlines()) == 2
+    ctx.autotune_cache_clear()
+    t3 = time.perf_counter()
+    d = ctx.autotune_build(hits, seeds, sev, reps=1, **kw)
+    t4 = time.perf_counter()
+    assert d["block_threads"] == a["block_threads"] and d["blocks"] == a["blocks"]
+    assert d["lanes_per_seed"] == a["lanes_per_seed"] and d["seeds_per_wave"] == a["seeds_per_wave"]
+    assert d["scan_tile"] == a["scan_tile"] and d["waves_per_simd"] == a["waves_per_simd"]
+    assert (t4 - t3) < 0.2 * (t1 - t0)
+    ctx.autotune_cache_clear()
+    monkeypatch.delenv("KFX_AUTOTUNE_CACHE")
+
+
 def test_build_timing_split(dev, kfx, setup):
     import torch
     ev, ctx, hits, seeds, sev, kw = setup

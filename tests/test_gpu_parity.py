@@ -172,6 +172,113 @@ def test_step_compatibility_lists(dev, kfx, ev_build):
     assert near <= 2
 
 
+def _states_along_truth(ev, tracks, n_upd):
+    """FP64 oracle states of truth tracks after their seed and n_upd more
+    hits (navigate, predict, update along the recorded hits), with the
+    covariance rounded to float32 (the GPU's storage) so that both sides get
+    identical inputs; returns (p, C, layer) of the tracks that get there."""
+    ps, Cs, _, ok = oracle.seed_states(ev, seeds=ev.seeds[tracks], prior=PRIOR)
+    P, C, L = [], [], []
+    for i, t in enumerate(tracks):
+        if not ok[i]:
+            continue
+        p, c = ps[i], Cs[i]
+        hl = ev.trk_hits[ev.trk_offsets[t] + 3:ev.trk_offsets[t + 1]]
+        if hl.size < n_upd + 1:
+            continue
+        cur = int(ev.layer[ev.seeds[t][2]])
+        good = True
+        for h in hl[:n_upd]:
+            nl = int(ev.layer[h])
+            p, c = oracle.predict(ev.geometry, ev.bz, nl, p, c)
+            if p is None:
+                good = False
+                break
+            p, c, _ = oracle.update(ev.geometry, nl, p, c, np.array([ev.x[h], ev.y[h], ev.z[h]], np.float64))
+            cur = nl
+        if good:
+            P.append(p)
+            C.append(c.astype(np.float32).astype(np.float64))
+            L.append(cur)
+    return np.array(P), np.array(C), np.array(L, np.int32)
+
+
+def _s_mismatch(geometry, layer, p, Cg, Co):
+    """How far the GPU's predicted covariance moves the pair covariance S =
+    H C H^T + V from the oracle's, in S's own metric: the largest |lambda|
+    of S_o^-1/2 (S_g - S_o) S_o^-1/2.  A pair's chi2 r^T S^-1 r then
+    differs by at most about chi2 times that."""
+    r = np.hypot(p[0], p[1])
+    c, s_ = p[0] / r, p[1] / r
+    bar = geometry.kind[layer] == 0
+    H = np.zeros((3, 6))
+    H[0, 0], H[0, 1] = -s_, c
+    if bar:
+        H[1, 2] = 1.0
+        H[2, 0], H[2, 1] = c, s_
+    else:
+        H[1, 0], H[1, 1] = c, s_
+        H[2, 2] = 1.0
+    V = np.diag([geometry.su[layer] ** 2, geometry.sv[layer] ** 2, geometry.sn[layer] ** 2])
+    So = H @ Co @ H.T + V
+    Sg = H @ Cg @ H.T + V
+    w, U = np.linalg.eigh(So)
+    Si2 = U @ np.diag(w ** -0.5) @ U.T
+    return float(np.abs(np.linalg.eigvalsh(Si2 @ (Sg - So) @ Si2)).max())
+
+
+@pytest.mark.parametrize("n_upd", [2, 6, 11])
+def test_step_compatibility_lists_later_steps(dev, kfx, ev_build, n_upd):
+    """The identical-input step parity deeper into the search: states of
+    truth tracks after n_upd updates past the seed (the oracle's, given to
+    both sides), one step each: the same next surface, the prediction
+    within the state tolerances, and the same compatible hits in the same
+    order (pairs within 1e-3 of the cut may differ, at most 2 in all).
+    A pair's chi2 is within 1e-3, or, where the FP32 transport of a
+    strongly correlated covariance moved S by a relative eps (measured from
+    the two predictions, which the state bounds hold), within
+    1e-3 + 1.5 eps chi2; how many pairs need that is printed."""
+    ev = ev_build
+    ctx = make_ctx(kfx, ev)
+    hits = kfx.DeviceHits.from_events(ev, dev)
+    ctx.bin_hits(hits)
+    pin, Cin, lay = _states_along_truth(ev, np.arange(0, ev.n_tracks, 5), n_upd)
+    assert len(lay) > 300
+    nxt_o, p1o, C1o, offp, ph, pc = oracle.step_compat(ev, 0, lay, pin, Cin, 30.0)
+    nxt_g, predg, cntg, phg, pcg = ctx.step_compat(hits, np.zeros(len(lay), np.int32), lay,
+                                                   kfx.States.from_numpy(pin, Cin, dev), 30.0, max_pairs=64)
+    nxt_g = nxt_g.cpu().numpy()
+    assert np.array_equal(nxt_g, nxt_o)
+    m = nxt_o >= 0
+    p1g, C1g = predg.to_numpy()
+    check_states(p1g[m], C1g[m], p1o[m], C1o[m], ev.geometry.kind[nxt_o[m]], f"step prediction after {n_upd}")
+    cntg, phg, pcg = cntg.cpu().numpy(), phg.cpu().numpy(), pcg.cpu().numpy()
+    near = 0
+    worst = 0.0
+    beyond = 0
+    for i in np.nonzero(m)[0]:
+        lo, co = ph[offp[i]:offp[i + 1]], pc[offp[i]:offp[i + 1]]
+        n = min(cntg[i], 64)
+        lg, cg = phg[i, :n], pcg[i, :n]
+        if np.array_equal(lo, lg):
+            if lo.size:
+                d = np.abs(co - cg)
+                worst = max(worst, d.max())
+                if d.max() > 1e-3:
+                    eps = _s_mismatch(ev.geometry, nxt_o[i], p1o[i], C1g[i], C1o[i])
+                    assert np.all(d <= 1e-3 + 1.5 * eps * co), (i, d, co, eps)
+                    beyond += int(np.sum(d > 1e-3))
+            continue
+        diff = np.setxor1d(lo, lg)
+        cut_pairs = [h for h in diff if (h in lo and abs(co[list(lo).index(h)] - 30.0) < 1e-3)
+                     or (h in lg and abs(cg[list(lg).index(h)] - 30.0) < 1e-3)]
+        assert len(cut_pairs) == len(diff), (i, lo, co, lg, cg)
+        near += len(diff)
+    print(f"after {n_upd} updates: {len(lay)} states, pair chi2 max diff {worst:.3g}, "
+          f"{beyond} pairs above 1e-3 (within their S-mismatch bound), {near} pairs at the cut")
+    assert near <= 2
+
+
 def test_step_with_bad_candidates(dev, kfx, ev_build):
     """NaN states, unknown layers and events give 'no next surface'."""
     ev = ev_build
