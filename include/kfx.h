@@ -128,6 +128,14 @@ typedef struct {
                             update, hit and chi2 term; right after h1 in the
                             hit list).  Sec. 3 of the paper names recovering
                             hits of overlapping modules as planned work. */
+  int32_t score;         /* 0: children ranked by hits (more first), holes
+                            (fewer first), chi2 sum (smaller first); nonzero:
+                            by the score score_hit n_hits - score_hole
+                            n_holes - score_chi2 chi2 (float32, higher
+                            first).  Both then by parent slot and rank; Sec.
+                            3 of the paper re-tunes the score for short
+                            tracks without a formula.                        */
+  float score_hit, score_hole, score_chi2;
 } kfx_build_params;
 
 /* Output of building, per seed s and slot j < K, best first (device). */

@@ -197,9 +197,11 @@ def step_compat(ev, event, cur_layer, p_in, C_in, chi2_cut=30.0, brute=False,
 
 
 def build_tracks(ev, seeds=None, seed_event=None, chi2_cut=None, max_cands=None,
-          max_holes=None, brute=False, prior=DEFAULT_PRIOR, max_hits=64, overlap=False):
+          max_holes=None, brute=False, prior=DEFAULT_PRIOR, max_hits=64, overlap=False, score=None):
     """Beam-search track building.  Returns a dict of arrays per seed x K.
-    overlap: recover a second hit on the layer of every kept hit child."""
+    overlap: recover a second hit on the layer of every kept hit child.
+    score: None (rank by hits, holes, chi2) or (w_hit, w_hole, w_chi2):
+    rank by w_hit n_hits - w_hole n_holes - w_chi2 chi2, highest first."""
     w = ev.workload
     chi2_cut = w.chi2_cut if chi2_cut is None else chi2_cut
     K = w.max_cands if max_cands is None else max_cands
@@ -218,10 +220,11 @@ def build_tracks(ev, seeds=None, seed_event=None, chi2_cut=None, max_cands=None,
         chi2=np.zeros((ns, K)), p=np.zeros((ns, K, 6)), C=np.zeros((ns, K, 6, 6)),
         stats=np.zeros(3, np.int64))
     pr = _f64(prior)
+    sw = None if score is None else _f64(score)
     lib().kfo_build(_p(L), L.shape[0], _D(ev.bz), int(w.n_eta_bins), int(w.n_phi_bins),
                     _p(x), _p(y), _p(z), _p(lay), _p(off), int(off.shape[0] - 1), _p(seeds),
                     _p(seed_event), ns, _D(chi2_cut), int(K), int(max_holes), int(bool(brute)),
-                    int(bool(overlap)), _p(pr), int(max_hits), _p(out["n"]), _p(out["hits"]), _p(out["nhits"]),
+                    int(bool(overlap)), None if sw is None else _p(sw), _p(pr), int(max_hits), _p(out["n"]), _p(out["hits"]), _p(out["nhits"]),
                     _p(out["nholes"]), _p(out["chi2"]), _p(out["p"]), _p(out["C"]),
                     _p(out["stats"]))
     return out

@@ -711,6 +711,21 @@ static bool child_less(const Child& a, const Child& b) {
   return ha < hb;
 }
 
+// Score ranking (Sec. 3 re-tunes the score that decides which candidates
+// are best, for short tracks; the paper gives no formula, the reading is
+// ours): score = w_hit n_hits - w_hole n_holes - w_chi2 chi2, higher first,
+// then parent slot, then hit index (holes after hits).
+struct ScoreLess {
+  double wh, wm, wc;
+  double score(const Child& c) const { return wh * c.nhits - wm * c.nholes - wc * c.chi2; }
+  bool operator()(const Child& a, const Child& b) const {
+    const double sa = score(a), sb = score(b);
+    if (sa != sb) return sa > sb;
+    if (a.parent != b.parent) return a.parent < b.parent;
+    return (unsigned)a.hit < (unsigned)b.hit;
+  }
+};
+
 struct BuildParams {
   double chi2_cut = 30.0;
   int max_cands = 6;
@@ -718,6 +733,8 @@ struct BuildParams {
   int max_steps = 64;
   int brute = 0;
   int overlap = 0;  // recover a second hit on the layer of a kept hit child
+  int score = 0;    // rank by ScoreLess with these weights (0: child_less)
+  double w_hit = 0.0, w_hole = 0.0, w_chi2 = 0.0;
 };
 
 struct SeedResult {
@@ -795,7 +812,10 @@ static SeedResult build_seed(const Geom& g, const EventHits& ev, const int sh[3]
         kids.push_back(Child{slot, -1, c.nhits, c.nholes + 1, c.chi2, 0.0});
       if ((int)kids.size() == n0) kids.push_back(stop);
     }
-    std::sort(kids.begin(), kids.end(), child_less);
+    if (bp.score)
+      std::sort(kids.begin(), kids.end(), ScoreLess{bp.w_hit, bp.w_hole, bp.w_chi2});
+    else
+      std::sort(kids.begin(), kids.end(), child_less);
     if ((int)kids.size() > bp.max_cands) kids.resize(bp.max_cands);
     std::vector<Cand> nb;
     for (const Child& k : kids) {
@@ -1092,13 +1112,18 @@ long kfo_step_compat(const double* layers, int nl, double bz, int neta, int nphi
 void kfo_build(const double* layers, int nl, double bz, int neta, int nphi, const float* x,
                const float* y, const float* z, const int* layer, const int* ev_off, int nev,
                const int* seeds, const int* seed_event, int ns, double chi2_cut, int K,
-               int max_holes, int brute, int overlap, const double* prior, int maxh, int* out_n,
+               int max_holes, int brute, int overlap, const double* score_w, const double* prior, int maxh,
+               int* out_n,
                int* out_hits, int* out_nhits, int* out_nholes, double* out_chi2,
                double* out_p, double* out_C, long* stats) {
   Geom g = make_geom(layers, nl, bz, neta, nphi);
   BuildParams bp;
   bp.chi2_cut = chi2_cut; bp.max_cands = K; bp.max_holes = max_holes; bp.brute = brute;
   bp.overlap = overlap;
+  if (score_w) {
+    bp.score = 1;
+    bp.w_hit = score_w[0]; bp.w_hole = score_w[1]; bp.w_chi2 = score_w[2];
+  }
   Prior pr{prior[0], prior[1], prior[2], prior[3]};
   std::vector<EventHits> evs(nev);
   for (int e = 0; e < nev; ++e) {

@@ -442,6 +442,8 @@ int build_impl(kfx_ctx* c, const kfx_hits* hits, const int32_t* seeds, const int
   if (p->mode != KFX_MODE_PLAIN && p->mode != KFX_MODE_FUSED) return fail(c, KFX_EINVAL, "unknown mode");
   if (!(p->window_inflate == 0.0f || (p->window_inflate >= 1.0f && p->window_inflate <= 1e4f)))
     return fail(c, KFX_EINVAL, "window_inflate must be 0 or in [1, 1e4]");
+  if (p->score && !(std::isfinite(p->score_hit) && std::isfinite(p->score_hole) && std::isfinite(p->score_chi2)))
+    return fail(c, KFX_EINVAL, "score weights must be finite");
   if (p->block_threads != 0 && (p->block_threads < 64 || p->block_threads > 256 || p->block_threads % 64))
     return fail(c, KFX_EINVAL, "block_threads must be 0 or a multiple of 64 in [64, 256]");
   if (p->blocks < 0) return fail(c, KFX_EINVAL, "blocks < 0");
@@ -509,6 +511,7 @@ int build_impl(kfx_ctx* c, const kfx_hits* hits, const int32_t* seeds, const int
   a.max_holes = p->max_holes;
   a.max_steps = p->max_steps;
   a.overlap = p->overlap ? 1 : 0;
+  a.rank = RankW{p->score_hit, p->score_hole, p->score_chi2, p->score ? 1 : 0};
   a.inflate = p->window_inflate > 0.0f ? p->window_inflate : 1.0f;
   a.coop_min = p->scan_tile ? p->scan_tile : 64;
   {
@@ -744,9 +747,11 @@ std::string tune_key(const kfx_ctx* c, const kfx_hits* h, int n_seeds, const kfx
   hipDeviceProp_t prop{};
   (void)hipGetDeviceProperties(&prop, c->device);
   char buf[512];
-  snprintf(buf, sizeof(buf), "%s/%d|S%d|H%d|E%d|K%d|holes%d|steps%d|cut%.9g|infl%.9g|ov%d", prop.gcnArchName,
-           prop.multiProcessorCount, n_seeds, h ? h->n_hits : -1, h ? h->n_events : -1, p->max_cands,
-           p->max_holes, p->max_steps, (double)p->chi2_cut, (double)p->window_inflate, p->overlap ? 1 : 0);
+  snprintf(buf, sizeof(buf), "%s/%d|S%d|H%d|E%d|K%d|holes%d|steps%d|cut%.9g|infl%.9g|ov%d|score%d:%.9g:%.9g:%.9g",
+           prop.gcnArchName, prop.multiProcessorCount, n_seeds, h ? h->n_hits : -1, h ? h->n_events : -1,
+           p->max_cands, p->max_holes, p->max_steps, (double)p->chi2_cut, (double)p->window_inflate,
+           p->overlap ? 1 : 0, p->score ? 1 : 0, (double)p->score_hit, (double)p->score_hole,
+           (double)p->score_chi2);
   return buf;
 }
 

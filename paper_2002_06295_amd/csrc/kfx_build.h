@@ -26,6 +26,7 @@ struct BuildArgs {
   int max_holes;
   int max_steps;
   int overlap;            // recover a second hit on the layer of a kept hit child
+  RankW rank;             // ranking of the children (key or score)
   float inflate;          // window widening (>= 1; the window is a superset at 1)
   int coop_min;           // fused: window size scanned by the whole wave
   int groups_per_wave;    // fused: seed groups of a wavefront that take seeds
@@ -177,21 +178,21 @@ KFX_HD KidStream kid_stream(const BuildArgs& a, int meta, float chi2, int next_l
 }
 
 // key of child number r of a stream (r < nkids: hit child r; r == nkids:
-// hole; stop: r == 0); ~0 when exhausted.
-KFX_HD uint64_t kid_key(const KidStream& k, int K, int r, const float* kc, float& chi2_out) {
+// hole; stop: r == 0) under the call's ranking w; ~0 when exhausted.
+KFX_HD uint64_t kid_key(const RankW& w, const KidStream& k, int K, int r, const float* kc, float& chi2_out) {
   if (!k.live) return ~0ull;
   if (k.stop) {
     if (r > 0) return ~0ull;
     chi2_out = k.chi2;
-    return child_key(k.nh, k.nho, k.chi2, k.parent, 0);
+    return rank_key(w, k.nh, k.nho, k.chi2, k.parent, 0);
   }
   if (r < k.nkids) {
     chi2_out = k.chi2 + kc[r];
-    return child_key(k.nh + 1, k.nho, chi2_out, k.parent, r);
+    return rank_key(w, k.nh + 1, k.nho, chi2_out, k.parent, r);
   }
   if (r == k.nkids && k.hole) {
     chi2_out = k.chi2;
-    return child_key(k.nh, k.nho + 1, k.chi2, k.parent, K);
+    return rank_key(w, k.nh, k.nho + 1, k.chi2, k.parent, K);
   }
   return ~0ull;
 }
@@ -208,7 +209,7 @@ KFX_HD void select_seed(const BuildArgs& a, int cur, int s) {
     ks[j] = kid_stream(a, a.meta[cur][slot], a.chi2[cur][slot], a.next_layer[slot],
                        a.next_layer[slot] >= 0 ? a.kid_n[slot] : 0, j);
     pos[j] = 0;
-    head[j] = kid_key(ks[j], K, 0, a.kid_c + slot * K, hc[j]);
+    head[j] = kid_key(a.rank, ks[j], K, 0, a.kid_c + slot * K, hc[j]);
   }
   for (int i = 0; i < K; ++i) {
     int w = -1;
@@ -234,7 +235,7 @@ KFX_HD void select_seed(const BuildArgs& a, int cur, int s) {
     a.sel_code[out] = code;
     a.sel_chi2[out] = hc[w];
     pos[w]++;
-    head[w] = kid_key(ks[w], K, pos[w], a.kid_c + ps * K, hc[w]);
+    head[w] = kid_key(a.rank, ks[w], K, pos[w], a.kid_c + ps * K, hc[w]);
   }
 }
 

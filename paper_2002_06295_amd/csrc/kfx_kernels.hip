@@ -957,15 +957,15 @@ k_build_fused(BuildArgs a, TracksOut o, int* seed_counter) {
       if (ks.live) {
         if (ks.stop) {
           if (idx == 0) {
-            head = child_key(ks.nh, ks.nho, ks.chi2, ks.parent, 0);
+            head = rank_key(a.rank, ks.nh, ks.nho, ks.chi2, ks.parent, 0);
             hchi2 = ks.chi2;
           }
         } else if (idx < best.n) {
           hchi2 = ks.chi2 + pair_key_chi2(best.k[0]);
-          head = child_key(ks.nh + 1, ks.nho, hchi2, ks.parent, idx);
+          head = rank_key(a.rank, ks.nh + 1, ks.nho, hchi2, ks.parent, idx);
           hcode = pair_key_hit(best.k[0]);
         } else if (idx == best.n && ks.hole) {
-          head = child_key(ks.nh, ks.nho + 1, ks.chi2, ks.parent, K);
+          head = rank_key(a.rank, ks.nh, ks.nho + 1, ks.chi2, ks.parent, K);
           hcode = kHole;
           hchi2 = ks.chi2;
         }

@@ -214,6 +214,24 @@ KFX_HD uint64_t child_key(int nhits, int nholes, float chi2, int parent, int ran
          ((uint64_t)parent << 10) | ((uint64_t)rank << 5);
 }
 
+// The ranking of a call: the key above, or a score (reading 19: Sec. 3
+// re-tunes the score that decides which candidates are best, for short
+// tracks; no formula is given) s = w_hit n_hits - w_hole n_holes - w_chi2
+// chi2 in FP32, highest first, then parent slot, then rank.
+struct RankW {
+  float w_hit, w_hole, w_chi2;
+  int on;
+};
+
+// Order-preserving integer image of a float (below).
+KFX_HD uint32_t chi2_image(float c);
+
+KFX_HD uint64_t rank_key(const RankW& w, int nhits, int nholes, float chi2, int parent, int rank) {
+  if (!w.on) return child_key(nhits, nholes, chi2, parent, rank);
+  const float sc = w.w_hit * (float)nhits - w.w_hole * (float)nholes - w.w_chi2 * chi2;
+  return ((uint64_t)chi2_image(-sc) << 32) | ((uint64_t)parent << 10) | ((uint64_t)rank << 5);
+}
+
 // Child codes: hit index >= 0, kHole, kStop.
 constexpr int kHole = -1;
 constexpr int kStop = -2;

@@ -55,7 +55,9 @@ class c_build_params(ctypes.Structure):
                 ("prior", c_prior), ("mode", ctypes.c_int32), ("block_threads", ctypes.c_int32),
                 ("blocks", ctypes.c_int32), ("lanes_per_seed", ctypes.c_int32), ("scan_tile", ctypes.c_int32),
                 ("waves_per_simd", ctypes.c_int32), ("seeds_per_wave", ctypes.c_int32),
-                ("window_inflate", ctypes.c_float), ("overlap", ctypes.c_int32)]
+                ("window_inflate", ctypes.c_float), ("overlap", ctypes.c_int32),
+                ("score", ctypes.c_int32), ("score_hit", ctypes.c_float), ("score_hole", ctypes.c_float),
+                ("score_chi2", ctypes.c_float)]
 
 
 class c_tracks(ctypes.Structure):
@@ -363,7 +365,7 @@ class Context:
     def _build_args(self, seeds, seed_event, chi2_cut=30.0, max_cands=6, max_holes=3, max_steps=32,
                     prior=(0.1, 0.5, 0.05, 0.05), mode=MODE_FUSED, block_threads=0, blocks=0, lanes_per_seed=0,
                     scan_tile=0, waves_per_simd=0, seeds_per_wave=0, max_hits=48, out=None, window_inflate=0.0,
-                    overlap=False):
+                    overlap=False, score=None):
         import torch
         d = self.device
         if not isinstance(seeds, torch.Tensor):
@@ -376,14 +378,16 @@ class Context:
             out = self.alloc_tracks(S, K, max_hits)
         p = c_build_params(float(chi2_cut), K, int(max_holes), int(max_steps), prior_struct(prior), int(mode),
                            int(block_threads), int(blocks), int(lanes_per_seed), int(scan_tile),
-                           int(waves_per_simd), int(seeds_per_wave), float(window_inflate), int(bool(overlap)))
+                           int(waves_per_simd), int(seeds_per_wave), float(window_inflate), int(bool(overlap)),
+                           0 if score is None else 1, *(float(v) for v in (score or (0.0, 0.0, 0.0))))
         return seeds, seed_event, S, p, out
 
     def build_tracks(self, hits: DeviceHits, seeds, seed_event, **kw):
         """Returns a dict of device tensors (see kfx_tracks in kfx.h).
         Keywords: chi2_cut, max_cands, max_holes, max_steps, prior, mode,
         block_threads, blocks, lanes_per_seed, scan_tile, waves_per_simd, seeds_per_wave, max_hits,
-        out, window_inflate, overlap (overlap recovery)."""
+        out, window_inflate, overlap (overlap recovery), score (None, or the weights (w_hit, w_hole,
+        w_chi2) of the score ranking)."""
         seeds, seed_event, S, p, out = self._build_args(seeds, seed_event, **kw)
         self._check(self.lib.kfx_build_tracks(self.h, ctypes.byref(hits.struct), _ptr(seeds), _ptr(seed_event), S,
                                               ctypes.byref(p), ctypes.byref(out["_struct"]), self._stream()))

@@ -605,7 +605,7 @@ def _python_recover(ev, layer, p, C, h1, cut):
     return best
 
 
-def _python_beam(ev, seed, K, max_holes, cut, prior, overlap=False):
+def _python_beam(ev, seed, K, max_holes, cut, prior, overlap=False, score=None):
     """Reading 11 written out in Python over the oracle's per-step
     primitives (step_compat: navigation, prediction and the compatible hits;
     update: the Kalman update): every child of every candidate is listed,
@@ -640,7 +640,12 @@ def _python_beam(ev, seed, K, max_holes, cut, prior, overlap=False):
                 kids.append((slot, -1, c["nh"], c["nho"] + 1, c["chi2"]))
             if len(kids) == n0:
                 kids.append(stop)
-        best = heapq.nsmallest(K, kids, key=lambda k: (-k[2], k[3], k[4], k[0], k[1] % (1 << 32)))
+        if score is None:
+            best = heapq.nsmallest(K, kids, key=lambda k: (-k[2], k[3], k[4], k[0], k[1] % (1 << 32)))
+        else:
+            wh, wm, wc = score
+            best = heapq.nsmallest(K, kids, key=lambda k: (-(wh * k[2] - wm * k[3] - wc * k[4]), k[0],
+                                                           k[1] % (1 << 32)))
         nb = []
         for parent, hit, nh, nho, x2 in best:
             c = dict(beam[parent])
@@ -768,3 +773,74 @@ def test_overlap_recovery_finds_the_second_hits():
         assert len(set(ev.layer[one].tolist())) == len(one)  # one hit per layer
     assert full >= 0.9 * n, full
     assert on["nhits"][:, 0].sum() > 1.8 * off["nhits"][:, 0].sum()
+
+
+@pytest.mark.parametrize("score", [(10.0, 10.0, 1.0), (10.0, 2.0, 0.5)])
+def test_score_ranking_matches_python_beam(score):
+    """Reading 19 (score ranking) in the oracle against the Python beam whose
+    heap selection ranks by the score written out: same candidates, order,
+    lists, counts, chi2 and states."""
+    w = kfsynth.workload("build5k", tracks_per_event=60, noise_per_event=6000, ineff=0.1)
+    ev = kfsynth.generate(w)
+    prior = oracle.DEFAULT_PRIOR
+    seeds = ev.seeds[:12]
+    o = oracle.build_tracks(ev, seeds=seeds, seed_event=np.zeros(len(seeds), np.int32), max_hits=64, prior=prior,
+                            score=score)
+    for i, s in enumerate(seeds):
+        ref = _python_beam(ev, s, w.max_cands, w.max_holes, w.chi2_cut, prior, score=score)
+        assert o["n"][i] == len(ref)
+        for j, c in enumerate(ref):
+            row = o["hits"][i, j]
+            assert row[:len(c["hits"])].tolist() == c["hits"] and (row[len(c["hits"]):] == -3).all()
+            assert o["nhits"][i, j] == c["nh"] and o["nholes"][i, j] == c["nho"]
+            np.testing.assert_allclose(o["p"][i, j], c["p"], rtol=1e-12, atol=1e-12)
+
+
+def _truncated_noisy_event(noise):
+    """A build5k-like event with `noise` noise hits in which 80 particles
+    lose every hit after their sixth (their layers set to -1)."""
+    import dataclasses
+    w = kfsynth.workload("build5k", tracks_per_event=600, noise_per_event=noise)
+    ev = kfsynth.generate(w)
+    nrec = np.diff(ev.trk_offsets)
+    cut = np.nonzero(nrec >= 12)[0][::4][:80]
+    lay = ev.layer.copy()
+    for t in cut:
+        lay[ev.trk_hits[ev.trk_offsets[t] + 6: ev.trk_offsets[t + 1]]] = -1
+    return ev, dataclasses.replace(ev, layer=lay), cut
+
+
+def short_track_scores(ev, o, cut):
+    """Fraction of the cut particles whose best candidate is exactly their
+    six hits (then holes), and the matched fraction (> 75 % of the hits
+    from the particle) of the other particles."""
+    exact = 0
+    for t in cut:
+        truth = ev.trk_hits[ev.trk_offsets[t]: ev.trk_offsets[t] + 6]
+        row = o["hits"][t, 0]
+        exact += bool(np.array_equal(row[:6], truth) and (row[6:] < 0).all() and o["nhits"][t, 0] == 6)
+    others = np.setdiff1d(np.arange(ev.n_tracks), cut)
+    matched = 0
+    for t in others:
+        b = o["hits"][t, 0]
+        f = b[b >= 0]
+        matched += bool(f.size and np.mean(ev.sim[f] == t) > 0.75)
+    return exact / len(cut), matched / len(others)
+
+
+def test_score_ranking_keeps_short_tracks_in_dense_events():
+    """Sec. 3: re-tuning the score recovered short tracks.  In an event with
+    300k noise hits, particles cut after six hits come out exactly as their
+    six hits far more often under the score ranking (10 per hit, 10 per
+    hole, 1 per chi2 unit: a noise hit of chi2 above 10 lowers a
+    candidate's score, so a finished short track beats its fake
+    continuations) than under the key ranking (hits first), and the other
+    particles are found no less often."""
+    ev, ev2, cut = _truncated_noisy_event(300000)
+    o_key = oracle.build_tracks(ev2, max_hits=48)
+    o_sc = oracle.build_tracks(ev2, max_hits=48, score=(10.0, 10.0, 1.0))
+    ek, mk = short_track_scores(ev, o_key, cut)
+    es, ms = short_track_scores(ev, o_sc, cut)
+    print(f"short exact: key {ek:.3f}, score {es:.3f}; others matched: key {mk:.4f}, score {ms:.4f}")
+    assert es >= ek + 0.08
+    assert ms >= mk
