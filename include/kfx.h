@@ -136,6 +136,12 @@ typedef struct {
                             3 of the paper re-tunes the score for short
                             tracks without a formula.                        */
   float score_hit, score_hole, score_chi2;
+  int32_t binning;       /* hit index of the build: 0 automatic (2 from 64
+                            events on, else 1), 1 counting sort over the
+                            whole batch with global atomics, 2 one workgroup
+                            per event counting in LDS (falls back to 1 when
+                            an event's bins do not fit LDS).  Same tracks
+                            either way (the order within a bin differs).     */
 } kfx_build_params;
 
 /* Output of building, per seed s and slot j < K, best first (device). */
@@ -372,6 +378,14 @@ int kfx_fit_tracks_backward_noalloc(kfx_ctx* ctx, const kfx_hits* hits, const in
                                     const int32_t* status, const float* dchi2, int32_t dchi2_per_track,
                                     double* dalign, double* dfield, void* stream);
 
+/* Keys per event of the hit index that the last kfx_bin_hits or
+ * kfx_build_tracks call on this context built (host int64): n_layers *
+ * n_eta * n_phi for the counting sort over the batch, one more for the
+ * index made one workgroup per event (kfx_build_params.binning).
+ * KFX_ESTATE when the context holds no index (none built yet, or the last
+ * build was captured into a graph, which owns its index). */
+int kfx_index_keys_per_event(kfx_ctx* ctx, int64_t* keys);
+
 /* Timing of kfx_build_tracks with HIP events recorded on the caller's
  * stream, kept for the last n_calls calls (0 turns timing off; at most
  * 4096).  Off by default. */
@@ -404,18 +418,22 @@ void kfx_graph_destroy(kfx_graph* graph);
  * tasks at the level of events, regions and seed bunches; how many seeds a
  * block holds and how windows are shared is a property of the workload).
  * Times kfx_build_tracks with HIP events on `stream` (one warm-up and `reps`
- * timed calls per shape, the minimum kept) while moving one parameter at a
- * time: scan_tile in {16, 32, 64, 128, 256}, block_threads in {64, 128,
- * 256}, blocks in {1, 2, 4, 8} per compute unit, lanes_per_seed from the
- * smallest power of two >= K up to 16, waves_per_simd in {1, 2},
- * seeds_per_wave from 2 up to 64 / lanes_per_seed.  Writes the fastest shape into
+ * timed calls per shape, the minimum kept): first one and two wavefronts
+ * per SIMD at the default shape (when waves_per_simd is 0), then from the
+ * faster one parameter at a time: scan_tile in {16, 32, 64, 128, 256},
+ * block_threads in {64, 128, 256}, blocks in {1, 2, 4, 8} per compute
+ * unit, lanes_per_seed from the smallest power of two >= K up to 16,
+ * waves_per_simd in {1, 2}, seeds_per_wave from 2 up to 64 /
+ * lanes_per_seed, then scan_tile, block_threads and waves_per_simd once
+ * more.  Writes the fastest shape into
  * params (mode becomes KFX_MODE_FUSED) and its time into *best_ms
  * (nullable).  Every shape gives identical results; out holds the last
  * call's, out->stats is restored.  Synchronises the stream.
  *
  * Results are cached per device (its architecture name and compute-unit
  * count) and workload signature (seed, hit and event counts, K, holes,
- * steps, chi2 cut, window inflation, overlap recovery): a call with a
+ * steps, chi2 cut, window inflation, overlap recovery, score ranking,
+ * binning): a call with a
  * cached key returns the cached shape and time without building (out is
  * then untouched).  When the environment variable KFX_AUTOTUNE_CACHE names
  * a file, the cache is read from it on first use and every new entry is

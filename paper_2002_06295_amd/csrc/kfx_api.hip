@@ -35,6 +35,7 @@ struct kfx_ctx {
   const void* index_hits_key[3] = {nullptr, nullptr, nullptr};
   int index_n_hits = -1, index_n_events = -1;
   BinWork bw{};
+  bool bin_event_ok = false;  // one-workgroup-per-event binning available
   // optional timing of build calls: per call, events before binning, after
   // binning, after the seed start, after the search and after the output,
   // recorded on the caller's stream into a ring of `ring_n` calls
@@ -188,11 +189,22 @@ int check_prior(kfx_ctx* c, const kfx_prior* p) {
   return KFX_OK;
 }
 
-// Build the hit index into the context workspace.
-int build_index(kfx_ctx* c, const kfx_hits* h, int32_t* bin_out, bool stable, hipStream_t st) {
+// Events from which the automatic choice bins one event per workgroup (a
+// quarter of the CUs busy at least; below, the counting sort over the whole
+// batch spreads the hits over the machine).
+constexpr int kBinEventMin = 64;
+
+// Build the hit index into the context workspace.  binning: 0 automatic,
+// 1 counting sort over the batch, 2 one workgroup per event (where the
+// event's bins fit LDS); the stable order (bin_out, kfx_bin_hits) always
+// takes the counting sort.
+int build_index(kfx_ctx* c, const kfx_hits* h, int32_t* bin_out, bool stable, hipStream_t st, int binning = 1) {
   const Geometry& G = c->host_geo;
   const long nb = (long)G.n_eta * G.n_phi;
-  const long n_keys = (long)h->n_events * G.n_layers * nb;
+  const bool per_event = !stable && !bin_out && c->bin_event_ok && h->n_events > 0 &&
+                         (binning == 2 || (binning == 0 && h->n_events >= kBinEventMin)) &&
+                         bin_event_lds_bytes(G.n_layers * nb) <= c->max_lds;
+  const long n_keys = (long)h->n_events * (G.n_layers * nb + (per_event ? 1 : 0));
   if (n_keys >= (1L << 31) - 2) return fail(c, KFX_EINVAL, "events x layers x bins exceeds 2^31");
   int rc;
   BinWork& w = c->bw;
@@ -204,7 +216,10 @@ int build_index(kfx_ctx* c, const kfx_hits* h, int32_t* bin_out, bool stable, hi
   w.perm = (int*)ws(c, "bin.perm", nh * 4, st, rc); if (rc) return rc;
   w.sorted = (float4*)ws(c, "bin.sorted", nh * 16, st, rc); if (rc) return rc;
   w.scan_scratch = (int*)ws(c, "bin.scan", ((n_keys + 1) / 4096 + 4) * 4, st, rc); if (rc) return rc;
-  launch_bin(c->dev_geo, view(h), G.n_layers, (int)nb, w, bin_out, stable, st);
+  if (per_event)
+    launch_bin_events(c->dev_geo, view(h), G.n_layers, (int)nb, w, st);
+  else
+    launch_bin(c->dev_geo, view(h), G.n_layers, (int)nb, w, bin_out, stable, st);
   if ((rc = hip_check(c, hipGetLastError(), "binning kernels"))) return rc;
   c->have_index = true;
   c->index_hits_key[0] = h->x;
@@ -221,6 +236,7 @@ BinIndex index_view(const kfx_ctx* c) {
   B.sorted = c->bw.sorted;
   B.n_layers = c->host_geo.n_layers;
   B.n_bins = c->host_geo.n_eta * c->host_geo.n_phi;
+  B.ev_stride = c->bw.ev_stride;
   return B;
 }
 
@@ -244,6 +260,10 @@ int kfx_create(int device, kfx_ctx** out) {
     c->max_lds = (size_t)lds;
   {
     DeviceGuard dg(device);
+    // the per-event binning's LDS above the default limit of a launch (if
+    // the runtime refuses, the counting sort over the batch is used)
+    c->bin_event_ok = bin_event_init(c->max_lds) == hipSuccess;
+    (void)hipGetLastError();
     if (resolve_scratch(device) != hipSuccess) {
       delete c;
       return KFX_EHIP;
@@ -374,6 +394,15 @@ int kfx_bin_hits(kfx_ctx* c, const kfx_hits* hits, int32_t* bin_out, int32_t* of
   return KFX_OK;
 }
 
+int kfx_index_keys_per_event(kfx_ctx* c, int64_t* keys) {
+  if (!c) return KFX_EINVAL;
+  c->err.clear();
+  if (!keys) return fail(c, KFX_EINVAL, "keys is NULL");
+  if (!c->have_index) return fail(c, KFX_ESTATE, "no hit index on this context");
+  *keys = c->bw.ev_stride;
+  return KFX_OK;
+}
+
 int kfx_seed_states(kfx_ctx* c, const kfx_hits* hits, const int32_t* seeds, int32_t n, const kfx_prior* prior,
                     kfx_states* out, float* chi2, int32_t* status, void* stream) {
   if (!c) return KFX_EINVAL;
@@ -444,6 +473,7 @@ int build_impl(kfx_ctx* c, const kfx_hits* hits, const int32_t* seeds, const int
     return fail(c, KFX_EINVAL, "window_inflate must be 0 or in [1, 1e4]");
   if (p->score && !(std::isfinite(p->score_hit) && std::isfinite(p->score_hole) && std::isfinite(p->score_chi2)))
     return fail(c, KFX_EINVAL, "score weights must be finite");
+  if (p->binning < 0 || p->binning > 2) return fail(c, KFX_EINVAL, "binning must be 0, 1 or 2");
   if (p->block_threads != 0 && (p->block_threads < 64 || p->block_threads > 256 || p->block_threads % 64))
     return fail(c, KFX_EINVAL, "block_threads must be 0 or a multiple of 64 in [64, 256]");
   if (p->blocks < 0) return fail(c, KFX_EINVAL, "blocks < 0");
@@ -487,7 +517,7 @@ int build_impl(kfx_ctx* c, const kfx_hits* hits, const int32_t* seeds, const int
   };
   auto bin = [&]() -> int {
     // the building does not depend on the order within a bin: no sort
-    int r = build_index(c, hits, nullptr, false, st);
+    int r = build_index(c, hits, nullptr, false, st, p->binning);
     if (!r && tev) r = hip_check(c, hipEventRecord(tev[1], st), "timing event");
     return r;
   };
@@ -747,11 +777,12 @@ std::string tune_key(const kfx_ctx* c, const kfx_hits* h, int n_seeds, const kfx
   hipDeviceProp_t prop{};
   (void)hipGetDeviceProperties(&prop, c->device);
   char buf[512];
-  snprintf(buf, sizeof(buf), "%s/%d|S%d|H%d|E%d|K%d|holes%d|steps%d|cut%.9g|infl%.9g|ov%d|score%d:%.9g:%.9g:%.9g",
+  snprintf(buf, sizeof(buf),
+           "%s/%d|S%d|H%d|E%d|K%d|holes%d|steps%d|cut%.9g|infl%.9g|ov%d|score%d:%.9g:%.9g:%.9g|bin%d",
            prop.gcnArchName, prop.multiProcessorCount, n_seeds, h ? h->n_hits : -1, h ? h->n_events : -1,
            p->max_cands, p->max_holes, p->max_steps, (double)p->chi2_cut, (double)p->window_inflate,
            p->overlap ? 1 : 0, p->score ? 1 : 0, (double)p->score_hit, (double)p->score_hole,
-           (double)p->score_chi2);
+           (double)p->score_chi2, p->binning);
   return buf;
 }
 
@@ -854,8 +885,23 @@ int kfx_autotune_build(kfx_ctx* c, const kfx_hits* hits, const int32_t* seeds, c
   };
   float best = 3.0e38f;
   if (!rc) rc = timeit(cur, best);
-  // coordinate descent: one parameter at a time, the others held
-  for (int dim = 0; dim < 6 && !rc; ++dim) {
+  if (!rc && p->waves_per_simd == 0) {
+    // start from the better of one and two wavefronts per SIMD: the other
+    // parameters' best values depend on it, and a descent that starts on
+    // the wrong side can settle there
+    kfx_build_params q = cur;
+    q.waves_per_simd = 3 - cur.waves_per_simd;
+    float t = 0.0f;
+    if (fused_shape_fits(c, &q) && !(rc = timeit(q, t)) && t < best) {
+      best = t;
+      cur = q;
+    }
+  }
+  // coordinate descent: one parameter at a time, the others held; a second
+  // sweep over the scan tile, the block size and the occupancy
+  constexpr int kDims[] = {0, 1, 2, 3, 4, 5, 0, 1, 4};
+  for (int dim : kDims) {
+    if (rc) break;
     std::vector<kfx_build_params> cand;
     kfx_build_params q = cur;
     if (dim == 0) {

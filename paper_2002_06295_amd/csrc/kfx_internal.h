@@ -19,6 +19,7 @@ struct BinWork {
   int* perm;      // [n_hits]
   float4* sorted; // [n_hits]
   int* scan_scratch;  // [n_keys / tile + 2]
+  long ev_stride;     // keys per event of the index last built
 };
 
 // Duplicate removal over the best candidate (slot 0) of every seed.
@@ -99,6 +100,12 @@ void launch_fill(int* p, long n, int v, hipStream_t st);
 void exclusive_scan(const int* in, long n, int* out, int* scratch, hipStream_t st);
 void launch_bin(const Geometry* G, const HitsView& H, int n_layers, int n_bins, BinWork& w, int* bin_out,
                 bool stable, hipStream_t st);
+// One workgroup per event (sets w.ev_stride = n_layers * n_bins + 1):
+// usable when bin_event_lds_bytes(n_layers * n_bins) fits a workgroup's LDS
+// and bin_event_init has raised the kernel's dynamic LDS limit to it.
+size_t bin_event_lds_bytes(long keys_per_event);
+hipError_t bin_event_init(size_t max_lds);
+void launch_bin_events(const Geometry* G, const HitsView& H, int n_layers, int n_bins, BinWork& w, hipStream_t st);
 void launch_fit(const Geometry* G, const HitsView& H, const int* trk_off, const int* trk_hits, int n,
                 const Prior& pr, const float* align, float fscale, const FitOut& o, hipStream_t st);
 int fit_backward_blocks(int n);

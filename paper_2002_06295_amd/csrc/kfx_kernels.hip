@@ -17,6 +17,14 @@
 namespace kfx {
 
 // ---------------------------------------------------------------- utility
+// logical block of this workgroup when workgroups are dealt to the 8 XCDs
+// in turn: XCD x takes logical blocks [x * per, (x + 1) * per); -1 = idle
+__device__ inline int xcd_block(int nblk) {
+  const int per = (nblk + 7) >> 3;
+  const int lb = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+  return lb < nblk ? lb : -1;
+}
+
 __global__ void __launch_bounds__(256) k_fill_i32(int* p, long n, int v) {
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) p[i] = v;
 }
@@ -38,8 +46,9 @@ constexpr int kScanThreads = 256;
 constexpr int kScanItems = 16;
 constexpr int kScanTile = kScanThreads * kScanItems;
 
+template <int NT = kScanThreads>
 __device__ inline int block_exclusive_scan(int v, int* lds, int& total) {
-  // wave-level inclusive scan (64 lanes), then across the 4 waves
+  // wave-level inclusive scan (64 lanes), then across the NT / 64 waves
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   int x = v;
 #pragma unroll
@@ -50,7 +59,7 @@ __device__ inline int block_exclusive_scan(int v, int* lds, int& total) {
   if (lane == 63) lds[wid] = x;
   __syncthreads();
   int base = 0, tot = 0;
-  for (int w = 0; w < kScanThreads / 64; ++w) {
+  for (int w = 0; w < NT / 64; ++w) {
     if (w < wid) base += lds[w];
     tot += lds[w];
   }
@@ -162,8 +171,8 @@ __device__ inline int event_of(const int* ev_off, int n_events, int hit) {
   return lo;
 }
 
-__global__ void __launch_bounds__(256) k_bin_keys(const Geometry* __restrict__ G, HitsView H, int* key_out, int* bin_out,
-                           int* counts, int* rank) {
+__global__ void __launch_bounds__(256) k_bin_keys(const Geometry* __restrict__ G, HitsView H, long ev_stride,
+                                                  int* key_out, int* bin_out, int* counts, int* rank) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= H.n_hits) return;
   const int l = H.layer[i];
@@ -173,7 +182,7 @@ __global__ void __launch_bounds__(256) k_bin_keys(const Geometry* __restrict__ G
   if (l >= 0 && l < G->n_layers) bin = hit_bin_fast(*G, l, H.x[i], H.y[i], H.z[i]);
   if (bin >= 0) {
     const int e = event_of(H.ev_off, H.n_events, i);
-    key = ((long)e * G->n_layers + l) * nb + bin;
+    key = (long)e * ev_stride + (long)l * nb + bin;
     // the hit's place among its bin's hits (arrival order; the per-bin sort
     // restores ascending hit index)
     rank[i] = atomicAdd(counts + key, 1);
@@ -224,6 +233,178 @@ __global__ void __launch_bounds__(256) k_bin_gather(HitsView H, const int* perm,
   float w;
   __builtin_memcpy(&w, &h, 4);
   sorted[p] = make_float4(H.x[h], H.y[h], H.z[h], w);
+}
+
+// ---- binning of a batch of events: one workgroup per event ---------------
+// With many events, each workgroup takes one event: its hits are counted
+// per (layer, bin) in LDS, the counts are scanned there, and every hit gets
+// its place in the event's own part [ev_off[e], ev_off[e+1]) of the sorted
+// array (offsets clamped to the hit count).  No global atomics and no scan
+// over the whole key space are needed.  The index then has n_layers *
+// n_bins + 1 keys per event: the last holds no bin, and its range is the
+// tail of the event's part that its hits without a bin leave unused.  The
+// counters are 8 bits, four to a word; a bin that reaches 255 hits (far
+// more than a bin of these geometries holds) makes the workgroup count the
+// event again with global atomics, which have no such limit.  The scan
+// also keeps the offset of every group of 8 keys in LDS, so that a hit's
+// place is found there (the group's offset plus the counts of the keys
+// before it in the group) rather than by a read of the offsets in HBM.  The
+// hits are then moved by k_bin_place, with the blocks over the hits dealt to the
+// XCDs in contiguous ranges: the 16-byte writes of an XCD then land in the
+// few events it is placing at the time, whose part of the sorted array its
+// L2 holds until the lines are whole (moved by the workgroup of each event,
+// the writes of the 32 events in flight on an XCD outgrew its L2 and left
+// as partial lines: three quarters of the binning time).
+constexpr int kBinEvThreads = 1024;
+constexpr int kBinEvBatch = 4;  // hits per thread in flight in the passes over the hits
+constexpr unsigned int kNoBin = 0xffffffffu;
+
+// packed: on return, the hit's place in the sorted array (-1: none; hits
+// outside every event's range keep what the caller filled in)
+__global__ void __launch_bounds__(kBinEvThreads) k_bin_event(const Geometry* __restrict__ G, HitsView H,
+                                                            long ev_stride, unsigned int* packed, int* rank,
+                                                            int* gcounts, int* off) {
+  extern __shared__ unsigned int bin_cnt[];
+  __shared__ int wsum[kBinEvThreads / 64];
+  __shared__ int ovf;
+  const int e = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int n = H.n_hits;
+  const int lo = min(max(H.ev_off[e], 0), n);
+  const int hi = min(max(H.ev_off[e + 1], lo), n);
+  const int L = G->n_layers, nb = G->n_eta * G->n_phi;
+  const int nk = L * nb;
+  const int ng = (nk + 7) >> 3;  // groups of 8 keys
+  const int nw = 2 * ng;         // counter words (4 keys each)
+  unsigned int* goff = bin_cnt + nw;  // [ng] global offset of each group
+  const long kbase = (long)e * ev_stride;
+  for (int i = tid; i < nw; i += kBinEvThreads) bin_cnt[i] = 0u;
+  if (tid == 0) ovf = 0;
+  __syncthreads();
+  // count: key = layer * n_bins + bin and the hit's place among its bin's
+  // hits, packed as key | place << 24 (kNoBin: no bin)
+  constexpr int kStep = kBinEvThreads * kBinEvBatch;
+  for (int i0 = lo + tid; i0 < hi; i0 += kStep) {
+    int l[kBinEvBatch];
+    float x[kBinEvBatch], y[kBinEvBatch], z[kBinEvBatch];
+#pragma unroll
+    for (int u = 0; u < kBinEvBatch; ++u) {
+      const int i = i0 + u * kBinEvThreads;
+      l[u] = i < hi ? H.layer[i] : -1;
+      x[u] = i < hi ? H.x[i] : 0.0f;
+      y[u] = i < hi ? H.y[i] : 0.0f;
+      z[u] = i < hi ? H.z[i] : 0.0f;
+    }
+#pragma unroll
+    for (int u = 0; u < kBinEvBatch; ++u) {
+      const int i = i0 + u * kBinEvThreads;
+      if (i >= hi) break;
+      unsigned int p = kNoBin;
+      if (l[u] >= 0 && l[u] < L) {
+        const int b = hit_bin_fast(*G, l[u], x[u], y[u], z[u]);
+        if (b >= 0) {
+          const int key = l[u] * nb + b;
+          const int sh = (key & 3) << 3;
+          const unsigned int r = (atomicAdd(&bin_cnt[key >> 2], 1u << sh) >> sh) & 255u;
+          if (r == 255u) ovf = 1;
+          p = (unsigned int)key | (r << 24);
+        }
+      }
+      packed[i] = p;
+    }
+  }
+  __syncthreads();
+  const bool glob = ovf != 0;  // the same for the whole workgroup
+  if (glob) {
+    for (int k = tid; k < nk; k += kBinEvThreads) gcounts[kbase + k] = 0;
+    __syncthreads();
+    for (int i = lo + tid; i < hi; i += kBinEvThreads) {
+      const unsigned int p = packed[i];
+      if (p != kNoBin) rank[i] = atomicAdd(&gcounts[kbase + (p & 0xffffffu)], 1);
+    }
+    __syncthreads();
+  }
+  // exclusive scan of the counts in tiles of 4 keys per thread; the
+  // offsets are global positions (the event's part starts at lo)
+  int running = lo;
+  for (int w0 = 0; w0 < nw; w0 += kBinEvThreads) {
+    const int wi = w0 + tid;
+    int c[4] = {0, 0, 0, 0};
+    if (wi < nw) {
+      if (!glob) {
+        const unsigned int v = bin_cnt[wi];
+        c[0] = (int)(v & 255u);
+        c[1] = (int)((v >> 8) & 255u);
+        c[2] = (int)((v >> 16) & 255u);
+        c[3] = (int)(v >> 24);
+      } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          c[j] = 4 * wi + j < nk ? __hip_atomic_load(&gcounts[kbase + 4 * wi + j], __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT)
+                                 : 0;
+      }
+    }
+    int tot;
+    int pre = running + block_exclusive_scan<kBinEvThreads>(c[0] + c[1] + c[2] + c[3], wsum, tot);
+    if (wi < nw && !(wi & 1)) goff[wi >> 1] = (unsigned int)pre;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (4 * wi + j < nk) off[kbase + 4 * wi + j] = pre;
+      pre += c[j];
+    }
+    running += tot;
+  }
+  if (tid == 0) {
+    off[kbase + nk] = running;                              // the unused tail
+    if (e == (int)gridDim.x - 1) off[kbase + ev_stride] = hi;  // one past the last key
+  }
+  __syncthreads();
+  // places: each thread handles the hits it counted
+  for (int i0 = lo + tid; i0 < hi; i0 += kStep) {
+    unsigned int p[kBinEvBatch];
+    int r[kBinEvBatch];
+#pragma unroll
+    for (int u = 0; u < kBinEvBatch; ++u) {
+      const int i = i0 + u * kBinEvThreads;
+      p[u] = i < hi ? packed[i] : kNoBin;
+      r[u] = (glob && p[u] != kNoBin) ? rank[i] : (int)(p[u] >> 24);
+    }
+#pragma unroll
+    for (int u = 0; u < kBinEvBatch; ++u) {
+      const int i = i0 + u * kBinEvThreads;
+      if (i >= hi) break;
+      unsigned int q = kNoBin;
+      if (p[u] != kNoBin) {
+        const int key = (int)(p[u] & 0xffffffu);
+        if (glob) {
+          q = (unsigned int)(off[kbase + key] + r[u]);
+        } else {
+          // the counts of the keys before this one in its group of 8
+          const int g = key >> 3, j = key & 7;
+          const unsigned int w0 = bin_cnt[2 * g], w1 = bin_cnt[2 * g + 1];
+          const unsigned int m0 = j >= 4 ? 0xffffffffu : (j == 0 ? 0u : 0xffffffffu >> (32 - 8 * j));
+          const unsigned int m1 = j <= 4 ? 0u : 0xffffffffu >> (64 - 8 * j);
+          const unsigned int before = __builtin_amdgcn_sad_u8(w0 & m0, 0u, 0u) + __builtin_amdgcn_sad_u8(w1 & m1, 0u, 0u);
+          q = goff[g] + before + (unsigned int)r[u];
+        }
+      }
+      packed[i] = q;
+    }
+  }
+}
+
+// The hits to their places (pos[i] < 0: none), blocks in XCD order.
+__global__ void __launch_bounds__(256) k_bin_place(HitsView H, const int* pos, int nblk, float4* sorted) {
+  const int lb = xcd_block(nblk);
+  if (lb < 0) return;
+  const int i = lb * 256 + (int)threadIdx.x;
+  if (i >= H.n_hits) return;
+  const int p = pos[i];
+  if (p < 0) return;
+  float w;
+  __builtin_memcpy(&w, &i, 4);
+  sorted[p] = make_float4(H.x[i], H.y[i], H.z[i], w);
 }
 
 // ---------------------------------------------------------------- fit (a10)
@@ -398,7 +579,11 @@ __device__ inline void add_stat(unsigned long long* p, unsigned long long v) {
   if ((threadIdx.x & 63) == 0 && s) atomicAdd(p, s);
 }
 
-__global__ void __launch_bounds__(128) k_build_init(BuildArgs a) {
+// Two wavefronts per SIMD (at most 256 registers; the FP64 seed fit needs
+// a little more, and spills a few): one seed per thread, so a batch's
+// seeds are many rounds of the machine, and two resident wavefronts hide
+// part of each other's latency.
+__global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2, 2))) k_build_init(BuildArgs a) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= a.n_seeds) return;
   init_seed_slots(a, s);
@@ -1076,14 +1261,6 @@ k_build_fused(BuildArgs a, TracksOut o, int* seed_counter) {
 
 constexpr int kDupRows = 4;  // tracks (wavefronts) per block
 
-// logical block of this workgroup when workgroups are dealt to the 8 XCDs
-// in turn: XCD x takes logical blocks [x * per, (x + 1) * per); -1 = idle
-__device__ inline int xcd_block(int nblk) {
-  const int per = (nblk + 7) >> 3;
-  const int lb = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
-  return lb < nblk ? lb : -1;
-}
-
 // ascending sort of one value per lane over the 64 lanes
 __device__ inline int wave_sort_asc(int v, int lane) {
 #pragma unroll
@@ -1290,11 +1467,12 @@ void launch_fill(int* p, long n, int v, hipStream_t st) {
 // sets and counts ignore the scan order, ties go by hit index)
 void launch_bin(const Geometry* G, const HitsView& H, int n_layers, int n_bins, BinWork& w,
                 int* bin_out, bool stable, hipStream_t st) {
-  const long n_keys = (long)H.n_events * n_layers * n_bins;
+  w.ev_stride = (long)n_layers * n_bins;
+  const long n_keys = (long)H.n_events * w.ev_stride;
   launch_fill(w.counts, n_keys + 1, 0, st);
   if (H.n_hits > 0)
-    hipLaunchKernelGGL(k_bin_keys, dim3(nblk(H.n_hits, 256)), dim3(256), 0, st, G, H, w.key, bin_out, w.counts,
-                       w.rank);
+    hipLaunchKernelGGL(k_bin_keys, dim3(nblk(H.n_hits, 256)), dim3(256), 0, st, G, H, w.ev_stride, w.key, bin_out,
+                       w.counts, w.rank);
   exclusive_scan(w.counts, n_keys, w.off, w.scan_scratch, st);
   if (H.n_hits > 0)
     hipLaunchKernelGGL(k_bin_scatter, dim3(nblk(H.n_hits, 256)), dim3(256), 0, st, H, w.key, w.off, w.rank,
@@ -1305,6 +1483,33 @@ void launch_bin(const Geometry* G, const HitsView& H, int n_layers, int n_bins, 
     if (H.n_hits > 0)
       hipLaunchKernelGGL(k_bin_gather, dim3(nblk(H.n_hits, 256)), dim3(256), 0, st, H, w.perm, w.off + n_keys,
                          w.sorted);
+  }
+}
+
+size_t bin_event_dyn_lds(long keys_per_event) {
+  const long ng = (keys_per_event + 7) / 8;
+  return (size_t)ng * 12;  // two counter words and one offset per group of 8 keys
+}
+size_t bin_event_lds_bytes(long keys_per_event) {
+  return bin_event_dyn_lds(keys_per_event) + sizeof(int) * (kBinEvThreads / 64 + 1);
+}
+
+hipError_t bin_event_init(size_t max_lds) {
+  const size_t dyn = max_lds - sizeof(int) * (kBinEvThreads / 64 + 1);
+  return hipFuncSetAttribute((const void*)k_bin_event, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
+}
+
+void launch_bin_events(const Geometry* G, const HitsView& H, int n_layers, int n_bins, BinWork& w, hipStream_t st) {
+  const long nk = (long)n_layers * n_bins;
+  w.ev_stride = nk + 1;
+  if (H.n_events <= 0) return;
+  // a hit outside every event's range has no place
+  if (H.n_hits > 0) launch_fill(w.key, H.n_hits, -1, st);
+  hipLaunchKernelGGL(k_bin_event, dim3(H.n_events), dim3(kBinEvThreads), bin_event_dyn_lds(nk), st, G, H,
+                     w.ev_stride, reinterpret_cast<unsigned int*>(w.key), w.rank, w.counts, w.off);
+  if (H.n_hits > 0) {
+    const int nb = (int)nblk(H.n_hits, 256);
+    hipLaunchKernelGGL(k_bin_place, dim3((nb + 7) / 8 * 8), dim3(256), 0, st, H, w.key, nb, w.sorted);
   }
 }
 

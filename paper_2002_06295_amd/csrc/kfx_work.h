@@ -342,15 +342,18 @@ struct HitsView {
 };
 
 // Binned index: for event e, layer l, bin b the sorted hits (x, y, z, index
-// as bits) occupy [off[key], off[key+1]), key = (e L + l) nb + b.
+// as bits) occupy [off[key], off[key+1]), key = e ev_stride + l nb + b, with
+// ev_stride = L nb (one counting sort over the batch) or L nb + 1 (one
+// workgroup per event: the extra key of an event holds no bin).
 struct BinIndex {
   const int* off;
   const float4* sorted;
   int n_layers, n_bins;
+  long ev_stride;
 };
 
 KFX_HD long bin_key(const BinIndex& B, int ev, int layer, int bin) {
-  return ((long)ev * B.n_layers + layer) * B.n_bins + bin;
+  return (long)ev * B.ev_stride + (long)layer * B.n_bins + bin;
 }
 
 // ---- window scan ---------------------------------------------------------

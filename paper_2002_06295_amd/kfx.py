@@ -31,7 +31,7 @@ EXPORTED = ["kfx_create", "kfx_destroy", "kfx_last_error", "kfx_load_layers", "k
             "kfx_seed_states", "kfx_step_compat", "kfx_build_tracks", "kfx_fit_tracks",
             "kfx_fit_tracks_backward", "kfx_fit_tracks_backward_noalloc", "kfx_enable_timing", "kfx_build_times", "kfx_build_graph",
             "kfx_graph_launch", "kfx_graph_destroy", "kfx_autotune_build", "kfx_autotune_cache_clear", "kfx_find_duplicates", "kfx_mask_hits",
-            "kfx_cluster_strips"]
+            "kfx_cluster_strips", "kfx_index_keys_per_event"]
 
 
 class c_states(ctypes.Structure):
@@ -57,7 +57,7 @@ class c_build_params(ctypes.Structure):
                 ("waves_per_simd", ctypes.c_int32), ("seeds_per_wave", ctypes.c_int32),
                 ("window_inflate", ctypes.c_float), ("overlap", ctypes.c_int32),
                 ("score", ctypes.c_int32), ("score_hit", ctypes.c_float), ("score_hole", ctypes.c_float),
-                ("score_chi2", ctypes.c_float)]
+                ("score_chi2", ctypes.c_float), ("binning", ctypes.c_int32)]
 
 
 class c_tracks(ctypes.Structure):
@@ -365,7 +365,7 @@ class Context:
     def _build_args(self, seeds, seed_event, chi2_cut=30.0, max_cands=6, max_holes=3, max_steps=32,
                     prior=(0.1, 0.5, 0.05, 0.05), mode=MODE_FUSED, block_threads=0, blocks=0, lanes_per_seed=0,
                     scan_tile=0, waves_per_simd=0, seeds_per_wave=0, max_hits=48, out=None, window_inflate=0.0,
-                    overlap=False, score=None):
+                    overlap=False, score=None, binning=0):
         import torch
         d = self.device
         if not isinstance(seeds, torch.Tensor):
@@ -379,7 +379,8 @@ class Context:
         p = c_build_params(float(chi2_cut), K, int(max_holes), int(max_steps), prior_struct(prior), int(mode),
                            int(block_threads), int(blocks), int(lanes_per_seed), int(scan_tile),
                            int(waves_per_simd), int(seeds_per_wave), float(window_inflate), int(bool(overlap)),
-                           0 if score is None else 1, *(float(v) for v in (score or (0.0, 0.0, 0.0))))
+                           0 if score is None else 1, *(float(v) for v in (score or (0.0, 0.0, 0.0))),
+                           int(binning))
         return seeds, seed_event, S, p, out
 
     def build_tracks(self, hits: DeviceHits, seeds, seed_event, **kw):
@@ -387,7 +388,8 @@ class Context:
         Keywords: chi2_cut, max_cands, max_holes, max_steps, prior, mode,
         block_threads, blocks, lanes_per_seed, scan_tile, waves_per_simd, seeds_per_wave, max_hits,
         out, window_inflate, overlap (overlap recovery), score (None, or the weights (w_hit, w_hole,
-        w_chi2) of the score ranking)."""
+        w_chi2) of the score ranking), binning (0 automatic, 1 global counting sort, 2 one workgroup
+        per event)."""
         seeds, seed_event, S, p, out = self._build_args(seeds, seed_event, **kw)
         self._check(self.lib.kfx_build_tracks(self.h, ctypes.byref(hits.struct), _ptr(seeds), _ptr(seed_event), S,
                                               ctypes.byref(p), ctypes.byref(out["_struct"]), self._stream()))
@@ -421,6 +423,14 @@ class Context:
 
     def autotune_cache_clear(self):
         self.lib.kfx_autotune_cache_clear()
+
+    def index_keys_per_event(self):
+        """Keys per event of the hit index the last bin/build call made:
+        n_layers * n_bins (counting sort over the batch) or one more (one
+        workgroup per event)."""
+        k = ctypes.c_int64()
+        self._check(self.lib.kfx_index_keys_per_event(self.h, ctypes.byref(k)))
+        return int(k.value)
 
     def enable_timing(self, n_calls=64):
         self._check(self.lib.kfx_enable_timing(self.h, int(n_calls)))
