@@ -19,6 +19,10 @@ FLAGS = [
     # contract a*b+c into FMA only within one expression, so that a device
     # function inlined into different kernels rounds identically everywhere
     "-ffp-contract=on",
+    # FP32 division and square root by the hardware's reciprocal and square
+    # root (within 2.5 ulp) rather than correctly rounded sequences; the FP64
+    # parts of the kernels keep correctly rounded division and square root
+    "-fno-hip-fp32-correctly-rounded-divide-sqrt",
     "-Wall", "-Wno-unused-function", "-Wno-unused-result",
 ]
 

@@ -629,16 +629,19 @@ __global__ void __launch_bounds__(128) k_build_finalize(BuildArgs a, int fin, Tr
 }
 
 // Hit lists of the fused build (the fused kernel wrote the counts, chi2
-// sums and states itself).  A block takes `rs` consecutive seeds (256 / the
-// power of two >= K, so that the walks fill the block): it first copies
-// their histories (n_steps x K words each, contiguous in HBM) into LDS with
-// coalesced loads, then one thread per (seed, slot) walks its slot's parent
-// pointers in LDS.  A walk is a chain of dependent reads; in LDS each costs
-// tens of cycles instead of an HBM round trip.  When the block's rows fit
-// in LDS too (stage_rows), they are built there and then written to HBM as
-// one contiguous range (the rows of consecutive seeds are adjacent), in
-// 16-byte stores across the block; otherwise each thread writes its row.
-constexpr int kRowThreads = 256;
+// sums and states itself).  A block takes `rs` consecutive seeds (128 / the
+// power of two >= K, so that the walks fill the block): it first copies the
+// steps each seed took of its history (n_steps x K words, contiguous in
+// HBM) into LDS with coalesced 16-byte loads, then one thread per (seed,
+// slot) walks its slot's parent pointers in LDS.  A walk is a chain of
+// dependent reads; in LDS each costs tens of cycles instead of an HBM round
+// trip.  A thread fetches its row's counts before the copy, so that their
+// latency overlaps it.  When the block's rows fit in LDS too (stage_rows),
+// they are built there and then written to HBM as one contiguous range (the
+// rows of consecutive seeds are adjacent), in 16-byte stores across the
+// block; otherwise each thread writes its row.  Small blocks (about 30 KB
+// of LDS for K = 6) let five share a CU, each in its own phase.
+constexpr int kRowThreads = 128;
 constexpr size_t kRowLds = 65536;
 
 struct LdsWordHist {
@@ -653,16 +656,15 @@ struct LdsWordHist {
   }
 };
 
-// n words from HBM to LDS by the block, 16 bytes at a time where both ends
-// allow it
-__device__ inline void copy_words(unsigned int* dst, const unsigned int* src, long n) {
-  if (((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) & 15) == 0) {
-    const long n4 = n >> 2;
-    for (long i = threadIdx.x; i < n4; i += blockDim.x)
-      reinterpret_cast<uint4*>(dst)[i] = reinterpret_cast<const uint4*>(src)[i];
-    for (long i = (n4 << 2) + threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
+// the first n words of src to dst by `tps` threads (sub = 0 .. tps - 1), 16
+// bytes at a time where both are aligned; rounding n up to whole 16-byte
+// chunks stays within `cap` words
+__device__ inline void copy_prefix(unsigned int* dst, const unsigned int* src, int n, int cap, int sub, int tps) {
+  if (((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) & 15) == 0 && (cap & 3) == 0) {
+    const int n4 = (n + 3) >> 2;
+    for (int i = sub; i < n4; i += tps) reinterpret_cast<uint4*>(dst)[i] = reinterpret_cast<const uint4*>(src)[i];
   } else {
-    for (long i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
+    for (int i = sub; i < n; i += tps) dst[i] = src[i];
   }
 }
 
@@ -670,30 +672,44 @@ __global__ void __launch_bounds__(kRowThreads) k_build_fused_rows(BuildArgs a, T
   // [rs][max_steps][K] history words, with recovery as many recovered hits,
   // then (stage_rows) the [rs K][max_hits] rows
   extern __shared__ __align__(16) unsigned int hist_lds[];
-  __shared__ int nst[kRowThreads / 4];
   const int K = a.K;
   const long s0 = (long)blockIdx.x * rs;
   const int ns = (int)min((long)rs, (long)a.n_seeds - s0);
-  if (threadIdx.x < ns) nst[threadIdx.x] = min(a.n_steps[s0 + threadIdx.x], a.max_steps);
-  __syncthreads();
   const int per = a.max_steps * K;  // words per seed
   int* ov_lds = a.overlap ? reinterpret_cast<int*>(hist_lds + (size_t)rs * per) : nullptr;
-  // the block's whole history range, steps past a seed's end included (they
-  // are never read): a straight copy, no index arithmetic per word
-  copy_words(hist_lds, a.hist_word + s0 * per, (long)ns * per);
-  if (ov_lds) copy_words(reinterpret_cast<unsigned int*>(ov_lds),
-                         reinterpret_cast<const unsigned int*>(a.hist_ov) + s0 * per, (long)ns * per);
+  // this thread's row: seed q / K, slot q % K (rs K <= the block's threads)
+  const int q = threadIdx.x;
+  const bool has_row = q < ns * K;
+  int T = 0, total = 0;
+  bool live = false;
+  if (has_row) {
+    const long s = s0 + q / K, slot = s * K + q % K;
+    T = min(a.n_steps[s], a.max_steps);
+    const int nc = o.n_cands[s], nh = o.n_hits[slot], nho = o.n_holes[slot];
+    live = q % K < nc;
+    total = live ? nh + nho : 0;
+  }
+  {
+    // the steps each seed took: kRowThreads / rs threads per seed
+    const int tps = kRowThreads / rs, sl = threadIdx.x / tps, sub = threadIdx.x % tps;
+    if (sl < ns) {
+      const int used = min(a.n_steps[s0 + sl], a.max_steps) * K;
+      copy_prefix(hist_lds + sl * per, a.hist_word + (s0 + sl) * per, used, per, sub, tps);
+      if (ov_lds)
+        copy_prefix(reinterpret_cast<unsigned int*>(ov_lds) + sl * per,
+                    reinterpret_cast<const unsigned int*>(a.hist_ov) + (s0 + sl) * per, used, per, sub, tps);
+    }
+  }
   __syncthreads();
   const int H = o.max_hits;
   // rows after the histories, at a 16-byte boundary (as the launch sized it)
   const size_t hwords = (size_t)rs * per * (a.overlap ? 2 : 1);
   int* rows = reinterpret_cast<int*>(reinterpret_cast<char*>(hist_lds) + ((hwords * 4 + 15) & ~(size_t)15));
-  for (int q = threadIdx.x; q < ns * K; q += kRowThreads) {
+  if (has_row) {
     const int sl = q / K, j = q % K;
     const long s = s0 + sl, slot = s * K + j;
-    const bool live = j < o.n_cands[s];
     int* out = stage_rows ? rows + (size_t)q * H : o.hits + slot * H;
-    write_hit_row(a, out, H, (int)s, j, nst[sl], live, live ? o.n_hits[slot] + o.n_holes[slot] : 0,
+    write_hit_row(a, out, H, (int)s, j, T, live, total,
                   LdsWordHist{hist_lds + sl * per, ov_lds ? ov_lds + sl * per : nullptr, K});
   }
   if (!stage_rows) return;
