@@ -506,11 +506,20 @@ def main():
         result["parity"] = parity_check(ev, out, idx, ores, oracle_prior())
         log(f"[bench] oracle {cb['value']:.3e} steps/s ({cb['cores']} threads), "
             f"{cb['single_thread_steps_per_s']:.3e} on one; parity {result['parity']}")
+    dedup = None
+    if not args.no_secondary:
+        # duplicate removal on this workload's own output
+        dms, dres = time_dedup(ctx, out, ev.n_hits)
+        dedup = {"ms": dms, "tracks_per_s": ev.n_tracks / (dms * 1e-3), "flagged": int((dres >= 0).sum()),
+                 "roofline": hbm_roofline(dedup_bytes(out, ev.n_hits), dms,
+                                          "per track 12 max_hits + 52 B, per (track, hit) entry 20 B, 4 B per hit")}
+        log(f"[bench] duplicate removal on {args.workload}: {dms * 1e3:.1f} us, {dedup['flagged']} flagged")
     del out
     torch.cuda.empty_cache()
 
     if not args.no_secondary:
         result["secondary"] = secondary(args, kfx, kfsynth, dev, ctx, hits, ev, shape)
+        result["secondary"][f"duplicate_removal_{args.workload}"] = dedup
     print(json.dumps(result), flush=True)
 
 

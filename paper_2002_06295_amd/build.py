@@ -23,6 +23,10 @@ FLAGS = [
     # root (within 2.5 ulp) rather than correctly rounded sequences; the FP64
     # parts of the kernels keep correctly rounded division and square root
     "-fno-hip-fp32-correctly-rounded-divide-sqrt",
+    # FP32 denormals flushed to zero: the reciprocal and square root then
+    # need no range scaling (no FP32 value of these kernels comes near
+    # 1e-38; FP64 keeps its denormals)
+    "-fgpu-flush-denormals-to-zero",
     "-Wall", "-Wno-unused-function", "-Wno-unused-result",
 ]
 

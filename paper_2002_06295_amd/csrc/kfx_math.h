@@ -166,9 +166,13 @@ KFX_HD void sincos_d(double x, double& s, double& c) {
                                 fma(y, 1.0 / 479001600.0, -1.0 / 3628800.0)),
                         fma(y2, fma(y, 1.0 / 40320.0, -1.0 / 720.0), fma(y, 1.0 / 24.0, -0.5)));
   const double cr = fma(pc, y, 1.0);
-  const int qi = (int)(q - 4.0 * floor(0.25 * q));  // q mod 4, exact
-  s = qi == 0 ? sr : (qi == 1 ? cr : (qi == 2 ? -sr : -cr));
-  c = qi == 0 ? cr : (qi == 1 ? -sr : (qi == 2 ? -cr : sr));
+  // quadrant q mod 4 (|q| < 2^31 here, two's complement): odd quadrants
+  // swap sine and cosine, quadrants 2 and 3 negate the sine, 1 and 2 the
+  // cosine; selects rather than branches
+  const int qi = (int)q & 3;
+  const double a = (qi & 1) ? cr : sr, b = (qi & 1) ? sr : cr;
+  s = (qi & 2) ? -a : a;
+  c = ((qi + 1) & 2) ? -b : b;
 }
 
 KFX_HD double wrap_pi(double a) {  // to (-pi, pi]

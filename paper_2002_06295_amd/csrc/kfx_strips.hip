@@ -49,11 +49,16 @@ __device__ inline bool strips_linked(const StripArgs& a, int j, int i) {
 // (c + 1) * kStripChunk) and classifies their digis in every event, so that
 // the chunk's calibration (noise and bad flags of its strips, ~60 KB) is
 // fetched once and reused from the cache by all events, instead of every
-// event gathering its own sectors of the table.  bnd[e * (C + 1) + c] is
-// the first digi of event e in chunk c (chunk 0 starts at the event's
-// first digi and chunk C is its end, so digis outside the table are
-// classified too).
+// event gathering its own sectors of the table.  The events go in rounds
+// of kStripEvents, whose gathers are all in flight together: the chunk's
+// calibration is then read while it is in L2, once per round (in rounds of
+// four, the tables of the ~120 chunks in flight on an XCD outgrew its L2
+// between rounds and were fetched again for every round).
+// bnd[e * (C + 1) + c] is the first digi of event e in chunk c (chunk 0
+// starts at the event's first digi and chunk C is its end, so digis
+// outside the table are classified too).
 constexpr int kStripChunk = 16;
+constexpr int kStripEvents = 16;
 
 __global__ void __launch_bounds__(256) k_strip_bounds(StripArgs a, int C) {
   const long n_b = (long)a.n_events * (C + 1);
@@ -81,15 +86,14 @@ __global__ void __launch_bounds__(256) k_strip_bounds(StripArgs a, int C) {
 
 // Code of a digi: bit 0 cluster strip (in the table, not bad, adc >
 // chan_thr * noise), bit 1 seed (adc > seed_thr * noise); its noise (0 for
-// a bad strip or one outside the table).  Four events per round, their
-// digis' loads and gathers in flight together.
+// a bad strip or one outside the table).
 __global__ void __launch_bounds__(256) k_strip_codes(StripArgs a, int C) {
   const int c = blockIdx.x;
-  for (int e0 = 0; e0 < a.n_events; e0 += 4) {
-    int lo[4], cnt[4];
+  for (int e0 = 0; e0 < a.n_events; e0 += kStripEvents) {
+    int lo[kStripEvents], cnt[kStripEvents];
     int span = 0;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < kStripEvents; ++u) {
       const int e = e0 + u;
       lo[u] = 0;
       cnt[u] = 0;
@@ -100,30 +104,29 @@ __global__ void __launch_bounds__(256) k_strip_codes(StripArgs a, int C) {
       span = max(span, cnt[u]);
     }
     for (int k = threadIdx.x; k < span; k += blockDim.x) {
-      int mm[4], ss[4], qq[4];
+      int cal[kStripEvents], qq[kStripEvents];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < kStripEvents; ++u) {
         const bool in = k < cnt[u];
         const int i = lo[u] + k;
-        mm[u] = in ? a.module[i] : -1;
-        ss[u] = in ? a.strip[i] : 0;
+        const int m = in ? a.module[i] : -1;
+        const int st = in ? a.strip[i] : 0;
         qq[u] = in ? (int)a.adc[i] : 0;
+        cal[u] = (m >= 0 && m < a.n_modules && st >= 0 && st < a.spm) ? m * a.spm + st : -1;
       }
-      float nzv[4];
-      bool bd[4], valid[4];
+      float nzv[kStripEvents];
+      bool bd[kStripEvents];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        valid[u] = mm[u] >= 0 && mm[u] < a.n_modules && ss[u] >= 0 && ss[u] < a.spm;
-        const int cal = valid[u] ? mm[u] * a.spm + ss[u] : 0;
-        nzv[u] = valid[u] ? a.noise[cal] : 0.0f;
-        bd[u] = valid[u] ? a.bad[cal] != 0 : true;
+      for (int u = 0; u < kStripEvents; ++u) {
+        nzv[u] = cal[u] >= 0 ? a.noise[cal[u]] : 0.0f;
+        bd[u] = cal[u] >= 0 ? a.bad[cal[u]] != 0 : true;
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < kStripEvents; ++u) {
         if (k >= cnt[u]) continue;
         unsigned char cd = 0;
         float nzo = 0.0f;
-        if (valid[u] && !bd[u]) {
+        if (cal[u] >= 0 && !bd[u]) {
           nzo = nzv[u];
           const float adc = (float)qq[u];
           if (adc > a.chan_thr * nzv[u]) cd = (unsigned char)(1 | ((adc > a.seed_thr * nzv[u]) ? 2 : 0));
@@ -201,11 +204,13 @@ __global__ void __launch_bounds__(256) k_strip_flags(StripArgs a) {
   if (blockIdx.x == 0 && threadIdx.x == 0) a.flag[a.n] = 0;
 }
 
-// pass 3 (after the scan of the flags): the kept clusters in order
+// pass 3 (after the scan of the flags): the kept clusters in order; digi i
+// is kept when the scan steps after it (pos[i + 1] > pos[i]: two coalesced
+// reads instead of the flags and a scattered read of the kept ones' slots)
 __global__ void __launch_bounds__(256) k_strip_write(StripArgs a) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += gridDim.x * blockDim.x) {
-    if (!a.flag[i]) continue;
     const int p = a.pos[i];
+    if (a.pos[i + 1] == p) continue;
     if (p >= a.capacity) continue;
     const StripRec r = a.rec[i];
     a.out_event[p] = r.event;
