@@ -255,54 +255,81 @@ def host_cpu_model():
     return "unknown CPU"
 
 
+def _event_view(ev, e):
+    """The hits of event e alone, as the oracle reads them (its hit
+    indices start at 0; the event's first hit in the batch is returned)."""
+    from types import SimpleNamespace
+    lo, hi = int(ev.event_offsets[e]), int(ev.event_offsets[e + 1])
+    return SimpleNamespace(workload=ev.workload, geometry=ev.geometry, bz=ev.bz, x=ev.x[lo:hi], y=ev.y[lo:hi],
+                           z=ev.z[lo:hi], layer=ev.layer[lo:hi],
+                           event_offsets=np.array([0, hi - lo], dtype=np.int32)), lo
+
+
 def cpu_baseline(ev, idx, prior, min_seconds=4.0):
     """The FP64 oracle (as it is) on the host's cores, building the sampled
-    seeds: split into one chunk per thread (seeds are independent; the
-    oracle holds no shared state and the ctypes call releases the GIL),
-    repeated until min_seconds have passed; then on one thread over a part
-    of the sample for about min_seconds.  Returns the baseline record and
-    the oracle's results for the seeds."""
+    seeds: one task per sampled event, given that event's hits alone (the
+    oracle bins every event it is given, and seeds are independent; the
+    ctypes call releases the GIL), on up to 16 threads, repeated until
+    min_seconds have passed; then on one thread over the tasks for about
+    min_seconds.  Returns the baseline record and the oracle's results for
+    the seeds (hit indices in the batch's numbering)."""
     from concurrent.futures import ThreadPoolExecutor
 
     import oracle
     oracle.lib()
     threads = max(1, min(16, os.cpu_count() or 1))
-    seeds = ev.seeds[idx]
-    se = ev.trk_event[idx].astype(np.int32)
-    n = len(idx)
-    chunks = [c for c in np.array_split(np.arange(n), threads) if len(c)]
+    te = ev.trk_event[idx]
+    events = list(np.unique(te))
+    tasks = [(e, np.nonzero(te == e)[0]) for e in events]  # positions in idx, in idx order per event
+    views = {e: _event_view(ev, e) for e in events}
 
-    def run(sub):
-        return oracle.build_tracks(ev, seeds=seeds[sub], seed_event=se[sub], max_hits=48, prior=prior)
+    def run(task):
+        e, pos = task
+        view, lo = views[e]
+        seeds = (ev.seeds[idx[pos]] - lo).astype(np.int32)
+        q = oracle.build_tracks(view, seeds=seeds, seed_event=np.zeros(len(pos), np.int32), max_hits=48,
+                                prior=prior)
+        q["hits"] = np.where(q["hits"] >= 0, q["hits"] + lo, q["hits"])
+        return pos, q
 
     steps = 0
     reps = 0
     parts = None
-    with ThreadPoolExecutor(len(chunks)) as ex:
+    nthr = min(threads, len(tasks))
+    with ThreadPoolExecutor(nthr) as ex:
         t0 = time.perf_counter()
         while reps < 1 or time.perf_counter() - t0 < min_seconds:
-            parts = list(ex.map(run, chunks))
-            steps += sum(int(q["stats"][0]) for q in parts)
+            parts = list(ex.map(run, tasks))
+            steps += sum(int(q["stats"][0]) for _, q in parts)
             reps += 1
         dt = time.perf_counter() - t0
-    res = {k: np.concatenate([q[k] for q in parts]) for k in parts[0] if k != "stats"}
-    res["stats"] = sum(q["stats"] for q in parts)
-    # one thread: consecutive chunks of the sample until min_seconds
+    n = len(idx)
+    res = {}
+    for k in parts[0][1]:
+        if k == "stats":
+            continue
+        first = parts[0][1][k]
+        arr = np.zeros((n,) + first.shape[1:], dtype=first.dtype)
+        for pos, q in parts:
+            arr[pos] = q[k]
+        res[k] = arr
+    res["stats"] = sum(q["stats"] for _, q in parts)
+    # one thread: the tasks in turn until min_seconds
     st1, sd1, t1 = 0, 0, time.perf_counter()
-    for c in chunks:
-        q = run(c)
+    for task in tasks:
+        _, q = run(task)
         st1 += int(q["stats"][0])
-        sd1 += len(c)
+        sd1 += len(task[1])
         if time.perf_counter() - t1 >= min_seconds:
             break
     dt1 = time.perf_counter() - t1
-    rec = dict(value=steps / dt, unit="steps/s", cores=len(chunks), kind="oracle",
+    rec = dict(value=steps / dt, unit="steps/s", cores=nthr, kind="oracle",
                tracks_per_s=reps * n / dt,
                single_thread_steps_per_s=st1 / dt1, single_thread_tracks_per_s=sd1 / dt1,
-               sample=f"{n} seeds sampled over {np.unique(ev.trk_event[idx]).size} events of the "
-                      f"{ev.workload.name} workload, x {reps}, FP64 building with the binned compatibility "
-                      f"search, {len(chunks)} threads on {host_cpu_model()}, {dt:.1f} s wall; one thread: "
-                      f"{sd1} of the seeds, {dt1:.1f} s")
+               sample=f"{n} seeds sampled over {len(events)} events of the {ev.workload.name} workload, one "
+                      f"task per event with that event's hits (binned by the oracle in every task), x {reps}, "
+                      f"FP64 building with the binned compatibility search, {nthr} threads on "
+                      f"{host_cpu_model()}, {dt:.1f} s wall; one thread: {sd1} of the seeds, {dt1:.1f} s")
     return rec, res
 
 
