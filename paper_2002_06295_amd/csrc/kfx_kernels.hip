@@ -912,9 +912,12 @@ __device__ int wave_scan(const BinIndex& B, int n_phi, int lane, bool has, const
     const int o = __ffsll((long long)owners) - 1;
     owners &= owners - 1ull;
     PairFrame P;
-    P.x = rl_d(pf.x, o);
-    P.y = rl_d(pf.y, o);
-    P.z = rl_d(pf.z, o);
+    P.xh = rl_f(pf.xh, o);
+    P.xl = rl_f(pf.xl, o);
+    P.yh = rl_f(pf.yh, o);
+    P.yl = rl_f(pf.yl, o);
+    P.zh = rl_f(pf.zh, o);
+    P.zl = rl_f(pf.zl, o);
     P.c = rl_f(pf.c, o);
     P.s = rl_f(pf.s, o);
     P.disk = rl_i(pf.disk, o);
