@@ -466,25 +466,39 @@ __global__ void __launch_bounds__(64) k_fit_backward(const Geometry* __restrict_
 }
 
 // dalign[3 l + c] = sum over blocks of the partial rows (0 for disks),
-// dfield = the last row; summed in block order.
-__global__ void __launch_bounds__(64) k_grad_reduce(const Geometry* __restrict__ G, const double* partial, int nblocks, double* dalign,
-                              double* dfield) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+// dfield = the last row.  One workgroup per output: thread t adds the
+// partials of blocks t, t + 256, ... in that order, then a fixed tree over
+// the 256 sums; the order depends only on the number of blocks, so the
+// result does not depend on scheduling.  (Summed by one thread, the
+// thousands of dependent adds of a large fit took longer than the adjoint.)
+constexpr int kReduceThreads = 256;
+__global__ void __launch_bounds__(kReduceThreads) k_grad_reduce(const Geometry* __restrict__ G, const double* partial,
+                                                                int nblocks, double* dalign, double* dfield) {
+  __shared__ double part[kReduceThreads];
+  const int i = blockIdx.x;
   const int nl = G->n_layers, nrow = 3 * G->n_barrel + 1;
   if (i > 3 * nl) return;
   int row = nrow - 1;
   if (i < 3 * nl) {
     const int r = G->brank[i / 3];
     if (r < 0) {
-      dalign[i] = 0.0;
+      if (threadIdx.x == 0) dalign[i] = 0.0;
       return;
     }
     row = 3 * r + i % 3;
   }
   double s = 0.0;
-  for (int b = 0; b < nblocks; ++b) s += partial[(long)b * nrow + row];
-  if (i < 3 * nl) dalign[i] = s;
-  else *dfield = s;
+  for (int b = threadIdx.x; b < nblocks; b += kReduceThreads) s += partial[(long)b * nrow + row];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = kReduceThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    if (i < 3 * nl) dalign[i] = part[0];
+    else *dfield = part[0];
+  }
 }
 
 // ------------------------------------------------------ seeds and step (a2-a6)
@@ -1557,7 +1571,7 @@ hipError_t launch_fit_backward(const Geometry* G, int n_barrel, int n_layers, co
                        fscale, ckpt, status, dchi2, per_track, partial);
   }
   const int nout = 3 * n_layers + 1;
-  hipLaunchKernelGGL(k_grad_reduce, dim3(nblk(nout, 64)), dim3(64), 0, st, G, partial, n > 0 ? nblocks : 0, dalign,
+  hipLaunchKernelGGL(k_grad_reduce, dim3(nout), dim3(kReduceThreads), 0, st, G, partial, n > 0 ? nblocks : 0, dalign,
                      dfield);
   return hipGetLastError();
 }
