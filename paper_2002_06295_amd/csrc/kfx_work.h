@@ -623,19 +623,26 @@ KFX_HD void fit_track(const Geometry& G, const HitsView& H, const int* trk_off, 
   // checkpoints beyond the caller's capacity: the track is not fitted
   const bool ckpt_fits = !o.ckpt.par || (long)(n - 1) * o.n_tracks + t < o.ckpt.stride;
   ok = ok && ckpt_fits;
-  for (int i = 0; ok && i < n; ++i) {
+  // a hit outside the arrays, on no layer or not finite fails the track;
+  // each hit is checked where it is read (the filter below stops at the
+  // first such hit, and a failed track's outputs are zeros whatever it had
+  // filtered), so that its four values are fetched once per fit: scattered
+  // over the tracks of a wavefront, every read costs a memory sector
+  auto valid = [&](int h) {
+    return h >= 0 && h < H.n_hits && H.layer[h] >= 0 && H.layer[h] < G.n_layers && finite_hit(H.x[h], H.y[h], H.z[h]);
+  };
+  double m0[3][3];
+  for (int i = 0; ok && i < 3; ++i) {
     const int h = trk_hits[b + i];
-    if (h < 0 || h >= H.n_hits || H.layer[h] < 0 || H.layer[h] >= G.n_layers) ok = false;
-    else if (!finite_hit(H.x[h], H.y[h], H.z[h])) ok = false;
-  }
-  if (ok) {
-    double m0[3][3];
-    for (int i = 0; i < 3; ++i) {
-      const int h = trk_hits[b + i];
+    if (!valid(h)) {
+      ok = false;
+    } else {
       m0[i][0] = H.x[h];
       m0[i][1] = H.y[h];
       m0[i][2] = H.z[h];
     }
+  }
+  if (ok) {
     // The fit runs the whole filter with an FP64 covariance: a crossing at
     // angle a to the layer normal scales the covariance terms by 1/cos^2(a),
     // and over a few steep crossings the FP32 rounding of the covariance
@@ -647,6 +654,10 @@ KFX_HD void fit_track(const Geometry& G, const HitsView& H, const int* trk_off, 
     const double kappa_d = -kHcD * G.bz * (double)fscale;
     for (int i = 0; i < n && ok; ++i) {
       const int h = trk_hits[b + i];
+      if (i >= 3 && !valid(h)) {
+        ok = false;
+        break;
+      }
       const int l = H.layer[h];
       const Layer& Ld = G.L[l];
       const float* a = align ? align + 3 * l : nullptr;
