@@ -89,7 +89,7 @@ def source_sha256():
     return h.hexdigest()
 
 
-def stored_traffic(name="k_build_fused_build5k_traffic.json"):
+def stored_traffic(name="k_build_fused_batch256_traffic.json"):
     """HBM bytes per launch of the fused kernel from the committed rocprofv3
     FETCH_SIZE / WRITE_SIZE summary (calibrated against a copy of known
     size), or None when the kernel sources changed since it was taken."""
