@@ -1070,14 +1070,20 @@ int kfx_cluster_strips(kfx_ctx* c, const kfx_digis* d, const kfx_strip_calib* ca
   a.clus_thr2 = p->clus_thr * p->clus_thr;
   a.max_gap = p->max_gap;
   a.min_charge = p->min_charge;
-  a.bnd = (int*)ws(c, "strip.bnd", (size_t)d->n_events * (strip_chunks(cal->n_modules) + 1) * 4, st, rc);
+  // chunks of up to 8 modules whose calibration fits 32 KB of LDS; staged
+  // when several events reuse it (a module wider than that, or a call of
+  // fewer than four events, gathers from HBM what its digis need)
+  a.chunk = std::max(1, std::min(8, (int)(32768 / strip_cal_lds(1, a.spm))));
+  a.stage = (strip_cal_lds(a.chunk, a.spm) <= 32768 && d->n_events >= 4) ? 1 : 0;
+  const long nchunks = strip_chunks(cal->n_modules, a.chunk);
+  const size_t nec = (size_t)d->n_events * nchunks;
+  a.bnd = (int*)ws(c, "strip.bnd", (size_t)d->n_events * (nchunks + 1) * 4, st, rc);
   if (rc) return rc;
-  a.code = (unsigned char*)ws(c, "strip.code", (size_t)d->n + 16, st, rc); if (rc) return rc;
-  a.nz = (float*)ws(c, "strip.nz", (size_t)d->n * 4, st, rc); if (rc) return rc;
-  a.rec = (StripRec*)ws(c, "strip.rec", (size_t)d->n * sizeof(StripRec), st, rc); if (rc) return rc;
-  a.flag = (int*)ws(c, "strip.flag", ((size_t)d->n + 1) * 4, st, rc); if (rc) return rc;
-  a.pos = (int*)ws(c, "strip.pos", ((size_t)d->n + 2) * 4, st, rc); if (rc) return rc;
-  int* scratch = (int*)ws(c, "strip.scan", (((size_t)d->n + 1) / 4096 + 4) * 4, st, rc); if (rc) return rc;
+  a.cnt = (int*)ws(c, "strip.cnt", (nec + 1) * 4, st, rc); if (rc) return rc;
+  a.cnt_off = (int*)ws(c, "strip.cnt_off", (nec + 2) * 4, st, rc); if (rc) return rc;
+  a.rec = (StripRec*)ws(c, "strip.rec", std::max<size_t>((size_t)d->n, 1) * sizeof(StripRec), st, rc);
+  if (rc) return rc;
+  int* scratch = (int*)ws(c, "strip.scan", ((nec + 1) / 4096 + 4) * 4, st, rc); if (rc) return rc;
   a.out_event = out->event;
   a.out_module = out->module;
   a.out_first = out->first;

@@ -79,13 +79,14 @@ struct StripArgs {
   float seed_thr, chan_thr;
   double clus_thr2;         // clus_thr squared
   int max_gap, min_charge;
+  int chunk;                // modules per chunk
+  int stage;                // the chunk's calibration staged in LDS
   int* bnd;                 // [n_events * (chunks + 1)] first digi of each
                             // (event, module chunk)
-  unsigned char* code;      // [n] bit 0 cluster strip, bit 1 seed
-  float* nz;                // [n] noise of each digi
-  int* flag;                // [n + 1] kept-cluster head flags
-  int* pos;                 // [n + 1] their exclusive scan
-  StripRec* rec;            // [n] per kept head: its cluster's sums
+  int* cnt;                 // [n_events * chunks] kept clusters of each
+  int* cnt_off;             // [n_events * chunks + 1] their exclusive scan
+  StripRec* rec;            // [n] kept clusters of (event, chunk) from the
+                            // chunk's first digi on
   int* out_event;           // [capacity] kept clusters
   int* out_module;
   int* out_first;
@@ -131,7 +132,8 @@ void launch_build_fused(const BuildArgs& a, const TracksOut& o, int* seed_counte
 int fused_lanes_for(int K);
 void launch_find_duplicates(const DupArgs& a, hipStream_t st);
 void launch_mask_hits(const MaskArgs& a, const int* layer_in, hipStream_t st);
-int strip_chunks(int n_modules);
+int strip_chunks(int n_modules, int chunk);
+size_t strip_cal_lds(int chunk, int spm);
 void launch_cluster_strips(const StripArgs& a, int* scan_scratch, hipStream_t st);
 
 }  // namespace kfx

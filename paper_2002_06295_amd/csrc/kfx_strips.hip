@@ -6,14 +6,14 @@
 // times the quadrature sum of the noise and the charge reaches a minimum.
 //
 // Data-parallel over the digis of a whole batch of events (the paper's
-// remedy for single-event GPU runs dominated by overheads).  The first pass
-// classifies every digi once (the calibration gathers, module-major across
-// the events) into a code byte and its noise; in the second one thread per digi decides, from the codes of
-// its neighbours, whether it starts a cluster, and if so walks the cluster
-// and keeps its sums when the cluster passes; an exclusive scan of the
-// kept flags gives every kept cluster its output slot, in (event, module,
-// first strip) order; the last pass writes them.  Digis and codes are read
-// coalesced, neighbours through the caches.
+// remedy for single-event GPU runs dominated by overheads), in one pass
+// over the digis: a block per chunk of modules holds the chunk's
+// calibration in LDS and takes the chunk's digis event by event; one
+// thread per digi decides whether it starts a cluster, and if so walks the
+// cluster and keeps its sums when the cluster passes; the kept clusters of
+// each (event, chunk) are compacted in the block.  An exclusive scan of the
+// per-(event, chunk) counts gives every kept cluster its output slot, in
+// (event, module, first strip) order, and a last pass moves them there.
 #include <hip/hip_runtime.h>
 
 #include "kfx_internal.h"
@@ -22,44 +22,107 @@ namespace kfx {
 
 namespace {
 
-__device__ inline int strip_event_of(const int* ev_off, int n_events, int i) {
-  int lo = 0, hi = n_events;  // ev_off[lo] <= i < ev_off[hi]
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (ev_off[mid] <= i) lo = mid; else hi = mid;
-  }
-  return lo;
+constexpr int kStripThreads = 256;
+
+// LDS of the strip clustering block: the chunk's calibration (4-byte noise
+// and 1-byte bad flag per strip), then one window per wavefront (module,
+// strip and noise 4 bytes each, ADC 2, code 1 per digi); 16-byte aligned
+__host__ __device__ inline size_t strip_cal_lds_al(int chunk, int spm) {
+  return ((size_t)chunk * spm * 5 + 15) & ~(size_t)15;
+}
+__host__ __device__ inline size_t strip_win_lds(int wn) { return ((size_t)wn * 15 + 15) & ~(size_t)15; }
+
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// consecutive cluster strips j < i (digi order) of one cluster: same module,
-// at most max_gap strips between them, all of them bad
-__device__ inline bool strips_linked(const StripArgs& a, int j, int i) {
-  const int m = a.module[j];
-  if (a.module[i] != m) return false;
-  const int sj = a.strip[j], si = a.strip[i];
+__device__ inline bool in_table(const StripArgs& a, int m, int s) {
+  return m >= 0 && m < a.n_modules && s >= 0 && s < a.spm;
+}
+
+// The calibration a block works with: its chunk's modules staged in LDS
+// (nm of them from m0; none when the table is not staged), any other
+// module read from HBM (the digis next to a chunk's edge, or a module out
+// of order).
+struct Calib {
+  const float* nz;
+  const unsigned char* bd;
+  int m0, nm;
+  __device__ float noise(const StripArgs& a, int m, int s) const {
+    return (m >= m0 && m < m0 + nm) ? nz[(m - m0) * a.spm + s] : a.noise[(long)m * a.spm + s];
+  }
+  __device__ bool bad(const StripArgs& a, int m, int s) const {
+    return ((m >= m0 && m < m0 + nm) ? bd[(m - m0) * a.spm + s] : a.bad[(long)m * a.spm + s]) != 0;
+  }
+};
+
+// Code of a digi (module m, strip st, ADC q): bit 0 cluster strip (in the
+// table, not bad, adc > chan_thr * noise), bit 1 seed (adc > seed_thr *
+// noise); nzo its noise.
+__device__ inline unsigned int code_from(const StripArgs& a, const Calib& K, int m, int st, int q, float& nzo) {
+  nzo = 0.0f;
+  if (!in_table(a, m, st) || K.bad(a, m, st)) return 0u;
+  const float nzv = K.noise(a, m, st);
+  nzo = nzv;
+  const float adc = (float)q;
+  if (!(adc > a.chan_thr * nzv)) return 0u;
+  return 1u | ((adc > a.seed_thr * nzv) ? 2u : 0u);
+}
+
+// consecutive cluster strips j < i (digi order) of one cluster, given
+// their modules and strips: same module, at most max_gap strips between
+// them, all of them bad
+__device__ inline bool strips_linked(const StripArgs& a, const Calib& K, int mj, int sj, int mi, int si) {
+  if (mi != mj) return false;
   if (si <= sj || si - sj - 1 > a.max_gap) return false;
   for (int t = sj + 1; t < si; ++t)
-    if (!a.bad[m * a.spm + t]) return false;
+    if (!K.bad(a, mj, t)) return false;
   return true;
+}
+
+// A wavefront's window of digis [w0, w1) in LDS: module, strip, ADC, code
+// and noise of each; a digi outside it is read from HBM and classified again.
+struct Win {
+  int w0, w1;
+  int* m;
+  int* s;
+  float* nz;
+  unsigned short* q;
+  unsigned char* c;
+};
+
+struct Digi {
+  int m, s, q;
+  unsigned int code;
+  float nz;
+};
+
+__device__ inline Digi digi_at(const StripArgs& a, const Calib& K, const Win& w, int j) {
+  Digi d;
+  if (j >= w.w0 && j < w.w1) {
+    const int k = j - w.w0;
+    d.m = w.m[k];
+    d.s = w.s[k];
+    d.q = w.q[k];
+    d.code = w.c[k];
+    d.nz = w.nz[k];
+  } else {
+    d.m = a.module[j];
+    d.s = a.strip[j];
+    d.q = a.adc[j];
+    d.code = code_from(a, K, d.m, d.s, d.q, d.nz);
+  }
+  return d;
 }
 
 }  // namespace
 
-// pass 1 runs module-major: block c owns modules [c * kStripChunk,
-// (c + 1) * kStripChunk) and classifies their digis in every event, so that
-// the chunk's calibration (noise and bad flags of its strips, ~60 KB) is
-// fetched once and reused from the cache by all events, instead of every
-// event gathering its own sectors of the table.  The events go in rounds
-// of kStripEvents, whose gathers are all in flight together: the chunk's
-// calibration is then read while it is in L2, once per round (in rounds of
-// four, the tables of the ~120 chunks in flight on an XCD outgrew its L2
-// between rounds and were fetched again for every round).
-// bnd[e * (C + 1) + c] is the first digi of event e in chunk c (chunk 0
-// starts at the event's first digi and chunk C is its end, so digis
-// outside the table are classified too).
-constexpr int kStripChunk = 16;
-constexpr int kStripEvents = 16;
-
+// The digis of event e in chunk c (a chunk: `chunk` consecutive modules)
+// are [bnd[e * (C + 1) + c], bnd[e * (C + 1) + c + 1]): chunk 0 starts at the
+// event's first digi and chunk C - 1 ends at its last, so digis outside
+// the table are covered too.  Offsets are clamped to the digis.
 __global__ void __launch_bounds__(256) k_strip_bounds(StripArgs a, int C) {
   const long n_b = (long)a.n_events * (C + 1);
   for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n_b; t += (long)gridDim.x * blockDim.x) {
@@ -71,8 +134,8 @@ __global__ void __launch_bounds__(256) k_strip_bounds(StripArgs a, int C) {
     } else if (c == C) {
       b = hi;
     } else {
-      // first digi of the event whose module is >= c * kStripChunk
-      const int m = c * kStripChunk;
+      // first digi of the event whose module is >= c * chunk
+      const int m = c * a.chunk;
       int l = lo, h = hi;
       while (l < h) {
         const int mid = (l + h) >> 1;
@@ -84,156 +147,174 @@ __global__ void __launch_bounds__(256) k_strip_bounds(StripArgs a, int C) {
   }
 }
 
-// Code of a digi: bit 0 cluster strip (in the table, not bad, adc >
-// chan_thr * noise), bit 1 seed (adc > seed_thr * noise); its noise (0 for
-// a bad strip or one outside the table).
-__global__ void __launch_bounds__(256) k_strip_codes(StripArgs a, int C) {
-  const int c = blockIdx.x;
-  for (int e0 = 0; e0 < a.n_events; e0 += kStripEvents) {
-    int lo[kStripEvents], cnt[kStripEvents];
-    int span = 0;
-#pragma unroll
-    for (int u = 0; u < kStripEvents; ++u) {
-      const int e = e0 + u;
-      lo[u] = 0;
-      cnt[u] = 0;
-      if (e < a.n_events) {
-        lo[u] = a.bnd[(long)e * (C + 1) + c];
-        cnt[u] = max(a.bnd[(long)e * (C + 1) + c + 1] - lo[u], 0);
-      }
-      span = max(span, cnt[u]);
-    }
-    for (int k = threadIdx.x; k < span; k += blockDim.x) {
-      int cal[kStripEvents], qq[kStripEvents];
-#pragma unroll
-      for (int u = 0; u < kStripEvents; ++u) {
-        const bool in = k < cnt[u];
-        const int i = lo[u] + k;
-        const int m = in ? a.module[i] : -1;
-        const int st = in ? a.strip[i] : 0;
-        qq[u] = in ? (int)a.adc[i] : 0;
-        cal[u] = (m >= 0 && m < a.n_modules && st >= 0 && st < a.spm) ? m * a.spm + st : -1;
-      }
-      float nzv[kStripEvents];
-      bool bd[kStripEvents];
-#pragma unroll
-      for (int u = 0; u < kStripEvents; ++u) {
-        nzv[u] = cal[u] >= 0 ? a.noise[cal[u]] : 0.0f;
-        bd[u] = cal[u] >= 0 ? a.bad[cal[u]] != 0 : true;
-      }
-#pragma unroll
-      for (int u = 0; u < kStripEvents; ++u) {
-        if (k >= cnt[u]) continue;
-        unsigned char cd = 0;
-        float nzo = 0.0f;
-        if (cal[u] >= 0 && !bd[u]) {
-          nzo = nzv[u];
-          const float adc = (float)qq[u];
-          if (adc > a.chan_thr * nzv[u]) cd = (unsigned char)(1 | ((adc > a.seed_thr * nzv[u]) ? 2 : 0));
-        }
-        a.code[lo[u] + k] = cd;
-        a.nz[lo[u] + k] = nzo;
-      }
-    }
+// One pass over the digis, module-major: block c stages the calibration of
+// its chunk (noise and bad flags of `chunk` modules, 30 KB for 8 modules of
+// 768 strips) in LDS once, then each of its wavefronts takes the chunk's
+// digis of one event after another (wavefront w: events w, w + 4, ...), 64
+// at a time: the 64 digis and max_gap + 1 on each side are read and
+// classified once into an LDS window, where the neighbour tests and walks
+// find them (a walk that leaves the window reads HBM).  A
+// cluster strip whose nearest cluster strip before it (within max_gap + 1
+// digis of the event: a linked one cannot be farther) is not linked to it
+// starts a cluster; its thread walks the cluster forward the same way,
+// summing charge, sum adc^2, sum strip * adc and sum noise^2 in strip order.
+// The kept clusters of (event, chunk) are compacted by a ballot and stored
+// from the chunk's first digi on (never more clusters than digis), in digi
+// order, with their count; k_strip_emit then moves them to their place in
+// the output.  The calibration is read once and the digis once
+// (neighbours through the caches); no per-digi codes or flags go through
+// HBM.
+__global__ void __launch_bounds__(kStripThreads) k_strip_cluster(StripArgs a, int C) {
+  extern __shared__ __align__(16) unsigned char cal_lds[];
+  const int c = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
+  Calib K;
+  K.m0 = c * a.chunk;
+  K.nm = a.stage ? max(0, min(a.chunk, a.n_modules - K.m0)) : 0;
+  float* nz_l = reinterpret_cast<float*>(cal_lds);
+  unsigned char* bd_l = cal_lds + (size_t)a.chunk * a.spm * 4;
+  K.nz = nz_l;
+  K.bd = bd_l;
+  const int ncal = K.nm * a.spm;
+  for (int k = tid; k < ncal; k += kStripThreads) {
+    nz_l[k] = a.noise[(long)K.m0 * a.spm + k];
+    bd_l[k] = a.bad[(long)K.m0 * a.spm + k];
   }
-}
-
-// pass 2: a cluster strip with no linked cluster strip before it starts a
-// cluster; it walks the cluster (the nearest cluster strip after the
-// current one, within max_gap + 1 digis of the event, while linked) and
-// flags it when kept, storing its last strip, charge and sum strip * adc
-__global__ void __launch_bounds__(256) k_strip_flags(StripArgs a) {
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += gridDim.x * blockDim.x) {
-    int kept = 0;
-    // a digi outside every event's range (before the first event, after
-    // the last, or skipped by offsets that go backwards) was not
-    // classified: its code byte is not read
-    const int e = strip_event_of(a.ev_off, a.n_events, i);
-    // clamped to the digis, so that malformed offsets cannot lead a walk
-    // out of the arrays
-    const int ev_start = max(a.ev_off[e], 0), ev_end = min(a.ev_off[e + 1], a.n);
-    const bool in_event = i >= ev_start && i < ev_end;
-    const unsigned char ci = in_event ? a.code[i] : 0;
-    if (ci & 1) {
-      bool head = true;
-      for (int j = i - 1, lo = max(ev_start, i - 1 - a.max_gap); j >= lo; --j)
-        if (a.code[j] & 1) {
-          head = !strips_linked(a, j, i);
-          break;
+  // this wavefront's window: 64 digis and max_gap + 1 on each side
+  const int halo = a.max_gap + 1, wn = 64 + 2 * halo;
+  unsigned char* wbase = cal_lds + strip_cal_lds_al(a.stage ? a.chunk : 0, a.spm) + (size_t)(tid >> 6) * strip_win_lds(wn);
+  Win W;
+  W.m = reinterpret_cast<int*>(wbase);
+  W.s = W.m + wn;
+  W.nz = reinterpret_cast<float*>(W.s + wn);
+  W.q = reinterpret_cast<unsigned short*>(W.nz + wn);
+  W.c = reinterpret_cast<unsigned char*>(W.q + wn);
+  __syncthreads();
+  for (int e = tid >> 6; e < a.n_events; e += kStripThreads / 64) {
+    const int ev_start = min(max(a.ev_off[e], 0), a.n), ev_end = min(max(a.ev_off[e + 1], ev_start), a.n);
+    const int lo = a.bnd[(long)e * (C + 1) + c];
+    const int hi = max(a.bnd[(long)e * (C + 1) + c + 1], lo);
+    int running = 0;
+    for (int base = lo; base < hi; base += 64) {
+      // the window's digis, classified once, in LDS
+      W.w0 = max(ev_start, base - halo);
+      W.w1 = min(ev_end, base + 64 + halo);
+      for (int j = W.w0 + lane; j < W.w1; j += 64) {
+        const int k = j - W.w0;
+        const int m = a.module[j], st = a.strip[j], q = a.adc[j];
+        float nzj;
+        W.c[k] = (unsigned char)code_from(a, K, m, st, q, nzj);
+        W.m[k] = m;
+        W.s[k] = st;
+        W.q[k] = (unsigned short)q;
+        W.nz[k] = nzj;
+      }
+      wave_sync();
+      const int i = base + lane;
+      int kept = 0;
+      StripRec r;
+      const Digi di = i < hi ? digi_at(a, K, W, i) : Digi{0, 0, 0, 0u, 0.0f};
+      if (di.code & 1u) {
+        bool head = true;
+        for (int j = i - 1, jl = max(ev_start, i - 1 - a.max_gap); j >= jl; --j) {
+          const Digi dj = digi_at(a, K, W, j);
+          if (dj.code & 1u) {
+            head = !strips_linked(a, K, dj.m, dj.s, di.m, di.s);
+            break;
+          }
         }
-      if (head) {
-        int cur = i, charge = 0, last = 0;
-        long sq = 0, sa = 0;
-        double nsq = 0.0;
-        bool seed = false;
-        for (;;) {
-          const int q = a.adc[cur];
-          const int st = a.strip[cur];
-          charge += q;
-          sq += (long)q * q;
-          sa += (long)st * q;
-          const double nzd = (double)a.nz[cur];
-          nsq += nzd * nzd;
-          seed |= (a.code[cur] & 2) != 0;
-          last = st;
-          int nx = -1;
-          for (int j = cur + 1, lim = min(ev_end, cur + 2 + a.max_gap); j < lim; ++j)
-            if (a.code[j] & 1) {
-              nx = j;
-              break;
+        if (head) {
+          int cur = i, charge = 0, last = 0;
+          Digi dc = di;
+          long sq = 0, sa = 0;
+          double nsq = 0.0;
+          bool seed = false;
+          for (;;) {
+            charge += dc.q;
+            sq += (long)dc.q * dc.q;
+            sa += (long)dc.s * dc.q;
+            const double nzd = (double)dc.nz;
+            nsq += nzd * nzd;
+            seed |= (dc.code & 2u) != 0;
+            last = dc.s;
+            int nx = -1;
+            Digi dn = dc;
+            for (int j = cur + 1, lim = min(ev_end, cur + 2 + a.max_gap); j < lim; ++j) {
+              const Digi dj = digi_at(a, K, W, j);
+              if (dj.code & 1u) {
+                nx = j;
+                dn = dj;
+                break;
+              }
             }
-          if (nx < 0 || !strips_linked(a, cur, nx)) break;
-          cur = nx;
-        }
-        if (seed && (double)sq > a.clus_thr2 * nsq && charge >= a.min_charge) {
-          kept = 1;
-          StripRec r;
-          r.sa = sa;
-          r.last = last;
-          r.charge = charge;
-          r.event = e;
-          r.module = a.module[i];
-          r.first = a.strip[i];
-          r.pad = 0;
-          a.rec[i] = r;
+            if (nx < 0 || !strips_linked(a, K, dc.m, dc.s, dn.m, dn.s)) break;
+            cur = nx;
+            dc = dn;
+          }
+          if (seed && (double)sq > a.clus_thr2 * nsq && charge >= a.min_charge) {
+            kept = 1;
+            r.sa = sa;
+            r.last = last;
+            r.charge = charge;
+            r.event = e;
+            r.module = di.m;
+            r.first = di.s;
+            r.pad = 0;
+          }
         }
       }
+      const unsigned long long km = __ballot(kept);
+      if (kept) a.rec[lo + running + __popcll(km & ((1ull << lane) - 1ull))] = r;
+      running += __popcll(km);
+      wave_sync();  // the window is refilled for the next 64 digis
     }
-    a.flag[i] = kept;
+    if (lane == 0) a.cnt[(long)e * C + c] = running;
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) a.flag[a.n] = 0;
 }
 
-// pass 3 (after the scan of the flags): the kept clusters in order; digi i
-// is kept when the scan steps after it (pos[i + 1] > pos[i]: two coalesced
-// reads instead of the flags and a scattered read of the kept ones' slots)
-__global__ void __launch_bounds__(256) k_strip_write(StripArgs a) {
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += gridDim.x * blockDim.x) {
-    const int p = a.pos[i];
-    if (a.pos[i + 1] == p) continue;
-    if (p >= a.capacity) continue;
-    const StripRec r = a.rec[i];
-    a.out_event[p] = r.event;
-    a.out_module[p] = r.module;
-    a.out_first[p] = r.first;
-    a.out_size[p] = r.last - r.first + 1;
-    a.out_charge[p] = r.charge;
-    a.out_bary[p] = (float)((double)r.sa / (double)r.charge);
+// The kept clusters to their output slots (offsets: the exclusive scan of
+// the per-(event, chunk) counts, event-major): one wavefront per (event,
+// chunk), coalesced reads of its records and coalesced writes.
+__global__ void __launch_bounds__(256) k_strip_emit(StripArgs a, int C) {
+  const long nw = (long)a.n_events * C;
+  const int lane = threadIdx.x & 63;
+  const long step = ((long)gridDim.x * blockDim.x) >> 6;
+  for (long w = ((long)blockIdx.x * blockDim.x + threadIdx.x) >> 6; w < nw; w += step) {
+    const int e = (int)(w / C), c = (int)(w - (long)e * C);
+    const int lo = a.bnd[(long)e * (C + 1) + c];
+    const int k0 = a.cnt_off[w], cnt = a.cnt[w];
+    for (int k = lane; k < cnt; k += 64) {
+      const int p = k0 + k;
+      if (p >= a.capacity) break;
+      const StripRec r = a.rec[lo + k];
+      a.out_event[p] = r.event;
+      a.out_module[p] = r.module;
+      a.out_first[p] = r.first;
+      a.out_size[p] = r.last - r.first + 1;
+      a.out_charge[p] = r.charge;
+      a.out_bary[p] = (float)((double)r.sa / (double)r.charge);
+    }
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) *a.n_out = a.pos[a.n];
+  if (blockIdx.x == 0 && threadIdx.x == 0) *a.n_out = a.cnt_off[nw];
 }
 
-int strip_chunks(int n_modules) { return (n_modules + kStripChunk - 1) / kStripChunk; }
+int strip_chunks(int n_modules, int chunk) { return (n_modules + chunk - 1) / chunk; }
+
+size_t strip_cal_lds(int chunk, int spm) { return (size_t)chunk * spm * 5; }
+
+size_t strip_cluster_lds(int chunk, int spm, int stage, int max_gap) {
+  return strip_cal_lds_al(stage ? chunk : 0, spm) + (kStripThreads / 64) * strip_win_lds(64 + 2 * (max_gap + 1));
+}
 
 void launch_cluster_strips(const StripArgs& a, int* scan_scratch, hipStream_t st) {
-  const int nb = std::max(1, (int)std::min<long>(((long)a.n + 255) / 256, 16384));
-  const int C = strip_chunks(a.n_modules);
+  const int C = strip_chunks(a.n_modules, a.chunk);
   const long n_b = (long)a.n_events * (C + 1);
   hipLaunchKernelGGL(k_strip_bounds, dim3((unsigned)std::min<long>((n_b + 255) / 256, 16384)), dim3(256), 0, st, a, C);
-  hipLaunchKernelGGL(k_strip_codes, dim3((unsigned)C), dim3(256), 0, st, a, C);
-  hipLaunchKernelGGL(k_strip_flags, dim3(nb), dim3(256), 0, st, a);
-  exclusive_scan(a.flag, a.n, a.pos, scan_scratch, st);
-  hipLaunchKernelGGL(k_strip_write, dim3(nb), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(k_strip_cluster, dim3((unsigned)C), dim3(kStripThreads),
+                     strip_cluster_lds(a.chunk, a.spm, a.stage, a.max_gap), st, a, C);
+  const long nw = (long)a.n_events * C;
+  exclusive_scan(a.cnt, nw, a.cnt_off, scan_scratch, st);
+  const long nb = std::max<long>(1, std::min<long>((nw * 64 + 255) / 256, 16384));
+  hipLaunchKernelGGL(k_strip_emit, dim3((unsigned)nb), dim3(256), 0, st, a, C);
 }
 
 }  // namespace kfx
