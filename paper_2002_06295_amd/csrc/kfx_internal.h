@@ -9,6 +9,17 @@
 
 namespace kfx {
 
+// Logical block of this workgroup when workgroups are dealt to the 8 XCDs
+// in turn: XCD x takes logical blocks [x * per, (x + 1) * per), so that
+// neighbouring logical blocks share an XCD and its L2; -1 = idle (launch
+// 8 * per workgroups).
+__device__ inline int xcd_block(int nblk) {
+  const int per = (nblk + 7) >> 3;
+  const int lb = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+  return lb < nblk ? lb : -1;
+}
+inline int xcd_grid(int nblk) { return ((nblk + 7) >> 3) << 3; }
+
 // Workspace of the hit binning (a counting sort keyed by event, layer and
 // (eta, phi) bin).  counts must hold n_keys + 1 entries.
 struct BinWork {
@@ -31,12 +42,15 @@ struct DupArgs {
   const float* chi2_c;   // [S*K]
   int S, K, H, n_hits;   // seeds, slots per seed, list capacity, hit count
   int num, den;          // shared-hit fraction
-  int* list;             // [S][H] ascending distinct hits of each track, -1 after
+  int* list;             // [S][H] ascending distinct hits of each track; the
+                         // lists of a block's tracks back to back from the
+                         // block's first row on
   int* next;             // [S][H] next entry holding the same hit, -1 at the end
   int* head;             // [n_hits] one holder's entry, -2 once the hit is
                          // known to be shared
   int* head2;            // [n_hits] of a shared hit: last entry pushed, -1 none
-  int4* key;             // [S] n_hits, n_holes, chi2 bits, hit count of the list
+  int4* key;             // [S] n_hits, n_holes, chi2 bits, and the hit count
+                         // of the list | its offset in the block's rows << 8
   int* dup_of;           // [S] output
 };
 

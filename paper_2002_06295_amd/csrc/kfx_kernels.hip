@@ -17,13 +17,6 @@
 namespace kfx {
 
 // ---------------------------------------------------------------- utility
-// logical block of this workgroup when workgroups are dealt to the 8 XCDs
-// in turn: XCD x takes logical blocks [x * per, (x + 1) * per); -1 = idle
-__device__ inline int xcd_block(int nblk) {
-  const int per = (nblk + 7) >> 3;
-  const int lb = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
-  return lb < nblk ? lb : -1;
-}
 
 __global__ void __launch_bounds__(256) k_fill_i32(int* p, long n, int v) {
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) p[i] = v;
@@ -1308,14 +1301,25 @@ __device__ inline int wave_sort_asc(int v, int lane) {
   return v;
 }
 
+// The lists of a block's tracks lie back to back in the block's segment of
+// the list array (kDupRows * H entries from the block's first track on), so
+// that the later passes, which read a list's entries only, fetch about one
+// line for the four short lists together; key.w holds a track's list length
+// (bits 0-7) and its offset in the segment (bits 8 on).
+__device__ inline int dup_len(int w) { return w & 0xff; }
+__device__ inline const int* dup_list(const DupArgs& a, int b, int w) {
+  return a.list + (long)(b / kDupRows) * kDupRows * a.H + (w >> 8);
+}
+
 __global__ void __launch_bounds__(256) k_dup_lists(DupArgs a, int nblk) {
+  __shared__ int nrow[kDupRows];
   const int lb = xcd_block(nblk);
-  if (lb < 0) return;
-  const int lane = threadIdx.x & 63;
-  const int b = lb * kDupRows + (int)(threadIdx.x >> 6);
-  if (b >= a.S) return;  // whole wavefront
+  if (lb < 0) return;  // whole block
+  const int lane = threadIdx.x & 63, wv = (int)(threadIdx.x >> 6);
+  const int b = lb * kDupRows + wv;
+  const bool valid = b < a.S;  // whole wavefront
   const int H = a.H;
-  const int nc = a.n_cands[b];
+  const int nc = valid ? a.n_cands[b] : 0;
   int v = INT_MAX;
   if (nc > 0 && lane < H) {
     const int h = a.hits[(long)b * a.K * H + lane];
@@ -1327,16 +1331,18 @@ __global__ void __launch_bounds__(256) k_dup_lists(DupArgs a, int nblk) {
   const unsigned long long m = __ballot(keep);
   const int n = __popcll(m);
   const int pos = __popcll(m & ((1ull << lane) - 1ull));
-  int* row = a.list + (long)b * H;
-  // positions n..H-1 are cleared by their own lanes; kept lanes write below n
-  if (lane >= n && lane < H) row[lane] = -1;
+  if (lane == 0) nrow[wv] = n;
+  __syncthreads();
+  if (!valid) return;
+  int off = 0;
+  for (int w = 0; w < wv; ++w) off += nrow[w];
   if (keep) {
-    row[pos] = v;
+    a.list[(long)lb * kDupRows * H + off + pos] = v;
     a.head[v] = b * H + pos;  // one of the hit's holders wins
   }
   if (lane == 0) {
     const long e = (long)b * a.K;
-    a.key[b] = nc > 0 ? make_int4(a.n_hits_c[e], a.n_holes_c[e], __float_as_int(a.chi2_c[e]), n)
+    a.key[b] = nc > 0 ? make_int4(a.n_hits_c[e], a.n_holes_c[e], __float_as_int(a.chi2_c[e]), n | (off << 8))
                       : make_int4(0, 0, 0, 0);
     a.dup_of[b] = nc > 0 ? -1 : -2;
   }
@@ -1355,9 +1361,9 @@ __global__ void __launch_bounds__(256) k_dup_mark(DupArgs a, int nblk) {
   const int b = lb * kDupRows + (int)(threadIdx.x >> 6);
   if (b >= a.S) return;
   const int H = a.H;
-  const int nb = a.key[b].w;
+  const int w = a.key[b].w, nb = dup_len(w);
   if (lane < nb) {
-    const int h = a.list[(long)b * H + lane];
+    const int h = dup_list(a, b, w)[lane];
     if (a.head[h] != b * H + lane) {
       a.head[h] = -2;
       a.head2[h] = -1;
@@ -1372,9 +1378,9 @@ __global__ void __launch_bounds__(256) k_dup_push(DupArgs a, int nblk) {
   const int b = lb * kDupRows + (int)(threadIdx.x >> 6);
   if (b >= a.S) return;
   const int H = a.H;
-  const int nb = a.key[b].w;
+  const int w = a.key[b].w, nb = dup_len(w);
   if (lane < nb) {
-    const int h = a.list[(long)b * H + lane];
+    const int h = dup_list(a, b, w)[lane];
     if (a.head[h] == -2) {
       const int e = b * H + lane;
       a.next[e] = atomicExch(a.head2 + h, e);
@@ -1407,10 +1413,10 @@ __global__ void __launch_bounds__(256) k_dup_find(DupArgs a, int nblk) {
   const int b = lb * kDupRows + (int)(threadIdx.x >> 6);
   if (b >= a.S) return;  // whole wavefront
   const int4 kb = a.key[b];
-  const int nb = kb.w;
+  const int nb = dup_len(kb.w);
   if (nb == 0) return;  // dup_of already -1 (no hits) or -2 (no track)
   const int H = a.H;
-  const int h = lane < nb ? a.list[(long)b * H + lane] : -1;
+  const int h = lane < nb ? dup_list(a, b, kb.w)[lane] : -1;
   int e = (lane < nb && a.head[h] == -2) ? a.head2[h] : -1;  // -1: no other holder
   int best = -1;  // uniform across the wave
   int4 kbest = make_int4(0, 0, 0, 0);
@@ -1438,8 +1444,8 @@ __global__ void __launch_bounds__(256) k_dup_find(DupArgs a, int nblk) {
     const int l = __ffsll((long long)m) - 1;
     const int J = rl_i(j, l);
     const int4 kJ = make_int4(rl_i(kj.x, l), rl_i(kj.y, l), rl_i(kj.z, l), rl_i(kj.w, l));
-    const int nJ = kJ.w;
-    const int v = lane < nJ ? a.list[(long)J * H + lane] : -2;
+    const int nJ = dup_len(kJ.w);
+    const int v = lane < nJ ? dup_list(a, J, kJ.w)[lane] : -2;
     bool hit = false;
     for (int y = 0; y < nJ; ++y) hit |= (lane < nb) && (h == rl_i(v, y));
     const int shared = __popcll(__ballot(hit));

@@ -22,7 +22,7 @@ namespace kfx {
 
 namespace {
 
-constexpr int kStripThreads = 256;
+constexpr int kStripThreads = 512;  // 8 wavefronts
 
 // LDS of the strip clustering block: the chunk's calibration (4-byte noise
 // and 1-byte bad flag per strip), then one window per wavefront (module,
@@ -42,10 +42,9 @@ __device__ inline bool in_table(const StripArgs& a, int m, int s) {
   return m >= 0 && m < a.n_modules && s >= 0 && s < a.spm;
 }
 
-// The calibration a block works with: its chunk's modules staged in LDS
-// (nm of them from m0; none when the table is not staged), any other
-// module read from HBM (the digis next to a chunk's edge, or a module out
-// of order).
+// The calibration a block works with: its chunk's modules [m0, m0 + nm)
+// staged in LDS (nm = 0 when the table is not staged), any other module
+// read from HBM.
 struct Calib {
   const float* nz;
   const unsigned char* bd;
@@ -83,9 +82,19 @@ __device__ inline bool strips_linked(const StripArgs& a, const Calib& K, int mj,
 }
 
 // A wavefront's window of digis [w0, w1) in LDS: module, strip, ADC, code
-// and noise of each; a digi outside it is read from HBM and classified again.
+// and noise of each; a digi outside it is read from HBM.  The window's
+// digis of modules outside the block's chunk (the digis around the chunk's
+// edges) are not classified when the window is filled, and a digi read
+// from HBM is not classified when read (code kUnclassified): the cluster
+// searches below look at such a digi's code only when a digi of the
+// searched module lies beyond it, which in sorted input never happens, and
+// then classify it (resolve).  `sorted`: the window's digis are in
+// ascending module order.
+constexpr unsigned int kUnclassified = 4;
+
 struct Win {
   int w0, w1;
+  bool sorted;
   int* m;
   int* s;
   float* nz;
@@ -99,7 +108,7 @@ struct Digi {
   float nz;
 };
 
-__device__ inline Digi digi_at(const StripArgs& a, const Calib& K, const Win& w, int j) {
+__device__ inline Digi digi_at(const StripArgs& a, const Win& w, int j) {
   Digi d;
   if (j >= w.w0 && j < w.w1) {
     const int k = j - w.w0;
@@ -112,9 +121,63 @@ __device__ inline Digi digi_at(const StripArgs& a, const Calib& K, const Win& w,
     d.m = a.module[j];
     d.s = a.strip[j];
     d.q = a.adc[j];
-    d.code = code_from(a, K, d.m, d.s, d.q, d.nz);
+    d.code = kUnclassified;
+    d.nz = 0.0f;
   }
   return d;
+}
+
+__device__ inline void resolve(const StripArgs& a, const Calib& K, Digi& d) {
+  if (d.code == kUnclassified) d.code = code_from(a, K, d.m, d.s, d.q, d.nz);
+}
+
+// The chunk's calibration (ncal strips from module m0 on) into LDS: 16-byte
+// loads, four per thread in flight, where both tables' ranges are 16-byte
+// aligned and whole (the common case: strips_per_module a multiple of 16),
+// else one strip at a time.
+__device__ inline void stage_calibration(const StripArgs& a, int m0, int ncal, float* nz_l, unsigned char* bd_l,
+                                         int tid) {
+  const float* nz = a.noise + (long)m0 * a.spm;
+  const unsigned char* bd = a.bad + (long)m0 * a.spm;
+  const bool al = ((reinterpret_cast<uintptr_t>(nz) | reinterpret_cast<uintptr_t>(bd)) & 15) == 0 &&
+                  ((size_t)a.chunk * a.spm * 4 & 15) == 0 && (ncal & 15) == 0;  // bd_l's offset too
+  if (al) {
+    const float4* nz4 = reinterpret_cast<const float4*>(nz);
+    const uint4* bd16 = reinterpret_cast<const uint4*>(bd);
+    float4* nzl4 = reinterpret_cast<float4*>(nz_l);
+    uint4* bdl16 = reinterpret_cast<uint4*>(bd_l);
+    const int n4 = ncal >> 2, n16 = ncal >> 4;
+    // iteration i: noise words tid + T (4 i + u), u < 4, and bad-flag word
+    // tid + T i (a quarter as many; T threads); indices clamped to the last word
+    // (which is then copied by several threads, with the same value) so
+    // that no load waits behind a branch
+    for (int k = tid; k < n4; k += 4 * kStripThreads) {
+      const int kb = min(tid + ((k - tid) >> 2), n16 - 1);
+      int ix[4];
+      float4 v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        ix[u] = min(k + u * kStripThreads, n4 - 1);
+        v[u] = nz4[ix[u]];
+      }
+      const uint4 w = bd16[kb];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) nzl4[ix[u]] = v[u];
+      bdl16[kb] = w;
+    }
+  } else {
+    for (int k = tid; k < ncal; k += kStripThreads) {
+      nz_l[k] = nz[k];
+      bd_l[k] = bd[k];
+    }
+  }
+}
+
+// a digi of module m among the digis [j0, j1)
+__device__ inline bool module_in(const StripArgs& a, const Win& w, int m, int j0, int j1) {
+  for (int t = j0; t < j1; ++t)
+    if (((t >= w.w0 && t < w.w1) ? w.m[t - w.w0] : a.module[t]) == m) return true;
+  return false;
 }
 
 }  // namespace
@@ -150,7 +213,7 @@ __global__ void __launch_bounds__(256) k_strip_bounds(StripArgs a, int C) {
 // One pass over the digis, module-major: block c stages the calibration of
 // its chunk (noise and bad flags of `chunk` modules, 30 KB for 8 modules of
 // 768 strips) in LDS once, then each of its wavefronts takes the chunk's
-// digis of one event after another (wavefront w: events w, w + 4, ...), 64
+// digis of one event after another (wavefront w: events w, w + 8, ...), 64
 // at a time: the 64 digis and max_gap + 1 on each side are read and
 // classified once into an LDS window, where the neighbour tests and walks
 // find them (a walk that leaves the window reads HBM).  A
@@ -162,23 +225,24 @@ __global__ void __launch_bounds__(256) k_strip_bounds(StripArgs a, int C) {
 // from the chunk's first digi on (never more clusters than digis), in digi
 // order, with their count; k_strip_emit then moves them to their place in
 // the output.  The calibration is read once and the digis once
-// (neighbours through the caches); no per-digi codes or flags go through
-// HBM.
+// (neighbours through the caches; the window's digis of the neighbouring
+// chunks are not classified, as the Win note says); no per-digi codes or
+// flags go through HBM.
 __global__ void __launch_bounds__(kStripThreads) k_strip_cluster(StripArgs a, int C) {
   extern __shared__ __align__(16) unsigned char cal_lds[];
-  const int c = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
+  // neighbouring chunks on one XCD: the digis at their common edge are
+  // read through one L2
+  const int c = xcd_block(C), tid = threadIdx.x, lane = tid & 63;
+  if (c < 0) return;  // whole block
   Calib K;
   K.m0 = c * a.chunk;
   K.nm = a.stage ? max(0, min(a.chunk, a.n_modules - K.m0)) : 0;
+  const int chunk_lo = K.m0, chunk_hi = K.m0 + a.chunk;
   float* nz_l = reinterpret_cast<float*>(cal_lds);
   unsigned char* bd_l = cal_lds + (size_t)a.chunk * a.spm * 4;
   K.nz = nz_l;
   K.bd = bd_l;
-  const int ncal = K.nm * a.spm;
-  for (int k = tid; k < ncal; k += kStripThreads) {
-    nz_l[k] = a.noise[(long)K.m0 * a.spm + k];
-    bd_l[k] = a.bad[(long)K.m0 * a.spm + k];
-  }
+  stage_calibration(a, K.m0, K.nm * a.spm, nz_l, bd_l, tid);
   // this wavefront's window: 64 digis and max_gap + 1 on each side
   const int halo = a.max_gap + 1, wn = 64 + 2 * halo;
   unsigned char* wbase = cal_lds + strip_cal_lds_al(a.stage ? a.chunk : 0, a.spm) + (size_t)(tid >> 6) * strip_win_lds(wn);
@@ -198,25 +262,48 @@ __global__ void __launch_bounds__(kStripThreads) k_strip_cluster(StripArgs a, in
       // the window's digis, classified once, in LDS
       W.w0 = max(ev_start, base - halo);
       W.w1 = min(ev_end, base + 64 + halo);
-      for (int j = W.w0 + lane; j < W.w1; j += 64) {
-        const int k = j - W.w0;
-        const int m = a.module[j], st = a.strip[j], q = a.adc[j];
-        float nzj;
-        W.c[k] = (unsigned char)code_from(a, K, m, st, q, nzj);
+      auto put = [&](int k, int m, int st, int q) {
+        float nzj = 0.0f;
+        W.c[k] = (m >= chunk_lo && m < chunk_hi) ? (unsigned char)code_from(a, K, m, st, q, nzj)
+                                                 : (unsigned char)kUnclassified;
         W.m[k] = m;
         W.s[k] = st;
         W.q[k] = (unsigned short)q;
         W.nz[k] = nzj;
+      };
+      // two digis a lane at a time, their loads together (the second index
+      // clamped to the window's last digi, written then twice, alike)
+      for (int j = W.w0 + lane; j < W.w1; j += 128) {
+        const int j2 = min(j + 64, W.w1 - 1);
+        const int m = a.module[j], st = a.strip[j], q = a.adc[j];
+        const int m2 = a.module[j2], st2 = a.strip[j2], q2 = a.adc[j2];
+        put(j - W.w0, m, st, q);
+        put(j2 - W.w0, m2, st2, q2);
       }
       wave_sync();
+      {
+        bool up = true;
+        for (int k = lane; k + 1 < W.w1 - W.w0; k += 64) up &= W.m[k] <= W.m[k + 1];
+        W.sorted = __ballot(!up) == 0;
+      }
       const int i = base + lane;
       int kept = 0;
       StripRec r;
-      const Digi di = i < hi ? digi_at(a, K, W, i) : Digi{0, 0, 0, 0u, 0.0f};
+      Digi di = Digi{0, 0, 0, 0u, 0.0f};
+      if (i < hi) {
+        di = digi_at(a, W, i);
+        resolve(a, K, di);
+      }
       if (di.code & 1u) {
         bool head = true;
         for (int j = i - 1, jl = max(ev_start, i - 1 - a.max_gap); j >= jl; --j) {
-          const Digi dj = digi_at(a, K, W, j);
+          Digi dj = digi_at(a, W, j);
+          // past a digi of another module, only a digi of di.m farther back
+          // could still be linked to di; without one, di heads a cluster
+          // whatever the codes in between (in a sorted window, [jl, j) lies
+          // in it and holds none)
+          if (dj.m != di.m && (W.sorted || !module_in(a, W, di.m, jl, j))) break;
+          resolve(a, K, dj);
           if (dj.code & 1u) {
             head = !strips_linked(a, K, dj.m, dj.s, di.m, di.s);
             break;
@@ -239,7 +326,10 @@ __global__ void __launch_bounds__(kStripThreads) k_strip_cluster(StripArgs a, in
             int nx = -1;
             Digi dn = dc;
             for (int j = cur + 1, lim = min(ev_end, cur + 2 + a.max_gap); j < lim; ++j) {
-              const Digi dj = digi_at(a, K, W, j);
+              Digi dj = digi_at(a, W, j);
+              // the same: without a digi of dc.m from j on, the cluster ends
+              if (dj.m != dc.m && ((W.sorted && lim <= W.w1) || !module_in(a, W, dc.m, j + 1, lim))) break;
+              resolve(a, K, dj);
               if (dj.code & 1u) {
                 nx = j;
                 dn = dj;
@@ -309,7 +399,7 @@ void launch_cluster_strips(const StripArgs& a, int* scan_scratch, hipStream_t st
   const int C = strip_chunks(a.n_modules, a.chunk);
   const long n_b = (long)a.n_events * (C + 1);
   hipLaunchKernelGGL(k_strip_bounds, dim3((unsigned)std::min<long>((n_b + 255) / 256, 16384)), dim3(256), 0, st, a, C);
-  hipLaunchKernelGGL(k_strip_cluster, dim3((unsigned)C), dim3(kStripThreads),
+  hipLaunchKernelGGL(k_strip_cluster, dim3((unsigned)xcd_grid(C)), dim3(kStripThreads),
                      strip_cluster_lds(a.chunk, a.spm, a.stage, a.max_gap), st, a, C);
   const long nw = (long)a.n_events * C;
   exclusive_scan(a.cnt, nw, a.cnt_off, scan_scratch, st);
