@@ -479,9 +479,10 @@ int build_impl(kfx_ctx* c, const kfx_hits* hits, const int32_t* seeds, const int
   if (p->blocks < 0) return fail(c, KFX_EINVAL, "blocks < 0");
   if (p->scan_tile < 0) return fail(c, KFX_EINVAL, "scan_tile < 0");
   if (p->waves_per_simd < 0 || p->waves_per_simd > 2) return fail(c, KFX_EINVAL, "waves_per_simd must be 0, 1 or 2");
-  if (p->lanes_per_seed != 0 && ((p->lanes_per_seed != 4 && p->lanes_per_seed != 8 && p->lanes_per_seed != 16) ||
-                                 p->lanes_per_seed < p->max_cands))
-    return fail(c, KFX_EINVAL, "lanes_per_seed must be 0, or 4, 8 or 16 and at least max_cands");
+  if (p->lanes_per_seed != 0 && ((p->lanes_per_seed != 4 && p->lanes_per_seed != 6 && p->lanes_per_seed != 8 &&
+                                  p->lanes_per_seed != 16) ||
+                                 p->lanes_per_seed < p->max_cands || (p->lanes_per_seed == 6 && p->max_cands < 5)))
+    return fail(c, KFX_EINVAL, "lanes_per_seed must be 0, or 4, 6 (K of 5 or 6), 8 or 16 and at least max_cands");
   {
     const int lanes = p->lanes_per_seed ? p->lanes_per_seed : fused_lanes_for(p->max_cands);
     if (p->seeds_per_wave < 0 || p->seeds_per_wave > 64 / lanes)
@@ -861,10 +862,10 @@ int kfx_autotune_build(kfx_ctx* c, const kfx_hits* hits, const int32_t* seeds, c
   if (!rc) rc = hip_check(c, hipStreamSynchronize(st), "stats save");
   kfx_build_params cur = *p;
   cur.mode = KFX_MODE_FUSED;
-  const int lp0 = fused_lanes_for(p->max_cands);
+  const int lp0 = fused_lanes_pow2(p->max_cands);
   if (cur.block_threads == 0) cur.block_threads = 256;
   if (cur.blocks == 0) cur.blocks = c->n_cu * 4;
-  if (cur.lanes_per_seed == 0) cur.lanes_per_seed = lp0;
+  if (cur.lanes_per_seed == 0) cur.lanes_per_seed = fused_lanes_for(p->max_cands);
   if (cur.scan_tile == 0) cur.scan_tile = 64;
   if (cur.waves_per_simd == 0) cur.waves_per_simd = 1;
   if (cur.seeds_per_wave == 0) cur.seeds_per_wave = 64 / cur.lanes_per_seed;
@@ -911,8 +912,12 @@ int kfx_autotune_build(kfx_ctx* c, const kfx_hits* hits, const int32_t* seeds, c
     } else if (dim == 2) {
       for (int b : {1, 2, 4, 8}) { q.blocks = c->n_cu * b; cand.push_back(q); }
     } else if (dim == 3) {
-      // a full wavefront of seeds for each lane count
-      for (int l = lp0; l <= 16; l <<= 1) {
+      // a full wavefront of seeds for each lane count (6-lane groups for K
+      // of 5 or 6)
+      std::vector<int> ls;
+      if (p->max_cands >= 5 && p->max_cands <= 6) ls.push_back(6);
+      for (int l = lp0; l <= 16; l <<= 1) ls.push_back(l);
+      for (int l : ls) {
         q.lanes_per_seed = l;
         q.seeds_per_wave = 64 / l;
         cand.push_back(q);

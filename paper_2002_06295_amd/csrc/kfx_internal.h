@@ -143,7 +143,8 @@ size_t fused_static_lds_bytes();
 void launch_build_init(const BuildArgs& a, hipStream_t st);
 void launch_build_fused(const BuildArgs& a, const TracksOut& o, int* seed_counter, int blocks, int threads,
                         int lanes, int waves_per_simd, hipStream_t st, const hipEvent_t* ev);
-int fused_lanes_for(int K);
+int fused_lanes_for(int K);   // default lanes per seed group
+int fused_lanes_pow2(int K);  // the smallest power of two >= max(K, 4)
 void launch_find_duplicates(const DupArgs& a, hipStream_t st);
 void launch_mask_hits(const MaskArgs& a, const int* layer_in, hipStream_t st);
 int strip_chunks(int n_modules, int chunk);

@@ -103,7 +103,7 @@ def test_autotune_shapes_are_bit_identical(dev, kfx, setup):
     ref = snapshot(ctx.build_tracks(hits, seeds, sev, **kw))
     choice = ctx.autotune_build(hits, seeds, sev, reps=1, **kw)
     assert choice["block_threads"] in (64, 128, 256)
-    assert choice["lanes_per_seed"] in (8, 16) and choice["scan_tile"] in (16, 32, 64, 128, 256)
+    assert choice["lanes_per_seed"] in (6, 8, 16) and choice["scan_tile"] in (16, 32, 64, 128, 256)
     assert choice["blocks"] > 0 and choice["ms"] > 0
     assert 1 <= choice["seeds_per_wave"] <= 64 // choice["lanes_per_seed"]
     tuned = {k: v for k, v in choice.items() if k != "ms"}
@@ -113,7 +113,11 @@ def test_autotune_shapes_are_bit_identical(dev, kfx, setup):
                   dict(block_threads=128, blocks=1000, lanes_per_seed=8, scan_tile=100000),
                   dict(block_threads=256, waves_per_simd=2, scan_tile=8),
                   dict(lanes_per_seed=8, seeds_per_wave=1, blocks=7),
-                  dict(lanes_per_seed=16, seeds_per_wave=3, scan_tile=32)):
+                  dict(lanes_per_seed=16, seeds_per_wave=3, scan_tile=32),
+                  # groups of 6 lanes: ten seeds a wavefront, lanes 60-63 idle
+                  dict(lanes_per_seed=6),
+                  dict(lanes_per_seed=6, waves_per_simd=2, block_threads=128, scan_tile=16),
+                  dict(lanes_per_seed=6, seeds_per_wave=3, blocks=5, scan_tile=100000)):
         assert same(snapshot(ctx.build_tracks(hits, seeds, sev, **kw, **shape)), ref), shape
 
 
@@ -167,7 +171,9 @@ def test_build_timing_split(dev, kfx, setup):
 def test_bad_launch_shapes_rejected(dev, kfx, setup):
     ev, ctx, hits, seeds, sev, kw = setup
     for bad in (dict(lanes_per_seed=4), dict(lanes_per_seed=12), dict(scan_tile=-1), dict(block_threads=96),
-                dict(waves_per_simd=3), dict(seeds_per_wave=9), dict(lanes_per_seed=16, seeds_per_wave=5),
+                dict(waves_per_simd=3), dict(seeds_per_wave=11), dict(lanes_per_seed=8, seeds_per_wave=9),
+                dict(lanes_per_seed=16, seeds_per_wave=5),
+                dict(lanes_per_seed=6, seeds_per_wave=11), dict(lanes_per_seed=5),
                 dict(seeds_per_wave=-1)):
         with pytest.raises(kfx.KfxError):
             ctx.build_tracks(hits, seeds, sev, **kw, **bad)
