@@ -105,8 +105,9 @@ typedef struct {
   int32_t lanes_per_seed;/* fused: lanes of the group that holds one seed's
                             candidates (one lane per slot): 4, 8 or 16, at
                             least K, or 6 for K of 5 or 6 (ten seeds a
-                            wavefront); 0 = 6 for K of 5 or 6, else the
-                            smallest power of two that fits K                */
+                            wavefront), or 12 for K of 9 to 12 (five);
+                            0 = 6 for K of 5 or 6, else the smallest power
+                            of two that fits K                               */
   int32_t scan_tile;     /* fused: windows holding more hits than this are
                             scanned by the whole wavefront together; smaller
                             ones by their own lane; 0 = 64                    */
@@ -424,8 +425,8 @@ void kfx_graph_destroy(kfx_graph* graph);
  * per SIMD at the default shape (when waves_per_simd is 0), then from the
  * faster one parameter at a time: scan_tile in {16, 32, 64, 128, 256},
  * block_threads in {64, 128, 256}, blocks in {1, 2, 4, 8} per compute
- * unit, lanes_per_seed 6 (K of 5 or 6) and from the smallest power of
- * two >= K up to 16,
+ * unit, lanes_per_seed 6 (K of 5 or 6) or 12 (K of 9 to 12) and from
+ * the smallest power of two >= K up to 16,
  * waves_per_simd in {1, 2}, seeds_per_wave from 2 up to 64 /
  * lanes_per_seed, then scan_tile, block_threads and waves_per_simd once
  * more.  Writes the fastest shape into

@@ -480,9 +480,11 @@ int build_impl(kfx_ctx* c, const kfx_hits* hits, const int32_t* seeds, const int
   if (p->scan_tile < 0) return fail(c, KFX_EINVAL, "scan_tile < 0");
   if (p->waves_per_simd < 0 || p->waves_per_simd > 2) return fail(c, KFX_EINVAL, "waves_per_simd must be 0, 1 or 2");
   if (p->lanes_per_seed != 0 && ((p->lanes_per_seed != 4 && p->lanes_per_seed != 6 && p->lanes_per_seed != 8 &&
-                                  p->lanes_per_seed != 16) ||
-                                 p->lanes_per_seed < p->max_cands || (p->lanes_per_seed == 6 && p->max_cands < 5)))
-    return fail(c, KFX_EINVAL, "lanes_per_seed must be 0, or 4, 6 (K of 5 or 6), 8 or 16 and at least max_cands");
+                                  p->lanes_per_seed != 12 && p->lanes_per_seed != 16) ||
+                                 p->lanes_per_seed < p->max_cands || (p->lanes_per_seed == 6 && p->max_cands < 5) ||
+                                 (p->lanes_per_seed == 12 && p->max_cands < 9)))
+    return fail(c, KFX_EINVAL,
+                "lanes_per_seed must be 0, or 4, 6 (K of 5 or 6), 8, 12 (K of 9 to 12) or 16 and at least max_cands");
   {
     const int lanes = p->lanes_per_seed ? p->lanes_per_seed : fused_lanes_for(p->max_cands);
     if (p->seeds_per_wave < 0 || p->seeds_per_wave > 64 / lanes)
@@ -913,9 +915,10 @@ int kfx_autotune_build(kfx_ctx* c, const kfx_hits* hits, const int32_t* seeds, c
       for (int b : {1, 2, 4, 8}) { q.blocks = c->n_cu * b; cand.push_back(q); }
     } else if (dim == 3) {
       // a full wavefront of seeds for each lane count (6-lane groups for K
-      // of 5 or 6)
+      // of 5 or 6, 12-lane groups for K of 9 to 12)
       std::vector<int> ls;
       if (p->max_cands >= 5 && p->max_cands <= 6) ls.push_back(6);
+      if (p->max_cands >= 9 && p->max_cands <= 12) ls.push_back(12);
       for (int l = lp0; l <= 16; l <<= 1) ls.push_back(l);
       for (int l : ls) {
         q.lanes_per_seed = l;

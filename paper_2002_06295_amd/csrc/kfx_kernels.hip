@@ -736,8 +736,8 @@ __global__ void __launch_bounds__(kRowThreads) k_build_fused_rows(BuildArgs a, T
 
 // ---------------------------------------------- fused persistent kernel (a12)
 // One wavefront runs 64 / G seed groups of G lanes (G = lanes per seed:
-// 4, 8 or 16 and >= K, or 6 for K of 5 or 6, which leaves 4 of the 64 lanes
-// idle instead of 16); each lane holds one candidate slot in registers
+// 4, 8 or 16 and >= K, or 6 for K of 5 or 6 and 12 for K of 9 to 12, which
+// leave 4 of the 64 lanes idle); each lane holds one candidate slot in registers
 // for the whole search.  A group takes a new seed from a device counter as
 // soon as its seed finishes, so uneven events and candidates of uneven
 // length share the machine.  The per-step pieces are those of the plain
@@ -794,20 +794,28 @@ __device__ inline uint64_t dpp_min_step(uint64_t v) {
   return o < v ? o : v;
 }
 
-// Groups of 6 lanes (lanes 6 j .. 6 j + 5; lanes 60-63 idle) do not align
-// with the DPP rows: three lane shuffles instead, each lane taking the
-// minimum with the lane one, then two, then again two places further round
-// its group (src1, src2), so that it has seen 2, then 4, then all 6.
+// Groups of 6 or 12 lanes (lanes G j .. G j + G - 1; the last 4 lanes of
+// the wavefront idle) do not align with the DPP rows: lane shuffles
+// instead.  A lane that holds the minimum over c consecutive lanes of its
+// group (counted round the group) takes the minimum with the lane
+// min(c, G - c) places further round, which holds the next ones; from
+// c = 1 this covers the group in 3 steps for G = 6 (1, 2, 2) and 4 for
+// G = 12 (1, 2, 4, 4).
 __device__ inline uint64_t shfl_min_step(uint64_t v, int src) {
   const int lo = __shfl((int)(uint32_t)v, src, 64);
   const int hi = __shfl((int)(uint32_t)(v >> 32), src, 64);
   const uint64_t o = ((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo;
   return o < v ? o : v;
 }
-__device__ inline uint64_t group_min6(uint64_t v, int src1, int src2) {
-  v = shfl_min_step(v, src1);
-  v = shfl_min_step(v, src2);
-  return shfl_min_step(v, src2);
+template <int G>
+__device__ inline uint64_t group_min_rot(uint64_t v, int glane, int gl) {
+#pragma unroll
+  for (int c = 1; c < G; c += (c < G - c ? c : G - c)) {
+    const int off = c < G - c ? c : G - c;
+    const int j = gl + off;
+    v = shfl_min_step(v, glane + (j >= G ? j - G : j));
+  }
+  return v;
 }
 
 template <int G>
@@ -1068,8 +1076,6 @@ k_build_fused(BuildArgs a, TracksOut o, int* seed_counter) {
   const int K = a.K;
   const double kappa = -kHcD * G.bz;
   const unsigned long long gmask = ((G_LANES == 64) ? ~0ull : ((1ull << G_LANES) - 1ull)) << glane;
-  // 6-lane groups: the lanes one and two places further round the group
-  const int src1 = glane + (gl + 1) % G_LANES, src2 = glane + (gl + 2) % G_LANES;
 
   // per-lane counters (a lane sees at most a few thousand steps per launch)
   unsigned int n_steps = 0, n_pairs = 0, n_upd = 0;
@@ -1204,7 +1210,7 @@ k_build_fused(BuildArgs a, TracksOut o, int* seed_counter) {
       // no group of the wave has a child left: the remaining slots stay empty
       if (__ballot(head != ~0ull) == 0) break;
       uint64_t mn;
-      if constexpr (G_LANES == 6) mn = group_min6(head, src1, src2);
+      if constexpr (G_LANES == 6 || G_LANES == 12) mn = group_min_rot<G_LANES>(head, glane, gl);
       else mn = group_min<G_LANES>(head);
       const unsigned long long win = __ballot(head == mn && mn != ~0ull) & gmask;
       // winner lane in the wave (unique: keys differ by parent slot); it
@@ -1670,6 +1676,9 @@ void launch_build_fused(const BuildArgs& a, const TracksOut& o, int* seed_counte
       break;
     case 6:
       if (two) KFX_FUSED_KM(6, 2, 6); else KFX_FUSED_KM(6, 1, 6);
+      break;
+    case 12:
+      if (two) KFX_FUSED_KM(12, 2, 12); else KFX_FUSED_KM(12, 1, 12);
       break;
     case 8:
       // K of 5 or 6 keeps a 6-entry best-K list

@@ -121,6 +121,21 @@ def test_autotune_shapes_are_bit_identical(dev, kfx, setup):
         assert same(snapshot(ctx.build_tracks(hits, seeds, sev, **kw, **shape)), ref), shape
 
 
+def test_twelve_lane_groups_bit_identical(dev, kfx, setup):
+    """K = 10 on groups of 12 lanes (five seeds a wavefront, lanes 60-63
+    idle, group minimum by lane shuffles) gives the same tracks as on groups
+    of 16, at one and two wavefronts per SIMD."""
+    ev, ctx, hits, seeds, sev, kw = setup
+    kw10 = dict(kw, max_cands=10)
+    ref = snapshot(ctx.build_tracks(hits, seeds, sev, **kw10, lanes_per_seed=16))
+    assert ref["n_cands"].max() > 6
+    for shape in (dict(lanes_per_seed=12), dict(lanes_per_seed=12, waves_per_simd=2, block_threads=128),
+                  dict(lanes_per_seed=12, seeds_per_wave=2, scan_tile=16)):
+        assert same(snapshot(ctx.build_tracks(hits, seeds, sev, **kw10, **shape)), ref), shape
+    with pytest.raises(kfx.KfxError):
+        ctx.build_tracks(hits, seeds, sev, **kw, lanes_per_seed=12)  # K = 6
+
+
 def test_autotune_cache(dev, kfx, setup, tmp_path, monkeypatch):
     """A second autotuner call with the same device and workload signature
     returns the cached shape and time without building; another signature
